@@ -1,0 +1,200 @@
+"""FP64 CPU oracle of the fast guided filtering layer (arXiv 1803.05619).
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and
+the ``cpu_baseline`` leg of ``bench.py`` may import this package.  The
+product path (``paper_1803_05619_amd``) never imports it, and this package
+never imports the product path: the two share no code.
+
+The arithmetic lives in ``gf_oracle.c`` (plain C, double precision,
+brute-force window loops; see its header for the definition it follows,
+Sec. III-B/C/D, Eq. (1)-(2) and Algorithm 1 of the paper).  This module
+only builds it with gcc and marshals numpy arrays through ctypes.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gf_oracle.c")
+_LIB = os.path.join(_HERE, "libgf_oracle.so")
+
+GUIDE_MODES = {"identity": 0, "grey": 1, "transform": 2}
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile gf_oracle.c into libgf_oracle.so (gcc, -O2, OpenMP)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99",
+               "-Wall", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Guide(ctypes.Structure):
+    _fields_ = [
+        ("hidden", ctypes.c_int),
+        ("w1", ctypes.POINTER(ctypes.c_double)),
+        ("w2", ctypes.POINTER(ctypes.c_double)),
+        ("b2", ctypes.POINTER(ctypes.c_double)),
+        ("lam", ctypes.c_double),
+        ("mu", ctypes.c_double),
+        ("gamma", ctypes.POINTER(ctypes.c_double)),
+        ("beta", ctypes.POINTER(ctypes.c_double)),
+        ("bn_eps", ctypes.c_double),
+        ("slope", ctypes.c_double),
+    ]
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ci = ctypes.c_int
+        lib.gfo_forward.argtypes = [ci] * 11 + [ctypes.POINTER(_Guide), dp, dp, dp, dp, ci, dp]
+        lib.gfo_forward.restype = ci
+        lib.gfo_backward.argtypes = ([ci] * 11 + [ctypes.POINTER(_Guide), dp, dp, dp, dp, ci]
+                                     + [dp] * 6)
+        lib.gfo_backward.restype = ci
+        lib.gfo_guide_apply.argtypes = [ci, ctypes.POINTER(_Guide), ci, ci, ci, ctypes.c_long, dp, dp]
+        lib.gfo_guide_apply.restype = ci
+        lib.gfo_guide_grad_size.argtypes = [ci, ci, ci]
+        lib.gfo_guide_grad_size.restype = ctypes.c_long
+        _lib = lib
+    return _lib
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _guide_struct(guide, keep):
+    """Build the ctypes struct for a transform-guide parameter dict."""
+    if guide is None:
+        return None
+    arrs = {k: _f64(guide[k]).ravel() for k in ("w1", "w2", "b2", "gamma", "beta")}
+    keep.extend(arrs.values())
+    hidden = int(np.asarray(guide["w1"]).shape[0])
+    g = _Guide(hidden, _ptr(arrs["w1"]), _ptr(arrs["w2"]), _ptr(arrs["b2"]),
+               float(guide["lam"]), float(guide["mu"]), _ptr(arrs["gamma"]),
+               _ptr(arrs["beta"]), float(guide.get("bn_eps", 1e-5)),
+               float(guide.get("slope", 0.2)))
+    return g
+
+
+def _mode(guide_mode, guide):
+    if guide_mode is None:
+        guide_mode = "transform" if guide is not None else "identity"
+    return GUIDE_MODES[guide_mode]
+
+
+def _common(I_lo, p_lo, I_hi, eps):
+    I_lo, p_lo, I_hi = _f64(I_lo), _f64(p_lo), _f64(I_hi)
+    n, cin, h, w = I_lo.shape
+    n2, c, h2, w2 = p_lo.shape
+    n3, cin3, H, W = I_hi.shape
+    if (n2, h2, w2) != (n, h, w) or (n3, cin3) != (n, cin):
+        raise ValueError("inconsistent shapes")
+    e = _f64(np.atleast_1d(eps)).ravel()
+    if e.size not in (1, n):
+        raise ValueError("eps must have 1 or n entries")
+    return I_lo, p_lo, I_hi, e, (n, c, h, w, H, W, cin)
+
+
+def forward(I_lo, p_lo, I_hi, r, eps, *, align_corners=False, mean_ab=True,
+            guide=None, guide_mode=None):
+    """q = GF(I_lo, p_lo, I_hi) in float64 (shape [n, c, H, W])."""
+    lib = _load()
+    I_lo, p_lo, I_hi, e, (n, c, h, w, H, W, cin) = _common(I_lo, p_lo, I_hi, eps)
+    keep = []
+    g = _guide_struct(guide, keep)
+    q = np.empty((n, c, H, W), np.float64)
+    rc = lib.gfo_forward(n, c, h, w, H, W, int(r), int(bool(align_corners)),
+                         int(bool(mean_ab)), _mode(guide_mode, guide), cin,
+                         ctypes.byref(g) if g is not None else None,
+                         _ptr(I_lo), _ptr(p_lo), _ptr(I_hi), _ptr(e), e.size, _ptr(q))
+    if rc != 0:
+        raise RuntimeError(f"gfo_forward failed ({rc})")
+    return q
+
+
+def backward(I_lo, p_lo, I_hi, r, eps, dq, *, align_corners=False, mean_ab=True,
+             guide=None, guide_mode=None):
+    """Gradients of <q, dq> w.r.t. every input, in float64.
+
+    Returns a dict with dI_lo, dp_lo, dI_hi, deps (one entry per eps entry)
+    and, for the transform guide, dguide (flat, see guide_grad_split).
+    """
+    lib = _load()
+    I_lo, p_lo, I_hi, e, (n, c, h, w, H, W, cin) = _common(I_lo, p_lo, I_hi, eps)
+    dq = _f64(dq)
+    if dq.shape != (n, c, H, W):
+        raise ValueError("dq shape")
+    keep = []
+    g = _guide_struct(guide, keep)
+    mode = _mode(guide_mode, guide)
+    dI_lo = np.empty_like(I_lo)
+    dp_lo = np.empty_like(p_lo)
+    dI_hi = np.empty_like(I_hi)
+    deps = np.empty(e.size, np.float64)
+    dguide = None
+    if mode == GUIDE_MODES["transform"]:
+        dguide = np.zeros(lib.gfo_guide_grad_size(cin, c, g.hidden), np.float64)
+    rc = lib.gfo_backward(n, c, h, w, H, W, int(r), int(bool(align_corners)),
+                          int(bool(mean_ab)), mode, cin,
+                          ctypes.byref(g) if g is not None else None,
+                          _ptr(I_lo), _ptr(p_lo), _ptr(I_hi), _ptr(e), e.size, _ptr(dq),
+                          _ptr(dI_lo), _ptr(dp_lo), _ptr(dI_hi), _ptr(deps), _ptr(dguide))
+    if rc != 0:
+        raise RuntimeError(f"gfo_backward failed ({rc})")
+    out = {"dI_lo": dI_lo, "dp_lo": dp_lo, "dI_hi": dI_hi, "deps": deps}
+    if dguide is not None:
+        out["dguide"] = dguide
+    return out
+
+
+def guide_apply(X, guide=None, guide_mode=None, cout=None):
+    """G = F(X) for one call (X: [n, cin, H, W]); batch statistics of X."""
+    lib = _load()
+    X = _f64(X)
+    n, cin, H, W = X.shape
+    mode = _mode(guide_mode, guide)
+    if cout is None:
+        cout = np.asarray(guide["w2"]).shape[0] if guide is not None else cin
+    keep = []
+    g = _guide_struct(guide, keep)
+    G = np.empty((n, cout, H, W), np.float64)
+    rc = lib.gfo_guide_apply(mode, ctypes.byref(g) if g is not None else None,
+                             n, cin, cout, H * W, _ptr(X), _ptr(G))
+    if rc != 0:
+        raise RuntimeError(f"gfo_guide_apply failed ({rc})")
+    return G
+
+
+def guide_grad_split(flat, cin, cout, hidden):
+    """Split the flat guide gradient into named parts."""
+    o = 0
+    out = {}
+    for name, size, shape in (("w1", hidden * cin, (hidden, cin)),
+                              ("w2", cout * hidden, (cout, hidden)),
+                              ("b2", cout, (cout,)), ("lam", 1, ()), ("mu", 1, ()),
+                              ("gamma", hidden, (hidden,)), ("beta", hidden, (hidden,))):
+        out[name] = np.asarray(flat[o:o + size]).reshape(shape)
+        o += size
+    return out

@@ -1,0 +1,54 @@
+"""Independent float64 PyTorch compositions used to pin the oracle.
+
+Built from library primitives (avg_pool2d with count_include_pad=False for
+the clipped box mean, F.interpolate for bilinear upsampling, conv2d and
+batch_norm for the guidance transform) and the one-pass statistics form
+that Algorithm 1's adjoint terms imply, so that an error in the oracle's
+brute-force loops or in its hand-written adjoint shows up as a mismatch.
+"""
+import torch
+import torch.nn.functional as F
+
+
+def box(x, r):
+    return F.avg_pool2d(x, 2 * r + 1, stride=1, padding=r, count_include_pad=False)
+
+
+def up(x, H, W, align_corners):
+    return F.interpolate(x, size=(H, W), mode="bilinear", align_corners=bool(align_corners))
+
+
+def transform(x, g):
+    """F(I): 1x1 conv -> lam*h + mu*BN_train(h) -> leaky ReLU -> 1x1 conv + bias."""
+    w1 = torch.as_tensor(g["w1"], dtype=x.dtype)
+    w2 = torch.as_tensor(g["w2"], dtype=x.dtype)
+    b2 = torch.as_tensor(g["b2"], dtype=x.dtype)
+    gamma = torch.as_tensor(g["gamma"], dtype=x.dtype)
+    beta = torch.as_tensor(g["beta"], dtype=x.dtype)
+    return transform_params(x, w1, w2, b2, g["lam"], g["mu"], gamma, beta,
+                            g.get("bn_eps", 1e-5), g.get("slope", 0.2))
+
+
+def transform_params(x, w1, w2, b2, lam, mu, gamma, beta, bn_eps=1e-5, slope=0.2):
+    h = F.conv2d(x, w1[:, :, None, None])
+    bn = F.batch_norm(h, None, None, gamma, beta, training=True, eps=bn_eps)
+    y = lam * h + mu * bn
+    z = F.leaky_relu(y, slope)
+    return F.conv2d(z, w2[:, :, None, None], b2)
+
+
+def guided_filter(G_lo, p_lo, G_hi, r, eps, mean_ab=True, align_corners=False):
+    """q from guides already transformed (G = F(I)); eps: scalar or [n]."""
+    eps = torch.as_tensor(eps, dtype=G_lo.dtype)
+    if eps.ndim == 1 and eps.numel() > 1:
+        eps = eps.view(-1, 1, 1, 1)
+    mI = box(G_lo, r)
+    mP = box(p_lo, r)
+    var = box(G_lo * G_lo, r) - mI * mI
+    cov = box(G_lo * p_lo, r) - mI * mP
+    A = cov / (var + eps)
+    b = mP - A * mI
+    if mean_ab:
+        A, b = box(A, r), box(b, r)
+    H, W = G_hi.shape[-2:]
+    return up(A, H, W, align_corners) * G_hi + up(b, H, W, align_corners)
