@@ -1,0 +1,122 @@
+/*
+ * gf.h — C ABI of the MI355X (gfx950) fast guided filtering layer.
+ *
+ * The operator is the guided filtering layer of Wu et al., "Fast End-to-End
+ * Trainable Guided Filter" (arXiv 1803.05619), Sec. III: given a low-res
+ * guide I_l, a low-res input p_l (the paper's O_l) and a high-res guide I_h,
+ * it returns the high-res output q (the paper's O_h):
+ *
+ *   G = F(I)                     guidance map (identity here; Sec. III-D)
+ *   mean_I, mean_p, var, cov     (2r+1)^2 window means over G_l, p_l, the
+ *                                window clipped to the image and normalised
+ *                                by its in-image pixel count N (box filter
+ *                                f_mu, Sec. III-C)
+ *   A = cov / (var + eps)        local linear model, Eq. (1); A := 0 when
+ *   b = mean_p - A mean_I        var + eps == 0
+ *   Abar, bbar                   window means of A and b (mean_ab = 1, the
+ *                                guided filter the layer reformulates) or
+ *                                A, b themselves (mean_ab = 0, the form of
+ *                                Algorithm 1)
+ *   A_h, b_h                     bilinear upsampling f_up, half-pixel centres
+ *   q = A_h * G_h + b_h          Eq. (2)
+ *
+ * gf_backward is the adjoint (Algorithm 1, extended by the window mean of
+ * A and b when mean_ab = 1): gradients of <q, dq> with respect to I_l, p_l,
+ * I_h and eps.
+ *
+ * Conventions shared by every entry point
+ *  - Tensor pointers are DEVICE pointers (HIP global memory), NCHW
+ *    contiguous, 16-byte aligned.  Shapes:
+ *        I_lo, p_lo      [n, c, h_lo, w_lo]   io_dtype
+ *        I_hi, q_hi      [n, c, h_hi, w_hi]   io_dtype
+ *        dq_hi, dI_hi    [n, c, h_hi, w_hi]   io_dtype
+ *        dI_lo, dp_lo    [n, c, h_lo, w_lo]   float32 (any io_dtype)
+ *        eps, deps       [eps_count]          float32, eps_count = 1 or n
+ *  - h_hi = s * h_lo and w_hi = s * w_lo with one integer factor
+ *    s in {1, 2, 4, 8}; other ratios return GF_ERR_UNSUPPORTED.
+ *  - The caller owns all memory.  Scratch memory is passed in as `ws`
+ *    (device pointer, ws_bytes long, at least gf_workspace_size(...)).
+ *    The library allocates nothing.
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL = default stream)
+ *    and is asynchronous: a return of GF_OK means the arguments were valid
+ *    and the kernels were launched.  Faults inside kernels surface at the
+ *    next synchronisation, as with any HIP launch.
+ *  - Argument checks run on the host before any HIP call; invalid input
+ *    returns an error code, never aborts, and launches nothing.
+ *  - Gradient outputs are overwritten, never accumulated.  deps with
+ *    eps_count = 1 receives the sum over all images.
+ *  - Not re-entrant on one workspace: concurrent calls need distinct ws.
+ */
+#ifndef GF_H
+#define GF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { GF_F32 = 0, GF_F16 = 1, GF_BF16 = 2 } gf_dtype_t;
+
+typedef enum {
+  GF_OK = 0,
+  GF_ERR_INVALID_ARG = 1, /* null pointer, bad size, negative radius/eps ... */
+  GF_ERR_UNSUPPORTED = 2, /* valid for the method, not implemented here     */
+  GF_ERR_WORKSPACE = 3,   /* ws too small (or NULL with nonzero need)       */
+  GF_ERR_HIP = 4          /* a HIP runtime call failed                      */
+} gf_status_t;
+
+/* Problem description (host struct, read during the call only). */
+typedef struct {
+  int32_t n;        /* images                                             */
+  int32_t c;        /* channels; guide channel k filters input channel k  */
+  int32_t h_lo;     /* low-res height                                     */
+  int32_t w_lo;     /* low-res width                                      */
+  int32_t h_hi;     /* high-res height = s * h_lo                         */
+  int32_t w_hi;     /* high-res width  = s * w_lo                         */
+  int32_t r;        /* box radius, >= 0 (window side 2r + 1)              */
+  int32_t mean_ab;  /* 1: window-mean A and b before upsampling; 0: not   */
+  int32_t io_dtype; /* gf_dtype_t of I_lo, p_lo, I_hi, q_hi, dq_hi, dI_hi */
+} gf_desc_t;
+
+/* Bytes of scratch memory gf_forward (backward = 0) or gf_backward
+ * (backward = 1) needs for this problem; 0 for an invalid description. */
+size_t gf_workspace_size(const gf_desc_t *desc, int32_t backward);
+
+/* Forward pass (Sec. III-B/C, Eq. (1)-(2)): writes q_hi. */
+int32_t gf_forward(const gf_desc_t *desc, const void *I_lo, const void *p_lo,
+                   const void *I_hi, const float *eps, int32_t eps_count,
+                   void *q_hi, void *ws, size_t ws_bytes, void *stream);
+
+/* Backward pass (Algorithm 1): gradients of sum(q * dq_hi).  Each output
+ * pointer may be NULL (that gradient is not computed).  The low-res box
+ * statistics and coefficients are recomputed from the inputs, not taken
+ * from the forward pass. */
+int32_t gf_backward(const gf_desc_t *desc, const void *I_lo,
+                    const void *p_lo, const void *I_hi, const float *eps,
+                    int32_t eps_count, const void *dq_hi, float *dI_lo,
+                    float *dp_lo, void *dI_hi, float *deps, void *ws,
+                    size_t ws_bytes, void *stream);
+
+/* Human-readable name of a status code (static string). */
+const char *gf_status_string(int32_t status);
+
+/* Detail of the last error raised on the calling thread ("" if none). */
+const char *gf_last_error_detail(void);
+
+/* Kernel timing on the launch stream (hipEvents recorded around every
+ * kernel the library launches).  gf_profile_enable(1) starts recording
+ * (and clears earlier records); gf_profile_read synchronises the events,
+ * then fills up to `cap` entries with the kernel name and the summed
+ * milliseconds and launch count of each kernel, and returns the number of
+ * distinct kernels.  For measurement only: recording adds two event
+ * records per launch. */
+int32_t gf_profile_enable(int32_t on);
+int32_t gf_profile_read(char (*names)[48], double *ms, int32_t *launches,
+                        int32_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GF_H */

@@ -462,7 +462,7 @@ int gfo_backward(int n, int c, int h, int w, int H, int W, int r,
                  const double *p_lo, const double *I_hi, const double *eps,
                  int eps_count, const double *dq, double *dI_lo,
                  double *dp_lo, double *dI_hi, double *deps,
-                 double *dguide) {
+                 double *deps_abs, double *dguide) {
   if (check_args(n, c, h, w, H, W, r, eps_count)) return -1;
   if (!guide_cout_ok(guide_mode, cin, c, gd)) return -1;
   const long Pl = (long)h * w, Ph = (long)H * W;
@@ -470,7 +470,7 @@ int gfo_backward(int n, int c, int h, int w, int H, int W, int r,
   double *Gh = (double *)malloc(sizeof(double) * (size_t)n * c * Ph);
   double *dGl = (double *)calloc((size_t)n * c * Pl, sizeof(double));
   double *dGh = (double *)calloc((size_t)n * c * Ph, sizeof(double));
-  double *dep = (double *)calloc((size_t)n * c, sizeof(double));
+  double *dep = (double *)calloc((size_t)n * c * 2, sizeof(double));
   if (!Gl || !Gh || !dGl || !dGh || !dep) {
     free(Gl);
     free(Gh);
@@ -566,7 +566,7 @@ int gfo_backward(int n, int c, int h, int w, int H, int W, int r,
       double *dg = dGl + pl * Pl;
       double *dp = dp_lo ? dp_lo + pl * Pl : NULL;
       if (dp) memset(dp, 0, sizeof(double) * Pl);
-      double de = 0.0;
+      double de = 0.0, dabs = 0.0;
       for (int i = 0; i < h; ++i)
         for (int j = 0; j < w; ++j) {
           int k = i * w + j;
@@ -582,6 +582,7 @@ int gfo_backward(int n, int c, int h, int w, int H, int W, int r,
             dvr = -dAk * cv[k] / (den * den);
           }
           de += dvr;
+          dabs += fabs(dvr);
           int a0, a1, c0, c1;
           window(&geo, i, j, &a0, &a1, &c0, &c1);
           double N = (double)((a1 - a0 + 1) * (c1 - c0 + 1));
@@ -595,19 +596,25 @@ int gfo_backward(int n, int c, int h, int w, int H, int W, int r,
             }
         }
       dep[pl] = de;
+      dep[n * c + pl] = dabs;
       free(buf);
     }
   }
-  if (!fail && deps) {
+  /* per eps entry: the gradient, and the sum of the magnitudes of its
+   * terms (a scale for judging the rounding error of the sum) */
+  for (int which = 0; which < 2 && !fail; ++which) {
+    double *out = which == 0 ? deps : deps_abs;
+    const double *src = dep + (size_t)which * n * c;
+    if (!out) continue;
     if (eps_count == 1) {
       double s = 0.0;
-      for (int pl = 0; pl < n * c; ++pl) s += dep[pl];
-      deps[0] = s;
+      for (int pl = 0; pl < n * c; ++pl) s += src[pl];
+      out[0] = s;
     } else {
       for (int b = 0; b < n; ++b) {
         double s = 0.0;
-        for (int ch = 0; ch < c; ++ch) s += dep[b * c + ch];
-        deps[b] = s;
+        for (int ch = 0; ch < c; ++ch) s += src[b * c + ch];
+        out[b] = s;
       }
     }
   }

@@ -9,6 +9,9 @@
  *   q / dq / dI_hi at high resolution, dI_lo / dp_lo at low resolution.
  * eps has eps_count entries: 1 (shared) or n (one per image); deps likewise.
  * Any output pointer of the backward may be NULL (not computed).
+ * deps_abs receives, per eps entry, the sum over pixels and channels of
+ * |d var| (the magnitudes of the terms deps sums): the scale against which
+ * the rounding error of a computed deps is judged.
  * Return 0 on success, -1 on invalid arguments, -2 on allocation failure.
  */
 #ifndef GF_ORACLE_H
@@ -55,7 +58,8 @@ int gfo_backward(int n, int c, int h, int w, int H, int W, int r,
                  const gfo_guide_t *g, const double *I_lo,
                  const double *p_lo, const double *I_hi, const double *eps,
                  int eps_count, const double *dq, double *dI_lo,
-                 double *dp_lo, double *dI_hi, double *deps, double *dguide);
+                 double *dp_lo, double *dI_hi, double *deps, double *deps_abs,
+                 double *dguide);
 
 #ifdef __cplusplus
 }

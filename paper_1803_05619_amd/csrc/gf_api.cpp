@@ -1,0 +1,315 @@
+// C ABI of the guided filtering layer: argument checks, launch planning,
+// workspace layout and kernel timing.  Every check runs on the host before
+// any HIP call, so invalid input is reported without touching a device.
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "gf_internal.h"
+
+namespace gf {
+namespace {
+
+thread_local std::string g_detail;
+
+int fail(int code, const std::string& why) {
+  g_detail = why;
+  return code;
+}
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+int dtype_size(int t) {
+  switch (t) {
+    case GF_F32: return 4;
+    case GF_F16: return 2;
+    case GF_BF16: return 2;
+  }
+  return 0;
+}
+
+constexpr size_t kMaxLds = 64 * 1024;
+constexpr size_t kLdsTarget = 40 * 1024;  // leaves room for 4 workgroups per CU
+
+// Pick a low-res tile (th x tw outputs) for a kernel whose LDS footprint is
+// lds_floats(th, tw) and whose loaded region is (th + 2 halo) x (tw + 2 halo):
+// maximise the fraction of loaded pixels that are outputs, prefer footprints
+// that leave room for several workgroups per CU.
+template <typename F>
+bool choose_tile(int h, int w, int halo, F lds_bytes, int* th_out, int* tw_out, size_t* lds_out) {
+  static const int cand[] = {64, 32, 16, 8, 4};
+  double best = -1.0;
+  bool found = false;
+  for (int pass = 0; pass < 2 && !found; ++pass) {
+    const size_t limit = pass == 0 ? kLdsTarget : kMaxLds;
+    for (int th : cand) {
+      for (int tw : cand) {
+        if (th > 4 && th / 2 >= h) continue;  // tile far larger than the image
+        if (tw > 4 && tw / 2 >= w) continue;
+        const size_t lds = lds_bytes(th, tw);
+        if (lds > limit) continue;
+        const double eff = (double)(th * tw) / (double)((th + 2 * halo) * (tw + 2 * halo));
+        const double score = eff + 1e-6 * th * tw + 1e-7 * tw;
+        if (score > best) {
+          best = score;
+          *th_out = th;
+          *tw_out = tw;
+          *lds_out = lds;
+          found = true;
+        }
+      }
+    }
+  }
+  return found;
+}
+
+}  // namespace
+
+int make_plan(const gf_desc_t* d, Plan* p, const char** why) {
+  static thread_local std::string msg;
+  auto bad = [&](int code, const std::string& m) {
+    msg = m;
+    *why = msg.c_str();
+    return code;
+  };
+  if (!d) return bad(GF_ERR_INVALID_ARG, "desc is NULL");
+  if (d->n < 1 || d->c < 1) return bad(GF_ERR_INVALID_ARG, "n and c must be >= 1");
+  if (d->h_lo < 1 || d->w_lo < 1 || d->h_hi < 1 || d->w_hi < 1)
+    return bad(GF_ERR_INVALID_ARG, "image sizes must be >= 1");
+  if (d->h_lo > d->h_hi || d->w_lo > d->w_hi)
+    return bad(GF_ERR_INVALID_ARG, "low-res size must not exceed high-res size");
+  if (d->r < 0) return bad(GF_ERR_INVALID_ARG, "radius r must be >= 0");
+  if (d->mean_ab != 0 && d->mean_ab != 1) return bad(GF_ERR_INVALID_ARG, "mean_ab must be 0 or 1");
+  if (dtype_size(d->io_dtype) == 0) return bad(GF_ERR_INVALID_ARG, "unknown io_dtype");
+  if (d->h_hi % d->h_lo || d->w_hi % d->w_lo || d->h_hi / d->h_lo != d->w_hi / d->w_lo)
+    return bad(GF_ERR_UNSUPPORTED, "high/low size ratio must be one integer factor for both axes");
+  const int S = d->h_hi / d->h_lo;
+  if (S != 1 && S != 2 && S != 4 && S != 8)
+    return bad(GF_ERR_UNSUPPORTED, "upsampling factor must be 1, 2, 4 or 8");
+  const double hi_elems = (double)d->n * d->c * d->h_hi * d->w_hi;
+  if (hi_elems > 9.0e15 || (double)d->h_hi * d->w_hi > 2.0e9)
+    return bad(GF_ERR_UNSUPPORTED, "problem too large");
+  Plan& q = *p;
+  q.n = d->n;
+  q.c = d->c;
+  q.h = d->h_lo;
+  q.w = d->w_lo;
+  q.H = d->h_hi;
+  q.W = d->w_hi;
+  q.r = d->r;
+  q.mean_ab = d->mean_ab;
+  q.dtype = d->io_dtype;
+  q.S = S;
+  q.planes = d->n * d->c;
+  const int V = 16 / dtype_size(d->io_dtype);
+  q.VEC = (q.W % V == 0) ? V : 1;
+
+  const int r = q.r;
+  const int hb = q.mean_ab ? r : 0;
+  auto co_lds = [&](int th, int tw) {
+    const size_t nr0 = th + 2 * (hb + r), nc0 = tw + 2 * (hb + r);
+    const size_t nr1 = th + 2 * hb, nc1 = tw + 2 * hb;
+    return sizeof(float) * (2 * nr0 * nc0 + 4 * nr1 * nc0 + 2 * nr1 * nc1);
+  };
+  if (!choose_tile(q.h, q.w, hb + r, co_lds, &q.coTH, &q.coTW, &q.coLDS))
+    return bad(GF_ERR_UNSUPPORTED, "radius too large for the low-res tile kernels");
+  auto lo_lds = [&](int th, int tw) {
+    const size_t nr0 = th + 4 * r, nc0 = tw + 4 * r, nr1 = th + 2 * r, nc1 = tw + 2 * r;
+    return sizeof(float) * (4 * nr0 * nc0 + 6 * nr1 * nc0 + 4 * nr1 * nc1) + 1024;
+  };
+  if (!choose_tile(q.h, q.w, 2 * r, lo_lds, &q.loTH, &q.loTW, &q.loLDS))
+    return bad(GF_ERR_UNSUPPORTED, "radius too large for the low-res tile kernels");
+  q.loLDS -= 1024;  // the static reduction buffer is not dynamic LDS
+  q.lo_ntx = (q.w + q.loTW - 1) / q.loTW;
+  q.lo_nty = (q.h + q.loTH - 1) / q.loTH;
+
+  q.RB = S * (S >= 32 ? 1 : 32 / S);
+  q.nrb = (q.H + q.RB - 1) / q.RB;
+  q.nxv = q.W / q.VEC;
+
+  q.bh = S >= 32 ? 2 : (64 / S < 2 ? 2 : 64 / S);
+  q.tw = 64 * q.VEC / S;
+  q.nby = (q.h + q.bh - 1) / q.bh;
+  q.nbx = (q.W + 64 * q.VEC - 1) / (64 * q.VEC);
+  q.ublk_floats = (size_t)2 * (q.bh + 2) * (q.tw + 2);
+
+  const size_t lo_plane = (size_t)q.planes * q.h * q.w * sizeof(float);
+  q.off_abar = 0;
+  q.off_bbar = align_up(lo_plane, 256);
+  q.ws_fwd = q.off_bbar + align_up(lo_plane, 256);
+  q.off_u = align_up(lo_plane, 256);
+  const size_t ubytes = (size_t)q.planes * q.nby * q.nbx * q.ublk_floats * sizeof(float);
+  q.off_eps = q.off_u + align_up(ubytes, 256);
+  q.ws_bwd = q.off_eps + align_up((size_t)q.planes * q.lo_ntx * q.lo_nty * sizeof(float), 256);
+  return GF_OK;
+}
+
+// ------------------------------------------------------------ profiling
+
+namespace {
+struct Rec {
+  const char* name;
+  hipEvent_t a, b;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<Rec> g_recs;
+const char* g_pending_name = nullptr;
+hipEvent_t g_pending_ev = nullptr;
+
+void prof_clear() {
+  for (auto& r : g_recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  g_recs.clear();
+  if (g_pending_ev) (void)hipEventDestroy(g_pending_ev);
+  g_pending_ev = nullptr;
+}
+}  // namespace
+
+void prof_begin(const char* name, hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  if (!g_prof_on) return;
+  hipEvent_t ev;
+  if (hipEventCreate(&ev) != hipSuccess) return;
+  (void)hipEventRecord(ev, s);
+  g_pending_name = name;
+  g_pending_ev = ev;
+}
+
+void prof_end(hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  if (!g_prof_on || !g_pending_ev) return;
+  hipEvent_t ev;
+  if (hipEventCreate(&ev) != hipSuccess) return;
+  (void)hipEventRecord(ev, s);
+  g_recs.push_back({g_pending_name, g_pending_ev, ev});
+  g_pending_ev = nullptr;
+}
+
+}  // namespace gf
+
+// ------------------------------------------------------------ C ABI
+
+using gf::fail;
+
+static bool misaligned(const void* ptr) { return ((uintptr_t)ptr & 15u) != 0; }
+
+extern "C" {
+
+size_t gf_workspace_size(const gf_desc_t* desc, int32_t backward) {
+  gf::Plan p;
+  const char* why = nullptr;
+  if (gf::make_plan(desc, &p, &why) != GF_OK) return 0;
+  return backward ? p.ws_bwd : p.ws_fwd;
+}
+
+int32_t gf_forward(const gf_desc_t* desc, const void* I_lo, const void* p_lo, const void* I_hi,
+                   const float* eps, int32_t eps_count, void* q_hi, void* ws, size_t ws_bytes,
+                   void* stream) {
+  gf::g_detail.clear();
+  gf::Plan p;
+  const char* why = nullptr;
+  int st = gf::make_plan(desc, &p, &why);
+  if (st != GF_OK) return fail(st, why);
+  if (!I_lo || !p_lo || !I_hi || !eps || !q_hi)
+    return fail(GF_ERR_INVALID_ARG, "a required pointer is NULL");
+  if (eps_count != 1 && eps_count != desc->n)
+    return fail(GF_ERR_INVALID_ARG, "eps_count must be 1 or n");
+  if (misaligned(I_lo) || misaligned(p_lo) || misaligned(I_hi) || misaligned(q_hi) ||
+      misaligned(ws))
+    return fail(GF_ERR_INVALID_ARG, "tensor pointers must be 16-byte aligned");
+  if (!ws || ws_bytes < p.ws_fwd)
+    return fail(GF_ERR_WORKSPACE, "workspace smaller than gf_workspace_size(desc, 0) = " +
+                                      std::to_string(p.ws_fwd));
+  gf::FwdArgs a{I_lo, p_lo, I_hi, eps, eps_count, q_hi, static_cast<char*>(ws)};
+  hipError_t e = gf::launch_forward(p, a, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail(GF_ERR_HIP, hipGetErrorString(e));
+  return GF_OK;
+}
+
+int32_t gf_backward(const gf_desc_t* desc, const void* I_lo, const void* p_lo, const void* I_hi,
+                    const float* eps, int32_t eps_count, const void* dq_hi, float* dI_lo,
+                    float* dp_lo, void* dI_hi, float* deps, void* ws, size_t ws_bytes,
+                    void* stream) {
+  gf::g_detail.clear();
+  gf::Plan p;
+  const char* why = nullptr;
+  int st = gf::make_plan(desc, &p, &why);
+  if (st != GF_OK) return fail(st, why);
+  if (!I_lo || !p_lo || !I_hi || !eps || !dq_hi)
+    return fail(GF_ERR_INVALID_ARG, "a required pointer is NULL");
+  if (eps_count != 1 && eps_count != desc->n)
+    return fail(GF_ERR_INVALID_ARG, "eps_count must be 1 or n");
+  if (misaligned(I_lo) || misaligned(p_lo) || misaligned(I_hi) || misaligned(dq_hi) ||
+      misaligned(dI_lo) || misaligned(dp_lo) || misaligned(dI_hi) || misaligned(ws))
+    return fail(GF_ERR_INVALID_ARG, "tensor pointers must be 16-byte aligned");
+  if (!ws || ws_bytes < p.ws_bwd)
+    return fail(GF_ERR_WORKSPACE, "workspace smaller than gf_workspace_size(desc, 1) = " +
+                                      std::to_string(p.ws_bwd));
+  gf::BwdArgs a{I_lo, p_lo, I_hi, dq_hi, eps, eps_count, dI_lo, dp_lo, deps, dI_hi,
+                static_cast<char*>(ws)};
+  hipError_t e = gf::launch_backward(p, a, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail(GF_ERR_HIP, hipGetErrorString(e));
+  return GF_OK;
+}
+
+const char* gf_status_string(int32_t status) {
+  switch (status) {
+    case GF_OK: return "GF_OK";
+    case GF_ERR_INVALID_ARG: return "GF_ERR_INVALID_ARG";
+    case GF_ERR_UNSUPPORTED: return "GF_ERR_UNSUPPORTED";
+    case GF_ERR_WORKSPACE: return "GF_ERR_WORKSPACE";
+    case GF_ERR_HIP: return "GF_ERR_HIP";
+  }
+  return "GF_ERR_UNKNOWN";
+}
+
+const char* gf_last_error_detail(void) { return gf::g_detail.c_str(); }
+
+int32_t gf_profile_enable(int32_t on) {
+  std::lock_guard<std::mutex> lk(gf::g_prof_mu);
+  gf::prof_clear();
+  gf::g_prof_on = on != 0;
+  return GF_OK;
+}
+
+int32_t gf_profile_read(char (*names)[48], double* ms, int32_t* launches, int32_t cap) {
+  std::lock_guard<std::mutex> lk(gf::g_prof_mu);
+  std::vector<std::string> keys;
+  std::vector<double> tot;
+  std::vector<int> cnt;
+  for (auto& r : gf::g_recs) {
+    if (hipEventSynchronize(r.b) != hipSuccess) continue;
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) continue;
+    size_t k = 0;
+    while (k < keys.size() && keys[k] != r.name) ++k;
+    if (k == keys.size()) {
+      keys.push_back(r.name);
+      tot.push_back(0.0);
+      cnt.push_back(0);
+    }
+    tot[k] += t;
+    cnt[k] += 1;
+  }
+  gf::prof_clear();
+  const int m = (int)keys.size();
+  for (int k = 0; k < m && k < cap; ++k) {
+    if (names) {
+      strncpy(names[k], keys[k].c_str(), 47);
+      names[k][47] = '\0';
+    }
+    if (ms) ms[k] = tot[k];
+    if (launches) launches[k] = cnt[k];
+  }
+  return m;
+}
+
+}  // extern "C"

@@ -1,0 +1,62 @@
+// Internal interface between the C-ABI layer (gf_api.cpp) and the HIP
+// kernels (gf_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/gf.h"
+
+namespace gf {
+
+// Geometry and launch shapes derived from a gf_desc_t on the host.
+struct Plan {
+  int n, c, h, w, H, W, r, mean_ab, dtype;
+  int S;        // integer upsampling factor (H = S h, W = S w)
+  int VEC;      // high-res elements per thread-load (16 bytes, or 1)
+  int planes;   // n * c
+  // low-res coefficient kernel tiles
+  int coTH, coTW;
+  size_t coLDS;
+  // high-res apply: rows per thread
+  int RB, nrb, nxv;
+  // backward high-res blocks (one wave each): bh low-res rows x tw low-res
+  // columns (64 * VEC high-res columns)
+  int bh, tw, nby, nbx;
+  size_t ublk_floats;  // floats per block (2 * (bh + 2) * (tw + 2))
+  // backward low-res tiles
+  int loTH, loTW, lo_ntx, lo_nty;
+  size_t loLDS;
+  // workspace layout (bytes)
+  size_t off_abar, off_bbar, off_u, off_eps, ws_fwd, ws_bwd;
+};
+
+// Returns GF_OK and fills `p`, or an error code with a message in `why`.
+int make_plan(const gf_desc_t* d, Plan* p, const char** why);
+
+struct FwdArgs {
+  const void *I_lo, *p_lo, *I_hi;
+  const float* eps;
+  int eps_count;
+  void* q;
+  char* ws;
+};
+
+struct BwdArgs {
+  const void *I_lo, *p_lo, *I_hi, *dq;
+  const float* eps;
+  int eps_count;
+  float *dI_lo, *dp_lo, *deps;
+  void* dI_hi;
+  char* ws;
+};
+
+hipError_t launch_forward(const Plan& p, const FwdArgs& a, hipStream_t s);
+hipError_t launch_backward(const Plan& p, const BwdArgs& a, hipStream_t s);
+
+// Profiling hooks (gf_api.cpp): wrap one kernel launch.
+void prof_begin(const char* name, hipStream_t s);
+void prof_end(hipStream_t s);
+
+}  // namespace gf

@@ -1,0 +1,87 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/gf.h declares, sizes workspaces, and rejects invalid
+arguments before any HIP call."""
+import ctypes
+
+import pytest
+
+gf = pytest.importorskip("paper_1803_05619_amd.gf")
+
+
+def desc(**kw):
+    d = dict(n=2, c=3, h_lo=64, w_lo=96, h_hi=256, w_hi=384, r=1, mean_ab=1, io_dtype=0)
+    d.update(kw)
+    return gf.gf_desc_t(*[d[k] for k, _ in gf.gf_desc_t._fields_])
+
+
+def test_exports_every_declared_symbol():
+    names = gf.header_functions()
+    assert {"gf_forward", "gf_backward", "gf_workspace_size", "gf_status_string",
+            "gf_last_error_detail", "gf_profile_enable", "gf_profile_read"} <= set(names)
+    for name in names:
+        assert hasattr(gf.lib, name), name
+
+
+def test_status_strings():
+    assert gf.gf_status_string(0) == "GF_OK"
+    assert gf.gf_status_string(3) == "GF_ERR_WORKSPACE"
+    assert gf.gf_status_string(99) == "GF_ERR_UNKNOWN"
+
+
+def test_workspace_sizes():
+    f = gf.gf_workspace_size(desc(), 0)
+    b = gf.gf_workspace_size(desc(), 1)
+    lo = 2 * 3 * 64 * 96 * 4
+    assert f >= 2 * lo          # Abar and bbar planes
+    assert b >= lo              # Abar plus the partial planes
+    assert gf.gf_workspace_size(desc(r=-1), 0) == 0
+    for dt in (0, 1, 2):
+        assert gf.gf_workspace_size(desc(io_dtype=dt), 1) > 0
+
+
+FAKE = 0x10000  # aligned, never dereferenced: every case below fails validation
+
+
+@pytest.mark.parametrize("kw, code", [
+    (dict(r=-1), gf.GF_ERR_INVALID_ARG),
+    (dict(n=0), gf.GF_ERR_INVALID_ARG),
+    (dict(c=0), gf.GF_ERR_INVALID_ARG),
+    (dict(h_lo=0), gf.GF_ERR_INVALID_ARG),
+    (dict(h_lo=300), gf.GF_ERR_INVALID_ARG),
+    (dict(mean_ab=2), gf.GF_ERR_INVALID_ARG),
+    (dict(io_dtype=7), gf.GF_ERR_INVALID_ARG),
+    (dict(h_hi=250), gf.GF_ERR_UNSUPPORTED),
+    (dict(h_hi=192, w_hi=288), gf.GF_ERR_UNSUPPORTED),    # factor 3
+    (dict(h_hi=128), gf.GF_ERR_UNSUPPORTED),              # different factors per axis
+    (dict(r=40), gf.GF_ERR_UNSUPPORTED),
+])
+def test_invalid_descriptions(kw, code):
+    d = desc(**kw)
+    st = gf.gf_forward(d, FAKE, FAKE, FAKE, FAKE, 1, FAKE, FAKE, 1 << 40, None)
+    assert st == code, gf.gf_last_error_detail()
+    assert gf.gf_last_error_detail() != ""
+    st = gf.gf_backward(d, FAKE, FAKE, FAKE, FAKE, 1, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE,
+                        1 << 40, None)
+    assert st == code
+
+
+def test_invalid_pointers_and_workspace():
+    d = desc()
+    big = 1 << 40
+    assert gf.gf_forward(d, None, FAKE, FAKE, FAKE, 1, FAKE, FAKE, big, None) == gf.GF_ERR_INVALID_ARG
+    assert gf.gf_forward(d, FAKE, FAKE, FAKE, None, 1, FAKE, FAKE, big, None) == gf.GF_ERR_INVALID_ARG
+    assert gf.gf_forward(d, FAKE, FAKE, FAKE, FAKE, 3, FAKE, FAKE, big, None) == gf.GF_ERR_INVALID_ARG
+    assert gf.gf_forward(d, FAKE + 4, FAKE, FAKE, FAKE, 1, FAKE, FAKE, big, None) == gf.GF_ERR_INVALID_ARG
+    need = gf.gf_workspace_size(d, 0)
+    assert gf.gf_forward(d, FAKE, FAKE, FAKE, FAKE, 1, FAKE, FAKE, need - 1, None) == gf.GF_ERR_WORKSPACE
+    assert gf.gf_forward(d, FAKE, FAKE, FAKE, FAKE, 1, FAKE, None, need, None) == gf.GF_ERR_WORKSPACE
+    needb = gf.gf_workspace_size(d, 1)
+    assert gf.gf_backward(d, FAKE, FAKE, FAKE, FAKE, 2, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE,
+                          needb - 1, None) == gf.GF_ERR_WORKSPACE
+    assert gf.gf_backward(d, FAKE, FAKE, FAKE, FAKE, 2, None, FAKE, FAKE, FAKE, FAKE, FAKE,
+                          needb, None) == gf.GF_ERR_INVALID_ARG
+
+
+def test_profile_read_empty():
+    gf.gf_profile_enable(False)
+    assert gf.gf_profile_read() == {}

@@ -1,0 +1,208 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs, element by element.
+
+Error measures (per output):
+  q            max |gpu - ref|                                  (absolute)
+  dI_lo, dp_lo, dI_hi
+               max |gpu - ref| / max(1, max |ref|)              (scaled)
+  deps         |gpu - ref| / max(1, sum |d var|)                 (scaled by the
+               sum of the magnitudes of the terms deps adds up)
+Bars: 1e-4 for FP32 I/O and 2e-2 for BF16/FP16 I/O (for half-precision I/O
+q and dI_hi are rounded once to the I/O type, so their error includes that
+rounding).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1803_05619_amd import datagen
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f32": 1e-4, "bf16": 2e-2, "f16": 2e-2}
+
+
+def _gf():
+    from paper_1803_05619_amd import gf
+    return gf
+
+
+def to_dev(prob):
+    dev = torch.device("cuda:0")
+    return {k: (prob[k].to(dev) if isinstance(prob.get(k), torch.Tensor) else prob.get(k))
+            for k in ("I_lo", "p_lo", "I_hi", "dq")}
+
+
+def run_both(prob, mean_ab=True, eps=None, backward=True):
+    gf = _gf()
+    d = to_dev(prob)
+    eps = prob["eps"] if eps is None else eps
+    print(f"case n={prob['n']} c={prob['c']} H={prob['H']} W={prob['W']} s={prob['s']} "
+          f"r={prob['r']} dtype={prob['io_dtype']} mean_ab={mean_ab}", flush=True)
+    q = gf.forward(d["I_lo"], d["p_lo"], d["I_hi"], eps, prob["r"], mean_ab)
+    out = {"q": q}
+    if backward:
+        dI_lo, dp_lo, dI_hi, deps = gf.backward(d["I_lo"], d["p_lo"], d["I_hi"], eps, d["dq"],
+                                                prob["r"], mean_ab)
+        out.update(dI_lo=dI_lo, dp_lo=dp_lo, dI_hi=dI_hi, deps=deps)
+    torch.cuda.synchronize()
+    out = {k: v.double().cpu().numpy() for k, v in out.items()}
+    args = [prob[k].double().numpy() for k in ("I_lo", "p_lo", "I_hi")]
+    ref = {"q": oracle.forward(*args, prob["r"], eps, mean_ab=mean_ab)}
+    if backward:
+        ref.update(oracle.backward(*args, prob["r"], eps, prob["dq"].double().numpy(),
+                                   mean_ab=mean_ab))
+    return out, ref
+
+
+def errors(out, ref):
+    err = {"q": float(np.abs(out["q"] - ref["q"]).max())}
+    for k in ("dI_lo", "dp_lo", "dI_hi"):
+        if k in out:
+            err[k] = float(np.abs(out[k] - ref[k]).max() / max(1.0, np.abs(ref[k]).max()))
+    if "deps" in out:
+        err["deps"] = float((np.abs(out["deps"] - ref["deps"]) /
+                             np.maximum(1.0, ref["deps_abs"])).max())
+    return err
+
+
+def check(prob, tol=None, **kw):
+    out, ref = run_both(prob, **kw)
+    err = errors(out, ref)
+    print("errors:", {k: f"{v:.3e}" for k, v in err.items()}, flush=True)
+    tol = TOL[prob["io_dtype"]] if tol is None else tol
+    for k, v in err.items():
+        assert v <= tol, (k, v, err)
+    return err
+
+
+# ------------------------------------------------------------ configurations
+
+def test_config0_forward_exact_size():
+    """64x64 -> 256x256, r=1, eps=1e-2, FP32, forward only."""
+    check(datagen.make_config(0, with_dq=False), backward=False)
+
+
+def test_config1_reduced():
+    """The fwd+bwd FP32 workload at 1/8 size (256x384, s=4): several tiles,
+    ragged column tile."""
+    check(datagen.make_config(1, div=8))
+
+
+@pytest.mark.parametrize("mean_ab", [False, True])
+def test_config1_reduced_mean_ab(mean_ab):
+    check(datagen.make_config(1, div=16, n=2), mean_ab=mean_ab)
+
+
+def test_config2_bf16_reduced():
+    """BF16 I/O with FP32 accumulation (identity guide)."""
+    check(datagen.make_config(2, div=8, n=2))
+
+
+@pytest.mark.parametrize("r", [1, 8])
+def test_config4_fp16_reduced(r):
+    """FP16 I/O, eps=1e-8, near-constant patches (variance cancellation)."""
+    check(datagen.make_config(4, div=8, r=r))
+
+
+# ------------------------------------------------------------ shapes and edge cases
+
+@pytest.mark.parametrize("s", [1, 2, 4, 8])
+@pytest.mark.parametrize("r", [0, 1, 3])
+def test_factors_and_radii(s, r):
+    prob = datagen.make_problem(2, 3, 8 * 13, 8 * 21, s, r, [1e-3, 3e-2], "f32", config=90)
+    check(prob)
+
+
+def test_scalar_path_odd_width():
+    """W not a multiple of 4: the element-wise (VEC = 1) kernels."""
+    prob = datagen.make_problem(1, 2, 2 * 37, 2 * 49, 2, 2, 1e-3, "f32", config=91)
+    check(prob)
+
+
+def test_tiny_images_and_huge_radius():
+    for (H, W, s, r) in ((4, 4, 4, 1), (8, 40, 8, 2), (16, 16, 4, 7), (2, 6, 2, 5)):
+        prob = datagen.make_problem(1, 3, H, W, s, r, 1e-2, "f32", config=92)
+        check(prob)
+
+
+def test_many_images_per_image_eps():
+    prob = datagen.make_problem(5, 3, 96, 128, 4, 2, [1e-4, 1e-3, 1e-2, 1e-1, 1.0], "f32",
+                                config=93)
+    check(prob)
+
+
+def test_optional_outputs_are_optional():
+    gf = _gf()
+    prob = datagen.make_config(1, div=16, n=1)
+    d = to_dev(prob)
+    full = gf.backward(d["I_lo"], d["p_lo"], d["I_hi"], prob["eps"], d["dq"], 1)
+    part = gf.backward(d["I_lo"], d["p_lo"], d["I_hi"], prob["eps"], d["dq"], 1,
+                       need_dI_lo=False, need_dI_hi=False, need_deps=False)
+    torch.cuda.synchronize()
+    assert part[0] is None and part[2] is None and part[3] is None
+    assert torch.equal(full[1], part[1])
+
+
+def test_bitwise_deterministic():
+    gf = _gf()
+    prob = datagen.make_config(1, div=8, n=2)
+    d = to_dev(prob)
+    runs = []
+    for _ in range(2):
+        q = gf.forward(d["I_lo"], d["p_lo"], d["I_hi"], prob["eps"], 1)
+        g = gf.backward(d["I_lo"], d["p_lo"], d["I_hi"], prob["eps"], d["dq"], 1)
+        runs.append([q, *g])
+    torch.cuda.synchronize()
+    for a, b in zip(*runs):
+        assert torch.equal(a, b)
+
+
+def test_outputs_stay_in_bounds():
+    """Canary bands around every output must be untouched."""
+    gf = _gf()
+    prob = datagen.make_problem(1, 3, 4 * 19, 4 * 23, 4, 1, 1e-2, "f32", config=94)
+    d = to_dev(prob)
+    pad = 1024
+
+    def canary(shape, dtype):
+        numel = int(np.prod(shape))
+        buf = torch.full((numel + 2 * pad,), 12345.0, dtype=dtype, device="cuda:0")
+        return buf, buf[pad:pad + numel].view(shape)
+
+    qb, q = canary(d["I_hi"].shape, torch.float32)
+    gf.forward(d["I_lo"], d["p_lo"], d["I_hi"], prob["eps"], 1, out=q)
+    b1, dI_lo = canary(d["I_lo"].shape, torch.float32)
+    b2, dp_lo = canary(d["p_lo"].shape, torch.float32)
+    b3, dI_hi = canary(d["I_hi"].shape, torch.float32)
+    b4, deps = canary((1,), torch.float32)
+    gf.backward(d["I_lo"], d["p_lo"], d["I_hi"], prob["eps"], d["dq"], 1,
+                outs=(dI_lo, dp_lo, dI_hi, deps))
+    torch.cuda.synchronize()
+    for buf in (qb, b1, b2, b3, b4):
+        assert torch.all(buf[:pad] == 12345.0) and torch.all(buf[-pad:] == 12345.0)
+
+
+def test_autograd_function():
+    gf = _gf()
+    prob = datagen.make_config(1, div=16, n=1)
+    d = to_dev(prob)
+    I_lo = d["I_lo"].clone().requires_grad_(True)
+    p_lo = d["p_lo"].clone().requires_grad_(True)
+    I_hi = d["I_hi"].clone().requires_grad_(True)
+    eps = torch.tensor(prob["eps"], dtype=torch.float32, device="cuda:0", requires_grad=True)
+    q = gf.guided_filter(I_lo, p_lo, I_hi, r=1, eps=eps)
+    (q * d["dq"]).sum().backward()
+    ref = gf.backward(d["I_lo"], d["p_lo"], d["I_hi"], eps.detach(), d["dq"], 1)
+    torch.cuda.synchronize()
+    for got, want in zip((I_lo.grad, p_lo.grad, I_hi.grad, eps.grad), ref):
+        assert torch.equal(got, want)
+
+
+# ------------------------------------------------------------ full size
+
+def test_config1_full_size():
+    """4 x 3 x 2048 x 3072 FP32, r=1, eps=1e-4: the benchmarked launch shapes,
+    every output compared with the full oracle."""
+    check(datagen.make_config(1))
