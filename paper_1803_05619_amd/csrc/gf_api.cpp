@@ -33,40 +33,10 @@ int dtype_size(int t) {
   return 0;
 }
 
-constexpr size_t kMaxLds = 64 * 1024;
-constexpr size_t kLdsTarget = 40 * 1024;  // leaves room for 4 workgroups per CU
-
-// Pick a low-res tile (th x tw outputs) for a kernel whose LDS footprint is
-// lds_floats(th, tw) and whose loaded region is (th + 2 halo) x (tw + 2 halo):
-// maximise the fraction of loaded pixels that are outputs, prefer footprints
-// that leave room for several workgroups per CU.
-template <typename F>
-bool choose_tile(int h, int w, int halo, F lds_bytes, int* th_out, int* tw_out, size_t* lds_out) {
-  static const int cand[] = {64, 32, 16, 8, 4};
-  double best = -1.0;
-  bool found = false;
-  for (int pass = 0; pass < 2 && !found; ++pass) {
-    const size_t limit = pass == 0 ? kLdsTarget : kMaxLds;
-    for (int th : cand) {
-      for (int tw : cand) {
-        if (th > 4 && th / 2 >= h) continue;  // tile far larger than the image
-        if (tw > 4 && tw / 2 >= w) continue;
-        const size_t lds = lds_bytes(th, tw);
-        if (lds > limit) continue;
-        const double eff = (double)(th * tw) / (double)((th + 2 * halo) * (tw + 2 * halo));
-        const double score = eff + 1e-6 * th * tw + 1e-7 * tw;
-        if (score > best) {
-          best = score;
-          *th_out = th;
-          *tw_out = tw;
-          *lds_out = lds;
-          found = true;
-        }
-      }
-    }
-  }
-  return found;
-}
+// Largest radius the column-walker kernels take: a wave of 64 lanes covers
+// the output columns plus a halo of 2r on each side.
+constexpr int kMaxRadius = 10;
+constexpr int kPrefetchRows = 4;  // rows per block of the walkers (kPF)
 
 }  // namespace
 
@@ -110,23 +80,18 @@ int make_plan(const gf_desc_t* d, Plan* p, const char** why) {
   q.VEC = (q.W % V == 0) ? V : 1;
 
   const int r = q.r;
-  const int hb = q.mean_ab ? r : 0;
-  auto co_lds = [&](int th, int tw) {
-    const size_t nr0 = th + 2 * (hb + r), nc0 = tw + 2 * (hb + r);
-    const size_t nr1 = th + 2 * hb, nc1 = tw + 2 * hb;
-    return sizeof(float) * (2 * nr0 * nc0 + 4 * nr1 * nc0 + 2 * nr1 * nc1);
-  };
-  if (!choose_tile(q.h, q.w, hb + r, co_lds, &q.coTH, &q.coTW, &q.coLDS))
-    return bad(GF_ERR_UNSUPPORTED, "radius too large for the low-res tile kernels");
-  auto lo_lds = [&](int th, int tw) {
-    const size_t nr0 = th + 4 * r, nc0 = tw + 4 * r, nr1 = th + 2 * r, nc1 = tw + 2 * r;
-    return sizeof(float) * (4 * nr0 * nc0 + 6 * nr1 * nc0 + 4 * nr1 * nc1) + 1024;
-  };
-  if (!choose_tile(q.h, q.w, 2 * r, lo_lds, &q.loTH, &q.loTW, &q.loLDS))
-    return bad(GF_ERR_UNSUPPORTED, "radius too large for the low-res tile kernels");
-  q.loLDS -= 1024;  // the static reduction buffer is not dynamic LDS
-  q.lo_ntx = (q.w + q.loTW - 1) / q.loTW;
-  q.lo_nty = (q.h + q.loTH - 1) / q.loTH;
+  if (r > kMaxRadius) return bad(GF_ERR_UNSUPPORTED, "radius above 10 is not supported");
+  const int hal = q.mean_ab ? 2 * r : r;  // halo of the coefficient walker
+  const size_t KR = 2 * r + kPrefetchRows;  // ring rows of the walkers
+  // rows per wave: long enough to amortise the 2*halo warm-up rows
+  q.coTR = r <= 2 ? 32 : 64;
+  q.co_nx = (q.w + (64 - 2 * hal) - 1) / (64 - 2 * hal);
+  q.co_ny = (q.h + q.coTR - 1) / q.coTR;
+  q.coLDS = 64 * (16 * KR + 24 * kPrefetchRows);  // (g,p), (A,b) rings + row buffers
+  q.loTR = q.coTR;
+  q.lo_nx = (q.w + (64 - 4 * r) - 1) / (64 - 4 * r);
+  q.lo_ny = (q.h + q.loTR - 1) / q.loTR;
+  q.loLDS = 64 * (32 * KR + 40 * kPrefetchRows);  // input and X rings + row buffers
 
   q.RB = S * (S >= 32 ? 1 : 32 / S);
   q.nrb = (q.H + q.RB - 1) / q.RB;
@@ -145,9 +110,29 @@ int make_plan(const gf_desc_t* d, Plan* p, const char** why) {
   q.off_u = align_up(lo_plane, 256);
   const size_t ubytes = (size_t)q.planes * q.nby * q.nbx * q.ublk_floats * sizeof(float);
   q.off_eps = q.off_u + align_up(ubytes, 256);
-  q.ws_bwd = q.off_eps + align_up((size_t)q.planes * q.lo_ntx * q.lo_nty * sizeof(float), 256);
+  q.ws_bwd = q.off_eps + align_up((size_t)q.planes * q.lo_nx * q.lo_ny * sizeof(float), 256);
   return GF_OK;
 }
+
+namespace {
+hipError_t launch_forward(const Plan& p, const FwdArgs& a, hipStream_t s) {
+  switch (p.dtype) {
+    case GF_F32: return launch_forward_f32(p, a, s);
+    case GF_F16: return launch_forward_f16(p, a, s);
+    case GF_BF16: return launch_forward_bf16(p, a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_backward(const Plan& p, const BwdArgs& a, hipStream_t s) {
+  switch (p.dtype) {
+    case GF_F32: return launch_backward_f32(p, a, s);
+    case GF_F16: return launch_backward_f16(p, a, s);
+    case GF_BF16: return launch_backward_bf16(p, a, s);
+  }
+  return hipErrorInvalidValue;
+}
+}  // namespace
 
 // ------------------------------------------------------------ profiling
 

@@ -16,8 +16,9 @@ struct Plan {
   int S;        // integer upsampling factor (H = S h, W = S w)
   int VEC;      // high-res elements per thread-load (16 bytes, or 1)
   int planes;   // n * c
-  // low-res coefficient kernel tiles
-  int coTH, coTW;
+  // low-res coefficient kernel: one wave per strip of 64 lanes (columns)
+  // x coTR output rows; co_nx strips, co_ny row segments
+  int coTR, co_nx, co_ny;
   size_t coLDS;
   // high-res apply: rows per thread
   int RB, nrb, nxv;
@@ -25,8 +26,8 @@ struct Plan {
   // columns (64 * VEC high-res columns)
   int bh, tw, nby, nbx;
   size_t ublk_floats;  // floats per block (2 * (bh + 2) * (tw + 2))
-  // backward low-res tiles
-  int loTH, loTW, lo_ntx, lo_nty;
+  // backward low-res kernel: same walker shape
+  int loTR, lo_nx, lo_ny;
   size_t loLDS;
   // workspace layout (bytes)
   size_t off_abar, off_bbar, off_u, off_eps, ws_fwd, ws_bwd;
@@ -52,8 +53,14 @@ struct BwdArgs {
   char* ws;
 };
 
-hipError_t launch_forward(const Plan& p, const FwdArgs& a, hipStream_t s);
-hipError_t launch_backward(const Plan& p, const BwdArgs& a, hipStream_t s);
+// One pair of launchers per image I/O type (gf_f32.hip, gf_f16.hip,
+// gf_bf16.hip); gf_api.cpp picks by desc->io_dtype.
+hipError_t launch_forward_f32(const Plan& p, const FwdArgs& a, hipStream_t s);
+hipError_t launch_backward_f32(const Plan& p, const BwdArgs& a, hipStream_t s);
+hipError_t launch_forward_f16(const Plan& p, const FwdArgs& a, hipStream_t s);
+hipError_t launch_backward_f16(const Plan& p, const BwdArgs& a, hipStream_t s);
+hipError_t launch_forward_bf16(const Plan& p, const FwdArgs& a, hipStream_t s);
+hipError_t launch_backward_bf16(const Plan& p, const BwdArgs& a, hipStream_t s);
 
 // Profiling hooks (gf_api.cpp): wrap one kernel launch.
 void prof_begin(const char* name, hipStream_t s);

@@ -1,0 +1,1090 @@
+#pragma once
+// HIP kernels of the fast guided filtering layer for gfx950 (MI355X).
+// Included once per I/O element type by gf_f32.hip, gf_f16.hip and
+// gf_bf16.hip, which instantiate the launchers for that type.
+//
+// Forward (Sec. III-B/C, Eq. (1)-(2)):
+//   coef_kernel   low-res tile in LDS: box statistics of the recentred guide
+//                 and input, A = cov/(var+eps), b = mean_p - A mean_I, then
+//                 their window means; writes Abar, bbar (low-res, fp32).
+//   apply_kernel  streams the high-res guide: bilinear Abar/bbar taps are
+//                 blended in registers (never stored at high resolution) and
+//                 q = A_h G_h + b_h is written with non-temporal stores.
+// Backward (Algorithm 1, plus the adjoint of the A/b window mean):
+//   coef_kernel   recomputes Abar.
+//   bwd_hi_kernel one wave per high-res block: dI_h = dq A_h, and the
+//                 transposed bilinear of dq G_h and dq accumulated first
+//                 vertically in registers, then horizontally through LDS,
+//                 into per-block partial low-res planes (no atomics).
+//   bwd_lo_kernel low-res tile: gathers the partial planes, recomputes the
+//                 box statistics and runs the adjoint chain; f_mu^T(y) is the
+//                 box SUM of y/N.  Writes dI_l, dp_l and per-tile deps partials.
+//   eps_reduce_kernel  fixed-order sum of the deps partials.
+// All reductions run in a fixed order, so results are bitwise reproducible.
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "gf_internal.h"
+
+namespace gf {
+namespace {
+
+// ------------------------------------------------------------ element I/O
+
+struct bf16 {
+  uint16_t u;
+};
+
+__device__ __forceinline__ float to_f(float v) { return v; }
+__device__ __forceinline__ float to_f(_Float16 v) { return (float)v; }
+__device__ __forceinline__ float to_f(bf16 v) { return __uint_as_float((uint32_t)v.u << 16); }
+
+template <typename T>
+__device__ __forceinline__ T from_f(float v);
+template <>
+__device__ __forceinline__ float from_f<float>(float v) {
+  return v;
+}
+template <>
+__device__ __forceinline__ _Float16 from_f<_Float16>(float v) {
+  return (_Float16)v;
+}
+template <>
+__device__ __forceinline__ bf16 from_f<bf16>(float v) {
+  uint32_t u = __float_as_uint(v);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return bf16{(uint16_t)((u >> 16) | 0x40u)};
+  u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
+  return bf16{(uint16_t)(u >> 16)};
+}
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+template <int BYTES>
+struct Carrier;
+template <>
+struct Carrier<16> {
+  typedef u32x4 type;
+};
+template <>
+struct Carrier<8> {
+  typedef u32x2 type;
+};
+template <>
+struct Carrier<4> {
+  typedef uint32_t type;
+};
+template <>
+struct Carrier<2> {
+  typedef uint16_t type;
+};
+
+template <typename T, int VEC>
+__device__ __forceinline__ void load_vec(const T* p, float (&out)[VEC]) {
+  typedef typename Carrier<sizeof(T) * VEC>::type C;
+  C c = *reinterpret_cast<const C*>(p);
+  T t[VEC];
+  __builtin_memcpy(t, &c, sizeof(C));
+#pragma unroll
+  for (int e = 0; e < VEC; ++e) out[e] = to_f(t[e]);
+}
+
+template <typename T, int VEC>
+__device__ __forceinline__ void store_vec_nt(T* p, const float (&v)[VEC]) {
+  typedef typename Carrier<sizeof(T) * VEC>::type C;
+  T t[VEC];
+#pragma unroll
+  for (int e = 0; e < VEC; ++e) t[e] = from_f<T>(v[e]);
+  C c;
+  __builtin_memcpy(&c, t, sizeof(C));
+  __builtin_nontemporal_store(c, reinterpret_cast<C*>(p));
+}
+
+// Synchronisation of the lanes of ONE wave around LDS exchanges.  Every
+// kernel that uses it runs single-wave workgroups: the LDS operations of a
+// wave execute in order, so a wavefront-scope fence (which orders them in the
+// compiler without waiting for outstanding global loads, unlike a workgroup
+// barrier) is all that is needed, and prefetched loads stay in flight.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Reciprocal with the hardware instruction (about 1 ulp); the low-res
+// kernels use it for window counts and variance denominators.
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// ------------------------------------------------------------ geometry
+
+// Pixels of the clipped window of radius r around index i on an axis of n.
+__device__ __forceinline__ int wcount(int i, int r, int n) {
+  return min(n - 1, i + r) - max(0, i - r) + 1;
+}
+
+// Half-pixel bilinear taps of high-res index y for an integer factor S over
+// a low-res axis of length n: source s = (2y + 1 - S) / (2S), clamped at 0;
+// taps floor(s) and floor(s)+1 (clamped to n-1) with weight frac(s).
+struct Tap {
+  int i0, i1;
+  float w;
+};
+__device__ __forceinline__ Tap tap(int y, int S, int n) {
+  Tap t;
+  const int num = 2 * y + 1 - S;
+  if (num < 0) {
+    t.i0 = 0;
+    t.i1 = min(1, n - 1);
+    t.w = 0.f;
+  } else {
+    t.i0 = num / (2 * S);
+    const int rem = num - t.i0 * 2 * S;
+    t.w = (float)rem / (float)(2 * S);
+    t.i1 = min(t.i0 + 1, n - 1);
+  }
+  return t;
+}
+
+// ------------------------------------------------------------ low-res column walkers
+//
+// The low-res kernels run one wave per strip of 64 adjacent columns (one
+// lane per column) and walk down a segment of rows, kPF rows per block.
+// Vertical windows live in per-wave LDS ring buffers (each lane only touches
+// its own column); horizontal windows read the neighbouring lanes' entries
+// of a row buffer after a wave-level sync.  Global rows are fetched one block
+// ahead.  Everything that depends on the radius is a compile-time constant,
+// so the window loops unroll and LDS reads use immediate offsets.  Pixels
+// outside the image are stored as zeros and excluded from every window by
+// explicit row/column masks (window sums run over the in-image part only).
+//
+// Window statistics are computed in two levels so that no step subtracts two
+// large, nearly equal numbers (the law of total variance over the window's
+// columns):
+//   per column, over the window's rows:  cm = mean, cvv = sum (g - cm_g)^2,
+//                                        cvp = sum (g - cm_g)(p - cm_p)
+//   over the window's columns:           mean = avg cm,
+//     var = sum cvv / N + avg (cm_g - mean_g)^2,
+//     cov = sum cvp / N + avg (cm_g - mean_g)(cm_p - mean_p).
+
+constexpr int kPF = 4;  // rows per block (and rows fetched ahead)
+
+struct WinStats {
+  float mI, mP, var, cov;
+};
+
+__device__ __forceinline__ bool row_ok(int t, int h) { return (unsigned)t < (unsigned)h; }
+
+// Column statistics of the K = 2R+1 rows centred on rc, read from a ring of
+// (g, p) pairs; rows outside the image hold zeros and are masked out.
+template <int R, int KR>
+__device__ __forceinline__ float4 column_stats(const float2* ring, int rc, int x0, int h,
+                                               int lane) {
+  constexpr int K = 2 * R + 1;
+  float2 v[K];
+  int nrow = 0;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int t = rc - R + k;
+    v[k] = ring[((t - x0) % KR) * 64 + lane];
+    nrow += row_ok(t, h) ? 1 : 0;
+  }
+  float s0 = 0.f, s1 = 0.f;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    s0 += v[k].x;
+    s1 += v[k].y;
+  }
+  const float inv = rcp((float)nrow);
+  const float cg = s0 * inv, cp = s1 * inv;
+  float vv = 0.f, vp = 0.f;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const bool ok = row_ok(rc - R + k, h);
+    const float dg = ok ? v[k].x - cg : 0.f;
+    const float dp = ok ? v[k].y - cp : 0.f;
+    vv += dg * dg;
+    vp += dg * dp;
+  }
+  return make_float4(cg, cp, vv, vp);
+}
+
+// Window statistics at this lane from the column-statistics row cs (entries
+// of lanes lane-R .. lane+R); cmask[k] = 1 for in-image columns.
+template <int R>
+__device__ __forceinline__ WinStats window_stats(const float4* cs, int lane,
+                                                 const float (&cmask)[2 * R + 1], float inv_ncol,
+                                                 float invN) {
+  constexpr int K = 2 * R + 1;
+  float4 c[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) c[k] = cs[lane + k - R];
+  float s0 = 0.f, s1 = 0.f, wv = 0.f, wp = 0.f;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    s0 += c[k].x;
+    s1 += c[k].y;
+    wv += c[k].z;
+    wp += c[k].w;
+  }
+  WinStats st;
+  st.mI = s0 * inv_ncol;
+  st.mP = s1 * inv_ncol;
+  float bv = 0.f, bp = 0.f;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const float dg = cmask[k] * (c[k].x - st.mI);
+    const float dp = c[k].y - st.mP;
+    bv += dg * dg;
+    bp += dg * dp;
+  }
+  st.var = wv * invN + bv * inv_ncol;
+  st.cov = wp * invN + bp * inv_ncol;
+  return st;
+}
+
+// ------------------------------------------------------------ forward: low-res
+
+struct CoefArgs {
+  const void* I_lo;
+  const void* p_lo;
+  const float* eps;
+  int eps_count, c, h, w, TR;
+  float* abar;  // [planes, h, w]
+  float* bbar;  // [planes, h, w] or null
+};
+
+// Abar, bbar (A, b when MAB is false) of a strip of 64 - 2(R + R_ab) output
+// columns x TR output rows.  The guide and input are recentred by their
+// values at the segment centre (variance and covariance are shift
+// invariant; b is formed from the actual means).
+template <typename T, int R, bool MAB>
+__global__ __launch_bounds__(64) void coef_kernel(CoefArgs a) {
+  constexpr int K = 2 * R + 1;
+  constexpr int HB = MAB ? R : 0;
+  constexpr int HAL = R + HB;
+  constexpr int TWo = 64 - 2 * HAL;
+  constexpr int KR = 2 * R + kPF;  // ring rows: a block writes kPF rows before reading
+  extern __shared__ float4 lds4[];
+  float2* gp = reinterpret_cast<float2*>(lds4);  // [KR][64] recentred (g, p)
+  float4* cs = reinterpret_cast<float4*>(gp + KR * 64);  // [kPF][64] column statistics
+  float2* ab = reinterpret_cast<float2*>(cs + kPF * 64);  // [KR][64] (A, b)
+  float2* vs = ab + KR * 64;                               // [kPF][64] column sums of (A, b)
+  const int lane = threadIdx.x;
+  const int plane = blockIdx.z;
+  const float e = a.eps[a.eps_count == 1 ? 0 : plane / a.c];
+  const int h = a.h, w = a.w;
+  const int j0 = blockIdx.x * TWo;
+  const int jl = j0 - HAL;  // image column of lane 0
+  const int j = jl + lane;
+  const bool colin = (unsigned)j < (unsigned)w;
+  const int i0 = blockIdx.y * a.TR, i1 = min(i0 + a.TR, h);
+  const size_t pofs = (size_t)plane * h * w;
+  const T* G = reinterpret_cast<const T*>(a.I_lo) + pofs;
+  const T* P = reinterpret_cast<const T*>(a.p_lo) + pofs;
+  float* Ab = a.abar + pofs;
+  float* Bb = a.bbar ? a.bbar + pofs : nullptr;
+  const int ic = min(i0 + a.TR / 2, h - 1), jc = min(max(j0 + TWo / 2, 0), w - 1);
+  const float cg = to_f(G[(size_t)ic * w + jc]);
+  const float cp = to_f(P[(size_t)ic * w + jc]);
+  float cmask[K];
+  float ncol = 0.f;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    cmask[k] = ((unsigned)(j + k - R) < (unsigned)w) ? 1.f : 0.f;
+    ncol += cmask[k];
+  }
+  const float inv_ncol = rcp(fmaxf(ncol, 1.f));
+  const bool a_lane = colin && lane >= R && lane < 64 - R;  // lanes that form (A, b)
+  const bool out_lane = colin && lane >= HAL && lane < HAL + TWo;
+  const int x0 = i0 - HAL, xend = i1 + HAL;  // input rows walked
+  auto ring = [&](int x) { return ((x - x0) % KR) * 64 + lane; };
+
+  // Loads are unconditional (clamped address) and the queue holds the raw
+  // values: a load inside a divergent branch, or arithmetic right after it,
+  // would make the wave wait for it there instead of a block later.
+  const int jcl = min(max(j, 0), w - 1);
+  auto load = [&](int x, T& g, T& p) {
+    const size_t o = (size_t)min(max(x, 0), h - 1) * w + jcl;
+    g = G[o];
+    p = P[o];
+  };
+
+  auto block = [&](int xb, const T (&gq)[kPF], const T (&pq)[kPF]) {
+#pragma unroll
+    for (int d = 0; d < kPF; ++d) {
+      const int x = xb + d;
+      const bool ok = colin && row_ok(x, h);
+      if (x < xend)
+        gp[ring(x)] = make_float2(ok ? to_f(gq[d]) - cg : 0.f, ok ? to_f(pq[d]) - cp : 0.f);
+    }
+    // rows rc = x - R whose windows are complete with this block
+#pragma unroll
+    for (int d = 0; d < kPF; ++d) {
+      const int rc = xb + d - R;
+      if (xb + d < xend && rc - R >= x0 && rc >= i0 - HB && rc < i1 + HB) {
+        float4 st = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (colin && row_ok(rc, h)) st = column_stats<R, KR>(gp, rc, x0, h, lane);
+        cs[d * 64 + lane] = st;
+      }
+    }
+    wave_sync();
+#pragma unroll
+    for (int d = 0; d < kPF; ++d) {
+      const int rc = xb + d - R;
+      if (xb + d < xend && rc - R >= x0 && rc >= i0 - HB && rc < i1 + HB) {
+        float A = 0.f, B = 0.f;
+        if (a_lane && row_ok(rc, h)) {
+          const int nrow = min(rc + R, h - 1) - max(rc - R, 0) + 1;
+          const float invN = inv_ncol * rcp((float)nrow);
+          const WinStats st = window_stats<R>(cs + d * 64, lane, cmask, inv_ncol, invN);
+          const float den = st.var + e;
+          A = den > 0.f ? st.cov * rcp(den) : 0.f;
+          B = (st.mP + cp) - A * (st.mI + cg);
+        }
+        if (!MAB) {
+          if (rc >= i0 && rc < i1 && out_lane) {
+            Ab[(size_t)rc * w + j] = A;
+            if (Bb) Bb[(size_t)rc * w + j] = B;
+          }
+        } else {
+          ab[ring(rc)] = make_float2(A, B);
+        }
+      }
+    }
+    if (MAB) {
+#pragma unroll
+      for (int d = 0; d < kPF; ++d) {
+        const int ra = xb + d - 2 * R;  // row whose (A, b) window is complete
+        if (xb + d < xend && ra >= i0 && ra < i1) {
+          float sa = 0.f, sb = 0.f;
+#pragma unroll
+          for (int k = 0; k < K; ++k) {
+            const float2 v = ab[ring(ra - R + k)];  // rows outside the image hold zeros
+            sa += v.x;
+            sb += v.y;
+          }
+          vs[d * 64 + lane] = make_float2(sa, sb);
+        }
+      }
+      wave_sync();
+#pragma unroll
+      for (int d = 0; d < kPF; ++d) {
+        const int ra = xb + d - 2 * R;
+        if (xb + d < xend && ra >= i0 && ra < i1 && out_lane) {
+          float sa = 0.f, sb = 0.f;
+#pragma unroll
+          for (int k = 0; k < K; ++k) {  // columns outside the image hold zeros
+            const float2 v = vs[d * 64 + lane + k - R];
+            sa += v.x;
+            sb += v.y;
+          }
+          const int nrow = min(ra + R, h - 1) - max(ra - R, 0) + 1;
+          const float invN = inv_ncol * rcp((float)nrow);
+          Ab[(size_t)ra * w + j] = sa * invN;
+          if (Bb) Bb[(size_t)ra * w + j] = sb * invN;
+        }
+      }
+    }
+    wave_sync();
+  };
+
+  T gq[kPF], pq[kPF];
+#pragma unroll
+  for (int d = 0; d < kPF; ++d) load(x0 + d, gq[d], pq[d]);
+  for (int base = x0; base < xend; base += kPF) {
+    T gn[kPF], pn[kPF];
+#pragma unroll
+    for (int d = 0; d < kPF; ++d) load(base + kPF + d, gn[d], pn[d]);
+    block(base, gq, pq);
+#pragma unroll
+    for (int d = 0; d < kPF; ++d) {
+      gq[d] = gn[d];
+      pq[d] = pn[d];
+    }
+  }
+}
+
+// ------------------------------------------------------------ forward: high-res
+
+struct ApplyArgs {
+  const void* I_hi;
+  void* q;
+  const float* abar;
+  const float* bbar;
+  int h, w, H, W, RB, nrb, nxv;
+  long long total;
+};
+
+// Horizontally interpolated low-res row `i` (clamped) at the VEC columns of
+// this thread.
+template <int VEC>
+__device__ __forceinline__ void hrow(const float* L, int i, int h, int w, const int (&j0)[VEC],
+                                     const int (&j1)[VEC], const float (&wx)[VEC],
+                                     float (&out)[VEC]) {
+  i = min(max(i, 0), h - 1);
+  const float* row = L + (size_t)i * w;
+#pragma unroll
+  for (int e = 0; e < VEC; ++e) {
+    const float a0 = row[j0[e]], a1 = row[j1[e]];
+    out[e] = a0 + wx[e] * (a1 - a0);
+  }
+}
+
+// One thread = VEC adjacent high-res columns x RB rows of one plane.  Rows
+// are walked one low-res row block (S rows) at a time; the three low-res
+// rows a block touches (i-1, i, i+1, clamped) are kept interpolated in
+// registers, so each high-res pixel costs one blend and one FMA.
+template <typename T, int S, int VEC>
+__global__ __launch_bounds__(256) void apply_kernel(ApplyArgs a) {
+  const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (t >= a.total) return;
+  const int xv = (int)(t % a.nxv);
+  const long long rest = t / a.nxv;
+  const int rb = (int)(rest % a.nrb);
+  const int plane = (int)(rest / a.nrb);
+  const int h = a.h, w = a.w, W = a.W;
+  const int x0 = xv * VEC;
+  int j0[VEC], j1[VEC];
+  float wx[VEC];
+#pragma unroll
+  for (int e = 0; e < VEC; ++e) {
+    const Tap tx = tap(x0 + e, S, w);
+    j0[e] = tx.i0;
+    j1[e] = tx.i1;
+    wx[e] = tx.w;
+  }
+  const float* Ab = a.abar + (size_t)plane * h * w;
+  const float* Bb = a.bbar + (size_t)plane * h * w;
+  const size_t hofs = (size_t)plane * a.H * W + x0;
+  const T* Gp = reinterpret_cast<const T*>(a.I_hi) + hofs;
+  T* Qp = reinterpret_cast<T*>(a.q) + hofs;
+  const int ib0 = rb * (a.RB / S);
+  const int ib1 = min(ib0 + a.RB / S, h);
+  float am[VEC], ac[VEC], ap[VEC], bm[VEC], bc[VEC], bp[VEC];
+  hrow<VEC>(Ab, ib0 - 1, h, w, j0, j1, wx, am);
+  hrow<VEC>(Bb, ib0 - 1, h, w, j0, j1, wx, bm);
+  hrow<VEC>(Ab, ib0, h, w, j0, j1, wx, ac);
+  hrow<VEC>(Bb, ib0, h, w, j0, j1, wx, bc);
+  for (int i = ib0; i < ib1; ++i) {
+    float g[S][VEC];
+#pragma unroll
+    for (int t = 0; t < S; ++t) load_vec<T, VEC>(Gp + (size_t)(S * i + t) * W, g[t]);
+    hrow<VEC>(Ab, i + 1, h, w, j0, j1, wx, ap);
+    hrow<VEC>(Bb, i + 1, h, w, j0, j1, wx, bp);
+#pragma unroll
+    for (int t = 0; t < S; ++t) {
+      const int num = 2 * t + 1 - S;
+      float q[VEC];
+      if (num < 0) {
+        const float wy = (float)(num + 2 * S) / (float)(2 * S);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+          const float A = am[e] + wy * (ac[e] - am[e]);
+          const float B = bm[e] + wy * (bc[e] - bm[e]);
+          q[e] = A * g[t][e] + B;
+        }
+      } else {
+        const float wy = (float)num / (float)(2 * S);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+          const float A = ac[e] + wy * (ap[e] - ac[e]);
+          const float B = bc[e] + wy * (bp[e] - bc[e]);
+          q[e] = A * g[t][e] + B;
+        }
+      }
+      store_vec_nt<T, VEC>(Qp + (size_t)(S * i + t) * W, q);
+    }
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      am[e] = ac[e];
+      ac[e] = ap[e];
+      bm[e] = bc[e];
+      bc[e] = bp[e];
+    }
+  }
+}
+
+// ------------------------------------------------------------ backward: high-res
+
+struct BwdHiArgs {
+  const void* I_hi;
+  const void* dq;
+  void* dI_hi;  // may be null
+  const float* abar;
+  float* U;     // per-block partial planes
+  int h, w, H, W, bh, tw, nby, nbx;
+};
+
+// One wave per block of bh low-res rows (S*bh high-res rows) x 64*VEC
+// high-res columns.  The block writes the transposed-bilinear contributions
+// of its own pixels to low-res rows i_a-1 .. i_a+bh and columns
+// j_a-1 .. j_a+tw: a (bh+2) x (tw+2) partial plane for dA_bar (from dq*G_h)
+// and one for db_bar (from dq).  The border rows/columns overlap the
+// neighbouring blocks' and are summed by the low-res kernel.
+template <typename T, int S, int VEC>
+__global__ __launch_bounds__(64) void bwd_hi_kernel(BwdHiArgs a) {
+  constexpr int TWH = 64 * VEC;  // high-res columns per block
+  __shared__ float sR[2][TWH];
+  const int lane = threadIdx.x;
+  const int bx = blockIdx.x, by = blockIdx.y, plane = blockIdx.z;
+  const int h = a.h, w = a.w, W = a.W, bh = a.bh, tw = a.tw;
+  const int X_a = bx * TWH;
+  const int x0 = X_a + lane * VEC;
+  const bool valid = x0 < W;
+  const int j_a = X_a / S;
+  const int i_a = by * bh;
+  const int i_b = min(i_a + bh, h);
+  int j0[VEC], j1[VEC];
+  float wx[VEC];
+#pragma unroll
+  for (int e = 0; e < VEC; ++e) {
+    const Tap tx = tap(valid ? x0 + e : 0, S, w);
+    j0[e] = tx.i0;
+    j1[e] = tx.i1;
+    wx[e] = tx.w;
+  }
+  const float* Ab = a.abar + (size_t)plane * h * w;
+  const size_t hofs = (size_t)plane * a.H * W + (valid ? x0 : 0);
+  const T* Gp = reinterpret_cast<const T*>(a.I_hi) + hofs;
+  const T* Dp = reinterpret_cast<const T*>(a.dq) + hofs;
+  T* Op = a.dI_hi ? reinterpret_cast<T*>(a.dI_hi) + hofs : nullptr;
+  const int UW = tw + 2;
+  const size_t UP = (size_t)(bh + 2) * UW;
+  float* Ub = a.U + (((size_t)plane * a.nby + by) * a.nbx + bx) * 2 * UP;
+
+  auto flush = [&](const float (&uA)[VEC], const float (&uB)[VEC], int lr) {
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      sR[0][lane * VEC + e] = uA[e];
+      sR[1][lane * VEC + e] = uB[e];
+    }
+    wave_sync();
+    for (int k = lane; k < UW; k += 64) {
+      const int j = j_a - 1 + k;
+      float sa = 0.f, sb = 0.f;
+      if (j >= 0 && j < w) {
+        const int xlo = max(max(S * (j - 1), X_a), 0);
+        const int xhi = min(min(S * (j + 2), X_a + TWH), W);
+        for (int x = xlo; x < xhi; ++x) {
+          const Tap tx = tap(x, S, w);
+          const float wt = (tx.i0 == j ? 1.f - tx.w : 0.f) + (tx.i1 == j ? tx.w : 0.f);
+          sa += wt * sR[0][x - X_a];
+          sb += wt * sR[1][x - X_a];
+        }
+      }
+      Ub[(size_t)lr * UW + k] = sa;
+      Ub[UP + (size_t)lr * UW + k] = sb;
+    }
+    wave_sync();
+  };
+
+  float am[VEC], ac[VEC], ap[VEC];
+  float pA[VEC], cA[VEC], nA[VEC], pB[VEC], cB[VEC], nB[VEC];
+#pragma unroll
+  for (int e = 0; e < VEC; ++e) pA[e] = cA[e] = nA[e] = pB[e] = cB[e] = nB[e] = 0.f;
+  hrow<VEC>(Ab, i_a - 1, h, w, j0, j1, wx, am);
+  hrow<VEC>(Ab, i_a, h, w, j0, j1, wx, ac);
+  for (int i = i_a; i < i_b; ++i) {
+    float g[S][VEC], d[S][VEC];
+    // unconditional loads (lanes past the image edge re-read column 0 and
+    // are zeroed), so that no load sits in a divergent branch
+#pragma unroll
+    for (int t = 0; t < S; ++t) {
+      load_vec<T, VEC>(Dp + (size_t)(S * i + t) * W, d[t]);
+      load_vec<T, VEC>(Gp + (size_t)(S * i + t) * W, g[t]);
+    }
+    if (!valid) {
+#pragma unroll
+      for (int t = 0; t < S; ++t)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) d[t][e] = 0.f;
+    }
+    hrow<VEC>(Ab, i + 1, h, w, j0, j1, wx, ap);
+    const bool top = (i == 0), bot = (i == h - 1);
+#pragma unroll
+    for (int t = 0; t < S; ++t) {
+      const int num = 2 * t + 1 - S;
+      float o[VEC];
+      if (num < 0) {
+        const float wy = (float)(num + 2 * S) / (float)(2 * S);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+          o[e] = d[t][e] * (am[e] + wy * (ac[e] - am[e]));
+          const float vA = d[t][e] * g[t][e], vB = d[t][e];
+          if (top) {
+            cA[e] += vA;
+            cB[e] += vB;
+          } else {
+            pA[e] += (1.f - wy) * vA;
+            cA[e] += wy * vA;
+            pB[e] += (1.f - wy) * vB;
+            cB[e] += wy * vB;
+          }
+        }
+      } else {
+        const float wy = (float)num / (float)(2 * S);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+          o[e] = d[t][e] * (ac[e] + wy * (ap[e] - ac[e]));
+          const float vA = d[t][e] * g[t][e], vB = d[t][e];
+          if (bot) {
+            cA[e] += vA;
+            cB[e] += vB;
+          } else {
+            cA[e] += (1.f - wy) * vA;
+            nA[e] += wy * vA;
+            cB[e] += (1.f - wy) * vB;
+            nB[e] += wy * vB;
+          }
+        }
+      }
+      if (Op && valid) store_vec_nt<T, VEC>(Op + (size_t)(S * i + t) * W, o);
+    }
+    flush(pA, pB, i - i_a);  // low-res row i-1 is complete
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      pA[e] = cA[e];
+      cA[e] = nA[e];
+      nA[e] = 0.f;
+      pB[e] = cB[e];
+      cB[e] = nB[e];
+      nB[e] = 0.f;
+      am[e] = ac[e];
+      ac[e] = ap[e];
+    }
+  }
+  flush(pA, pB, i_b - i_a);      // row i_b - 1
+  flush(cA, cB, i_b - i_a + 1);  // row i_b (contributions of the last rows)
+}
+
+// ------------------------------------------------------------ backward: low-res
+
+struct BwdLoArgs {
+  const void* I_lo;
+  const void* p_lo;
+  const float* eps;
+  int eps_count, c;
+  const float* U;
+  int bh, tw, nby, nbx;
+  int h, w, TR;
+  float* dI_lo;     // may be null
+  float* dp_lo;     // may be null
+  float* eps_part;  // [planes][gridDim.y][gridDim.x]
+};
+
+// The partial planes that cover low-res pixel (i, j) are the block that owns
+// it plus, on a block border, the neighbour whose halo row/column it is
+// (weights wb, wc = 1).  Four reads per plane are always issued (absent
+// neighbours re-read the owner, with weight 0) so that no load sits in a
+// divergent branch.
+struct URaw {
+  float a00, a01, a10, a11, v00, v01, v10, v11;
+};
+
+__device__ __forceinline__ void u_weights(const BwdLoArgs& a, int i, int j, int& b0, int& b1,
+                                          int& c0, int& c1, float& wb, float& wc) {
+  const int bh = a.bh, tw = a.tw;
+  b0 = i / bh;
+  c0 = j / tw;
+  const int ri = i - b0 * bh, rj = j - c0 * tw;
+  b1 = b0;
+  c1 = c0;
+  wb = 0.f;
+  wc = 0.f;
+  if (ri == 0 && b0 > 0) {
+    b1 = b0 - 1;
+    wb = 1.f;
+  } else if (ri == bh - 1 && b0 + 1 < a.nby) {
+    b1 = b0 + 1;
+    wb = 1.f;
+  }
+  if (rj == 0 && c0 > 0) {
+    c1 = c0 - 1;
+    wc = 1.f;
+  } else if (rj == tw - 1 && c0 + 1 < a.nbx) {
+    c1 = c0 + 1;
+    wc = 1.f;
+  }
+}
+
+__device__ __forceinline__ URaw gather_u_raw(const BwdLoArgs& a, int plane, int i, int j) {
+  const int bh = a.bh, tw = a.tw, UW = tw + 2;
+  const size_t UP = (size_t)(bh + 2) * UW;
+  int b0, b1, c0, c1;
+  float wb, wc;
+  u_weights(a, i, j, b0, b1, c0, c1, wb, wc);
+  const float* base = a.U + (size_t)plane * a.nby * a.nbx * 2 * UP;
+  auto at = [&](int by, int bx) {
+    return base + ((size_t)by * a.nbx + bx) * 2 * UP + (size_t)(i - (by * bh - 1)) * UW +
+           (j - (bx * tw - 1));
+  };
+  const float* p00 = at(b0, c0);
+  const float* p01 = at(b0, c1);
+  const float* p10 = at(b1, c0);
+  const float* p11 = at(b1, c1);
+  return URaw{p00[0], p01[0], p10[0], p11[0], p00[UP], p01[UP], p10[UP], p11[UP]};
+}
+
+// Adjoint of the low-res part (Algorithm 1 with the adjoint of the A/b window
+// mean): one wave per strip of 64 - 4R output columns x TR output rows.
+// Per input row: ring the recentred guide/input and the gathered upstream
+// planes dAbar, dbbar (divided by the window count N when MAB, so that
+// f_mu^T(y) = box sum of y/N); per row whose window is complete: statistics,
+// A, and the adjoint quantities X = (dmean_I, dmean_p, dcov, dvar) / N; per
+// row whose X window is complete: box sums of X give dG and dp.
+template <typename T, int R, bool MAB>
+__global__ __launch_bounds__(64) void bwd_lo_kernel(BwdLoArgs a) {
+  constexpr int K = 2 * R + 1;
+  constexpr int TWo = 64 - 4 * R;
+  constexpr int KR = 2 * R + kPF;  // ring rows: a block writes kPF rows before reading
+  extern __shared__ float4 lds4[];
+  float4* in = lds4;              // [KR][64] (g', p', dAbar, dbbar)
+  float4* cs = in + KR * 64;      // [kPF][64] column statistics
+  float2* cu = reinterpret_cast<float2*>(cs + kPF * 64);  // [kPF][64] column sums of dAbar, dbbar
+  float4* xr = reinterpret_cast<float4*>(cu + kPF * 64);  // [KR][64] X
+  float4* vs = xr + KR * 64;      // [kPF][64] column sums of X
+  const int lane = threadIdx.x;
+  const int plane = blockIdx.z;
+  const float e = a.eps[a.eps_count == 1 ? 0 : plane / a.c];
+  const int h = a.h, w = a.w;
+  const int j0 = blockIdx.x * TWo;
+  const int jl = j0 - 2 * R;
+  const int j = jl + lane;
+  const bool colin = (unsigned)j < (unsigned)w;
+  const int i0 = blockIdx.y * a.TR, i1 = min(i0 + a.TR, h);
+  const size_t pofs = (size_t)plane * h * w;
+  const T* G = reinterpret_cast<const T*>(a.I_lo) + pofs;
+  const T* P = reinterpret_cast<const T*>(a.p_lo) + pofs;
+  const int ic = min(i0 + a.TR / 2, h - 1), jc = min(max(j0 + TWo / 2, 0), w - 1);
+  const float cg = to_f(G[(size_t)ic * w + jc]);
+  const float cp = to_f(P[(size_t)ic * w + jc]);
+  float cmask[K];
+  float ncol = 0.f;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    cmask[k] = ((unsigned)(j + k - R) < (unsigned)w) ? 1.f : 0.f;
+    ncol += cmask[k];
+  }
+  const float inv_ncol = rcp(fmaxf(ncol, 1.f));
+  const bool x_lane = colin && lane >= R && lane < 64 - R;  // lanes that form X
+  const bool out_col = colin && lane >= 2 * R && lane < 2 * R + TWo;
+  const int x0 = i0 - 2 * R, xend = i1 + 2 * R;
+  auto ring = [&](int x) { return ((x - x0) % KR) * 64 + lane; };
+  float deps_acc = 0.f;
+
+  // Loads are unconditional (clamped address) and the queue holds the raw
+  // values: a load inside a divergent branch, or arithmetic right after it,
+  // would make the wave wait for it there instead of a block later.
+  const int jcl = min(max(j, 0), w - 1);
+  struct Raw {
+    T g, p;
+    URaw u;
+  };
+  auto load = [&](int x) {
+    const int xc = min(max(x, 0), h - 1);
+    const size_t o = (size_t)xc * w + jcl;
+    return Raw{G[o], P[o], gather_u_raw(a, plane, xc, jcl)};
+  };
+
+  auto block = [&](int xb, const Raw (&q)[kPF]) {
+#pragma unroll
+    for (int d = 0; d < kPF; ++d) {
+      const int x = xb + d;
+      if (x >= xend) continue;
+      const bool ok = colin && row_ok(x, h);
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (ok) {
+        int b0, b1, c0, c1;
+        float wb, wc;
+        u_weights(a, x, j, b0, b1, c0, c1, wb, wc);
+        const URaw& z = q[d].u;
+        float u = (z.a00 + wc * z.a01) + wb * (z.a10 + wc * z.a11);
+        float vv = (z.v00 + wc * z.v01) + wb * (z.v10 + wc * z.v11);
+        if (MAB) {  // f_mu^T(y) = box sum of y / N: divide by N here
+          const int nrow = min(x + R, h - 1) - max(x - R, 0) + 1;
+          const float invN = inv_ncol * rcp((float)nrow);
+          u *= invN;
+          vv *= invN;
+        }
+        v = make_float4(to_f(q[d].g) - cg, to_f(q[d].p) - cp, u, vv);
+      }
+      in[ring(x)] = v;
+    }
+    // rows rc = x - R whose windows are complete with this block
+#pragma unroll
+    for (int d = 0; d < kPF; ++d) {
+      const int rc = xb + d - R;
+      if (!(xb + d < xend && rc - R >= x0 && rc >= i0 - R && rc < i1 + R)) continue;
+      float4 st = make_float4(0.f, 0.f, 0.f, 0.f);
+      float2 su = make_float2(0.f, 0.f);
+      if (colin && row_ok(rc, h)) {
+        float4 v[K];
+        int nrow = 0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          v[k] = in[ring(rc - R + k)];
+          nrow += row_ok(rc - R + k, h) ? 1 : 0;
+        }
+        float s0 = 0.f, s1 = 0.f;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          s0 += v[k].x;
+          s1 += v[k].y;
+          su.x += v[k].z;
+          su.y += v[k].w;
+        }
+        const float inv = rcp((float)nrow);
+        st.x = s0 * inv;
+        st.y = s1 * inv;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const bool ok = row_ok(rc - R + k, h);
+          const float dg = ok ? v[k].x - st.x : 0.f;
+          const float dp = ok ? v[k].y - st.y : 0.f;
+          st.z += dg * dg;
+          st.w += dg * dp;
+        }
+      }
+      cs[d * 64 + lane] = st;
+      cu[d * 64 + lane] = su;
+    }
+    wave_sync();
+#pragma unroll
+    for (int d = 0; d < kPF; ++d) {
+      const int rc = xb + d - R;
+      if (!(xb + d < xend && rc - R >= x0 && rc >= i0 - R && rc < i1 + R)) continue;
+      float4 X = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (x_lane && row_ok(rc, h)) {
+        const int nrow = min(rc + R, h - 1) - max(rc - R, 0) + 1;
+        const float invN = inv_ncol * rcp((float)nrow);
+        const WinStats st = window_stats<R>(cs + d * 64, lane, cmask, inv_ncol, invN);
+        float dA, db;
+        if (MAB) {  // f_mu^T of the upstream planes: box sums of dAbar/N, dbbar/N
+          dA = 0.f;
+          db = 0.f;
+#pragma unroll
+          for (int k = 0; k < K; ++k) {
+            const float2 c = cu[d * 64 + lane + k - R];
+            dA += c.x;
+            db += c.y;
+          }
+        } else {
+          const float4 v = in[ring(rc)];
+          dA = v.z;
+          db = v.w;
+        }
+        const float den = st.var + e;
+        const float rden = den > 0.f ? rcp(den) : 0.f;  // A := 0 when var + eps == 0
+        const float A = st.cov * rden;
+        // b = mean_p - A mean_I (actual means), A = cov / (var + eps)
+        const float dAt = dA - db * (st.mI + cg);
+        const float dcov = dAt * rden;
+        const float dvar = -dAt * A * rden;
+        // var = E[g'^2] - mI'^2, cov = E[g'p'] - mI' mP' (recentred g', p')
+        const float dmI = -db * A - dcov * st.mP - 2.f * dvar * st.mI;
+        const float dmP = db - dcov * st.mI;
+        X = make_float4(dmI * invN, dmP * invN, dcov * invN, dvar * invN);
+        if (rc >= i0 && rc < i1 && out_col) deps_acc += dvar;
+      }
+      xr[ring(rc)] = X;
+    }
+    // rows rx = x - 2R whose X windows are complete
+#pragma unroll
+    for (int d = 0; d < kPF; ++d) {
+      const int rx = xb + d - 2 * R;
+      if (!(xb + d < xend && rx >= i0 && rx < i1)) continue;
+      float4 sum = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+      for (int k = 0; k < K; ++k) {  // rows outside the image hold zeros
+        const float4 v = xr[ring(rx - R + k)];
+        sum.x += v.x;
+        sum.y += v.y;
+        sum.z += v.z;
+        sum.w += v.w;
+      }
+      vs[d * 64 + lane] = sum;
+    }
+    wave_sync();
+#pragma unroll
+    for (int d = 0; d < kPF; ++d) {
+      const int rx = xb + d - 2 * R;
+      if (!(xb + d < xend && rx >= i0 && rx < i1 && out_col)) continue;
+      float4 B = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+      for (int k = 0; k < K; ++k) {  // columns outside the image hold zeros
+        const float4 v = vs[d * 64 + lane + k - R];
+        B.x += v.x;
+        B.y += v.y;
+        B.z += v.z;
+        B.w += v.w;
+      }
+      const float4 gpv = in[ring(rx)];
+      const size_t go = pofs + (size_t)rx * w + j;
+      if (a.dI_lo) a.dI_lo[go] = B.x + 2.f * B.w * gpv.x + B.z * gpv.y;
+      if (a.dp_lo) a.dp_lo[go] = B.y + B.z * gpv.x;
+    }
+    wave_sync();
+  };
+
+  Raw q[kPF];
+#pragma unroll
+  for (int d = 0; d < kPF; ++d) q[d] = load(x0 + d);
+  for (int base = x0; base < xend; base += kPF) {
+    Raw nq[kPF];
+#pragma unroll
+    for (int d = 0; d < kPF; ++d) nq[d] = load(base + kPF + d);
+    block(base, q);
+#pragma unroll
+    for (int d = 0; d < kPF; ++d) q[d] = nq[d];
+  }
+  // fixed-order wave reduction of this strip's deps contribution
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) deps_acc += __shfl_xor(deps_acc, off);
+  if (lane == 0)
+    a.eps_part[((size_t)plane * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = deps_acc;
+}
+
+__global__ __launch_bounds__(256) void eps_reduce_kernel(const float* part, int per_plane,
+                                                          int c, int n, int eps_count,
+                                                          float* deps) {
+  __shared__ float red[256];
+  const int k = blockIdx.x;
+  const size_t lo = (size_t)(eps_count == 1 ? 0 : k * c) * per_plane;
+  const size_t hi = (size_t)(eps_count == 1 ? n * c : (k + 1) * c) * per_plane;
+  float s = 0.f;
+  for (size_t q = lo + threadIdx.x; q < hi; q += 256) s += part[q];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) deps[k] = red[0];
+}
+
+// ------------------------------------------------------------ dispatch
+
+// Calls f(std::integral_constant<int, R>) for the runtime radius r.
+constexpr int kMaxR = 10;
+template <int R = 0, typename F>
+hipError_t with_radius(int r, F&& f) {
+  if constexpr (R > kMaxR) {
+    return hipErrorInvalidValue;
+  } else {
+    if (r == R) return f(std::integral_constant<int, R>{});
+    return with_radius<R + 1>(r, f);
+  }
+}
+
+template <typename T>
+hipError_t launch_coef(const Plan& p, const void* I_lo, const void* p_lo, const float* eps,
+                       int eps_count, float* abar, float* bbar, hipStream_t s) {
+  CoefArgs a{I_lo, p_lo, eps, eps_count, p.c, p.h, p.w, p.coTR, abar, bbar};
+  const dim3 grid(p.co_nx, p.co_ny, p.planes);
+  prof_begin("gf_coef", s);
+  hipError_t err = with_radius(p.r, [&](auto rc) {
+    constexpr int R = decltype(rc)::value;
+    if (p.mean_ab)
+      hipLaunchKernelGGL((coef_kernel<T, R, true>), grid, dim3(64), p.coLDS, s, a);
+    else
+      hipLaunchKernelGGL((coef_kernel<T, R, false>), grid, dim3(64), p.coLDS, s, a);
+    return hipGetLastError();
+  });
+  prof_end(s);
+  return err;
+}
+
+template <typename T, int S, int VEC>
+hipError_t launch_apply_t(const Plan& p, const FwdArgs& f, hipStream_t s) {
+  ApplyArgs a{f.I_hi, f.q, reinterpret_cast<const float*>(f.ws + p.off_abar),
+              reinterpret_cast<const float*>(f.ws + p.off_bbar), p.h, p.w, p.H, p.W, p.RB,
+              p.nrb, p.nxv, (long long)p.planes * p.nrb * p.nxv};
+  const unsigned blocks = (unsigned)((a.total + 255) / 256);
+  prof_begin("gf_apply", s);
+  hipLaunchKernelGGL((apply_kernel<T, S, VEC>), dim3(blocks), dim3(256), 0, s, a);
+  prof_end(s);
+  return hipGetLastError();
+}
+
+template <typename T, int S, int VEC>
+hipError_t launch_bwd_hi_t(const Plan& p, const BwdArgs& b, hipStream_t s) {
+  BwdHiArgs a{b.I_hi, b.dq, b.dI_hi, reinterpret_cast<const float*>(b.ws + p.off_abar),
+              reinterpret_cast<float*>(b.ws + p.off_u), p.h, p.w, p.H, p.W, p.bh, p.tw, p.nby,
+              p.nbx};
+  prof_begin("gf_bwd_hi", s);
+  hipLaunchKernelGGL((bwd_hi_kernel<T, S, VEC>), dim3(p.nbx, p.nby, p.planes), dim3(64), 0, s,
+                     a);
+  prof_end(s);
+  return hipGetLastError();
+}
+
+template <typename T, int VEC>
+hipError_t apply_by_s(const Plan& p, const FwdArgs& f, hipStream_t s) {
+  switch (p.S) {
+    case 1: return launch_apply_t<T, 1, VEC>(p, f, s);
+    case 2: return launch_apply_t<T, 2, VEC>(p, f, s);
+    case 4: return launch_apply_t<T, 4, VEC>(p, f, s);
+    case 8: return launch_apply_t<T, 8, VEC>(p, f, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T, int VEC>
+hipError_t bwd_hi_by_s(const Plan& p, const BwdArgs& b, hipStream_t s) {
+  switch (p.S) {
+    case 1: return launch_bwd_hi_t<T, 1, VEC>(p, b, s);
+    case 2: return launch_bwd_hi_t<T, 2, VEC>(p, b, s);
+    case 4: return launch_bwd_hi_t<T, 4, VEC>(p, b, s);
+    case 8: return launch_bwd_hi_t<T, 8, VEC>(p, b, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t forward_t(const Plan& p, const FwdArgs& f, hipStream_t s) {
+  float* abar = reinterpret_cast<float*>(f.ws + p.off_abar);
+  float* bbar = reinterpret_cast<float*>(f.ws + p.off_bbar);
+  hipError_t err = launch_coef<T>(p, f.I_lo, f.p_lo, f.eps, f.eps_count, abar, bbar, s);
+  if (err != hipSuccess) return err;
+  constexpr int V = 16 / sizeof(T);
+  return p.VEC == V ? apply_by_s<T, V>(p, f, s) : apply_by_s<T, 1>(p, f, s);
+}
+
+template <typename T>
+hipError_t backward_t(const Plan& p, const BwdArgs& b, hipStream_t s) {
+  float* abar = reinterpret_cast<float*>(b.ws + p.off_abar);
+  hipError_t err = launch_coef<T>(p, b.I_lo, b.p_lo, b.eps, b.eps_count, abar, nullptr, s);
+  if (err != hipSuccess) return err;
+  constexpr int V = 16 / sizeof(T);
+  err = p.VEC == V ? bwd_hi_by_s<T, V>(p, b, s) : bwd_hi_by_s<T, 1>(p, b, s);
+  if (err != hipSuccess) return err;
+  if (!b.dI_lo && !b.dp_lo && !b.deps) return hipSuccess;
+  float* part = reinterpret_cast<float*>(b.ws + p.off_eps);
+  BwdLoArgs a{b.I_lo, b.p_lo, b.eps, b.eps_count, p.c,
+              reinterpret_cast<const float*>(b.ws + p.off_u), p.bh, p.tw, p.nby, p.nbx,
+              p.h, p.w, p.loTR, b.dI_lo, b.dp_lo, part};
+  const dim3 grid(p.lo_nx, p.lo_ny, p.planes);
+  prof_begin("gf_bwd_lo", s);
+  err = with_radius(p.r, [&](auto rc) {
+    constexpr int R = decltype(rc)::value;
+    if (p.mean_ab)
+      hipLaunchKernelGGL((bwd_lo_kernel<T, R, true>), grid, dim3(64), p.loLDS, s, a);
+    else
+      hipLaunchKernelGGL((bwd_lo_kernel<T, R, false>), grid, dim3(64), p.loLDS, s, a);
+    return hipGetLastError();
+  });
+  prof_end(s);
+  err = hipGetLastError();
+  if (err != hipSuccess || !b.deps) return err;
+  prof_begin("gf_eps_reduce", s);
+  hipLaunchKernelGGL(eps_reduce_kernel, dim3(b.eps_count), dim3(256), 0, s, part,
+                     p.lo_nx * p.lo_ny, p.c, p.n, b.eps_count, b.deps);
+  prof_end(s);
+  return hipGetLastError();
+}
+
+}  // namespace
+}  // namespace gf

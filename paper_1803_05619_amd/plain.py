@@ -1,0 +1,32 @@
+"""Plain, unfused PyTorch composition of the guided filtering layer.
+
+The layer as a graph of framework operators, the way the paper describes it
+(Sec. III-C: a box filter, the local linear model's elementwise operators,
+bilinear upsampling and a final linear layer), differentiated by autograd.
+It is the "plain" baseline the fused HIP path is timed against; it computes
+in float32 (half-precision inputs are up-converted inside the call).
+"""
+import torch
+import torch.nn.functional as F
+
+
+def _box(x, r):
+    return F.avg_pool2d(x, 2 * r + 1, stride=1, padding=r, count_include_pad=False)
+
+
+def guided_filter(I_lo, p_lo, I_hi, r, eps, mean_ab=True):
+    I_lo, p_lo, I_hi = I_lo.float(), p_lo.float(), I_hi.float()
+    if isinstance(eps, torch.Tensor) and eps.numel() > 1:
+        eps = eps.view(-1, 1, 1, 1)
+    mI = _box(I_lo, r)
+    mP = _box(p_lo, r)
+    var = _box(I_lo * I_lo, r) - mI * mI
+    cov = _box(I_lo * p_lo, r) - mI * mP
+    A = cov / (var + eps)
+    b = mP - A * mI
+    if mean_ab:
+        A, b = _box(A, r), _box(b, r)
+    size = I_hi.shape[-2:]
+    A_h = F.interpolate(A, size=size, mode="bilinear", align_corners=False)
+    b_h = F.interpolate(b, size=size, mode="bilinear", align_corners=False)
+    return A_h * I_hi + b_h
