@@ -6,6 +6,8 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <stdlib.h>
+
 #include <mutex>
 #include <string>
 #include <vector>
@@ -36,7 +38,11 @@ int dtype_size(int t) {
 // Largest radius the column-walker kernels take: a wave of 64 lanes covers
 // the output columns plus a halo of 2r on each side.
 constexpr int kMaxRadius = 10;
-constexpr int kPrefetchRows = 4;  // rows per block of the walkers (kPF)
+
+int env_int(const char* name, int dflt) {
+  const char* v = getenv(name);
+  return v ? atoi(v) : dflt;
+}
 
 }  // namespace
 
@@ -76,28 +82,43 @@ int make_plan(const gf_desc_t* d, Plan* p, const char** why) {
   q.dtype = d->io_dtype;
   q.S = S;
   q.planes = d->n * d->c;
-  const int V = 16 / dtype_size(d->io_dtype);
+  // elements per lane-load on the high-res side: 16 bytes, at least S (a
+  // lane then covers whole low-res columns), 1 when W is not a multiple
+  int V = 16 / dtype_size(d->io_dtype);
+  if (V < S) V = S;
   q.VEC = (q.W % V == 0) ? V : 1;
 
   const int r = q.r;
   if (r > kMaxRadius) return bad(GF_ERR_UNSUPPORTED, "radius above 10 is not supported");
   const int hal = q.mean_ab ? 2 * r : r;  // halo of the coefficient walker
-  const size_t KR = 2 * r + kPrefetchRows;  // ring rows of the walkers
+  const size_t KRc = walker_ring_rows(r, kWalkBlock, kCoefRingPow2Max);
+  const size_t KRb = walker_ring_rows(r, kWalkBlock, kBwdLoRingPow2Max);
   // rows per wave: long enough to amortise the 2*halo warm-up rows
   q.coTR = r <= 2 ? 32 : 64;
+  if (env_int("GF_LO_ROWS", 0) > 0) q.coTR = env_int("GF_LO_ROWS", 0);
   q.co_nx = (q.w + (64 - 2 * hal) - 1) / (64 - 2 * hal);
   q.co_ny = (q.h + q.coTR - 1) / q.coTR;
-  q.coLDS = 64 * (16 * KR + 24 * kPrefetchRows);  // (g,p), (A,b) rings + row buffers
+  q.coLDS = 64 * (16 * KRc + 24 * kWalkBlock);  // (g,p), (A,b) rings + row buffers
   q.loTR = q.coTR;
   q.lo_nx = (q.w + (64 - 4 * r) - 1) / (64 - 4 * r);
   q.lo_ny = (q.h + q.loTR - 1) / q.loTR;
-  q.loLDS = 64 * (32 * KR + 40 * kPrefetchRows);  // input and X rings + row buffers
+  q.loLDS = 64 * (32 * KRb + 40 * kWalkBlock);  // input and X rings + row buffers
 
-  q.RB = S * (S >= 32 ? 1 : 32 / S);
+  // Launch-shape overrides (tuning experiments): GF_APPLY_ROWS = high-res rows
+  // per apply thread, GF_BWD_BH = low-res rows per backward high-res block.
+  const int rows_env = env_int("GF_APPLY_ROWS", 0), bh_env = env_int("GF_BWD_BH", 0);
+  // Short walks keep DRAM streams sequential (8 rows per thread measured
+  // best on MI355X for the 4 x 3 x 2048 x 3072 workload): two low-res row
+  // blocks at S = 4, one at S = 8.
+  q.RB = S >= 8 ? S : 8;
+  if (rows_env > 0) q.RB = ((rows_env + S - 1) / S) * S;
   q.nrb = (q.H + q.RB - 1) / q.RB;
   q.nxv = q.W / q.VEC;
 
-  q.bh = S >= 32 ? 2 : (64 / S < 2 ? 2 : 64 / S);
+  // Backward high-res blocks of 2 low-res rows (2 S high-res rows): short
+  // walks stream best; the partial planes' extra border rows cost less.
+  q.bh = 2;
+  if (bh_env >= 2) q.bh = bh_env;
   q.tw = 64 * q.VEC / S;
   q.nby = (q.h + q.bh - 1) / q.bh;
   q.nbx = (q.W + 64 * q.VEC - 1) / (64 * q.VEC);

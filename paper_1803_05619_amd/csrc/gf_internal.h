@@ -33,6 +33,19 @@ struct Plan {
   size_t off_abar, off_bbar, off_u, off_eps, ws_fwd, ws_bwd;
 };
 
+// Rows of the low-res walkers' LDS ring buffers for radius R: a block writes
+// `block` rows before reading 2R + 1, so at least 2R + block rows; rounded
+// up to a power of two (index by mask) when the LDS footprint stays within
+// 64 KB, i.e. up to `pow2_max` rows.
+constexpr int walker_ring_rows(int R, int block, int pow2_max) {
+  int need = 2 * R + block, p2 = 1;
+  while (p2 < need) p2 <<= 1;
+  return p2 <= pow2_max ? p2 : need;
+}
+constexpr int kWalkBlock = 4;        // rows per block of the low-res walkers
+constexpr int kCoefRingPow2Max = 32;  // coef: 64 * (16 KR + 24 * 4) bytes
+constexpr int kBwdLoRingPow2Max = 16;  // bwd_lo: 64 * (32 KR + 40 * 4) bytes
+
 // Returns GF_OK and fills `p`, or an error code with a message in `why`.
 int make_plan(const gf_desc_t* d, Plan* p, const char** why);
 

@@ -65,6 +65,12 @@ typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
 template <int BYTES>
 struct Carrier;
+typedef uint32_t u32x8 __attribute__((ext_vector_type(8)));
+
+template <>
+struct Carrier<32> {
+  typedef u32x8 type;
+};
 template <>
 struct Carrier<16> {
   typedef u32x4 type;
@@ -169,7 +175,7 @@ __device__ __forceinline__ Tap tap(int y, int S, int n) {
 //     var = sum cvv / N + avg (cm_g - mean_g)^2,
 //     cov = sum cvp / N + avg (cm_g - mean_g)(cm_p - mean_p).
 
-constexpr int kPF = 4;  // rows per block (and rows fetched ahead)
+constexpr int kPF = kWalkBlock;  // rows per block (and rows fetched ahead)
 
 struct WinStats {
   float mI, mP, var, cov;
@@ -188,7 +194,7 @@ __device__ __forceinline__ float4 column_stats(const float2* ring, int rc, int x
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const int t = rc - R + k;
-    v[k] = ring[((t - x0) % KR) * 64 + lane];
+    v[k] = ring[(int)((unsigned)(t - x0) % (unsigned)KR) * 64 + lane];
     nrow += row_ok(t, h) ? 1 : 0;
   }
   float s0 = 0.f, s1 = 0.f;
@@ -266,7 +272,7 @@ __global__ __launch_bounds__(64) void coef_kernel(CoefArgs a) {
   constexpr int HB = MAB ? R : 0;
   constexpr int HAL = R + HB;
   constexpr int TWo = 64 - 2 * HAL;
-  constexpr int KR = 2 * R + kPF;  // ring rows: a block writes kPF rows before reading
+  constexpr int KR = walker_ring_rows(R, kPF, kCoefRingPow2Max);
   extern __shared__ float4 lds4[];
   float2* gp = reinterpret_cast<float2*>(lds4);  // [KR][64] recentred (g, p)
   float4* cs = reinterpret_cast<float4*>(gp + KR * 64);  // [kPF][64] column statistics
@@ -300,19 +306,21 @@ __global__ __launch_bounds__(64) void coef_kernel(CoefArgs a) {
   const bool a_lane = colin && lane >= R && lane < 64 - R;  // lanes that form (A, b)
   const bool out_lane = colin && lane >= HAL && lane < HAL + TWo;
   const int x0 = i0 - HAL, xend = i1 + HAL;  // input rows walked
-  auto ring = [&](int x) { return ((x - x0) % KR) * 64 + lane; };
+  auto ring = [&](int x) __attribute__((always_inline)) {
+    return (int)((unsigned)(x - x0) % (unsigned)KR) * 64 + lane;
+  };
 
   // Loads are unconditional (clamped address) and the queue holds the raw
   // values: a load inside a divergent branch, or arithmetic right after it,
   // would make the wave wait for it there instead of a block later.
   const int jcl = min(max(j, 0), w - 1);
-  auto load = [&](int x, T& g, T& p) {
+  auto load = [&](int x, T& g, T& p) __attribute__((always_inline)) {
     const size_t o = (size_t)min(max(x, 0), h - 1) * w + jcl;
     g = G[o];
     p = P[o];
   };
 
-  auto block = [&](int xb, const T (&gq)[kPF], const T (&pq)[kPF]) {
+  auto block = [&](int xb, const T (&gq)[kPF], const T (&pq)[kPF]) __attribute__((always_inline)) {
 #pragma unroll
     for (int d = 0; d < kPF; ++d) {
       const int x = xb + d;
@@ -436,7 +444,10 @@ __device__ __forceinline__ void hrow(const float* L, int i, int h, int w, const 
 // One thread = VEC adjacent high-res columns x RB rows of one plane.  Rows
 // are walked one low-res row block (S rows) at a time; the three low-res
 // rows a block touches (i-1, i, i+1, clamped) are kept interpolated in
-// registers, so each high-res pixel costs one blend and one FMA.
+// registers, so each high-res pixel costs one blend and one FMA.  Two
+// register buffers alternate: while block i is computed, block i+1 is in
+// flight (its loads are issued after the low-res tap loads of block i, so
+// waiting for those does not wait for it).
 template <typename T, int S, int VEC>
 __global__ __launch_bounds__(256) void apply_kernel(ApplyArgs a) {
   const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
@@ -468,15 +479,18 @@ __global__ __launch_bounds__(256) void apply_kernel(ApplyArgs a) {
   hrow<VEC>(Bb, ib0 - 1, h, w, j0, j1, wx, bm);
   hrow<VEC>(Ab, ib0, h, w, j0, j1, wx, ac);
   hrow<VEC>(Bb, ib0, h, w, j0, j1, wx, bc);
-  for (int i = ib0; i < ib1; ++i) {
-    float g[S][VEC];
+
+  auto load_block = [&](int i, float (&g)[S][VEC]) __attribute__((always_inline)) {
 #pragma unroll
-    for (int t = 0; t < S; ++t) load_vec<T, VEC>(Gp + (size_t)(S * i + t) * W, g[t]);
+    for (int t2 = 0; t2 < S; ++t2) load_vec<T, VEC>(Gp + (size_t)(S * i + t2) * W, g[t2]);
+  };
+  auto body = [&](int i, float (&g)[S][VEC], float (&gn)[S][VEC]) __attribute__((always_inline)) {
     hrow<VEC>(Ab, i + 1, h, w, j0, j1, wx, ap);
     hrow<VEC>(Bb, i + 1, h, w, j0, j1, wx, bp);
+    if (i + 1 < ib1) load_block(i + 1, gn);
 #pragma unroll
-    for (int t = 0; t < S; ++t) {
-      const int num = 2 * t + 1 - S;
+    for (int t2 = 0; t2 < S; ++t2) {
+      const int num = 2 * t2 + 1 - S;
       float q[VEC];
       if (num < 0) {
         const float wy = (float)(num + 2 * S) / (float)(2 * S);
@@ -484,7 +498,7 @@ __global__ __launch_bounds__(256) void apply_kernel(ApplyArgs a) {
         for (int e = 0; e < VEC; ++e) {
           const float A = am[e] + wy * (ac[e] - am[e]);
           const float B = bm[e] + wy * (bc[e] - bm[e]);
-          q[e] = A * g[t][e] + B;
+          q[e] = A * g[t2][e] + B;
         }
       } else {
         const float wy = (float)num / (float)(2 * S);
@@ -492,10 +506,10 @@ __global__ __launch_bounds__(256) void apply_kernel(ApplyArgs a) {
         for (int e = 0; e < VEC; ++e) {
           const float A = ac[e] + wy * (ap[e] - ac[e]);
           const float B = bc[e] + wy * (bp[e] - bc[e]);
-          q[e] = A * g[t][e] + B;
+          q[e] = A * g[t2][e] + B;
         }
       }
-      store_vec_nt<T, VEC>(Qp + (size_t)(S * i + t) * W, q);
+      store_vec_nt<T, VEC>(Qp + (size_t)(S * i + t2) * W, q);
     }
 #pragma unroll
     for (int e = 0; e < VEC; ++e) {
@@ -504,6 +518,12 @@ __global__ __launch_bounds__(256) void apply_kernel(ApplyArgs a) {
       bm[e] = bc[e];
       bc[e] = bp[e];
     }
+  };
+  float ga[S][VEC], gb[S][VEC];
+  load_block(ib0, ga);
+  for (int i = ib0; i < ib1; i += 2) {
+    body(i, ga, gb);
+    if (i + 1 < ib1) body(i + 1, gb, ga);
   }
 }
 
@@ -524,10 +544,21 @@ struct BwdHiArgs {
 // j_a-1 .. j_a+tw: a (bh+2) x (tw+2) partial plane for dA_bar (from dq*G_h)
 // and one for db_bar (from dq).  The border rows/columns overlap the
 // neighbouring blocks' and are summed by the low-res kernel.
+//
+// Vertical: per high-res row, each lane adds its VEC values, weighted, into
+// accumulators of the low-res rows i-1, i, i+1 of the current row block;
+// after the block, row i-1 is complete and is flushed horizontally.
+// Horizontal: when the lane's VEC columns are whole low-res blocks
+// (VEC % S == 0) the weights are compile-time constants and the two
+// contributions that cross into the neighbouring lanes' columns move with
+// one lane shuffle each; otherwise (VEC = 1 fallback) through LDS.
+// Loads of row block i+1 are issued before block i is computed.
 template <typename T, int S, int VEC>
 __global__ __launch_bounds__(64) void bwd_hi_kernel(BwdHiArgs a) {
   constexpr int TWH = 64 * VEC;  // high-res columns per block
-  __shared__ float sR[2][TWH];
+  constexpr bool REG = (VEC % S) == 0;
+  constexpr int NB = REG ? VEC / S : 1;  // low-res columns per lane
+  __shared__ float sR[REG ? 1 : 2][REG ? 1 : TWH];
   const int lane = threadIdx.x;
   const int bx = blockIdx.x, by = blockIdx.y, plane = blockIdx.z;
   const int h = a.h, w = a.w, W = a.W, bh = a.bh, tw = a.tw;
@@ -554,31 +585,112 @@ __global__ __launch_bounds__(64) void bwd_hi_kernel(BwdHiArgs a) {
   const int UW = tw + 2;
   const size_t UP = (size_t)(bh + 2) * UW;
   float* Ub = a.U + (((size_t)plane * a.nby + by) * a.nbx + bx) * 2 * UP;
+  // this lane's first low-res column (register path) and the image-edge clamps
+  const int jb = x0 / S;
+  const bool left_edge = (x0 == 0);
+  const bool right_edge = valid && (jb + NB == w);
 
-  auto flush = [&](const float (&uA)[VEC], const float (&uB)[VEC], int lr) {
+  // Horizontal transposed interpolation of one completed low-res row
+  // (vertical sums uA/uB over this lane's VEC columns) into row lr of the
+  // block's partial planes.
+  auto flush = [&](const float (&uA)[VEC], const float (&uB)[VEC], int lr) __attribute__((always_inline)) {
+    if constexpr (REG) {
+      float oA[NB], oB[NB];
 #pragma unroll
-    for (int e = 0; e < VEC; ++e) {
-      sR[0][lane * VEC + e] = uA[e];
-      sR[1][lane * VEC + e] = uB[e];
-    }
-    wave_sync();
-    for (int k = lane; k < UW; k += 64) {
-      const int j = j_a - 1 + k;
-      float sa = 0.f, sb = 0.f;
-      if (j >= 0 && j < w) {
-        const int xlo = max(max(S * (j - 1), X_a), 0);
-        const int xhi = min(min(S * (j + 2), X_a + TWH), W);
-        for (int x = xlo; x < xhi; ++x) {
-          const Tap tx = tap(x, S, w);
-          const float wt = (tx.i0 == j ? 1.f - tx.w : 0.f) + (tx.i1 == j ? tx.w : 0.f);
-          sa += wt * sR[0][x - X_a];
-          sb += wt * sR[1][x - X_a];
+      for (int m = 0; m < NB; ++m) oA[m] = oB[m] = 0.f;
+      float lA = 0.f, lB = 0.f, rA = 0.f, rB = 0.f;  // spills to jb-1 and jb+NB
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) {
+        const int m = e / S, t2 = e % S;
+        const int num = 2 * t2 + 1 - S;
+        if (num < 0) {  // taps (jb+m-1, jb+m)
+          const float w1 = (float)(num + 2 * S) / (float)(2 * S);
+          const float cA = (1.f - w1) * uA[e], cB = (1.f - w1) * uB[e];
+          oA[m] += w1 * uA[e];
+          oB[m] += w1 * uB[e];
+          if (m == 0) {
+            if (left_edge) {  // source clamped to column 0: all weight there
+              oA[0] += cA;
+              oB[0] += cB;
+            } else {
+              lA += cA;
+              lB += cB;
+            }
+          } else {
+            oA[m - 1] += cA;
+            oB[m - 1] += cB;
+          }
+        } else {  // taps (jb+m, jb+m+1)
+          const float w1 = (float)num / (float)(2 * S);
+          const float cA = w1 * uA[e], cB = w1 * uB[e];
+          oA[m] += (1.f - w1) * uA[e];
+          oB[m] += (1.f - w1) * uB[e];
+          if (m == NB - 1) {
+            if (right_edge) {  // second tap clamped to the last column
+              oA[m] += cA;
+              oB[m] += cB;
+            } else {
+              rA += cA;
+              rB += cB;
+            }
+          } else {
+            oA[m + 1] += cA;
+            oB[m + 1] += cB;
+          }
         }
       }
-      Ub[(size_t)lr * UW + k] = sa;
-      Ub[UP + (size_t)lr * UW + k] = sb;
+      // lane l's right spill is column jb of lane l+1; its left spill is the
+      // last column of lane l-1
+      const float inA = __shfl_up(rA, 1), inB = __shfl_up(rB, 1);
+      const float fromA = __shfl_down(lA, 1), fromB = __shfl_down(lB, 1);
+      if (lane > 0) {
+        oA[0] += inA;
+        oB[0] += inB;
+      }
+      if (lane < 63) {
+        oA[NB - 1] += fromA;
+        oB[NB - 1] += fromB;
+      }
+      float* rowA = Ub + (size_t)lr * UW;
+      float* rowB = Ub + UP + (size_t)lr * UW;
+#pragma unroll
+      for (int m = 0; m < NB; ++m) {
+        rowA[1 + lane * NB + m] = oA[m];
+        rowB[1 + lane * NB + m] = oB[m];
+      }
+      if (lane == 0) {
+        rowA[0] = lA;
+        rowB[0] = lB;
+      }
+      if (lane == 63) {
+        rowA[UW - 1] = rA;
+        rowB[UW - 1] = rB;
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) {
+        sR[0][lane * VEC + e] = uA[e];
+        sR[1][lane * VEC + e] = uB[e];
+      }
+      wave_sync();
+      for (int k = lane; k < UW; k += 64) {
+        const int j = j_a - 1 + k;
+        float sa = 0.f, sb = 0.f;
+        if (j >= 0 && j < w) {
+          const int xlo = max(max(S * (j - 1), X_a), 0);
+          const int xhi = min(min(S * (j + 2), X_a + TWH), W);
+          for (int x = xlo; x < xhi; ++x) {
+            const Tap tx = tap(x, S, w);
+            const float wt = (tx.i0 == j ? 1.f - tx.w : 0.f) + (tx.i1 == j ? tx.w : 0.f);
+            sa += wt * sR[0][x - X_a];
+            sb += wt * sR[1][x - X_a];
+          }
+        }
+        Ub[(size_t)lr * UW + k] = sa;
+        Ub[UP + (size_t)lr * UW + k] = sb;
+      }
+      wave_sync();
     }
-    wave_sync();
   };
 
   float am[VEC], ac[VEC], ap[VEC];
@@ -587,61 +699,56 @@ __global__ __launch_bounds__(64) void bwd_hi_kernel(BwdHiArgs a) {
   for (int e = 0; e < VEC; ++e) pA[e] = cA[e] = nA[e] = pB[e] = cB[e] = nB[e] = 0.f;
   hrow<VEC>(Ab, i_a - 1, h, w, j0, j1, wx, am);
   hrow<VEC>(Ab, i_a, h, w, j0, j1, wx, ac);
-  for (int i = i_a; i < i_b; ++i) {
-    float g[S][VEC], d[S][VEC];
-    // unconditional loads (lanes past the image edge re-read column 0 and
-    // are zeroed), so that no load sits in a divergent branch
+
+  // unconditional loads (lanes past the image edge re-read column 0 and
+  // are zeroed), so that no load sits in a divergent branch
+  auto load_block = [&](int i, float (&d)[S][VEC], float (&g)[S][VEC]) __attribute__((always_inline)) {
 #pragma unroll
-    for (int t = 0; t < S; ++t) {
-      load_vec<T, VEC>(Dp + (size_t)(S * i + t) * W, d[t]);
-      load_vec<T, VEC>(Gp + (size_t)(S * i + t) * W, g[t]);
+    for (int t2 = 0; t2 < S; ++t2) {
+      load_vec<T, VEC>(Dp + (size_t)(S * i + t2) * W, d[t2]);
+      load_vec<T, VEC>(Gp + (size_t)(S * i + t2) * W, g[t2]);
     }
-    if (!valid) {
-#pragma unroll
-      for (int t = 0; t < S; ++t)
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) d[t][e] = 0.f;
-    }
+  };
+  auto body = [&](int i, float (&d)[S][VEC], float (&g)[S][VEC], float (&dn)[S][VEC],
+                  float (&gn)[S][VEC]) __attribute__((always_inline)) {
     hrow<VEC>(Ab, i + 1, h, w, j0, j1, wx, ap);
+    if (i + 1 < i_b) load_block(i + 1, dn, gn);
     const bool top = (i == 0), bot = (i == h - 1);
 #pragma unroll
-    for (int t = 0; t < S; ++t) {
-      const int num = 2 * t + 1 - S;
+    for (int t2 = 0; t2 < S; ++t2) {
+      const int num = 2 * t2 + 1 - S;
       float o[VEC];
+      // weights of this row on the low-res rows i-1, i, i+1; at the image's
+      // first/last row block the source row is clamped and all weight goes
+      // to row i (selected as weights, not as branches over accumulators)
       if (num < 0) {
         const float wy = (float)(num + 2 * S) / (float)(2 * S);
+        const float wp = top ? 0.f : 1.f - wy, wc = top ? 1.f : wy;
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
-          o[e] = d[t][e] * (am[e] + wy * (ac[e] - am[e]));
-          const float vA = d[t][e] * g[t][e], vB = d[t][e];
-          if (top) {
-            cA[e] += vA;
-            cB[e] += vB;
-          } else {
-            pA[e] += (1.f - wy) * vA;
-            cA[e] += wy * vA;
-            pB[e] += (1.f - wy) * vB;
-            cB[e] += wy * vB;
-          }
+          const float dv = valid ? d[t2][e] : 0.f;
+          o[e] = dv * (am[e] + wy * (ac[e] - am[e]));
+          const float vA = dv * g[t2][e], vB = dv;
+          pA[e] += wp * vA;
+          cA[e] += wc * vA;
+          pB[e] += wp * vB;
+          cB[e] += wc * vB;
         }
       } else {
         const float wy = (float)num / (float)(2 * S);
+        const float wc = bot ? 1.f : 1.f - wy, wn = bot ? 0.f : wy;
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
-          o[e] = d[t][e] * (ac[e] + wy * (ap[e] - ac[e]));
-          const float vA = d[t][e] * g[t][e], vB = d[t][e];
-          if (bot) {
-            cA[e] += vA;
-            cB[e] += vB;
-          } else {
-            cA[e] += (1.f - wy) * vA;
-            nA[e] += wy * vA;
-            cB[e] += (1.f - wy) * vB;
-            nB[e] += wy * vB;
-          }
+          const float dv = valid ? d[t2][e] : 0.f;
+          o[e] = dv * (ac[e] + wy * (ap[e] - ac[e]));
+          const float vA = dv * g[t2][e], vB = dv;
+          cA[e] += wc * vA;
+          nA[e] += wn * vA;
+          cB[e] += wc * vB;
+          nB[e] += wn * vB;
         }
       }
-      if (Op && valid) store_vec_nt<T, VEC>(Op + (size_t)(S * i + t) * W, o);
+      if (Op && valid) store_vec_nt<T, VEC>(Op + (size_t)(S * i + t2) * W, o);
     }
     flush(pA, pB, i - i_a);  // low-res row i-1 is complete
 #pragma unroll
@@ -655,6 +762,12 @@ __global__ __launch_bounds__(64) void bwd_hi_kernel(BwdHiArgs a) {
       am[e] = ac[e];
       ac[e] = ap[e];
     }
+  };
+  float da[S][VEC], ga[S][VEC], db[S][VEC], gb[S][VEC];
+  load_block(i_a, da, ga);
+  for (int i = i_a; i < i_b; i += 2) {
+    body(i, da, ga, db, gb);
+    if (i + 1 < i_b) body(i + 1, db, gb, da, ga);
   }
   flush(pA, pB, i_b - i_a);      // row i_b - 1
   flush(cA, cB, i_b - i_a + 1);  // row i_b (contributions of the last rows)
@@ -684,23 +797,23 @@ struct URaw {
   float a00, a01, a10, a11, v00, v01, v10, v11;
 };
 
-__device__ __forceinline__ void u_weights(const BwdLoArgs& a, int i, int j, int& b0, int& b1,
-                                          int& c0, int& c1, float& wb, float& wc) {
-  const int bh = a.bh, tw = a.tw;
-  b0 = i / bh;
-  c0 = j / tw;
-  const int ri = i - b0 * bh, rj = j - c0 * tw;
-  b1 = b0;
-  c1 = c0;
-  wb = 0.f;
-  wc = 0.f;
-  if (ri == 0 && b0 > 0) {
-    b1 = b0 - 1;
-    wb = 1.f;
-  } else if (ri == bh - 1 && b0 + 1 < a.nby) {
-    b1 = b0 + 1;
-    wb = 1.f;
-  }
+// Per-lane (column) part of the partial-plane addressing: block column c0
+// that owns column j and, on a block border, its neighbour c1 (weight wc).
+struct UCol {
+  int o0, o1;  // offsets of (block column, column within block) for c0, c1
+  float wc;
+};
+// Per-row part: block row b0 owning row i and neighbour b1 (weight wb).
+struct URow {
+  int o0, o1;  // offsets of (block row, row within block) for b0, b1
+  float wb;
+};
+
+__device__ __forceinline__ UCol u_col(const BwdLoArgs& a, int j) {
+  const int tw = a.tw, UP2 = 2 * (a.bh + 2) * (tw + 2);
+  const int c0 = j / tw, rj = j - c0 * tw;
+  int c1 = c0;
+  float wc = 0.f;
   if (rj == 0 && c0 > 0) {
     c1 = c0 - 1;
     wc = 1.f;
@@ -708,23 +821,33 @@ __device__ __forceinline__ void u_weights(const BwdLoArgs& a, int i, int j, int&
     c1 = c0 + 1;
     wc = 1.f;
   }
+  return UCol{c0 * UP2 + (j - (c0 * tw - 1)), c1 * UP2 + (j - (c1 * tw - 1)), wc};
 }
 
-__device__ __forceinline__ URaw gather_u_raw(const BwdLoArgs& a, int plane, int i, int j) {
-  const int bh = a.bh, tw = a.tw, UW = tw + 2;
-  const size_t UP = (size_t)(bh + 2) * UW;
-  int b0, b1, c0, c1;
-  float wb, wc;
-  u_weights(a, i, j, b0, b1, c0, c1, wb, wc);
-  const float* base = a.U + (size_t)plane * a.nby * a.nbx * 2 * UP;
-  auto at = [&](int by, int bx) {
-    return base + ((size_t)by * a.nbx + bx) * 2 * UP + (size_t)(i - (by * bh - 1)) * UW +
-           (j - (bx * tw - 1));
-  };
-  const float* p00 = at(b0, c0);
-  const float* p01 = at(b0, c1);
-  const float* p10 = at(b1, c0);
-  const float* p11 = at(b1, c1);
+__device__ __forceinline__ URow u_row(const BwdLoArgs& a, int i) {
+  const int bh = a.bh, UW = a.tw + 2, UP2 = 2 * (bh + 2) * UW;
+  const int b0 = i / bh, ri = i - b0 * bh;
+  int b1 = b0;
+  float wb = 0.f;
+  if (ri == 0 && b0 > 0) {
+    b1 = b0 - 1;
+    wb = 1.f;
+  } else if (ri == bh - 1 && b0 + 1 < a.nby) {
+    b1 = b0 + 1;
+    wb = 1.f;
+  }
+  return URow{b0 * a.nbx * UP2 + (i - (b0 * bh - 1)) * UW,
+              b1 * a.nbx * UP2 + (i - (b1 * bh - 1)) * UW, wb};
+}
+
+// The four partial-plane reads per plane (absent neighbours re-read the
+// owner, with weight 0, so that no load sits in a divergent branch).
+__device__ __forceinline__ URaw gather_u_raw(const float* base, size_t UP, const URow& ro,
+                                             const UCol& co) {
+  const float* p00 = base + ro.o0 + co.o0;
+  const float* p01 = base + ro.o0 + co.o1;
+  const float* p10 = base + ro.o1 + co.o0;
+  const float* p11 = base + ro.o1 + co.o1;
   return URaw{p00[0], p01[0], p10[0], p11[0], p00[UP], p01[UP], p10[UP], p11[UP]};
 }
 
@@ -739,7 +862,7 @@ template <typename T, int R, bool MAB>
 __global__ __launch_bounds__(64) void bwd_lo_kernel(BwdLoArgs a) {
   constexpr int K = 2 * R + 1;
   constexpr int TWo = 64 - 4 * R;
-  constexpr int KR = 2 * R + kPF;  // ring rows: a block writes kPF rows before reading
+  constexpr int KR = walker_ring_rows(R, kPF, kBwdLoRingPow2Max);
   extern __shared__ float4 lds4[];
   float4* in = lds4;              // [KR][64] (g', p', dAbar, dbbar)
   float4* cs = in + KR * 64;      // [kPF][64] column statistics
@@ -772,7 +895,9 @@ __global__ __launch_bounds__(64) void bwd_lo_kernel(BwdLoArgs a) {
   const bool x_lane = colin && lane >= R && lane < 64 - R;  // lanes that form X
   const bool out_col = colin && lane >= 2 * R && lane < 2 * R + TWo;
   const int x0 = i0 - 2 * R, xend = i1 + 2 * R;
-  auto ring = [&](int x) { return ((x - x0) % KR) * 64 + lane; };
+  auto ring = [&](int x) __attribute__((always_inline)) {
+    return (int)((unsigned)(x - x0) % (unsigned)KR) * 64 + lane;
+  };
   float deps_acc = 0.f;
 
   // Loads are unconditional (clamped address) and the queue holds the raw
@@ -783,13 +908,16 @@ __global__ __launch_bounds__(64) void bwd_lo_kernel(BwdLoArgs a) {
     T g, p;
     URaw u;
   };
-  auto load = [&](int x) {
+  const size_t UP = (size_t)(a.bh + 2) * (a.tw + 2);
+  const float* ubase = a.U + (size_t)plane * a.nby * a.nbx * 2 * UP;
+  const UCol ucol = u_col(a, jcl);
+  auto load = [&](int x) __attribute__((always_inline)) {
     const int xc = min(max(x, 0), h - 1);
     const size_t o = (size_t)xc * w + jcl;
-    return Raw{G[o], P[o], gather_u_raw(a, plane, xc, jcl)};
+    return Raw{G[o], P[o], gather_u_raw(ubase, UP, u_row(a, xc), ucol)};
   };
 
-  auto block = [&](int xb, const Raw (&q)[kPF]) {
+  auto block = [&](int xb, const Raw (&q)[kPF]) __attribute__((always_inline)) {
 #pragma unroll
     for (int d = 0; d < kPF; ++d) {
       const int x = xb + d;
@@ -797,9 +925,7 @@ __global__ __launch_bounds__(64) void bwd_lo_kernel(BwdLoArgs a) {
       const bool ok = colin && row_ok(x, h);
       float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
       if (ok) {
-        int b0, b1, c0, c1;
-        float wb, wc;
-        u_weights(a, x, j, b0, b1, c0, c1, wb, wc);
+        const float wb = u_row(a, x).wb, wc = ucol.wc;
         const URaw& z = q[d].u;
         float u = (z.a00 + wc * z.a01) + wb * (z.a10 + wc * z.a11);
         float vv = (z.v00 + wc * z.v01) + wb * (z.v10 + wc * z.v11);
@@ -1021,24 +1147,32 @@ hipError_t launch_bwd_hi_t(const Plan& p, const BwdArgs& b, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <typename T, int VEC>
-hipError_t apply_by_s(const Plan& p, const FwdArgs& f, hipStream_t s) {
+// High-res launch shapes: VEC is 16 bytes of elements, raised to S when S is
+// larger (so that a lane always covers whole low-res columns), or 1 when the
+// width is not a multiple of it.
+template <typename T, int S>
+constexpr int vec_for() {
+  return (int)(16 / sizeof(T)) >= S ? (int)(16 / sizeof(T)) : S;
+}
+
+template <typename T>
+hipError_t apply_dispatch(const Plan& p, const FwdArgs& f, hipStream_t s) {
   switch (p.S) {
-    case 1: return launch_apply_t<T, 1, VEC>(p, f, s);
-    case 2: return launch_apply_t<T, 2, VEC>(p, f, s);
-    case 4: return launch_apply_t<T, 4, VEC>(p, f, s);
-    case 8: return launch_apply_t<T, 8, VEC>(p, f, s);
+    case 1: return p.VEC == 1 ? launch_apply_t<T, 1, 1>(p, f, s) : launch_apply_t<T, 1, vec_for<T, 1>()>(p, f, s);
+    case 2: return p.VEC == 1 ? launch_apply_t<T, 2, 1>(p, f, s) : launch_apply_t<T, 2, vec_for<T, 2>()>(p, f, s);
+    case 4: return p.VEC == 1 ? launch_apply_t<T, 4, 1>(p, f, s) : launch_apply_t<T, 4, vec_for<T, 4>()>(p, f, s);
+    case 8: return p.VEC == 1 ? launch_apply_t<T, 8, 1>(p, f, s) : launch_apply_t<T, 8, vec_for<T, 8>()>(p, f, s);
   }
   return hipErrorInvalidValue;
 }
 
-template <typename T, int VEC>
-hipError_t bwd_hi_by_s(const Plan& p, const BwdArgs& b, hipStream_t s) {
+template <typename T>
+hipError_t bwd_hi_dispatch(const Plan& p, const BwdArgs& b, hipStream_t s) {
   switch (p.S) {
-    case 1: return launch_bwd_hi_t<T, 1, VEC>(p, b, s);
-    case 2: return launch_bwd_hi_t<T, 2, VEC>(p, b, s);
-    case 4: return launch_bwd_hi_t<T, 4, VEC>(p, b, s);
-    case 8: return launch_bwd_hi_t<T, 8, VEC>(p, b, s);
+    case 1: return p.VEC == 1 ? launch_bwd_hi_t<T, 1, 1>(p, b, s) : launch_bwd_hi_t<T, 1, vec_for<T, 1>()>(p, b, s);
+    case 2: return p.VEC == 1 ? launch_bwd_hi_t<T, 2, 1>(p, b, s) : launch_bwd_hi_t<T, 2, vec_for<T, 2>()>(p, b, s);
+    case 4: return p.VEC == 1 ? launch_bwd_hi_t<T, 4, 1>(p, b, s) : launch_bwd_hi_t<T, 4, vec_for<T, 4>()>(p, b, s);
+    case 8: return p.VEC == 1 ? launch_bwd_hi_t<T, 8, 1>(p, b, s) : launch_bwd_hi_t<T, 8, vec_for<T, 8>()>(p, b, s);
   }
   return hipErrorInvalidValue;
 }
@@ -1049,8 +1183,7 @@ hipError_t forward_t(const Plan& p, const FwdArgs& f, hipStream_t s) {
   float* bbar = reinterpret_cast<float*>(f.ws + p.off_bbar);
   hipError_t err = launch_coef<T>(p, f.I_lo, f.p_lo, f.eps, f.eps_count, abar, bbar, s);
   if (err != hipSuccess) return err;
-  constexpr int V = 16 / sizeof(T);
-  return p.VEC == V ? apply_by_s<T, V>(p, f, s) : apply_by_s<T, 1>(p, f, s);
+  return apply_dispatch<T>(p, f, s);
 }
 
 template <typename T>
@@ -1058,8 +1191,7 @@ hipError_t backward_t(const Plan& p, const BwdArgs& b, hipStream_t s) {
   float* abar = reinterpret_cast<float*>(b.ws + p.off_abar);
   hipError_t err = launch_coef<T>(p, b.I_lo, b.p_lo, b.eps, b.eps_count, abar, nullptr, s);
   if (err != hipSuccess) return err;
-  constexpr int V = 16 / sizeof(T);
-  err = p.VEC == V ? bwd_hi_by_s<T, V>(p, b, s) : bwd_hi_by_s<T, 1>(p, b, s);
+  err = bwd_hi_dispatch<T>(p, b, s);
   if (err != hipSuccess) return err;
   if (!b.dI_lo && !b.dp_lo && !b.deps) return hipSuccess;
   float* part = reinterpret_cast<float*>(b.ws + p.off_eps);
