@@ -29,7 +29,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 KERNEL_SRC = os.path.join(ROOT, "paper_1803_05619_amd", "csrc", "gf_kernels.h")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fp32_4x3x2048x3072.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_fp32_4x3x2048x3072.txt")
 
 
 def log(msg):
