@@ -81,6 +81,7 @@ int make_plan(const gf_desc_t* d, Plan* p, const char** why) {
   q.mean_ab = d->mean_ab;
   q.dtype = d->io_dtype;
   q.S = S;
+  q.xcd = env_int("GF_XCD", 0) != 0 ? 1 : 0;  // measured slower on MI355X: off by default
   q.planes = d->n * d->c;
   // elements per lane-load on the high-res side: 16 bytes, at least S (a
   // lane then covers whole low-res columns), 1 when W is not a multiple

@@ -14,6 +14,7 @@ namespace gf {
 struct Plan {
   int n, c, h, w, H, W, r, mean_ab, dtype;
   int S;        // integer upsampling factor (H = S h, W = S w)
+  int xcd;      // XCD-aware workgroup order for the high-res kernels
   int VEC;      // high-res elements per thread-load (16 bytes, or 1)
   int planes;   // n * c
   // low-res coefficient kernel: one wave per strip of 64 lanes (columns)

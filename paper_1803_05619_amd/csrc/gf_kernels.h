@@ -124,6 +124,18 @@ __device__ __forceinline__ void wave_sync() {
 // kernels use it for window counts and variance denominators.
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// XCD-aware workgroup order.  The dispatcher hands consecutive workgroups
+// to the 8 XCDs in turn, each XCD with its own L2; remapping the linear
+// workgroup id so that XCD k runs the contiguous k-th eighth of the work
+// keeps neighbouring row blocks (which share low-res taps) in one L2 and
+// each XCD's DRAM stream sequential.  A bijection on [0, n).
+__device__ __forceinline__ long long xcd_order(long long p, long long n, bool on) {
+  if (!on) return p;
+  const long long q = n / 8;
+  if (p >= 8 * q) return p;
+  return (p % 8) * q + p / 8;
+}
+
 // ------------------------------------------------------------ geometry
 
 // Pixels of the clipped window of radius r around index i on an axis of n.
@@ -424,6 +436,7 @@ struct ApplyArgs {
   const float* bbar;
   int h, w, H, W, RB, nrb, nxv;
   long long total;
+  int xcd;  // 1: XCD-aware workgroup order
 };
 
 // Horizontally interpolated low-res row `i` (clamped) at the VEC columns of
@@ -450,7 +463,7 @@ __device__ __forceinline__ void hrow(const float* L, int i, int h, int w, const 
 // waiting for those does not wait for it).
 template <typename T, int S, int VEC>
 __global__ __launch_bounds__(256) void apply_kernel(ApplyArgs a) {
-  const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+  const long long t = xcd_order(blockIdx.x, gridDim.x, a.xcd) * 256 + threadIdx.x;
   if (t >= a.total) return;
   const int xv = (int)(t % a.nxv);
   const long long rest = t / a.nxv;
@@ -536,6 +549,7 @@ struct BwdHiArgs {
   const float* abar;
   float* U;     // per-block partial planes
   int h, w, H, W, bh, tw, nby, nbx;
+  int xcd;  // 1: XCD-aware workgroup order
 };
 
 // One wave per block of bh low-res rows (S*bh high-res rows) x 64*VEC
@@ -560,7 +574,10 @@ __global__ __launch_bounds__(64) void bwd_hi_kernel(BwdHiArgs a) {
   constexpr int NB = REG ? VEC / S : 1;  // low-res columns per lane
   __shared__ float sR[REG ? 1 : 2][REG ? 1 : TWH];
   const int lane = threadIdx.x;
-  const int bx = blockIdx.x, by = blockIdx.y, plane = blockIdx.z;
+  const long long nwg = (long long)gridDim.x * gridDim.y * gridDim.z;
+  const long long lin = xcd_order(blockIdx.x + (long long)gridDim.x * (blockIdx.y + (long long)gridDim.y * blockIdx.z), nwg, a.xcd);
+  const int bx = (int)(lin % gridDim.x), by = (int)((lin / gridDim.x) % gridDim.y),
+            plane = (int)(lin / ((long long)gridDim.x * gridDim.y));
   const int h = a.h, w = a.w, W = a.W, bh = a.bh, tw = a.tw;
   const int X_a = bx * TWH;
   const int x0 = X_a + lane * VEC;
@@ -1127,7 +1144,7 @@ template <typename T, int S, int VEC>
 hipError_t launch_apply_t(const Plan& p, const FwdArgs& f, hipStream_t s) {
   ApplyArgs a{f.I_hi, f.q, reinterpret_cast<const float*>(f.ws + p.off_abar),
               reinterpret_cast<const float*>(f.ws + p.off_bbar), p.h, p.w, p.H, p.W, p.RB,
-              p.nrb, p.nxv, (long long)p.planes * p.nrb * p.nxv};
+              p.nrb, p.nxv, (long long)p.planes * p.nrb * p.nxv, p.xcd};
   const unsigned blocks = (unsigned)((a.total + 255) / 256);
   prof_begin("gf_apply", s);
   hipLaunchKernelGGL((apply_kernel<T, S, VEC>), dim3(blocks), dim3(256), 0, s, a);
@@ -1139,7 +1156,7 @@ template <typename T, int S, int VEC>
 hipError_t launch_bwd_hi_t(const Plan& p, const BwdArgs& b, hipStream_t s) {
   BwdHiArgs a{b.I_hi, b.dq, b.dI_hi, reinterpret_cast<const float*>(b.ws + p.off_abar),
               reinterpret_cast<float*>(b.ws + p.off_u), p.h, p.w, p.H, p.W, p.bh, p.tw, p.nby,
-              p.nbx};
+              p.nbx, p.xcd};
   prof_begin("gf_bwd_hi", s);
   hipLaunchKernelGGL((bwd_hi_kernel<T, S, VEC>), dim3(p.nbx, p.nby, p.planes), dim3(64), 0, s,
                      a);
