@@ -97,7 +97,7 @@ def main():
             torch.empty_like(t["I_hi"]),
             torch.empty(1, dtype=torch.float32, device=dev))
     desc = gf.make_desc(t["I_lo"], t["I_hi"], r)
-    ws = torch.empty(max(gf.gf_workspace_size(desc, 0), gf.gf_workspace_size(desc, 1)),
+    ws = torch.empty(max(gf.gf_workspace_size(desc, None, 0), gf.gf_workspace_size(desc, None, 1)),
                      dtype=torch.uint8, device=dev)
 
     def step():

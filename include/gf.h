@@ -6,7 +6,9 @@
  * guide I_l, a low-res input p_l (the paper's O_l) and a high-res guide I_h,
  * it returns the high-res output q (the paper's O_h):
  *
- *   G = F(I)                     guidance map (identity here; Sec. III-D)
+ *   G = F(I)                     guidance map (Sec. III-D): the identity, the
+ *                                channel mean (grey guide, Sec. IV-B), or the
+ *                                trainable transform of gf_guide_t
  *   mean_I, mean_p, var, cov     (2r+1)^2 window means over G_l, p_l, the
  *                                window clipped to the image and normalised
  *                                by its in-image pixel count N (box filter
@@ -80,24 +82,73 @@ typedef struct {
   int32_t io_dtype; /* gf_dtype_t of I_lo, p_lo, I_hi, q_hi, dq_hi, dI_hi */
 } gf_desc_t;
 
+/* Guidance map G = F(I) (Sec. III-D).  Pass NULL for the identity.
+ *
+ * GF_GUIDE_GREY: G_k = mean of the c_in input channels, for every output
+ *   channel k (the grey guide used when input and output channel counts
+ *   differ, Sec. IV-B); c_in in 1..4, c in 1..4.
+ * GF_GUIDE_TRANSFORM: the trainable transform of Sec. III-D / Table I,
+ *   per pixel x (c_in channels):
+ *     h = W1 x                      1x1 convolution, hidden channels, no bias
+ *     y = lam h + mu BN(h)          adaptive normalisation; BN with affine
+ *                                   gamma, beta and the batch statistics of
+ *                                   the call (all images and pixels of I_lo,
+ *                                   respectively of I_hi; biased variance)
+ *     z = leaky_relu(y, slope)      derivative `slope` for y <= 0
+ *     G = W2 z + b2                 1x1 convolution with bias
+ *   c_in == c == 3, hidden in 1..16.
+ * With a guide, I_lo is [n, c_in, h_lo, w_lo], I_hi [n, c_in, h_hi, w_hi],
+ * dI_lo [n, c_in, h_lo, w_lo] (float32) and dI_hi [n, c_in, h_hi, w_hi]. */
+typedef enum {
+  GF_GUIDE_IDENTITY = 0,
+  GF_GUIDE_GREY = 1,
+  GF_GUIDE_TRANSFORM = 2
+} gf_guide_mode_t;
+
+typedef struct {
+  int32_t mode;          /* gf_guide_mode_t                                 */
+  int32_t c_in;          /* channels of I_lo / I_hi                         */
+  int32_t hidden;        /* transform: hidden channels                      */
+  float bn_eps;          /* transform: batch-norm epsilon (e.g. 1e-5)       */
+  float slope;           /* transform: leaky-ReLU negative slope (0.2)      */
+  const float *params;   /* transform: DEVICE, gf_guide_param_count floats:
+                            W1 [hidden][c_in] | W2 [c][hidden] | b2 [c] |
+                            lam | mu | gamma [hidden] | beta [hidden]       */
+  float *stats;          /* transform, optional DEVICE buffer of
+                            gf_guide_stats_count floats: the batch mean and
+                            covariance of the I_lo and the I_hi call.
+                            gf_forward writes it (if not NULL);
+                            gf_backward reads it when use_stats != 0,
+                            otherwise recomputes the statistics            */
+  int32_t use_stats;
+} gf_guide_t;
+
+size_t gf_guide_param_count(int32_t c_in, int32_t c, int32_t hidden);
+size_t gf_guide_stats_count(int32_t c_in);
+
 /* Bytes of scratch memory gf_forward (backward = 0) or gf_backward
  * (backward = 1) needs for this problem; 0 for an invalid description. */
-size_t gf_workspace_size(const gf_desc_t *desc, int32_t backward);
+size_t gf_workspace_size(const gf_desc_t *desc, const gf_guide_t *guide,
+                         int32_t backward);
 
 /* Forward pass (Sec. III-B/C, Eq. (1)-(2)): writes q_hi. */
-int32_t gf_forward(const gf_desc_t *desc, const void *I_lo, const void *p_lo,
-                   const void *I_hi, const float *eps, int32_t eps_count,
-                   void *q_hi, void *ws, size_t ws_bytes, void *stream);
+int32_t gf_forward(const gf_desc_t *desc, const gf_guide_t *guide,
+                   const void *I_lo, const void *p_lo, const void *I_hi,
+                   const float *eps, int32_t eps_count, void *q_hi, void *ws,
+                   size_t ws_bytes, void *stream);
 
 /* Backward pass (Algorithm 1): gradients of sum(q * dq_hi).  Each output
  * pointer may be NULL (that gradient is not computed).  The low-res box
  * statistics and coefficients are recomputed from the inputs, not taken
- * from the forward pass. */
-int32_t gf_backward(const gf_desc_t *desc, const void *I_lo,
-                    const void *p_lo, const void *I_hi, const float *eps,
-                    int32_t eps_count, const void *dq_hi, float *dI_lo,
-                    float *dp_lo, void *dI_hi, float *deps, void *ws,
-                    size_t ws_bytes, void *stream);
+ * from the forward pass.  dparams (transform guide only, DEVICE,
+ * gf_guide_param_count floats, same layout as params) receives the
+ * gradient of every transform parameter, summed over the I_lo and I_hi
+ * calls of the shared transform. */
+int32_t gf_backward(const gf_desc_t *desc, const gf_guide_t *guide,
+                    const void *I_lo, const void *p_lo, const void *I_hi,
+                    const float *eps, int32_t eps_count, const void *dq_hi,
+                    float *dI_lo, float *dp_lo, void *dI_hi, float *deps,
+                    float *dparams, void *ws, size_t ws_bytes, void *stream);
 
 /* Human-readable name of a status code (static string). */
 const char *gf_status_string(int32_t status);

@@ -8,6 +8,7 @@
 
 #include <stdlib.h>
 
+#include <algorithm>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -46,7 +47,7 @@ int env_int(const char* name, int dflt) {
 
 }  // namespace
 
-int make_plan(const gf_desc_t* d, Plan* p, const char** why) {
+int make_plan(const gf_desc_t* d, const gf_guide_t* g, Plan* p, const char** why) {
   static thread_local std::string msg;
   auto bad = [&](int code, const std::string& m) {
     msg = m;
@@ -70,7 +71,31 @@ int make_plan(const gf_desc_t* d, Plan* p, const char** why) {
   const double hi_elems = (double)d->n * d->c * d->h_hi * d->w_hi;
   if (hi_elems > 9.0e15 || (double)d->h_hi * d->w_hi > 2.0e9)
     return bad(GF_ERR_UNSUPPORTED, "problem too large");
+  const int gmode = g ? g->mode : GF_GUIDE_IDENTITY;
+  if (gmode != GF_GUIDE_IDENTITY && gmode != GF_GUIDE_GREY && gmode != GF_GUIDE_TRANSFORM)
+    return bad(GF_ERR_INVALID_ARG, "unknown guide mode");
+  const int c_in = gmode == GF_GUIDE_IDENTITY ? d->c : g->c_in;
+  if (gmode == GF_GUIDE_IDENTITY && g && g->c_in != 0 && g->c_in != d->c)
+    return bad(GF_ERR_INVALID_ARG, "identity guide needs c_in == c");
+  if (gmode == GF_GUIDE_GREY && (c_in < 1 || c_in > 4 || d->c > 4))
+    return bad(GF_ERR_UNSUPPORTED, "grey guide supports 1..4 input and output channels");
+  if (gmode == GF_GUIDE_TRANSFORM) {
+    if (c_in != 3 || d->c != 3) return bad(GF_ERR_UNSUPPORTED, "transform guide needs c_in == c == 3");
+    if (g->hidden < 1 || g->hidden > 16) return bad(GF_ERR_UNSUPPORTED, "transform hidden width must be 1..16");
+    if (!g->params) return bad(GF_ERR_INVALID_ARG, "transform guide needs params");
+    if (!(g->bn_eps >= 0.f)) return bad(GF_ERR_INVALID_ARG, "bn_eps must be >= 0");
+    if (g->use_stats && !g->stats) return bad(GF_ERR_INVALID_ARG, "use_stats needs stats");
+  }
   Plan& q = *p;
+  q.gmode = gmode;
+  q.c_in = c_in;
+  q.hidden = gmode == GF_GUIDE_TRANSFORM ? g->hidden : 0;
+  q.KP = 16;
+  q.bn_eps = g ? g->bn_eps : 0.f;
+  q.slope = g ? g->slope : 0.f;
+  q.gparams = g ? g->params : nullptr;
+  q.gstats = g ? g->stats : nullptr;
+  q.use_stats = g ? g->use_stats : 0;
   q.n = d->n;
   q.c = d->c;
   q.h = d->h_lo;
@@ -85,7 +110,8 @@ int make_plan(const gf_desc_t* d, Plan* p, const char** why) {
   q.planes = d->n * d->c;
   // elements per lane-load on the high-res side: 16 bytes, at least S (a
   // lane then covers whole low-res columns), 1 when W is not a multiple
-  int V = 16 / dtype_size(d->io_dtype);
+  // (guided path: the high-res kernels read the float guide plane G_h)
+  int V = gmode == GF_GUIDE_IDENTITY ? 16 / dtype_size(d->io_dtype) : 4;
   if (V < S) V = S;
   q.VEC = (q.W % V == 0) ? V : 1;
 
@@ -133,11 +159,51 @@ int make_plan(const gf_desc_t* d, Plan* p, const char** why) {
   const size_t ubytes = (size_t)q.planes * q.nby * q.nbx * q.ublk_floats * sizeof(float);
   q.off_eps = q.off_u + align_up(ubytes, 256);
   q.ws_bwd = q.off_eps + align_up((size_t)q.planes * q.lo_nx * q.lo_ny * sizeof(float), 256);
+  if (gmode != GF_GUIDE_IDENTITY) {
+    // guided path: the guide planes and the transform's reductions follow the
+    // identity layout (a superset is allocated for both directions)
+    const size_t lo = (size_t)q.planes * q.h * q.w * sizeof(float);
+    const size_t hi = (size_t)q.planes * q.H * q.W * sizeof(float);
+    auto chunks = [](long long P) { return (int)std::min<long long>(64, (P + 16383) / 16384); };
+    q.g_chunks_lo = chunks((long long)q.h * q.w);
+    q.g_chunks_hi = chunks((long long)q.H * q.W);
+    size_t o = align_up(std::max(q.ws_fwd, q.ws_bwd), 256);
+    q.off_gl = o;
+    o += align_up(lo, 256);
+    q.off_gh = o;
+    o += align_up(hi, 256);
+    q.ws_fwd = o;  // forward: G_l, G_h (+ the shared statistics below)
+    q.off_dgl = o;
+    o += align_up(lo, 256);
+    q.off_dgh = o;
+    o += align_up(hi, 256);
+    q.off_mom = o;
+    o += align_up(sizeof(float) * kMomFloats * q.n * std::max(q.g_chunks_lo, q.g_chunks_hi) * 2, 256);
+    q.off_fold = o;
+    o += align_up(sizeof(float) * kFoldFloats * 2, 256);
+    q.off_accp = o;
+    o += align_up(sizeof(float) * kAccFloats * q.n * std::max(q.g_chunks_lo, q.g_chunks_hi) * 2, 256);
+    q.off_acct = o;
+    o += align_up(sizeof(float) * kAccFloats * 2, 256);
+    q.ws_bwd = o;
+    // the forward also needs the moments and folded parameters: place them
+    // after G_h as well (same offsets as in the backward layout are not
+    // required, the forward uses only its own)
+    q.ws_fwd = q.ws_bwd;
+  }
   return GF_OK;
 }
 
 namespace {
 hipError_t launch_forward(const Plan& p, const FwdArgs& a, hipStream_t s) {
+  if (p.gmode != GF_GUIDE_IDENTITY) {
+    switch (p.dtype) {
+      case GF_F32: return launch_forward_guided_f32(p, a, s);
+      case GF_F16: return launch_forward_guided_f16(p, a, s);
+      case GF_BF16: return launch_forward_guided_bf16(p, a, s);
+    }
+    return hipErrorInvalidValue;
+  }
   switch (p.dtype) {
     case GF_F32: return launch_forward_f32(p, a, s);
     case GF_F16: return launch_forward_f16(p, a, s);
@@ -147,6 +213,14 @@ hipError_t launch_forward(const Plan& p, const FwdArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_backward(const Plan& p, const BwdArgs& a, hipStream_t s) {
+  if (p.gmode != GF_GUIDE_IDENTITY) {
+    switch (p.dtype) {
+      case GF_F32: return launch_backward_guided_f32(p, a, s);
+      case GF_F16: return launch_backward_guided_f16(p, a, s);
+      case GF_BF16: return launch_backward_guided_bf16(p, a, s);
+    }
+    return hipErrorInvalidValue;
+  }
   switch (p.dtype) {
     case GF_F32: return launch_backward_f32(p, a, s);
     case GF_F16: return launch_backward_f16(p, a, s);
@@ -210,20 +284,30 @@ static bool misaligned(const void* ptr) { return ((uintptr_t)ptr & 15u) != 0; }
 
 extern "C" {
 
-size_t gf_workspace_size(const gf_desc_t* desc, int32_t backward) {
+size_t gf_guide_param_count(int32_t c_in, int32_t c, int32_t hidden) {
+  if (c_in < 1 || c < 1 || hidden < 1) return 0;
+  return (size_t)hidden * c_in + (size_t)c * hidden + c + 2 + 2 * (size_t)hidden;
+}
+
+size_t gf_guide_stats_count(int32_t c_in) {
+  if (c_in < 1) return 0;
+  return 2 * ((size_t)c_in + (size_t)c_in * c_in);
+}
+
+size_t gf_workspace_size(const gf_desc_t* desc, const gf_guide_t* guide, int32_t backward) {
   gf::Plan p;
   const char* why = nullptr;
-  if (gf::make_plan(desc, &p, &why) != GF_OK) return 0;
+  if (gf::make_plan(desc, guide, &p, &why) != GF_OK) return 0;
   return backward ? p.ws_bwd : p.ws_fwd;
 }
 
-int32_t gf_forward(const gf_desc_t* desc, const void* I_lo, const void* p_lo, const void* I_hi,
-                   const float* eps, int32_t eps_count, void* q_hi, void* ws, size_t ws_bytes,
-                   void* stream) {
+int32_t gf_forward(const gf_desc_t* desc, const gf_guide_t* guide, const void* I_lo,
+                   const void* p_lo, const void* I_hi, const float* eps, int32_t eps_count,
+                   void* q_hi, void* ws, size_t ws_bytes, void* stream) {
   gf::g_detail.clear();
   gf::Plan p;
   const char* why = nullptr;
-  int st = gf::make_plan(desc, &p, &why);
+  int st = gf::make_plan(desc, guide, &p, &why);
   if (st != GF_OK) return fail(st, why);
   if (!I_lo || !p_lo || !I_hi || !eps || !q_hi)
     return fail(GF_ERR_INVALID_ARG, "a required pointer is NULL");
@@ -233,7 +317,7 @@ int32_t gf_forward(const gf_desc_t* desc, const void* I_lo, const void* p_lo, co
       misaligned(ws))
     return fail(GF_ERR_INVALID_ARG, "tensor pointers must be 16-byte aligned");
   if (!ws || ws_bytes < p.ws_fwd)
-    return fail(GF_ERR_WORKSPACE, "workspace smaller than gf_workspace_size(desc, 0) = " +
+    return fail(GF_ERR_WORKSPACE, "workspace smaller than gf_workspace_size(desc, guide, 0) = " +
                                       std::to_string(p.ws_fwd));
   gf::FwdArgs a{I_lo, p_lo, I_hi, eps, eps_count, q_hi, static_cast<char*>(ws)};
   hipError_t e = gf::launch_forward(p, a, static_cast<hipStream_t>(stream));
@@ -241,26 +325,28 @@ int32_t gf_forward(const gf_desc_t* desc, const void* I_lo, const void* p_lo, co
   return GF_OK;
 }
 
-int32_t gf_backward(const gf_desc_t* desc, const void* I_lo, const void* p_lo, const void* I_hi,
-                    const float* eps, int32_t eps_count, const void* dq_hi, float* dI_lo,
-                    float* dp_lo, void* dI_hi, float* deps, void* ws, size_t ws_bytes,
-                    void* stream) {
+int32_t gf_backward(const gf_desc_t* desc, const gf_guide_t* guide, const void* I_lo,
+                    const void* p_lo, const void* I_hi, const float* eps, int32_t eps_count,
+                    const void* dq_hi, float* dI_lo, float* dp_lo, void* dI_hi, float* deps,
+                    float* dparams, void* ws, size_t ws_bytes, void* stream) {
   gf::g_detail.clear();
   gf::Plan p;
   const char* why = nullptr;
-  int st = gf::make_plan(desc, &p, &why);
+  int st = gf::make_plan(desc, guide, &p, &why);
   if (st != GF_OK) return fail(st, why);
   if (!I_lo || !p_lo || !I_hi || !eps || !dq_hi)
     return fail(GF_ERR_INVALID_ARG, "a required pointer is NULL");
   if (eps_count != 1 && eps_count != desc->n)
     return fail(GF_ERR_INVALID_ARG, "eps_count must be 1 or n");
+  if (dparams && p.gmode != GF_GUIDE_TRANSFORM)
+    return fail(GF_ERR_INVALID_ARG, "dparams needs the transform guide");
   if (misaligned(I_lo) || misaligned(p_lo) || misaligned(I_hi) || misaligned(dq_hi) ||
       misaligned(dI_lo) || misaligned(dp_lo) || misaligned(dI_hi) || misaligned(ws))
     return fail(GF_ERR_INVALID_ARG, "tensor pointers must be 16-byte aligned");
   if (!ws || ws_bytes < p.ws_bwd)
-    return fail(GF_ERR_WORKSPACE, "workspace smaller than gf_workspace_size(desc, 1) = " +
+    return fail(GF_ERR_WORKSPACE, "workspace smaller than gf_workspace_size(desc, guide, 1) = " +
                                       std::to_string(p.ws_bwd));
-  gf::BwdArgs a{I_lo, p_lo, I_hi, dq_hi, eps, eps_count, dI_lo, dp_lo, deps, dI_hi,
+  gf::BwdArgs a{I_lo, p_lo, I_hi, dq_hi, eps, eps_count, dI_lo, dp_lo, deps, dparams, dI_hi,
                 static_cast<char*>(ws)};
   hipError_t e = gf::launch_backward(p, a, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return fail(GF_ERR_HIP, hipGetErrorString(e));

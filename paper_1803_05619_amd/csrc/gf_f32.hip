@@ -1,5 +1,5 @@
 // Launchers of the guided filtering kernels for float image I/O.
-#include "gf_kernels.h"
+#include "gf_guide.h"
 
 namespace gf {
 
@@ -9,6 +9,14 @@ hipError_t launch_forward_f32(const Plan& p, const FwdArgs& a, hipStream_t s) {
 
 hipError_t launch_backward_f32(const Plan& p, const BwdArgs& a, hipStream_t s) {
   return backward_t<float>(p, a, s);
+}
+
+hipError_t launch_forward_guided_f32(const Plan& p, const FwdArgs& a, hipStream_t s) {
+  return forward_guided_t<float>(p, a, s);
+}
+
+hipError_t launch_backward_guided_f32(const Plan& p, const BwdArgs& a, hipStream_t s) {
+  return backward_guided_t<float>(p, a, s);
 }
 
 }  // namespace gf

@@ -278,7 +278,7 @@ struct CoefArgs {
 // columns x TR output rows.  The guide and input are recentred by their
 // values at the segment centre (variance and covariance are shift
 // invariant; b is formed from the actual means).
-template <typename T, int R, bool MAB>
+template <typename TG, typename TP, int R, bool MAB>
 __global__ __launch_bounds__(64) void coef_kernel(CoefArgs a) {
   constexpr int K = 2 * R + 1;
   constexpr int HB = MAB ? R : 0;
@@ -300,8 +300,8 @@ __global__ __launch_bounds__(64) void coef_kernel(CoefArgs a) {
   const bool colin = (unsigned)j < (unsigned)w;
   const int i0 = blockIdx.y * a.TR, i1 = min(i0 + a.TR, h);
   const size_t pofs = (size_t)plane * h * w;
-  const T* G = reinterpret_cast<const T*>(a.I_lo) + pofs;
-  const T* P = reinterpret_cast<const T*>(a.p_lo) + pofs;
+  const TG* G = reinterpret_cast<const TG*>(a.I_lo) + pofs;
+  const TP* P = reinterpret_cast<const TP*>(a.p_lo) + pofs;
   float* Ab = a.abar + pofs;
   float* Bb = a.bbar ? a.bbar + pofs : nullptr;
   const int ic = min(i0 + a.TR / 2, h - 1), jc = min(max(j0 + TWo / 2, 0), w - 1);
@@ -326,13 +326,13 @@ __global__ __launch_bounds__(64) void coef_kernel(CoefArgs a) {
   // values: a load inside a divergent branch, or arithmetic right after it,
   // would make the wave wait for it there instead of a block later.
   const int jcl = min(max(j, 0), w - 1);
-  auto load = [&](int x, T& g, T& p) __attribute__((always_inline)) {
+  auto load = [&](int x, TG& g, TP& p) __attribute__((always_inline)) {
     const size_t o = (size_t)min(max(x, 0), h - 1) * w + jcl;
     g = G[o];
     p = P[o];
   };
 
-  auto block = [&](int xb, const T (&gq)[kPF], const T (&pq)[kPF]) __attribute__((always_inline)) {
+  auto block = [&](int xb, const TG (&gq)[kPF], const TP (&pq)[kPF]) __attribute__((always_inline)) {
 #pragma unroll
     for (int d = 0; d < kPF; ++d) {
       const int x = xb + d;
@@ -411,11 +411,13 @@ __global__ __launch_bounds__(64) void coef_kernel(CoefArgs a) {
     wave_sync();
   };
 
-  T gq[kPF], pq[kPF];
+  TG gq[kPF];
+  TP pq[kPF];
 #pragma unroll
   for (int d = 0; d < kPF; ++d) load(x0 + d, gq[d], pq[d]);
   for (int base = x0; base < xend; base += kPF) {
-    T gn[kPF], pn[kPF];
+    TG gn[kPF];
+    TP pn[kPF];
 #pragma unroll
     for (int d = 0; d < kPF; ++d) load(base + kPF + d, gn[d], pn[d]);
     block(base, gq, pq);
@@ -461,7 +463,7 @@ __device__ __forceinline__ void hrow(const float* L, int i, int h, int w, const 
 // register buffers alternate: while block i is computed, block i+1 is in
 // flight (its loads are issued after the low-res tap loads of block i, so
 // waiting for those does not wait for it).
-template <typename T, int S, int VEC>
+template <typename TG, typename TQ, int S, int VEC>
 __global__ __launch_bounds__(256) void apply_kernel(ApplyArgs a) {
   const long long t = xcd_order(blockIdx.x, gridDim.x, a.xcd) * 256 + threadIdx.x;
   if (t >= a.total) return;
@@ -483,8 +485,8 @@ __global__ __launch_bounds__(256) void apply_kernel(ApplyArgs a) {
   const float* Ab = a.abar + (size_t)plane * h * w;
   const float* Bb = a.bbar + (size_t)plane * h * w;
   const size_t hofs = (size_t)plane * a.H * W + x0;
-  const T* Gp = reinterpret_cast<const T*>(a.I_hi) + hofs;
-  T* Qp = reinterpret_cast<T*>(a.q) + hofs;
+  const TG* Gp = reinterpret_cast<const TG*>(a.I_hi) + hofs;
+  TQ* Qp = reinterpret_cast<TQ*>(a.q) + hofs;
   const int ib0 = rb * (a.RB / S);
   const int ib1 = min(ib0 + a.RB / S, h);
   float am[VEC], ac[VEC], ap[VEC], bm[VEC], bc[VEC], bp[VEC];
@@ -495,7 +497,7 @@ __global__ __launch_bounds__(256) void apply_kernel(ApplyArgs a) {
 
   auto load_block = [&](int i, float (&g)[S][VEC]) __attribute__((always_inline)) {
 #pragma unroll
-    for (int t2 = 0; t2 < S; ++t2) load_vec<T, VEC>(Gp + (size_t)(S * i + t2) * W, g[t2]);
+    for (int t2 = 0; t2 < S; ++t2) load_vec<TG, VEC>(Gp + (size_t)(S * i + t2) * W, g[t2]);
   };
   auto body = [&](int i, float (&g)[S][VEC], float (&gn)[S][VEC]) __attribute__((always_inline)) {
     hrow<VEC>(Ab, i + 1, h, w, j0, j1, wx, ap);
@@ -522,7 +524,7 @@ __global__ __launch_bounds__(256) void apply_kernel(ApplyArgs a) {
           q[e] = A * g[t2][e] + B;
         }
       }
-      store_vec_nt<T, VEC>(Qp + (size_t)(S * i + t2) * W, q);
+      store_vec_nt<TQ, VEC>(Qp + (size_t)(S * i + t2) * W, q);
     }
 #pragma unroll
     for (int e = 0; e < VEC; ++e) {
@@ -567,7 +569,7 @@ struct BwdHiArgs {
 // contributions that cross into the neighbouring lanes' columns move with
 // one lane shuffle each; otherwise (VEC = 1 fallback) through LDS.
 // Loads of row block i+1 are issued before block i is computed.
-template <typename T, int S, int VEC>
+template <typename TG, typename TD, typename TO, int S, int VEC>
 __global__ __launch_bounds__(64) void bwd_hi_kernel(BwdHiArgs a) {
   constexpr int TWH = 64 * VEC;  // high-res columns per block
   constexpr bool REG = (VEC % S) == 0;
@@ -596,9 +598,9 @@ __global__ __launch_bounds__(64) void bwd_hi_kernel(BwdHiArgs a) {
   }
   const float* Ab = a.abar + (size_t)plane * h * w;
   const size_t hofs = (size_t)plane * a.H * W + (valid ? x0 : 0);
-  const T* Gp = reinterpret_cast<const T*>(a.I_hi) + hofs;
-  const T* Dp = reinterpret_cast<const T*>(a.dq) + hofs;
-  T* Op = a.dI_hi ? reinterpret_cast<T*>(a.dI_hi) + hofs : nullptr;
+  const TG* Gp = reinterpret_cast<const TG*>(a.I_hi) + hofs;
+  const TD* Dp = reinterpret_cast<const TD*>(a.dq) + hofs;
+  TO* Op = a.dI_hi ? reinterpret_cast<TO*>(a.dI_hi) + hofs : nullptr;
   const int UW = tw + 2;
   const size_t UP = (size_t)(bh + 2) * UW;
   float* Ub = a.U + (((size_t)plane * a.nby + by) * a.nbx + bx) * 2 * UP;
@@ -722,8 +724,8 @@ __global__ __launch_bounds__(64) void bwd_hi_kernel(BwdHiArgs a) {
   auto load_block = [&](int i, float (&d)[S][VEC], float (&g)[S][VEC]) __attribute__((always_inline)) {
 #pragma unroll
     for (int t2 = 0; t2 < S; ++t2) {
-      load_vec<T, VEC>(Dp + (size_t)(S * i + t2) * W, d[t2]);
-      load_vec<T, VEC>(Gp + (size_t)(S * i + t2) * W, g[t2]);
+      load_vec<TD, VEC>(Dp + (size_t)(S * i + t2) * W, d[t2]);
+      load_vec<TG, VEC>(Gp + (size_t)(S * i + t2) * W, g[t2]);
     }
   };
   auto body = [&](int i, float (&d)[S][VEC], float (&g)[S][VEC], float (&dn)[S][VEC],
@@ -765,7 +767,7 @@ __global__ __launch_bounds__(64) void bwd_hi_kernel(BwdHiArgs a) {
           nB[e] += wn * vB;
         }
       }
-      if (Op && valid) store_vec_nt<T, VEC>(Op + (size_t)(S * i + t2) * W, o);
+      if (Op && valid) store_vec_nt<TO, VEC>(Op + (size_t)(S * i + t2) * W, o);
     }
     flush(pA, pB, i - i_a);  // low-res row i-1 is complete
 #pragma unroll
@@ -875,7 +877,7 @@ __device__ __forceinline__ URaw gather_u_raw(const float* base, size_t UP, const
 // f_mu^T(y) = box sum of y/N); per row whose window is complete: statistics,
 // A, and the adjoint quantities X = (dmean_I, dmean_p, dcov, dvar) / N; per
 // row whose X window is complete: box sums of X give dG and dp.
-template <typename T, int R, bool MAB>
+template <typename TG, typename TP, int R, bool MAB>
 __global__ __launch_bounds__(64) void bwd_lo_kernel(BwdLoArgs a) {
   constexpr int K = 2 * R + 1;
   constexpr int TWo = 64 - 4 * R;
@@ -896,8 +898,8 @@ __global__ __launch_bounds__(64) void bwd_lo_kernel(BwdLoArgs a) {
   const bool colin = (unsigned)j < (unsigned)w;
   const int i0 = blockIdx.y * a.TR, i1 = min(i0 + a.TR, h);
   const size_t pofs = (size_t)plane * h * w;
-  const T* G = reinterpret_cast<const T*>(a.I_lo) + pofs;
-  const T* P = reinterpret_cast<const T*>(a.p_lo) + pofs;
+  const TG* G = reinterpret_cast<const TG*>(a.I_lo) + pofs;
+  const TP* P = reinterpret_cast<const TP*>(a.p_lo) + pofs;
   const int ic = min(i0 + a.TR / 2, h - 1), jc = min(max(j0 + TWo / 2, 0), w - 1);
   const float cg = to_f(G[(size_t)ic * w + jc]);
   const float cp = to_f(P[(size_t)ic * w + jc]);
@@ -922,7 +924,8 @@ __global__ __launch_bounds__(64) void bwd_lo_kernel(BwdLoArgs a) {
   // would make the wave wait for it there instead of a block later.
   const int jcl = min(max(j, 0), w - 1);
   struct Raw {
-    T g, p;
+    TG g;
+    TP p;
     URaw u;
   };
   const size_t UP = (size_t)(a.bh + 2) * (a.tw + 2);
@@ -1122,7 +1125,7 @@ hipError_t with_radius(int r, F&& f) {
   }
 }
 
-template <typename T>
+template <typename TG, typename TP>
 hipError_t launch_coef(const Plan& p, const void* I_lo, const void* p_lo, const float* eps,
                        int eps_count, float* abar, float* bbar, hipStream_t s) {
   CoefArgs a{I_lo, p_lo, eps, eps_count, p.c, p.h, p.w, p.coTR, abar, bbar};
@@ -1131,108 +1134,126 @@ hipError_t launch_coef(const Plan& p, const void* I_lo, const void* p_lo, const 
   hipError_t err = with_radius(p.r, [&](auto rc) {
     constexpr int R = decltype(rc)::value;
     if (p.mean_ab)
-      hipLaunchKernelGGL((coef_kernel<T, R, true>), grid, dim3(64), p.coLDS, s, a);
+      hipLaunchKernelGGL((coef_kernel<TG, TP, R, true>), grid, dim3(64), p.coLDS, s, a);
     else
-      hipLaunchKernelGGL((coef_kernel<T, R, false>), grid, dim3(64), p.coLDS, s, a);
+      hipLaunchKernelGGL((coef_kernel<TG, TP, R, false>), grid, dim3(64), p.coLDS, s, a);
     return hipGetLastError();
   });
   prof_end(s);
   return err;
 }
 
-template <typename T, int S, int VEC>
-hipError_t launch_apply_t(const Plan& p, const FwdArgs& f, hipStream_t s) {
-  ApplyArgs a{f.I_hi, f.q, reinterpret_cast<const float*>(f.ws + p.off_abar),
-              reinterpret_cast<const float*>(f.ws + p.off_bbar), p.h, p.w, p.H, p.W, p.RB,
+template <typename TG, typename TQ, int S, int VEC>
+hipError_t launch_apply_t(const Plan& p, const void* G_hi, void* q, const float* abar,
+                          const float* bbar, hipStream_t s) {
+  ApplyArgs a{G_hi, q, abar, bbar, p.h, p.w, p.H, p.W, p.RB,
               p.nrb, p.nxv, (long long)p.planes * p.nrb * p.nxv, p.xcd};
   const unsigned blocks = (unsigned)((a.total + 255) / 256);
   prof_begin("gf_apply", s);
-  hipLaunchKernelGGL((apply_kernel<T, S, VEC>), dim3(blocks), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((apply_kernel<TG, TQ, S, VEC>), dim3(blocks), dim3(256), 0, s, a);
   prof_end(s);
   return hipGetLastError();
 }
 
-template <typename T, int S, int VEC>
-hipError_t launch_bwd_hi_t(const Plan& p, const BwdArgs& b, hipStream_t s) {
-  BwdHiArgs a{b.I_hi, b.dq, b.dI_hi, reinterpret_cast<const float*>(b.ws + p.off_abar),
-              reinterpret_cast<float*>(b.ws + p.off_u), p.h, p.w, p.H, p.W, p.bh, p.tw, p.nby,
-              p.nbx, p.xcd};
+template <typename TG, typename TD, typename TO, int S, int VEC>
+hipError_t launch_bwd_hi_t(const Plan& p, const void* G_hi, const void* dq, void* out,
+                           const float* abar, float* U, hipStream_t s) {
+  BwdHiArgs a{G_hi, dq, out, abar, U, p.h, p.w, p.H, p.W, p.bh, p.tw, p.nby, p.nbx, p.xcd};
   prof_begin("gf_bwd_hi", s);
-  hipLaunchKernelGGL((bwd_hi_kernel<T, S, VEC>), dim3(p.nbx, p.nby, p.planes), dim3(64), 0, s,
-                     a);
+  hipLaunchKernelGGL((bwd_hi_kernel<TG, TD, TO, S, VEC>), dim3(p.nbx, p.nby, p.planes), dim3(64),
+                     0, s, a);
   prof_end(s);
   return hipGetLastError();
 }
 
-// High-res launch shapes: VEC is 16 bytes of elements, raised to S when S is
-// larger (so that a lane always covers whole low-res columns), or 1 when the
-// width is not a multiple of it.
-template <typename T, int S>
+// High-res launch shapes: VEC is 16 bytes of the guide type, raised to S
+// when S is larger (so that a lane always covers whole low-res columns), or
+// 1 when the width is not a multiple of it.
+template <typename TG, int S>
 constexpr int vec_for() {
-  return (int)(16 / sizeof(T)) >= S ? (int)(16 / sizeof(T)) : S;
+  return (int)(16 / sizeof(TG)) >= S ? (int)(16 / sizeof(TG)) : S;
 }
 
-template <typename T>
-hipError_t apply_dispatch(const Plan& p, const FwdArgs& f, hipStream_t s) {
+template <typename TG, typename TQ>
+hipError_t launch_apply(const Plan& p, const void* G_hi, void* q, const float* abar,
+                        const float* bbar, hipStream_t s) {
   switch (p.S) {
-    case 1: return p.VEC == 1 ? launch_apply_t<T, 1, 1>(p, f, s) : launch_apply_t<T, 1, vec_for<T, 1>()>(p, f, s);
-    case 2: return p.VEC == 1 ? launch_apply_t<T, 2, 1>(p, f, s) : launch_apply_t<T, 2, vec_for<T, 2>()>(p, f, s);
-    case 4: return p.VEC == 1 ? launch_apply_t<T, 4, 1>(p, f, s) : launch_apply_t<T, 4, vec_for<T, 4>()>(p, f, s);
-    case 8: return p.VEC == 1 ? launch_apply_t<T, 8, 1>(p, f, s) : launch_apply_t<T, 8, vec_for<T, 8>()>(p, f, s);
+#define GF_CASE(SS)                                                                        \
+  case SS:                                                                                 \
+    return p.VEC == 1 ? launch_apply_t<TG, TQ, SS, 1>(p, G_hi, q, abar, bbar, s)          \
+                      : launch_apply_t<TG, TQ, SS, vec_for<TG, SS>()>(p, G_hi, q, abar, bbar, s);
+    GF_CASE(1) GF_CASE(2) GF_CASE(4) GF_CASE(8)
+#undef GF_CASE
   }
   return hipErrorInvalidValue;
 }
 
-template <typename T>
-hipError_t bwd_hi_dispatch(const Plan& p, const BwdArgs& b, hipStream_t s) {
+template <typename TG, typename TD, typename TO>
+hipError_t launch_bwd_hi(const Plan& p, const void* G_hi, const void* dq, void* out,
+                         const float* abar, float* U, hipStream_t s) {
   switch (p.S) {
-    case 1: return p.VEC == 1 ? launch_bwd_hi_t<T, 1, 1>(p, b, s) : launch_bwd_hi_t<T, 1, vec_for<T, 1>()>(p, b, s);
-    case 2: return p.VEC == 1 ? launch_bwd_hi_t<T, 2, 1>(p, b, s) : launch_bwd_hi_t<T, 2, vec_for<T, 2>()>(p, b, s);
-    case 4: return p.VEC == 1 ? launch_bwd_hi_t<T, 4, 1>(p, b, s) : launch_bwd_hi_t<T, 4, vec_for<T, 4>()>(p, b, s);
-    case 8: return p.VEC == 1 ? launch_bwd_hi_t<T, 8, 1>(p, b, s) : launch_bwd_hi_t<T, 8, vec_for<T, 8>()>(p, b, s);
+#define GF_CASE(SS)                                                                         \
+  case SS:                                                                                  \
+    return p.VEC == 1                                                                       \
+               ? launch_bwd_hi_t<TG, TD, TO, SS, 1>(p, G_hi, dq, out, abar, U, s)           \
+               : launch_bwd_hi_t<TG, TD, TO, SS, vec_for<TG, SS>()>(p, G_hi, dq, out, abar, U, s);
+    GF_CASE(1) GF_CASE(2) GF_CASE(4) GF_CASE(8)
+#undef GF_CASE
   }
   return hipErrorInvalidValue;
+}
+
+template <typename TG, typename TP>
+hipError_t launch_bwd_lo(const Plan& p, const void* G_lo, const void* p_lo, const float* eps,
+                         int eps_count, const float* U, float* dG_lo, float* dp_lo,
+                         float* part, hipStream_t s) {
+  BwdLoArgs a{G_lo, p_lo, eps, eps_count, p.c, U, p.bh, p.tw, p.nby, p.nbx,
+              p.h, p.w, p.loTR, dG_lo, dp_lo, part};
+  const dim3 grid(p.lo_nx, p.lo_ny, p.planes);
+  prof_begin("gf_bwd_lo", s);
+  hipError_t err = with_radius(p.r, [&](auto rc) {
+    constexpr int R = decltype(rc)::value;
+    if (p.mean_ab)
+      hipLaunchKernelGGL((bwd_lo_kernel<TG, TP, R, true>), grid, dim3(64), p.loLDS, s, a);
+    else
+      hipLaunchKernelGGL((bwd_lo_kernel<TG, TP, R, false>), grid, dim3(64), p.loLDS, s, a);
+    return hipGetLastError();
+  });
+  prof_end(s);
+  return err;
+}
+
+hipError_t launch_eps_reduce(const Plan& p, const float* part, int eps_count, float* deps,
+                             hipStream_t s) {
+  prof_begin("gf_eps_reduce", s);
+  hipLaunchKernelGGL(eps_reduce_kernel, dim3(eps_count), dim3(256), 0, s, part,
+                     p.lo_nx * p.lo_ny, p.c, p.n, eps_count, deps);
+  prof_end(s);
+  return hipGetLastError();
 }
 
 template <typename T>
 hipError_t forward_t(const Plan& p, const FwdArgs& f, hipStream_t s) {
   float* abar = reinterpret_cast<float*>(f.ws + p.off_abar);
   float* bbar = reinterpret_cast<float*>(f.ws + p.off_bbar);
-  hipError_t err = launch_coef<T>(p, f.I_lo, f.p_lo, f.eps, f.eps_count, abar, bbar, s);
+  hipError_t err = launch_coef<T, T>(p, f.I_lo, f.p_lo, f.eps, f.eps_count, abar, bbar, s);
   if (err != hipSuccess) return err;
-  return apply_dispatch<T>(p, f, s);
+  return launch_apply<T, T>(p, f.I_hi, f.q, abar, bbar, s);
 }
 
 template <typename T>
 hipError_t backward_t(const Plan& p, const BwdArgs& b, hipStream_t s) {
   float* abar = reinterpret_cast<float*>(b.ws + p.off_abar);
-  hipError_t err = launch_coef<T>(p, b.I_lo, b.p_lo, b.eps, b.eps_count, abar, nullptr, s);
+  float* U = reinterpret_cast<float*>(b.ws + p.off_u);
+  hipError_t err = launch_coef<T, T>(p, b.I_lo, b.p_lo, b.eps, b.eps_count, abar, nullptr, s);
   if (err != hipSuccess) return err;
-  err = bwd_hi_dispatch<T>(p, b, s);
+  err = launch_bwd_hi<T, T, T>(p, b.I_hi, b.dq, b.dI_hi, abar, U, s);
   if (err != hipSuccess) return err;
   if (!b.dI_lo && !b.dp_lo && !b.deps) return hipSuccess;
   float* part = reinterpret_cast<float*>(b.ws + p.off_eps);
-  BwdLoArgs a{b.I_lo, b.p_lo, b.eps, b.eps_count, p.c,
-              reinterpret_cast<const float*>(b.ws + p.off_u), p.bh, p.tw, p.nby, p.nbx,
-              p.h, p.w, p.loTR, b.dI_lo, b.dp_lo, part};
-  const dim3 grid(p.lo_nx, p.lo_ny, p.planes);
-  prof_begin("gf_bwd_lo", s);
-  err = with_radius(p.r, [&](auto rc) {
-    constexpr int R = decltype(rc)::value;
-    if (p.mean_ab)
-      hipLaunchKernelGGL((bwd_lo_kernel<T, R, true>), grid, dim3(64), p.loLDS, s, a);
-    else
-      hipLaunchKernelGGL((bwd_lo_kernel<T, R, false>), grid, dim3(64), p.loLDS, s, a);
-    return hipGetLastError();
-  });
-  prof_end(s);
-  err = hipGetLastError();
+  err = launch_bwd_lo<T, T>(p, b.I_lo, b.p_lo, b.eps, b.eps_count, U, b.dI_lo, b.dp_lo, part, s);
   if (err != hipSuccess || !b.deps) return err;
-  prof_begin("gf_eps_reduce", s);
-  hipLaunchKernelGGL(eps_reduce_kernel, dim3(b.eps_count), dim3(256), 0, s, part,
-                     p.lo_nx * p.lo_ny, p.c, p.n, b.eps_count, b.deps);
-  prof_end(s);
-  return hipGetLastError();
+  return launch_eps_reduce(p, part, b.eps_count, b.deps, s);
 }
 
 }  // namespace

@@ -33,15 +33,31 @@ class gf_desc_t(ctypes.Structure):
                 ("n", "c", "h_lo", "w_lo", "h_hi", "w_hi", "r", "mean_ab", "io_dtype")]
 
 
+GF_GUIDE_IDENTITY, GF_GUIDE_GREY, GF_GUIDE_TRANSFORM = 0, 1, 2
+
+
+class gf_guide_t(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("c_in", ctypes.c_int32), ("hidden", ctypes.c_int32),
+                ("bn_eps", ctypes.c_float), ("slope", ctypes.c_float),
+                ("params", ctypes.c_void_p), ("stats", ctypes.c_void_p),
+                ("use_stats", ctypes.c_int32)]
+
+
 _vp = ctypes.c_void_p
 _fp = ctypes.c_void_p  # float* passed as raw addresses
-lib.gf_workspace_size.argtypes = [ctypes.POINTER(gf_desc_t), ctypes.c_int32]
+_dp = ctypes.POINTER(gf_desc_t)
+_gp = ctypes.POINTER(gf_guide_t)
+lib.gf_guide_param_count.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+lib.gf_guide_param_count.restype = ctypes.c_size_t
+lib.gf_guide_stats_count.argtypes = [ctypes.c_int32]
+lib.gf_guide_stats_count.restype = ctypes.c_size_t
+lib.gf_workspace_size.argtypes = [_dp, _gp, ctypes.c_int32]
 lib.gf_workspace_size.restype = ctypes.c_size_t
-lib.gf_forward.argtypes = [ctypes.POINTER(gf_desc_t), _vp, _vp, _vp, _fp, ctypes.c_int32, _vp,
-                           _vp, ctypes.c_size_t, _vp]
+lib.gf_forward.argtypes = [_dp, _gp, _vp, _vp, _vp, _fp, ctypes.c_int32, _vp, _vp,
+                           ctypes.c_size_t, _vp]
 lib.gf_forward.restype = ctypes.c_int32
-lib.gf_backward.argtypes = [ctypes.POINTER(gf_desc_t), _vp, _vp, _vp, _fp, ctypes.c_int32, _vp,
-                            _fp, _fp, _vp, _fp, _vp, ctypes.c_size_t, _vp]
+lib.gf_backward.argtypes = [_dp, _gp, _vp, _vp, _vp, _fp, ctypes.c_int32, _vp, _fp, _fp, _vp,
+                            _fp, _fp, _vp, ctypes.c_size_t, _vp]
 lib.gf_backward.restype = ctypes.c_int32
 lib.gf_status_string.argtypes = [ctypes.c_int32]
 lib.gf_status_string.restype = ctypes.c_char_p
@@ -68,19 +84,32 @@ class GFError(RuntimeError):
 
 # ------------------------------------------------------------------ raw C ABI
 
-def gf_workspace_size(desc: gf_desc_t, backward: int) -> int:
-    return int(lib.gf_workspace_size(ctypes.byref(desc), int(backward)))
+def _gref(guide):
+    return None if guide is None else ctypes.byref(guide)
 
 
-def gf_forward(desc, I_lo, p_lo, I_hi, eps, eps_count, q_hi, ws, ws_bytes, stream) -> int:
-    return int(lib.gf_forward(ctypes.byref(desc), I_lo, p_lo, I_hi, eps, eps_count, q_hi, ws,
-                              ws_bytes, stream))
+def gf_guide_param_count(c_in: int, c: int, hidden: int) -> int:
+    return int(lib.gf_guide_param_count(c_in, c, hidden))
 
 
-def gf_backward(desc, I_lo, p_lo, I_hi, eps, eps_count, dq_hi, dI_lo, dp_lo, dI_hi, deps, ws,
-                ws_bytes, stream) -> int:
-    return int(lib.gf_backward(ctypes.byref(desc), I_lo, p_lo, I_hi, eps, eps_count, dq_hi,
-                               dI_lo, dp_lo, dI_hi, deps, ws, ws_bytes, stream))
+def gf_guide_stats_count(c_in: int) -> int:
+    return int(lib.gf_guide_stats_count(c_in))
+
+
+def gf_workspace_size(desc: gf_desc_t, guide, backward: int) -> int:
+    return int(lib.gf_workspace_size(ctypes.byref(desc), _gref(guide), int(backward)))
+
+
+def gf_forward(desc, guide, I_lo, p_lo, I_hi, eps, eps_count, q_hi, ws, ws_bytes, stream) -> int:
+    return int(lib.gf_forward(ctypes.byref(desc), _gref(guide), I_lo, p_lo, I_hi, eps, eps_count,
+                              q_hi, ws, ws_bytes, stream))
+
+
+def gf_backward(desc, guide, I_lo, p_lo, I_hi, eps, eps_count, dq_hi, dI_lo, dp_lo, dI_hi, deps,
+                dparams, ws, ws_bytes, stream) -> int:
+    return int(lib.gf_backward(ctypes.byref(desc), _gref(guide), I_lo, p_lo, I_hi, eps,
+                               eps_count, dq_hi, dI_lo, dp_lo, dI_hi, deps, dparams, ws,
+                               ws_bytes, stream))
 
 
 def gf_status_string(code: int) -> str:
@@ -115,10 +144,56 @@ def _ptr(t):
     return None if t is None else t.data_ptr()
 
 
-def make_desc(I_lo: torch.Tensor, I_hi: torch.Tensor, r: int, mean_ab: bool = True) -> gf_desc_t:
-    n, c, h, w = I_lo.shape
+def make_desc(I_lo: torch.Tensor, I_hi: torch.Tensor, r: int, mean_ab: bool = True,
+              c: int = None) -> gf_desc_t:
+    """Problem description; `c` (output channels) defaults to I_lo's channels
+    (a guide may map c_in input channels to c)."""
+    n, c_in, h, w = I_lo.shape
     H, W = I_hi.shape[-2:]
-    return gf_desc_t(n, c, h, w, H, W, int(r), int(bool(mean_ab)), DTYPE_CODES[I_lo.dtype])
+    return gf_desc_t(n, c_in if c is None else int(c), h, w, H, W, int(r), int(bool(mean_ab)),
+                     DTYPE_CODES[I_lo.dtype])
+
+
+class Guide:
+    """Host description of the guidance map G = F(I) (gf_guide_t).
+
+    mode: GF_GUIDE_GREY (channel mean of c_in channels) or GF_GUIDE_TRANSFORM
+    (1x1 conv -> adaptive BN -> leaky ReLU -> 1x1 conv; `params` a float32
+    device tensor of gf_guide_param_count(c_in, c, hidden) entries, see
+    `pack_transform_params`).  `stats` (optional float32 device tensor of
+    gf_guide_stats_count(c_in) entries) receives the forward's batch
+    statistics; with use_stats the backward reads them back."""
+
+    def __init__(self, mode, c_in, hidden=0, params=None, bn_eps=1e-5, slope=0.2, stats=None,
+                 use_stats=False):
+        self.mode, self.c_in, self.hidden = int(mode), int(c_in), int(hidden)
+        self.params, self.stats, self.use_stats = params, stats, bool(use_stats)
+        self.bn_eps, self.slope = float(bn_eps), float(slope)
+
+    def struct(self) -> gf_guide_t:
+        return gf_guide_t(self.mode, self.c_in, self.hidden, self.bn_eps, self.slope,
+                          _ptr(self.params), _ptr(self.stats), int(self.use_stats))
+
+
+def pack_transform_params(w1, w2, b2, lam, mu, gamma, beta, device=None) -> torch.Tensor:
+    """Flat float32 parameter vector of the transform guide:
+    W1 [hidden][c_in] | W2 [c][hidden] | b2 [c] | lam | mu | gamma | beta."""
+    parts = [torch.as_tensor(x, dtype=torch.float32).reshape(-1)
+             for x in (w1, w2, b2, [float(lam)], [float(mu)], gamma, beta)]
+    return torch.cat(parts).to(device).contiguous()
+
+
+def unpack_transform_params(v: torch.Tensor, c_in: int, c: int, hidden: int) -> dict:
+    """Inverse of pack_transform_params (views into v)."""
+    sizes = [hidden * c_in, c * hidden, c, 1, 1, hidden, hidden]
+    names = ["w1", "w2", "b2", "lam", "mu", "gamma", "beta"]
+    out, o = {}, 0
+    for name, k in zip(names, sizes):
+        out[name] = v[o:o + k]
+        o += k
+    out["w1"] = out["w1"].reshape(hidden, c_in)
+    out["w2"] = out["w2"].reshape(c, hidden)
+    return out
 
 
 def _check(tensors, dtype, device):
@@ -154,16 +229,30 @@ def _stream(device):
     return torch.cuda.current_stream(device).cuda_stream
 
 
-def forward(I_lo, p_lo, I_hi, eps, r=1, mean_ab=True, out=None, ws=None):
-    """q = GF(I_lo, p_lo, I_hi): one gf_forward call on the current stream."""
+def _out_channels(I_lo, guide, c):
+    if c is not None:
+        return int(c)
+    if guide is not None and guide.mode == GF_GUIDE_TRANSFORM:
+        return 3
+    return I_lo.shape[1]
+
+
+def forward(I_lo, p_lo, I_hi, eps, r=1, mean_ab=True, out=None, ws=None, guide=None):
+    """q = GF(I_lo, p_lo, I_hi): one gf_forward call on the current stream.
+    With a Guide, I_lo and I_hi have guide.c_in channels and q has p_lo's."""
     dev = I_hi.device
     _check(dict(I_lo=I_lo, p_lo=p_lo, I_hi=I_hi, out=out), I_hi.dtype, dev)
-    desc = make_desc(I_lo, I_hi, r, mean_ab)
+    desc = make_desc(I_lo, I_hi, r, mean_ab, c=p_lo.shape[1])
+    g = None if guide is None else guide.struct()
     e = _eps_tensor(eps, desc.n, dev)
-    q = out if out is not None else torch.empty_like(I_hi)
-    need = gf_workspace_size(desc, 0)
+    q = out if out is not None else torch.empty(
+        (desc.n, desc.c, desc.h_hi, desc.w_hi), dtype=I_hi.dtype, device=dev)
+    need = gf_workspace_size(desc, g, 0)
+    if need == 0 and ws is None:
+        st = gf_forward(desc, g, None, None, None, None, 0, None, None, 0, None)
+        raise GFError(st if st != GF_OK else GF_ERR_INVALID_ARG)
     ws = _ws(need, dev, ws)
-    st = gf_forward(desc, _ptr(I_lo), _ptr(p_lo), _ptr(I_hi), _ptr(e), e.numel(), _ptr(q),
+    st = gf_forward(desc, g, _ptr(I_lo), _ptr(p_lo), _ptr(I_hi), _ptr(e), e.numel(), _ptr(q),
                     _ptr(ws), ws.numel(), _stream(dev))
     if st != GF_OK:
         raise GFError(st)
@@ -171,57 +260,84 @@ def forward(I_lo, p_lo, I_hi, eps, r=1, mean_ab=True, out=None, ws=None):
 
 
 def backward(I_lo, p_lo, I_hi, eps, dq, r=1, mean_ab=True, need_dI_lo=True, need_dp_lo=True,
-             need_dI_hi=True, need_deps=True, ws=None, outs=None):
-    """Gradients (dI_lo, dp_lo, dI_hi, deps) of sum(q * dq); None where not requested."""
+             need_dI_hi=True, need_deps=True, ws=None, outs=None, guide=None,
+             need_dparams=None):
+    """Gradients (dI_lo, dp_lo, dI_hi, deps, dparams) of sum(q * dq); None
+    where not requested.  dparams only with a transform Guide (requested by
+    default there)."""
     dev = I_hi.device
     _check(dict(I_lo=I_lo, p_lo=p_lo, I_hi=I_hi, dq=dq), I_hi.dtype, dev)
-    desc = make_desc(I_lo, I_hi, r, mean_ab)
+    desc = make_desc(I_lo, I_hi, r, mean_ab, c=p_lo.shape[1])
+    g = None if guide is None else guide.struct()
+    transform = guide is not None and guide.mode == GF_GUIDE_TRANSFORM
+    if need_dparams is None:
+        need_dparams = transform
     e = _eps_tensor(eps, desc.n, dev)
+    f32 = dict(dtype=torch.float32, device=dev)
     if outs is not None:
-        dI_lo, dp_lo, dI_hi, deps = outs
+        dI_lo, dp_lo, dI_hi, deps = outs[:4]
+        dparams = outs[4] if len(outs) > 4 else None
     else:
-        f32 = dict(dtype=torch.float32, device=dev)
         dI_lo = torch.empty(I_lo.shape, **f32) if need_dI_lo else None
         dp_lo = torch.empty(p_lo.shape, **f32) if need_dp_lo else None
         dI_hi = torch.empty_like(I_hi) if need_dI_hi else None
         deps = torch.empty(e.numel(), **f32) if need_deps else None
-    _check(dict(dI_lo=dI_lo, dp_lo=dp_lo, deps=deps), torch.float32, dev)
+        dparams = None
+        if need_dparams and transform:
+            dparams = torch.empty(gf_guide_param_count(guide.c_in, desc.c, guide.hidden), **f32)
+    _check(dict(dI_lo=dI_lo, dp_lo=dp_lo, deps=deps, dparams=dparams), torch.float32, dev)
     _check(dict(dI_hi=dI_hi), I_hi.dtype, dev)
-    nbytes = gf_workspace_size(desc, 1)
+    nbytes = gf_workspace_size(desc, g, 1)
     ws = _ws(nbytes, dev, ws)
-    st = gf_backward(desc, _ptr(I_lo), _ptr(p_lo), _ptr(I_hi), _ptr(e), e.numel(), _ptr(dq),
-                     _ptr(dI_lo), _ptr(dp_lo), _ptr(dI_hi), _ptr(deps), _ptr(ws), ws.numel(),
-                     _stream(dev))
+    st = gf_backward(desc, g, _ptr(I_lo), _ptr(p_lo), _ptr(I_hi), _ptr(e), e.numel(), _ptr(dq),
+                     _ptr(dI_lo), _ptr(dp_lo), _ptr(dI_hi), _ptr(deps), _ptr(dparams), _ptr(ws),
+                     ws.numel(), _stream(dev))
     if st != GF_OK:
         raise GFError(st)
-    return dI_lo, dp_lo, dI_hi, deps
+    return dI_lo, dp_lo, dI_hi, deps, dparams
 
 
 class GuidedFilterFn(torch.autograd.Function):
     """Differentiable guided filtering layer; the backward recomputes the
-    low-res statistics from the saved inputs (nothing else is stored)."""
+    low-res statistics from the saved inputs (nothing else is stored, apart
+    from the transform guide's 24 batch statistics)."""
 
     @staticmethod
-    def forward(ctx, I_lo, p_lo, I_hi, eps, r, mean_ab):
+    def forward(ctx, I_lo, p_lo, I_hi, eps, r, mean_ab, guide, params):
         e = _eps_tensor(eps, I_lo.shape[0], I_hi.device)
-        ctx.save_for_backward(I_lo, p_lo, I_hi, e)
         ctx.r, ctx.mean_ab = r, mean_ab
         ctx.eps_is_tensor = isinstance(eps, torch.Tensor)
-        return forward(I_lo, p_lo, I_hi, e, r, mean_ab)
+        ctx.guide = guide
+        stats = None
+        if guide is not None and guide.mode == GF_GUIDE_TRANSFORM:
+            stats = torch.empty(gf_guide_stats_count(guide.c_in), dtype=torch.float32,
+                                device=I_hi.device)
+            guide = Guide(guide.mode, guide.c_in, guide.hidden, params, guide.bn_eps,
+                          guide.slope, stats, False)
+        ctx.save_for_backward(I_lo, p_lo, I_hi, e, params, stats)
+        return forward(I_lo, p_lo, I_hi, e, r, mean_ab, guide=guide)
 
     @staticmethod
     def backward(ctx, dq):
-        I_lo, p_lo, I_hi, e = ctx.saved_tensors
+        I_lo, p_lo, I_hi, e, params, stats = ctx.saved_tensors
         need = ctx.needs_input_grad
-        dI_lo, dp_lo, dI_hi, deps = backward(
+        guide = ctx.guide
+        if guide is not None and guide.mode == GF_GUIDE_TRANSFORM:
+            guide = Guide(guide.mode, guide.c_in, guide.hidden, params, guide.bn_eps,
+                          guide.slope, stats, True)
+        dI_lo, dp_lo, dI_hi, deps, dparams = backward(
             I_lo, p_lo, I_hi, e, dq.contiguous(), ctx.r, ctx.mean_ab,
             need_dI_lo=need[0], need_dp_lo=need[1], need_dI_hi=need[2],
-            need_deps=need[3] and ctx.eps_is_tensor)
+            need_deps=need[3] and ctx.eps_is_tensor, guide=guide,
+            need_dparams=len(need) > 7 and need[7])
         cast = lambda g, ref: None if g is None else g.to(ref.dtype)
-        return cast(dI_lo, I_lo), cast(dp_lo, p_lo), dI_hi, deps, None, None
+        return (cast(dI_lo, I_lo), cast(dp_lo, p_lo), dI_hi, deps, None, None, None, dparams)
 
 
-def guided_filter(I_lo, p_lo, I_hi, r=1, eps=1e-8, mean_ab=True):
+def guided_filter(I_lo, p_lo, I_hi, r=1, eps=1e-8, mean_ab=True, guide=None):
     """Autograd entry point: q = GF(I_lo, p_lo, I_hi) with radius r and eps
-    (a float, or a float32 tensor of 1 or n entries to get its gradient)."""
-    return GuidedFilterFn.apply(I_lo, p_lo, I_hi, eps, r, mean_ab)
+    (a float, or a float32 tensor of 1 or n entries to get its gradient).
+    `guide` is None (identity) or a Guide; a transform Guide's `params`
+    tensor receives its gradient."""
+    params = guide.params if guide is not None else None
+    return GuidedFilterFn.apply(I_lo, p_lo, I_hi, eps, r, mean_ab, guide, params)

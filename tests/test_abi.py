@@ -29,14 +29,14 @@ def test_status_strings():
 
 
 def test_workspace_sizes():
-    f = gf.gf_workspace_size(desc(), 0)
-    b = gf.gf_workspace_size(desc(), 1)
+    f = gf.gf_workspace_size(desc(), None, 0)
+    b = gf.gf_workspace_size(desc(), None, 1)
     lo = 2 * 3 * 64 * 96 * 4
     assert f >= 2 * lo          # Abar and bbar planes
     assert b >= lo              # Abar plus the partial planes
-    assert gf.gf_workspace_size(desc(r=-1), 0) == 0
+    assert gf.gf_workspace_size(desc(r=-1), None, 0) == 0
     for dt in (0, 1, 2):
-        assert gf.gf_workspace_size(desc(io_dtype=dt), 1) > 0
+        assert gf.gf_workspace_size(desc(io_dtype=dt), None, 1) > 0
 
 
 FAKE = 0x10000  # aligned, never dereferenced: every case below fails validation
@@ -57,31 +57,81 @@ FAKE = 0x10000  # aligned, never dereferenced: every case below fails validation
 ])
 def test_invalid_descriptions(kw, code):
     d = desc(**kw)
-    st = gf.gf_forward(d, FAKE, FAKE, FAKE, FAKE, 1, FAKE, FAKE, 1 << 40, None)
+    st = gf.gf_forward(d, None, FAKE, FAKE, FAKE, FAKE, 1, FAKE, FAKE, 1 << 40, None)
     assert st == code, gf.gf_last_error_detail()
     assert gf.gf_last_error_detail() != ""
-    st = gf.gf_backward(d, FAKE, FAKE, FAKE, FAKE, 1, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE,
-                        1 << 40, None)
+    st = gf.gf_backward(d, None, FAKE, FAKE, FAKE, FAKE, 1, FAKE, FAKE, FAKE, FAKE, FAKE, None,
+                        FAKE, 1 << 40, None)
     assert st == code
 
 
 def test_invalid_pointers_and_workspace():
     d = desc()
     big = 1 << 40
-    assert gf.gf_forward(d, None, FAKE, FAKE, FAKE, 1, FAKE, FAKE, big, None) == gf.GF_ERR_INVALID_ARG
-    assert gf.gf_forward(d, FAKE, FAKE, FAKE, None, 1, FAKE, FAKE, big, None) == gf.GF_ERR_INVALID_ARG
-    assert gf.gf_forward(d, FAKE, FAKE, FAKE, FAKE, 3, FAKE, FAKE, big, None) == gf.GF_ERR_INVALID_ARG
-    assert gf.gf_forward(d, FAKE + 4, FAKE, FAKE, FAKE, 1, FAKE, FAKE, big, None) == gf.GF_ERR_INVALID_ARG
-    need = gf.gf_workspace_size(d, 0)
-    assert gf.gf_forward(d, FAKE, FAKE, FAKE, FAKE, 1, FAKE, FAKE, need - 1, None) == gf.GF_ERR_WORKSPACE
-    assert gf.gf_forward(d, FAKE, FAKE, FAKE, FAKE, 1, FAKE, None, need, None) == gf.GF_ERR_WORKSPACE
-    needb = gf.gf_workspace_size(d, 1)
-    assert gf.gf_backward(d, FAKE, FAKE, FAKE, FAKE, 2, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE,
-                          needb - 1, None) == gf.GF_ERR_WORKSPACE
-    assert gf.gf_backward(d, FAKE, FAKE, FAKE, FAKE, 2, None, FAKE, FAKE, FAKE, FAKE, FAKE,
-                          needb, None) == gf.GF_ERR_INVALID_ARG
+    assert gf.gf_forward(d, None, None, FAKE, FAKE, FAKE, 1, FAKE, FAKE, big, None) == gf.GF_ERR_INVALID_ARG
+    assert gf.gf_forward(d, None, FAKE, FAKE, FAKE, None, 1, FAKE, FAKE, big, None) == gf.GF_ERR_INVALID_ARG
+    assert gf.gf_forward(d, None, FAKE, FAKE, FAKE, FAKE, 3, FAKE, FAKE, big, None) == gf.GF_ERR_INVALID_ARG
+    assert gf.gf_forward(d, None, FAKE + 4, FAKE, FAKE, FAKE, 1, FAKE, FAKE, big, None) == gf.GF_ERR_INVALID_ARG
+    need = gf.gf_workspace_size(d, None, 0)
+    assert gf.gf_forward(d, None, FAKE, FAKE, FAKE, FAKE, 1, FAKE, FAKE, need - 1, None) == gf.GF_ERR_WORKSPACE
+    assert gf.gf_forward(d, None, FAKE, FAKE, FAKE, FAKE, 1, FAKE, None, need, None) == gf.GF_ERR_WORKSPACE
+    needb = gf.gf_workspace_size(d, None, 1)
+    assert gf.gf_backward(d, None, FAKE, FAKE, FAKE, FAKE, 2, FAKE, FAKE, FAKE, FAKE, FAKE, None,
+                          FAKE, needb - 1, None) == gf.GF_ERR_WORKSPACE
+    assert gf.gf_backward(d, None, FAKE, FAKE, FAKE, FAKE, 2, None, FAKE, FAKE, FAKE, FAKE, None,
+                          FAKE, needb, None) == gf.GF_ERR_INVALID_ARG
+    # dparams belongs to the transform guide only
+    assert gf.gf_backward(d, None, FAKE, FAKE, FAKE, FAKE, 2, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE,
+                          FAKE, needb, None) == gf.GF_ERR_INVALID_ARG
 
 
 def test_profile_read_empty():
     gf.gf_profile_enable(False)
     assert gf.gf_profile_read() == {}
+
+
+def guide(**kw):
+    g = dict(mode=gf.GF_GUIDE_TRANSFORM, c_in=3, hidden=15, bn_eps=1e-5, slope=0.2, params=FAKE,
+             stats=None, use_stats=0)
+    g.update(kw)
+    return gf.gf_guide_t(*[g[k] for k, _ in gf.gf_guide_t._fields_])
+
+
+def test_guide_counts():
+    # W1 15x3, W2 3x15, b2 3, lam, mu, gamma 15, beta 15
+    assert gf.gf_guide_param_count(3, 3, 15) == 45 + 45 + 3 + 2 + 30
+    assert gf.gf_guide_param_count(3, 3, 0) == 0
+    assert gf.gf_guide_stats_count(3) == 2 * (3 + 9)
+
+
+def test_guided_workspace_grows():
+    d = desc()
+    base = gf.gf_workspace_size(d, None, 1)
+    grey = gf.gf_workspace_size(d, guide(mode=gf.GF_GUIDE_GREY, c_in=1), 1)
+    tr = gf.gf_workspace_size(d, guide(), 1)
+    hi_plane = 2 * 3 * 256 * 384 * 4
+    assert grey >= base + 2 * hi_plane     # G_h and dG_h in float
+    assert tr >= grey
+    assert gf.gf_workspace_size(d, guide(), 0) > 0
+
+
+@pytest.mark.parametrize("kw, dkw, code", [
+    (dict(mode=5), {}, gf.GF_ERR_INVALID_ARG),
+    (dict(mode=gf.GF_GUIDE_GREY, c_in=5), {}, gf.GF_ERR_UNSUPPORTED),
+    (dict(mode=gf.GF_GUIDE_GREY, c_in=1), dict(c=5), gf.GF_ERR_UNSUPPORTED),
+    (dict(c_in=4), {}, gf.GF_ERR_UNSUPPORTED),
+    (dict(hidden=17), {}, gf.GF_ERR_UNSUPPORTED),
+    (dict(hidden=0), {}, gf.GF_ERR_UNSUPPORTED),
+    (dict(params=None), {}, gf.GF_ERR_INVALID_ARG),
+    (dict(use_stats=1), {}, gf.GF_ERR_INVALID_ARG),
+    (dict(bn_eps=-1.0), {}, gf.GF_ERR_INVALID_ARG),
+])
+def test_invalid_guides(kw, dkw, code):
+    d = desc(**dkw)
+    g = guide(**kw)
+    assert gf.gf_workspace_size(d, g, 1) == 0
+    st = gf.gf_forward(d, g, FAKE, FAKE, FAKE, FAKE, 1, FAKE, FAKE, 1 << 40, None)
+    assert st == code, gf.gf_last_error_detail()
+    st = gf.gf_backward(d, g, FAKE, FAKE, FAKE, FAKE, 1, FAKE, FAKE, FAKE, FAKE, FAKE, None,
+                        FAKE, 1 << 40, None)
+    assert st == code, gf.gf_last_error_detail()

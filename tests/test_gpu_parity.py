@@ -43,7 +43,7 @@ def run_both(prob, mean_ab=True, eps=None, backward=True):
     q = gf.forward(d["I_lo"], d["p_lo"], d["I_hi"], eps, prob["r"], mean_ab)
     out = {"q": q}
     if backward:
-        dI_lo, dp_lo, dI_hi, deps = gf.backward(d["I_lo"], d["p_lo"], d["I_hi"], eps, d["dq"],
+        dI_lo, dp_lo, dI_hi, deps, _ = gf.backward(d["I_lo"], d["p_lo"], d["I_hi"], eps, d["dq"],
                                                 prob["r"], mean_ab)
         out.update(dI_lo=dI_lo, dp_lo=dp_lo, dI_hi=dI_hi, deps=deps)
     torch.cuda.synchronize()
@@ -156,7 +156,7 @@ def test_bitwise_deterministic():
         runs.append([q, *g])
     torch.cuda.synchronize()
     for a, b in zip(*runs):
-        assert torch.equal(a, b)
+        assert (a is None and b is None) or torch.equal(a, b)
 
 
 def test_outputs_stay_in_bounds():
