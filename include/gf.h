@@ -150,6 +150,70 @@ int32_t gf_backward(const gf_desc_t *desc, const gf_guide_t *guide,
                     float *dI_lo, float *dp_lo, void *dI_hi, float *deps,
                     float *dparams, void *ws, size_t ws_bytes, void *stream);
 
+/* ------------------------------------------------------------- batched
+ * Many independent problems of different sizes, factors, radii and eps
+ * (identity guide, one io_dtype for all) run as one launch per phase and
+ * launch class (the radius for the low-res phases, the factor for the
+ * high-res ones) instead of one launch set per problem.  Each item follows
+ * gf_forward / gf_backward exactly (same kernels, same results).
+ *
+ * gf_plan_create validates the items on the host, derives every launch
+ * shape, and uploads the per-item launch tables to the current device (it
+ * allocates: call it outside stream capture).  The item pointers are
+ * stored in the plan: every gf_batched call reads and writes those
+ * buffers.  gf_batched allocates nothing and does not synchronise. */
+typedef struct {
+  gf_desc_t d;          /* the item's problem (d.io_dtype equal for all items) */
+  float eps;            /* its eps (>= 0), one for its d.n images              */
+  const void *I_lo, *p_lo, *I_hi;   /* inputs, as for gf_forward               */
+  void *q_hi;           /* forward output; NULL if the plan runs no forward    */
+  const void *dq_hi;    /* backward input; NULL if the plan runs no backward   */
+  float *dI_lo, *dp_lo; /* backward outputs, each may be NULL                  */
+  void *dI_hi;
+  float *deps;          /* one float: d<q, dq>/d eps summed over its images    */
+} gf_item_t;
+
+/* gf_batched modes: forward, backward, or both (the coefficients are then
+ * computed once); GF_RUN_GRAPH additionally records the launches into a
+ * HIP graph on the first call for a (mode, workspace) pair and replays it
+ * afterwards (the first such call instantiates the graph on the host). */
+enum { GF_RUN_FORWARD = 1, GF_RUN_BACKWARD = 2, GF_RUN_GRAPH = 4 };
+
+typedef struct gf_plan gf_plan_t;
+
+int32_t gf_plan_create(const gf_item_t *items, int32_t count, gf_plan_t **plan);
+/* Workspace bytes gf_batched needs (every mode); 0 for NULL. */
+size_t gf_plan_workspace_size(const gf_plan_t *plan);
+int32_t gf_batched(gf_plan_t *plan, int32_t mode, void *ws, size_t ws_bytes,
+                   void *stream);
+/* Frees the plan's device tables and graphs (no call may be in flight). */
+void gf_plan_destroy(gf_plan_t *plan);
+
+/* ------------------------------------------------------------- autotuner
+ * Times the candidate launch shapes of the four filter kernels (rows per
+ * low-res walker wave, high-res rows per apply thread, low-res rows per
+ * backward high-res block) on the caller's buffers, `iters` launches each,
+ * and keeps the fastest per kernel in a process-wide table keyed by
+ * (io_dtype, factor, radius, guide mode, mean_ab).  Later plans for that
+ * key (gf_forward, gf_backward, gf_plan_create) use the table.  Arguments
+ * as for gf_forward plus gf_backward; every output is overwritten.  Shapes
+ * whose workspace exceeds ws_bytes are skipped.  Synchronises the stream;
+ * uses the kernel timing of gf_profile_enable (clears its records and
+ * leaves it off). */
+int32_t gf_autotune(const gf_desc_t *desc, const gf_guide_t *guide,
+                    const void *I_lo, const void *p_lo, const void *I_hi,
+                    const float *eps, int32_t eps_count, void *q_hi,
+                    const void *dq_hi, float *dI_lo, float *dp_lo, void *dI_hi,
+                    float *deps, float *dparams, void *ws, size_t ws_bytes,
+                    int32_t iters, void *stream);
+/* The table as text, one entry per line:
+ *   dtype S r guide mean_ab : coef_rows lo_rows apply_rows bwd_rows
+ * gf_tune_export writes up to cap bytes (NUL-terminated) and returns the
+ * length of the full text; gf_tune_import adds the entries of such a text
+ * (GF_ERR_INVALID_ARG on a malformed line, nothing imported then). */
+size_t gf_tune_export(char *buf, size_t cap);
+int32_t gf_tune_import(const char *text);
+
 /* Human-readable name of a status code (static string). */
 const char *gf_status_string(int32_t status);
 

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <stdio.h>
 #include <string.h>
 
 #include <stdlib.h>
@@ -46,6 +47,8 @@ int env_int(const char* name, int dflt) {
 }
 
 }  // namespace
+
+int set_error(int code, const std::string& why) { return fail(code, why); }
 
 int make_plan(const gf_desc_t* d, const gf_guide_t* g, Plan* p, const char** why) {
   static thread_local std::string msg;
@@ -120,32 +123,38 @@ int make_plan(const gf_desc_t* d, const gf_guide_t* g, Plan* p, const char** why
   const int hal = q.mean_ab ? 2 * r : r;  // halo of the coefficient walker
   const size_t KRc = walker_ring_rows(r, kWalkBlock, kCoefRingPow2Max);
   const size_t KRb = walker_ring_rows(r, kWalkBlock, kBwdLoRingPow2Max);
-  // rows per wave: long enough to amortise the 2*halo warm-up rows
-  q.coTR = r <= 2 ? 32 : 64;
-  if (env_int("GF_LO_ROWS", 0) > 0) q.coTR = env_int("GF_LO_ROWS", 0);
+  // Launch shapes: the tuned entry for this key if the autotuner (or an
+  // import) made one, else the defaults below; environment overrides win
+  // (tuning experiments).
+  //  - rows per low-res walker wave: long enough to amortise the 2*halo
+  //    warm-up rows
+  //  - high-res rows per apply thread: short walks keep DRAM streams
+  //    sequential (8 measured best on MI355X for the 4 x 3 x 2048 x 3072
+  //    workload): two low-res row blocks at S = 4, one at S = 8
+  //  - low-res rows per backward high-res block: 2 (short walks stream
+  //    best; the partial planes' extra border rows cost less)
+  TuneVal tv{r <= 2 ? 32 : 64, r <= 2 ? 32 : 64, S >= 8 ? S : 8, 2};
+  TuneVal tuned;
+  if (tune_lookup(TuneKey{d->io_dtype, S, r, gmode, d->mean_ab}, &tuned)) tv = tuned;
+  if (env_int("GF_LO_ROWS", 0) > 0) tv.coTR = tv.loTR = env_int("GF_LO_ROWS", 0);
+  if (env_int("GF_APPLY_ROWS", 0) > 0) tv.RB = env_int("GF_APPLY_ROWS", 0);
+  if (env_int("GF_BWD_BH", 0) >= 2) tv.bh = env_int("GF_BWD_BH", 0);
+  if (tv.coTR < 1 || tv.loTR < 1 || tv.RB < 1 || tv.bh < 2)
+    return bad(GF_ERR_INVALID_ARG, "invalid launch shape");
+  q.coTR = tv.coTR;
   q.co_nx = (q.w + (64 - 2 * hal) - 1) / (64 - 2 * hal);
   q.co_ny = (q.h + q.coTR - 1) / q.coTR;
   q.coLDS = 64 * (16 * KRc + 24 * kWalkBlock);  // (g,p), (A,b) rings + row buffers
-  q.loTR = q.coTR;
+  q.loTR = tv.loTR;
   q.lo_nx = (q.w + (64 - 4 * r) - 1) / (64 - 4 * r);
   q.lo_ny = (q.h + q.loTR - 1) / q.loTR;
   q.loLDS = 64 * (32 * KRb + 40 * kWalkBlock);  // input and X rings + row buffers
 
-  // Launch-shape overrides (tuning experiments): GF_APPLY_ROWS = high-res rows
-  // per apply thread, GF_BWD_BH = low-res rows per backward high-res block.
-  const int rows_env = env_int("GF_APPLY_ROWS", 0), bh_env = env_int("GF_BWD_BH", 0);
-  // Short walks keep DRAM streams sequential (8 rows per thread measured
-  // best on MI355X for the 4 x 3 x 2048 x 3072 workload): two low-res row
-  // blocks at S = 4, one at S = 8.
-  q.RB = S >= 8 ? S : 8;
-  if (rows_env > 0) q.RB = ((rows_env + S - 1) / S) * S;
+  q.RB = ((tv.RB + S - 1) / S) * S;  // whole low-res row blocks
   q.nrb = (q.H + q.RB - 1) / q.RB;
   q.nxv = q.W / q.VEC;
 
-  // Backward high-res blocks of 2 low-res rows (2 S high-res rows): short
-  // walks stream best; the partial planes' extra border rows cost less.
-  q.bh = 2;
-  if (bh_env >= 2) q.bh = bh_env;
+  q.bh = tv.bh;
   q.tw = 64 * q.VEC / S;
   q.nby = (q.h + q.bh - 1) / q.bh;
   q.nbx = (q.W + 64 * q.VEC - 1) / (64 * q.VEC);
@@ -254,7 +263,11 @@ void prof_clear() {
 }
 }  // namespace
 
+thread_local bool g_prof_muted = false;
+void prof_mute(bool on) { g_prof_muted = on; }
+
 void prof_begin(const char* name, hipStream_t s) {
+  if (g_prof_muted) return;
   std::lock_guard<std::mutex> lk(g_prof_mu);
   if (!g_prof_on) return;
   hipEvent_t ev;
@@ -265,6 +278,7 @@ void prof_begin(const char* name, hipStream_t s) {
 }
 
 void prof_end(hipStream_t s) {
+  if (g_prof_muted) return;
   std::lock_guard<std::mutex> lk(g_prof_mu);
   if (!g_prof_on || !g_pending_ev) return;
   hipEvent_t ev;
@@ -403,6 +417,185 @@ int32_t gf_profile_read(char (*names)[48], double* ms, int32_t* launches, int32_
     if (launches) launches[k] = cnt[k];
   }
   return m;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ tile-shape table and autotuner
+
+namespace gf {
+namespace {
+std::mutex g_tune_mu;
+std::vector<std::pair<TuneKey, TuneVal>> g_tune;
+
+bool same_key(const TuneKey& a, const TuneKey& b) {
+  return a.dtype == b.dtype && a.S == b.S && a.r == b.r && a.gmode == b.gmode &&
+         a.mean_ab == b.mean_ab;
+}
+
+bool tune_erase(const TuneKey& k) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (size_t i = 0; i < g_tune.size(); ++i)
+    if (same_key(g_tune[i].first, k)) {
+      g_tune.erase(g_tune.begin() + i);
+      return true;
+    }
+  return false;
+}
+}  // namespace
+
+bool tune_lookup(const TuneKey& k, TuneVal* v) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (auto& e : g_tune)
+    if (same_key(e.first, k)) {
+      *v = e.second;
+      return true;
+    }
+  return false;
+}
+
+void tune_store(const TuneKey& k, const TuneVal& v) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (auto& e : g_tune)
+    if (same_key(e.first, k)) {
+      e.second = v;
+      return;
+    }
+  g_tune.push_back({k, v});
+}
+}  // namespace gf
+
+extern "C" {
+
+size_t gf_tune_export(char* buf, size_t cap) {
+  std::string out;
+  {
+    std::lock_guard<std::mutex> lk(gf::g_tune_mu);
+    for (auto& e : gf::g_tune) {
+      char line[160];
+      snprintf(line, sizeof line, "%d %d %d %d %d : %d %d %d %d\n", e.first.dtype, e.first.S,
+               e.first.r, e.first.gmode, e.first.mean_ab, e.second.coTR, e.second.loTR,
+               e.second.RB, e.second.bh);
+      out += line;
+    }
+  }
+  if (buf && cap > 0) {
+    const size_t n = std::min(cap - 1, out.size());
+    memcpy(buf, out.data(), n);
+    buf[n] = '\0';
+  }
+  return out.size();
+}
+
+int32_t gf_tune_import(const char* text) {
+  gf::g_detail.clear();
+  if (!text) return fail(GF_ERR_INVALID_ARG, "text is NULL");
+  std::vector<std::pair<gf::TuneKey, gf::TuneVal>> parsed;
+  const char* p = text;
+  int lineno = 0;
+  while (*p) {
+    const char* e = strchr(p, '\n');
+    std::string line(p, e ? (size_t)(e - p) : strlen(p));
+    p = e ? e + 1 : p + line.size();
+    ++lineno;
+    if (line.find_first_not_of(" \t\r") == std::string::npos) continue;
+    gf::TuneKey k;
+    gf::TuneVal v;
+    char colon = 0;
+    int used = 0;
+    if (sscanf(line.c_str(), " %d %d %d %d %d %c %d %d %d %d %n", &k.dtype, &k.S, &k.r, &k.gmode,
+               &k.mean_ab, &colon, &v.coTR, &v.loTR, &v.RB, &v.bh, &used) != 10 ||
+        colon != ':' || line.find_first_not_of(" \t\r", used) != std::string::npos ||
+        v.coTR < 1 || v.loTR < 1 || v.RB < 1 || v.bh < 2)
+      return fail(GF_ERR_INVALID_ARG, "malformed tuning line " + std::to_string(lineno));
+    parsed.push_back({k, v});
+  }
+  for (auto& kv : parsed) gf::tune_store(kv.first, kv.second);
+  return GF_OK;
+}
+
+int32_t gf_autotune(const gf_desc_t* desc, const gf_guide_t* guide, const void* I_lo,
+                    const void* p_lo, const void* I_hi, const float* eps, int32_t eps_count,
+                    void* q_hi, const void* dq_hi, float* dI_lo, float* dp_lo, void* dI_hi,
+                    float* deps, float* dparams, void* ws, size_t ws_bytes, int32_t iters,
+                    void* stream) {
+  gf::g_detail.clear();
+  gf::Plan p0;
+  const char* why = nullptr;
+  int st = gf::make_plan(desc, guide, &p0, &why);
+  if (st != GF_OK) return fail(st, why);
+  if (iters < 1 || iters > 1000) return fail(GF_ERR_INVALID_ARG, "iters must be 1..1000");
+  const gf::TuneKey key{desc->io_dtype, p0.S, p0.r, p0.gmode, desc->mean_ab};
+  gf::TuneVal saved;
+  const bool had = gf::tune_lookup(key, &saved);
+  // candidates, tried index by index (kernel k takes its k-th list)
+  const int lo_rows[] = {16, 32, 64, 128};
+  const int apply_rows[] = {4, 8, 16, 32};
+  const int bwd_rows[] = {2, 4, 8, 2};
+  const char* names[4] = {"gf_coef", "gf_bwd_lo", "gf_apply", "gf_bwd_hi"};
+  double best[4] = {1e30, 1e30, 1e30, 1e30};
+  gf::TuneVal pick{p0.coTR, p0.loTR, p0.RB, p0.bh};
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  auto restore = [&]() {
+    if (had)
+      gf::tune_store(key, saved);
+    else
+      gf::tune_erase(key);
+  };
+  for (int i = 0; i < 4; ++i) {
+    const gf::TuneVal v{lo_rows[i], lo_rows[i], apply_rows[i], bwd_rows[i]};
+    gf::tune_store(key, v);
+    gf::Plan p;
+    if (gf::make_plan(desc, guide, &p, &why) != GF_OK || p.ws_bwd > ws_bytes ||
+        p.ws_fwd > ws_bytes)
+      continue;
+    auto step = [&]() {
+      int a = gf_forward(desc, guide, I_lo, p_lo, I_hi, eps, eps_count, q_hi, ws, ws_bytes,
+                         stream);
+      if (a != GF_OK) return a;
+      return gf_backward(desc, guide, I_lo, p_lo, I_hi, eps, eps_count, dq_hi, dI_lo, dp_lo,
+                         dI_hi, deps, dparams, ws, ws_bytes, stream);
+    };
+    int a = step();  // warm-up
+    if (a != GF_OK) {
+      restore();
+      return a;
+    }
+    gf_profile_enable(1);
+    for (int it = 0; it < iters && a == GF_OK; ++it) a = step();
+    char nm[16][48];
+    double ms[16];
+    int32_t cnt[16];
+    const int m = gf_profile_read(nm, ms, cnt, 16);
+    gf_profile_enable(0);
+    if (a != GF_OK) {
+      restore();
+      return a;
+    }
+    for (int k = 0; k < 4; ++k)
+      for (int j = 0; j < m && j < 16; ++j)
+        if (strcmp(nm[j], names[k]) == 0 && cnt[j] > 0) {
+          const double avg = ms[j] / cnt[j];
+          if (avg < best[k]) {
+            best[k] = avg;
+            if (k == 0) pick.coTR = v.coTR;
+            if (k == 1) pick.loTR = v.loTR;
+            if (k == 2) pick.RB = v.RB;
+            if (k == 3) pick.bh = v.bh;
+          }
+        }
+  }
+  if (hipStreamSynchronize(s) != hipSuccess) {
+    restore();
+    return fail(GF_ERR_HIP, "stream synchronisation failed");
+  }
+  gf::tune_store(key, pick);
+  gf::Plan p;
+  if (gf::make_plan(desc, guide, &p, &why) != GF_OK || p.ws_bwd > ws_bytes) {
+    restore();
+    return fail(GF_ERR_WORKSPACE, "no tuned shape fits the workspace");
+  }
+  return GF_OK;
 }
 
 }  // extern "C"

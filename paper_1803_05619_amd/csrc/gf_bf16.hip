@@ -19,4 +19,8 @@ hipError_t launch_backward_guided_bf16(const Plan& p, const BwdArgs& a, hipStrea
   return backward_guided_t<bf16>(p, a, s);
 }
 
+hipError_t launch_batched_bf16(const BatchLaunch& b, int mode, char* ws, hipStream_t s) {
+  return batched_t<bf16>(b, mode, ws, s);
+}
+
 }  // namespace gf

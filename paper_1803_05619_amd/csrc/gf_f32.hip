@@ -19,4 +19,8 @@ hipError_t launch_backward_guided_f32(const Plan& p, const BwdArgs& a, hipStream
   return backward_guided_t<float>(p, a, s);
 }
 
+hipError_t launch_batched_f32(const BatchLaunch& b, int mode, char* ws, hipStream_t s) {
+  return batched_t<float>(b, mode, ws, s);
+}
+
 }  // namespace gf

@@ -6,6 +6,9 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <string>
+#include <vector>
+
 #include "../../include/gf.h"
 
 namespace gf {
@@ -83,6 +86,119 @@ struct BwdArgs {
   void* dI_hi;
   char* ws;
 };
+
+// Kernel arguments of the four filter kernels (one problem each).
+struct CoefArgs {
+  const void* I_lo;
+  const void* p_lo;
+  const float* eps;
+  int eps_count, c, h, w, TR;
+  float* abar;  // [planes, h, w]
+  float* bbar;  // [planes, h, w] or null
+};
+
+struct ApplyArgs {
+  const void* I_hi;
+  void* q;
+  const float* abar;
+  const float* bbar;
+  int h, w, H, W, RB, nrb, nxv;
+  long long total;
+  int xcd;  // 1: XCD-aware workgroup order
+};
+
+struct BwdHiArgs {
+  const void* I_hi;
+  const void* dq;
+  void* dI_hi;  // may be null
+  const float* abar;
+  float* U;     // per-block partial planes
+  int h, w, H, W, bh, tw, nby, nbx;
+  int xcd;  // 1: XCD-aware workgroup order
+};
+
+struct BwdLoArgs {
+  const void* I_lo;
+  const void* p_lo;
+  const float* eps;
+  int eps_count, c;
+  const float* U;
+  int bh, tw, nby, nbx;
+  int h, w, TR;
+  float* dI_lo;     // may be null
+  float* dp_lo;     // may be null
+  float* eps_part;  // [planes][pny][pnx]: one partial per strip segment
+  int pnx, pny;     // strips and row segments per plane
+};
+
+// ------------------------------------------------------------ batched launches
+// One launch per phase and launch class covers the tiles of many problems:
+// the items of a class are laid out in device memory as
+//   base[count] (first tile of each item, ascending, base[0] = 0)
+//   MultiItem<Args>[count]
+// and workgroup t (grid-stride when the grid is smaller than the tile count)
+// finds its item by a wave ballot over base[].  Workspace pointers inside
+// the item arguments are stored as (offset + 1) and rebased on the device
+// against the workspace passed at launch (0 stays null).
+template <typename Args>
+struct MultiItem {
+  Args a;
+  int nx, ny;  // tiles along x and y; the rest of the tile index is the plane
+  long long base;
+};
+
+struct EpsItem {
+  const float* part;  // workspace-relative (offset + 1)
+  long long count;
+  float* deps;
+};
+
+struct MultiLaunch {
+  const long long* base;
+  const void* items;
+  int count;
+  long long total;  // tiles
+  char* ws;         // set per launch
+  int grid;         // workgroups launched (<= total)
+};
+
+enum { kClassCoef = 0, kClassApply = 1, kClassBwdHi = 2, kClassBwdLo = 3 };
+
+struct BatchClass {
+  int kind;
+  int S, VEC;     // high-res classes
+  int R, MAB;     // low-res classes
+  size_t lds;     // dynamic LDS bytes (low-res classes)
+  MultiLaunch m;
+};
+
+struct BatchLaunch {
+  std::vector<BatchClass> coef, apply, bwd_hi, bwd_lo;
+  const EpsItem* eps_items;  // device
+  int eps_count;             // items with a deps output
+};
+
+hipError_t launch_batched_f32(const BatchLaunch& b, int mode, char* ws, hipStream_t s);
+hipError_t launch_batched_f16(const BatchLaunch& b, int mode, char* ws, hipStream_t s);
+hipError_t launch_batched_bf16(const BatchLaunch& b, int mode, char* ws, hipStream_t s);
+
+// ------------------------------------------------------------ tile-shape table
+// Launch shapes per (io dtype, factor S, radius, guide mode, mean_ab),
+// filled by the autotuner (or imported); make_plan uses an entry when one
+// exists, else its defaults.
+struct TuneKey {
+  int dtype, S, r, gmode, mean_ab;
+};
+struct TuneVal {
+  int coTR, loTR, RB, bh;
+};
+bool tune_lookup(const TuneKey& k, TuneVal* v);
+void tune_store(const TuneKey& k, const TuneVal& v);
+
+// Shared by the C-ABI files: sets the thread's error detail, returns code.
+int set_error(int code, const std::string& why);
+// Profiling hooks are muted while a stream is being captured into a graph.
+void prof_mute(bool on);
 
 // One pair of launchers per image I/O type (gf_f32.hip, gf_f16.hip,
 // gf_bf16.hip); gf_api.cpp picks by desc->io_dtype.

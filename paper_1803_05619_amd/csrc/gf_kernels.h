@@ -265,21 +265,15 @@ __device__ __forceinline__ WinStats window_stats(const float4* cs, int lane,
 
 // ------------------------------------------------------------ forward: low-res
 
-struct CoefArgs {
-  const void* I_lo;
-  const void* p_lo;
-  const float* eps;
-  int eps_count, c, h, w, TR;
-  float* abar;  // [planes, h, w]
-  float* bbar;  // [planes, h, w] or null
-};
+
 
 // Abar, bbar (A, b when MAB is false) of a strip of 64 - 2(R + R_ab) output
 // columns x TR output rows.  The guide and input are recentred by their
 // values at the segment centre (variance and covariance are shift
 // invariant; b is formed from the actual means).
 template <typename TG, typename TP, int R, bool MAB>
-__global__ __launch_bounds__(64) void coef_kernel(CoefArgs a) {
+__device__ __forceinline__ void coef_body(const CoefArgs& a, const int bx, const int by,
+                                          const int plane) {
   constexpr int K = 2 * R + 1;
   constexpr int HB = MAB ? R : 0;
   constexpr int HAL = R + HB;
@@ -291,14 +285,13 @@ __global__ __launch_bounds__(64) void coef_kernel(CoefArgs a) {
   float2* ab = reinterpret_cast<float2*>(cs + kPF * 64);  // [KR][64] (A, b)
   float2* vs = ab + KR * 64;                               // [kPF][64] column sums of (A, b)
   const int lane = threadIdx.x;
-  const int plane = blockIdx.z;
   const float e = a.eps[a.eps_count == 1 ? 0 : plane / a.c];
   const int h = a.h, w = a.w;
-  const int j0 = blockIdx.x * TWo;
+  const int j0 = bx * TWo;
   const int jl = j0 - HAL;  // image column of lane 0
   const int j = jl + lane;
   const bool colin = (unsigned)j < (unsigned)w;
-  const int i0 = blockIdx.y * a.TR, i1 = min(i0 + a.TR, h);
+  const int i0 = by * a.TR, i1 = min(i0 + a.TR, h);
   const size_t pofs = (size_t)plane * h * w;
   const TG* G = reinterpret_cast<const TG*>(a.I_lo) + pofs;
   const TP* P = reinterpret_cast<const TP*>(a.p_lo) + pofs;
@@ -429,17 +422,14 @@ __global__ __launch_bounds__(64) void coef_kernel(CoefArgs a) {
   }
 }
 
+template <typename TG, typename TP, int R, bool MAB>
+__global__ __launch_bounds__(64) void coef_kernel(CoefArgs a) {
+  coef_body<TG, TP, R, MAB>(a, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
 // ------------------------------------------------------------ forward: high-res
 
-struct ApplyArgs {
-  const void* I_hi;
-  void* q;
-  const float* abar;
-  const float* bbar;
-  int h, w, H, W, RB, nrb, nxv;
-  long long total;
-  int xcd;  // 1: XCD-aware workgroup order
-};
+
 
 // Horizontally interpolated low-res row `i` (clamped) at the VEC columns of
 // this thread.
@@ -464,8 +454,8 @@ __device__ __forceinline__ void hrow(const float* L, int i, int h, int w, const 
 // flight (its loads are issued after the low-res tap loads of block i, so
 // waiting for those does not wait for it).
 template <typename TG, typename TQ, int S, int VEC>
-__global__ __launch_bounds__(256) void apply_kernel(ApplyArgs a) {
-  const long long t = xcd_order(blockIdx.x, gridDim.x, a.xcd) * 256 + threadIdx.x;
+__device__ __forceinline__ void apply_body(const ApplyArgs& a, const long long blk) {
+  const long long t = blk * 256 + threadIdx.x;
   if (t >= a.total) return;
   const int xv = (int)(t % a.nxv);
   const long long rest = t / a.nxv;
@@ -542,17 +532,14 @@ __global__ __launch_bounds__(256) void apply_kernel(ApplyArgs a) {
   }
 }
 
+template <typename TG, typename TQ, int S, int VEC>
+__global__ __launch_bounds__(256) void apply_kernel(ApplyArgs a) {
+  apply_body<TG, TQ, S, VEC>(a, xcd_order(blockIdx.x, gridDim.x, a.xcd));
+}
+
 // ------------------------------------------------------------ backward: high-res
 
-struct BwdHiArgs {
-  const void* I_hi;
-  const void* dq;
-  void* dI_hi;  // may be null
-  const float* abar;
-  float* U;     // per-block partial planes
-  int h, w, H, W, bh, tw, nby, nbx;
-  int xcd;  // 1: XCD-aware workgroup order
-};
+
 
 // One wave per block of bh low-res rows (S*bh high-res rows) x 64*VEC
 // high-res columns.  The block writes the transposed-bilinear contributions
@@ -570,16 +557,13 @@ struct BwdHiArgs {
 // one lane shuffle each; otherwise (VEC = 1 fallback) through LDS.
 // Loads of row block i+1 are issued before block i is computed.
 template <typename TG, typename TD, typename TO, int S, int VEC>
-__global__ __launch_bounds__(64) void bwd_hi_kernel(BwdHiArgs a) {
+__device__ __forceinline__ void bwd_hi_body(const BwdHiArgs& a, const int bx, const int by,
+                                            const int plane) {
   constexpr int TWH = 64 * VEC;  // high-res columns per block
   constexpr bool REG = (VEC % S) == 0;
   constexpr int NB = REG ? VEC / S : 1;  // low-res columns per lane
   __shared__ float sR[REG ? 1 : 2][REG ? 1 : TWH];
   const int lane = threadIdx.x;
-  const long long nwg = (long long)gridDim.x * gridDim.y * gridDim.z;
-  const long long lin = xcd_order(blockIdx.x + (long long)gridDim.x * (blockIdx.y + (long long)gridDim.y * blockIdx.z), nwg, a.xcd);
-  const int bx = (int)(lin % gridDim.x), by = (int)((lin / gridDim.x) % gridDim.y),
-            plane = (int)(lin / ((long long)gridDim.x * gridDim.y));
   const int h = a.h, w = a.w, W = a.W, bh = a.bh, tw = a.tw;
   const int X_a = bx * TWH;
   const int x0 = X_a + lane * VEC;
@@ -792,20 +776,19 @@ __global__ __launch_bounds__(64) void bwd_hi_kernel(BwdHiArgs a) {
   flush(cA, cB, i_b - i_a + 1);  // row i_b (contributions of the last rows)
 }
 
+template <typename TG, typename TD, typename TO, int S, int VEC>
+__global__ __launch_bounds__(64) void bwd_hi_kernel(BwdHiArgs a) {
+  const long long nwg = (long long)gridDim.x * gridDim.y * gridDim.z;
+  const long long lin = xcd_order(
+      blockIdx.x + (long long)gridDim.x * (blockIdx.y + (long long)gridDim.y * blockIdx.z), nwg,
+      a.xcd);
+  bwd_hi_body<TG, TD, TO, S, VEC>(a, (int)(lin % gridDim.x), (int)((lin / gridDim.x) % gridDim.y),
+                                  (int)(lin / ((long long)gridDim.x * gridDim.y)));
+}
+
 // ------------------------------------------------------------ backward: low-res
 
-struct BwdLoArgs {
-  const void* I_lo;
-  const void* p_lo;
-  const float* eps;
-  int eps_count, c;
-  const float* U;
-  int bh, tw, nby, nbx;
-  int h, w, TR;
-  float* dI_lo;     // may be null
-  float* dp_lo;     // may be null
-  float* eps_part;  // [planes][gridDim.y][gridDim.x]
-};
+
 
 // The partial planes that cover low-res pixel (i, j) are the block that owns
 // it plus, on a block border, the neighbour whose halo row/column it is
@@ -878,7 +861,8 @@ __device__ __forceinline__ URaw gather_u_raw(const float* base, size_t UP, const
 // A, and the adjoint quantities X = (dmean_I, dmean_p, dcov, dvar) / N; per
 // row whose X window is complete: box sums of X give dG and dp.
 template <typename TG, typename TP, int R, bool MAB>
-__global__ __launch_bounds__(64) void bwd_lo_kernel(BwdLoArgs a) {
+__device__ __forceinline__ void bwd_lo_body(const BwdLoArgs& a, const int bx, const int by,
+                                            const int plane) {
   constexpr int K = 2 * R + 1;
   constexpr int TWo = 64 - 4 * R;
   constexpr int KR = walker_ring_rows(R, kPF, kBwdLoRingPow2Max);
@@ -889,14 +873,13 @@ __global__ __launch_bounds__(64) void bwd_lo_kernel(BwdLoArgs a) {
   float4* xr = reinterpret_cast<float4*>(cu + kPF * 64);  // [KR][64] X
   float4* vs = xr + KR * 64;      // [kPF][64] column sums of X
   const int lane = threadIdx.x;
-  const int plane = blockIdx.z;
   const float e = a.eps[a.eps_count == 1 ? 0 : plane / a.c];
   const int h = a.h, w = a.w;
-  const int j0 = blockIdx.x * TWo;
+  const int j0 = bx * TWo;
   const int jl = j0 - 2 * R;
   const int j = jl + lane;
   const bool colin = (unsigned)j < (unsigned)w;
-  const int i0 = blockIdx.y * a.TR, i1 = min(i0 + a.TR, h);
+  const int i0 = by * a.TR, i1 = min(i0 + a.TR, h);
   const size_t pofs = (size_t)plane * h * w;
   const TG* G = reinterpret_cast<const TG*>(a.I_lo) + pofs;
   const TP* P = reinterpret_cast<const TP*>(a.p_lo) + pofs;
@@ -1090,7 +1073,12 @@ __global__ __launch_bounds__(64) void bwd_lo_kernel(BwdLoArgs a) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) deps_acc += __shfl_xor(deps_acc, off);
   if (lane == 0)
-    a.eps_part[((size_t)plane * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = deps_acc;
+    a.eps_part[((size_t)plane * a.pny + by) * a.pnx + bx] = deps_acc;
+}
+
+template <typename TG, typename TP, int R, bool MAB>
+__global__ __launch_bounds__(64) void bwd_lo_kernel(BwdLoArgs a) {
+  bwd_lo_body<TG, TP, R, MAB>(a, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 __global__ __launch_bounds__(256) void eps_reduce_kernel(const float* part, int per_plane,
@@ -1109,6 +1097,105 @@ __global__ __launch_bounds__(256) void eps_reduce_kernel(const float* part, int 
     __syncthreads();
   }
   if (threadIdx.x == 0) deps[k] = red[0];
+}
+
+// ------------------------------------------------------------ batched (multi-problem) kernels
+
+template <typename T>
+__device__ __forceinline__ T* rebase(char* ws, T* rel) {
+  return rel ? reinterpret_cast<T*>(ws + (reinterpret_cast<uintptr_t>(rel) - 1)) : nullptr;
+}
+
+// Item whose tile range holds tile t: a ballot over the ascending bases.
+// Every lane of the wave gets the same (uniform) answer.
+__device__ __forceinline__ int find_item(const long long* base, int count, long long t) {
+  const int lane = threadIdx.x & 63;
+  int k = 0;
+  for (int c0 = 0; c0 < count; c0 += 64) {
+    const int i = c0 + lane;
+    const bool le = i < count && base[min(i, count - 1)] <= t;
+    const unsigned long long m = __ballot(le);
+    k += __popcll(m);
+    if (m != ~0ull) break;
+  }
+  return k - 1;
+}
+
+template <typename Args>
+__device__ __forceinline__ const MultiItem<Args>& item_of(const MultiLaunch& m, long long t,
+                                                          long long& local) {
+  const int k = find_item(m.base, m.count, t);
+  const MultiItem<Args>& it = reinterpret_cast<const MultiItem<Args>*>(m.items)[k];
+  local = t - it.base;
+  return it;
+}
+
+template <typename TG, typename TP, int R, bool MAB>
+__global__ __launch_bounds__(64) void coef_multi_kernel(MultiLaunch m) {
+  for (long long t = blockIdx.x; t < m.total; t += gridDim.x) {
+    long long l;
+    const MultiItem<CoefArgs>& it = item_of<CoefArgs>(m, t, l);
+    CoefArgs a = it.a;
+    a.abar = rebase(m.ws, a.abar);
+    a.bbar = rebase(m.ws, a.bbar);
+    const long long xy = (long long)it.nx * it.ny;
+    coef_body<TG, TP, R, MAB>(a, (int)(l % it.nx), (int)((l / it.nx) % it.ny), (int)(l / xy));
+  }
+}
+
+template <typename TG, typename TQ, int S, int VEC>
+__global__ __launch_bounds__(256) void apply_multi_kernel(MultiLaunch m) {
+  for (long long t = blockIdx.x; t < m.total; t += gridDim.x) {
+    long long l;
+    const MultiItem<ApplyArgs>& it = item_of<ApplyArgs>(m, t, l);
+    ApplyArgs a = it.a;
+    a.abar = rebase(m.ws, a.abar);
+    a.bbar = rebase(m.ws, a.bbar);
+    apply_body<TG, TQ, S, VEC>(a, l);
+  }
+}
+
+template <typename TG, typename TD, typename TO, int S, int VEC>
+__global__ __launch_bounds__(64) void bwd_hi_multi_kernel(MultiLaunch m) {
+  for (long long t = blockIdx.x; t < m.total; t += gridDim.x) {
+    long long l;
+    const MultiItem<BwdHiArgs>& it = item_of<BwdHiArgs>(m, t, l);
+    BwdHiArgs a = it.a;
+    a.abar = rebase(m.ws, a.abar);
+    a.U = rebase(m.ws, a.U);
+    const long long xy = (long long)it.nx * it.ny;
+    bwd_hi_body<TG, TD, TO, S, VEC>(a, (int)(l % it.nx), (int)((l / it.nx) % it.ny),
+                                    (int)(l / xy));
+  }
+}
+
+template <typename TG, typename TP, int R, bool MAB>
+__global__ __launch_bounds__(64) void bwd_lo_multi_kernel(MultiLaunch m) {
+  for (long long t = blockIdx.x; t < m.total; t += gridDim.x) {
+    long long l;
+    const MultiItem<BwdLoArgs>& it = item_of<BwdLoArgs>(m, t, l);
+    BwdLoArgs a = it.a;
+    a.U = rebase(m.ws, a.U);
+    a.eps_part = rebase(m.ws, a.eps_part);
+    const long long xy = (long long)it.nx * it.ny;
+    bwd_lo_body<TG, TP, R, MAB>(a, (int)(l % it.nx), (int)((l / it.nx) % it.ny), (int)(l / xy));
+  }
+}
+
+// One workgroup per item with a deps output: fixed-order sum of its partials.
+__global__ __launch_bounds__(256) void eps_multi_kernel(const EpsItem* items, char* ws) {
+  __shared__ float red[256];
+  const EpsItem it = items[blockIdx.x];
+  const float* part = rebase(ws, it.part);
+  float s = 0.f;
+  for (long long q = threadIdx.x; q < it.count; q += 256) s += part[q];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *it.deps = red[0];
 }
 
 // ------------------------------------------------------------ dispatch
@@ -1208,7 +1295,7 @@ hipError_t launch_bwd_lo(const Plan& p, const void* G_lo, const void* p_lo, cons
                          int eps_count, const float* U, float* dG_lo, float* dp_lo,
                          float* part, hipStream_t s) {
   BwdLoArgs a{G_lo, p_lo, eps, eps_count, p.c, U, p.bh, p.tw, p.nby, p.nbx,
-              p.h, p.w, p.loTR, dG_lo, dp_lo, part};
+              p.h, p.w, p.loTR, dG_lo, dp_lo, part, p.lo_nx, p.lo_ny};
   const dim3 grid(p.lo_nx, p.lo_ny, p.planes);
   prof_begin("gf_bwd_lo", s);
   hipError_t err = with_radius(p.r, [&](auto rc) {
@@ -1254,6 +1341,119 @@ hipError_t backward_t(const Plan& p, const BwdArgs& b, hipStream_t s) {
   err = launch_bwd_lo<T, T>(p, b.I_lo, b.p_lo, b.eps, b.eps_count, U, b.dI_lo, b.dp_lo, part, s);
   if (err != hipSuccess || !b.deps) return err;
   return launch_eps_reduce(p, part, b.eps_count, b.deps, s);
+}
+
+// ------------------------------------------------------------ batched launchers
+
+template <typename TG, typename TP>
+hipError_t launch_coef_multi(const BatchClass& c, char* ws, hipStream_t s) {
+  MultiLaunch m = c.m;
+  m.ws = ws;
+  prof_begin("gf_coef_multi", s);
+  hipError_t err = with_radius(c.R, [&](auto rc) {
+    constexpr int R = decltype(rc)::value;
+    if (c.MAB)
+      hipLaunchKernelGGL((coef_multi_kernel<TG, TP, R, true>), dim3(m.grid), dim3(64), c.lds, s, m);
+    else
+      hipLaunchKernelGGL((coef_multi_kernel<TG, TP, R, false>), dim3(m.grid), dim3(64), c.lds, s,
+                         m);
+    return hipGetLastError();
+  });
+  prof_end(s);
+  return err;
+}
+
+template <typename TG, typename TP>
+hipError_t launch_bwd_lo_multi(const BatchClass& c, char* ws, hipStream_t s) {
+  MultiLaunch m = c.m;
+  m.ws = ws;
+  prof_begin("gf_bwd_lo_multi", s);
+  hipError_t err = with_radius(c.R, [&](auto rc) {
+    constexpr int R = decltype(rc)::value;
+    if (c.MAB)
+      hipLaunchKernelGGL((bwd_lo_multi_kernel<TG, TP, R, true>), dim3(m.grid), dim3(64), c.lds, s,
+                         m);
+    else
+      hipLaunchKernelGGL((bwd_lo_multi_kernel<TG, TP, R, false>), dim3(m.grid), dim3(64), c.lds,
+                         s, m);
+    return hipGetLastError();
+  });
+  prof_end(s);
+  return err;
+}
+
+template <typename TG, typename TQ>
+hipError_t launch_apply_multi(const BatchClass& c, char* ws, hipStream_t s) {
+  MultiLaunch m = c.m;
+  m.ws = ws;
+  prof_begin("gf_apply_multi", s);
+  switch (c.S) {
+#define GF_CASE(SS)                                                                            \
+  case SS:                                                                                     \
+    if (c.VEC == 1)                                                                            \
+      hipLaunchKernelGGL((apply_multi_kernel<TG, TQ, SS, 1>), dim3(m.grid), dim3(256), 0, s, m); \
+    else                                                                                       \
+      hipLaunchKernelGGL((apply_multi_kernel<TG, TQ, SS, vec_for<TG, SS>()>), dim3(m.grid),    \
+                         dim3(256), 0, s, m);                                                  \
+    break;
+    GF_CASE(1) GF_CASE(2) GF_CASE(4) GF_CASE(8)
+#undef GF_CASE
+    default:
+      prof_end(s);
+      return hipErrorInvalidValue;
+  }
+  prof_end(s);
+  return hipGetLastError();
+}
+
+template <typename TG, typename TD, typename TO>
+hipError_t launch_bwd_hi_multi(const BatchClass& c, char* ws, hipStream_t s) {
+  MultiLaunch m = c.m;
+  m.ws = ws;
+  prof_begin("gf_bwd_hi_multi", s);
+  switch (c.S) {
+#define GF_CASE(SS)                                                                             \
+  case SS:                                                                                      \
+    if (c.VEC == 1)                                                                             \
+      hipLaunchKernelGGL((bwd_hi_multi_kernel<TG, TD, TO, SS, 1>), dim3(m.grid), dim3(64), 0, s, \
+                         m);                                                                    \
+    else                                                                                        \
+      hipLaunchKernelGGL((bwd_hi_multi_kernel<TG, TD, TO, SS, vec_for<TG, SS>()>), dim3(m.grid), \
+                         dim3(64), 0, s, m);                                                    \
+    break;
+    GF_CASE(1) GF_CASE(2) GF_CASE(4) GF_CASE(8)
+#undef GF_CASE
+    default:
+      prof_end(s);
+      return hipErrorInvalidValue;
+  }
+  prof_end(s);
+  return hipGetLastError();
+}
+
+// Forward (mode bit 1) and/or backward (bit 2) of every item; with both,
+// the coefficients are computed once.
+template <typename T>
+hipError_t batched_t(const BatchLaunch& b, int mode, char* ws, hipStream_t s) {
+  hipError_t e = hipSuccess;
+  for (const BatchClass& c : b.coef)
+    if ((e = launch_coef_multi<T, T>(c, ws, s)) != hipSuccess) return e;
+  if (mode & GF_RUN_FORWARD)
+    for (const BatchClass& c : b.apply)
+      if ((e = launch_apply_multi<T, T>(c, ws, s)) != hipSuccess) return e;
+  if (mode & GF_RUN_BACKWARD) {
+    for (const BatchClass& c : b.bwd_hi)
+      if ((e = launch_bwd_hi_multi<T, T, T>(c, ws, s)) != hipSuccess) return e;
+    for (const BatchClass& c : b.bwd_lo)
+      if ((e = launch_bwd_lo_multi<T, T>(c, ws, s)) != hipSuccess) return e;
+    if (b.eps_count > 0) {
+      prof_begin("gf_eps_multi", s);
+      hipLaunchKernelGGL(eps_multi_kernel, dim3(b.eps_count), dim3(256), 0, s, b.eps_items, ws);
+      prof_end(s);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+  }
+  return hipSuccess;
 }
 
 }  // namespace

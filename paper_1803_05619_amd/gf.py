@@ -59,6 +59,33 @@ lib.gf_forward.restype = ctypes.c_int32
 lib.gf_backward.argtypes = [_dp, _gp, _vp, _vp, _vp, _fp, ctypes.c_int32, _vp, _fp, _fp, _vp,
                             _fp, _fp, _vp, ctypes.c_size_t, _vp]
 lib.gf_backward.restype = ctypes.c_int32
+GF_RUN_FORWARD, GF_RUN_BACKWARD, GF_RUN_GRAPH = 1, 2, 4
+
+
+class gf_item_t(ctypes.Structure):
+    _fields_ = [("d", gf_desc_t), ("eps", ctypes.c_float),
+                ("I_lo", ctypes.c_void_p), ("p_lo", ctypes.c_void_p), ("I_hi", ctypes.c_void_p),
+                ("q_hi", ctypes.c_void_p), ("dq_hi", ctypes.c_void_p),
+                ("dI_lo", ctypes.c_void_p), ("dp_lo", ctypes.c_void_p),
+                ("dI_hi", ctypes.c_void_p), ("deps", ctypes.c_void_p)]
+
+
+lib.gf_plan_create.argtypes = [ctypes.POINTER(gf_item_t), ctypes.c_int32,
+                               ctypes.POINTER(ctypes.c_void_p)]
+lib.gf_plan_create.restype = ctypes.c_int32
+lib.gf_plan_workspace_size.argtypes = [_vp]
+lib.gf_plan_workspace_size.restype = ctypes.c_size_t
+lib.gf_batched.argtypes = [_vp, ctypes.c_int32, _vp, ctypes.c_size_t, _vp]
+lib.gf_batched.restype = ctypes.c_int32
+lib.gf_plan_destroy.argtypes = [_vp]
+lib.gf_plan_destroy.restype = None
+lib.gf_autotune.argtypes = [_dp, _gp, _vp, _vp, _vp, _fp, ctypes.c_int32, _vp, _vp, _fp, _fp, _vp,
+                            _fp, _fp, _vp, ctypes.c_size_t, ctypes.c_int32, _vp]
+lib.gf_autotune.restype = ctypes.c_int32
+lib.gf_tune_export.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
+lib.gf_tune_export.restype = ctypes.c_size_t
+lib.gf_tune_import.argtypes = [ctypes.c_char_p]
+lib.gf_tune_import.restype = ctypes.c_int32
 lib.gf_status_string.argtypes = [ctypes.c_int32]
 lib.gf_status_string.restype = ctypes.c_char_p
 lib.gf_last_error_detail.argtypes = []
@@ -110,6 +137,43 @@ def gf_backward(desc, guide, I_lo, p_lo, I_hi, eps, eps_count, dq_hi, dI_lo, dp_
     return int(lib.gf_backward(ctypes.byref(desc), _gref(guide), I_lo, p_lo, I_hi, eps,
                                eps_count, dq_hi, dI_lo, dp_lo, dI_hi, deps, dparams, ws,
                                ws_bytes, stream))
+
+
+def gf_plan_create(items, count):
+    """Returns (status, plan handle or None); `items` a ctypes gf_item_t array."""
+    h = ctypes.c_void_p()
+    st = int(lib.gf_plan_create(items, int(count), ctypes.byref(h)))
+    return st, (h.value if st == GF_OK else None)
+
+
+def gf_plan_workspace_size(plan) -> int:
+    return int(lib.gf_plan_workspace_size(plan))
+
+
+def gf_batched(plan, mode, ws, ws_bytes, stream) -> int:
+    return int(lib.gf_batched(plan, int(mode), ws, ws_bytes, stream))
+
+
+def gf_plan_destroy(plan) -> None:
+    lib.gf_plan_destroy(plan)
+
+
+def gf_autotune(desc, guide, I_lo, p_lo, I_hi, eps, eps_count, q_hi, dq_hi, dI_lo, dp_lo, dI_hi,
+                deps, dparams, ws, ws_bytes, iters, stream) -> int:
+    return int(lib.gf_autotune(ctypes.byref(desc), _gref(guide), I_lo, p_lo, I_hi, eps,
+                               eps_count, q_hi, dq_hi, dI_lo, dp_lo, dI_hi, deps, dparams, ws,
+                               ws_bytes, int(iters), stream))
+
+
+def gf_tune_export() -> str:
+    n = int(lib.gf_tune_export(None, 0))
+    buf = ctypes.create_string_buffer(n + 1)
+    lib.gf_tune_export(buf, n + 1)
+    return buf.value.decode()
+
+
+def gf_tune_import(text: str) -> int:
+    return int(lib.gf_tune_import(text.encode()))
 
 
 def gf_status_string(code: int) -> str:
@@ -341,3 +405,83 @@ def guided_filter(I_lo, p_lo, I_hi, r=1, eps=1e-8, mean_ab=True, guide=None):
     tensor receives its gradient."""
     params = guide.params if guide is not None else None
     return GuidedFilterFn.apply(I_lo, p_lo, I_hi, eps, r, mean_ab, guide, params)
+
+
+# ------------------------------------------------------------------ batched
+
+class BatchPlan:
+    """Many independent problems (identity guide, one dtype) run as one launch
+    per phase and launch class (gf_plan_create / gf_batched).
+
+    items: list of dicts with I_lo, p_lo, I_hi (device tensors), r, eps and
+    optionally mean_ab (default True) and the outputs q, dq, dI_lo, dp_lo,
+    dI_hi, deps (device tensors; deps one float32).  The plan keeps the
+    tensors alive and every run reads and writes them in place."""
+
+    def __init__(self, items):
+        self.items = [dict(it) for it in items]
+        arr = (gf_item_t * len(items))()
+        for k, it in enumerate(self.items):
+            I_lo, I_hi, p_lo = it["I_lo"], it["I_hi"], it["p_lo"]
+            dev = I_hi.device
+            _check({f"item {k} " + n: it.get(n) for n in ("I_lo", "p_lo", "I_hi", "q", "dq",
+                                                           "dI_hi")}, I_hi.dtype, dev)
+            _check({f"item {k} " + n: it.get(n) for n in ("dI_lo", "dp_lo", "deps")},
+                   torch.float32, dev)
+            arr[k].d = make_desc(I_lo, I_hi, it["r"], it.get("mean_ab", True), c=p_lo.shape[1])
+            arr[k].eps = float(it["eps"])
+            for field, key in (("I_lo", "I_lo"), ("p_lo", "p_lo"), ("I_hi", "I_hi"),
+                               ("q_hi", "q"), ("dq_hi", "dq"), ("dI_lo", "dI_lo"),
+                               ("dp_lo", "dp_lo"), ("dI_hi", "dI_hi"), ("deps", "deps")):
+                setattr(arr[k], field, _ptr(it.get(key)))
+        self._arr = arr
+        st, self.handle = gf_plan_create(arr, len(items))
+        if st != GF_OK:
+            raise GFError(st)
+        self.device = self.items[0]["I_hi"].device
+        self.ws = torch.empty(max(gf_plan_workspace_size(self.handle), 256), dtype=torch.uint8,
+                              device=self.device)
+
+    def run(self, mode=GF_RUN_FORWARD | GF_RUN_BACKWARD, graph=False):
+        m = int(mode) | (GF_RUN_GRAPH if graph else 0)
+        st = gf_batched(self.handle, m, self.ws.data_ptr(), self.ws.numel(),
+                        _stream(self.device))
+        if st != GF_OK:
+            raise GFError(st)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            gf_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune(I_lo, p_lo, I_hi, eps, dq, r=1, mean_ab=True, iters=5, guide=None):
+    """Times the candidate launch shapes on these buffers and stores the
+    fastest per kernel for this (dtype, factor, radius, guide, mean_ab)."""
+    dev = I_hi.device
+    desc = make_desc(I_lo, I_hi, r, mean_ab, c=p_lo.shape[1])
+    g = None if guide is None else guide.struct()
+    e = _eps_tensor(eps, desc.n, dev)
+    f32 = dict(dtype=torch.float32, device=dev)
+    q = torch.empty((desc.n, desc.c, desc.h_hi, desc.w_hi), dtype=I_hi.dtype, device=dev)
+    dI_lo = torch.empty(I_lo.shape, **f32)
+    dp_lo = torch.empty(p_lo.shape, **f32)
+    dI_hi = torch.empty_like(I_hi)
+    deps = torch.empty(e.numel(), **f32)
+    dparams = None
+    if guide is not None and guide.mode == GF_GUIDE_TRANSFORM:
+        dparams = torch.empty(gf_guide_param_count(guide.c_in, desc.c, guide.hidden), **f32)
+    # room for the largest candidate shapes
+    nbytes = 2 * max(gf_workspace_size(desc, g, 0), gf_workspace_size(desc, g, 1)) + (1 << 20)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    st = gf_autotune(desc, g, _ptr(I_lo), _ptr(p_lo), _ptr(I_hi), _ptr(e), e.numel(), _ptr(q),
+                     _ptr(dq), _ptr(dI_lo), _ptr(dp_lo), _ptr(dI_hi), _ptr(deps), _ptr(dparams),
+                     _ptr(ws), ws.numel(), iters, _stream(dev))
+    if st != GF_OK:
+        raise GFError(st)

@@ -135,3 +135,79 @@ def test_invalid_guides(kw, dkw, code):
     st = gf.gf_backward(d, g, FAKE, FAKE, FAKE, FAKE, 1, FAKE, FAKE, FAKE, FAKE, FAKE, None,
                         FAKE, 1 << 40, None)
     assert st == code, gf.gf_last_error_detail()
+
+
+# ------------------------------------------------------------ batched plans
+
+def item(**kw):
+    it = gf.gf_item_t()
+    it.d = desc(**kw.pop("d", {}))
+    it.eps = kw.pop("eps", 1e-3)
+    for f in ("I_lo", "p_lo", "I_hi", "q_hi", "dq_hi", "dI_lo", "dp_lo", "dI_hi", "deps"):
+        setattr(it, f, kw.pop(f, FAKE))
+    assert not kw
+    return it
+
+
+def items_of(*its):
+    arr = (gf.gf_item_t * len(its))()
+    for k, it in enumerate(its):
+        arr[k] = it
+    return arr
+
+
+@pytest.mark.parametrize("its, code", [
+    ([item(d=dict(r=-1))], gf.GF_ERR_INVALID_ARG),
+    ([item(d=dict(h_hi=192, w_hi=288))], gf.GF_ERR_UNSUPPORTED),
+    ([item(), item(d=dict(io_dtype=2))], gf.GF_ERR_INVALID_ARG),
+    ([item(eps=-1.0)], gf.GF_ERR_INVALID_ARG),
+    ([item(eps=float("inf"))], gf.GF_ERR_INVALID_ARG),
+    ([item(I_hi=None)], gf.GF_ERR_INVALID_ARG),
+    ([item(), item(dI_lo=FAKE + 8)], gf.GF_ERR_INVALID_ARG),
+])
+def test_plan_rejects_invalid_items(its, code):
+    st, plan = gf.gf_plan_create(items_of(*its), len(its))
+    assert st == code and plan is None
+    assert gf.gf_last_error_detail() != ""
+
+
+def test_plan_rejects_empty_and_null():
+    st, plan = gf.gf_plan_create(items_of(item()), 0)
+    assert st == gf.GF_ERR_INVALID_ARG and plan is None
+    assert gf.gf_plan_workspace_size(None) == 0
+    assert gf.gf_batched(None, gf.GF_RUN_FORWARD, FAKE, 1 << 40, None) == gf.GF_ERR_INVALID_ARG
+    gf.gf_plan_destroy(None)
+
+
+# ------------------------------------------------------------ tuning table
+
+def test_tune_import_export_roundtrip():
+    # a key no other test uses: bf16, S = 8, r = 7, identity, mean_ab = 0
+    assert gf.gf_tune_import("2 8 7 0 0 : 16 32 8 4\n") == gf.GF_OK
+    text = gf.gf_tune_export()
+    assert "2 8 7 0 0 : 16 32 8 4" in text
+    assert gf.gf_tune_import("2 8 7 0 0 : 64 64 16 2\n\n") == gf.GF_OK  # overwrite
+    assert "2 8 7 0 0 : 64 64 16 2" in gf.gf_tune_export()
+    assert "2 8 7 0 0 : 16 32 8 4" not in gf.gf_tune_export()
+
+
+@pytest.mark.parametrize("bad", ["1 2 3\n", "2 8 7 0 0 16 32 8 4\n", "2 8 7 0 0 : 16 32 8 1\n",
+                                 "2 8 7 0 0 : 16 32 8 4 extra\n", "2 8 7 0 0 : 0 32 8 4\n"])
+def test_tune_import_rejects_malformed(bad):
+    before = gf.gf_tune_export()
+    assert gf.gf_tune_import("2 4 9 0 1 : 16 16 8 2\n" + bad) == gf.GF_ERR_INVALID_ARG
+    assert gf.gf_tune_export() == before   # nothing imported
+
+
+def test_tuned_shapes_reach_the_planner():
+    # bf16, S = 4, r = 9, identity, mean_ab = 1: the backward workspace holds
+    # the per-block partial planes (bh + 2 rows per bh) and one deps partial
+    # per walker segment, so both follow the tuned rows
+    d = desc(io_dtype=2, r=9, h_lo=256, w_lo=256, h_hi=1024, w_hi=1024)
+    assert gf.gf_tune_import("2 4 9 0 1 : 64 64 8 2\n") == gf.GF_OK
+    b2 = gf.gf_workspace_size(d, None, 1)
+    assert gf.gf_tune_import("2 4 9 0 1 : 64 64 8 8\n") == gf.GF_OK
+    b8 = gf.gf_workspace_size(d, None, 1)
+    assert b8 < b2   # (8 + 2) / 8 < (2 + 2) / 2 partial rows per low-res row
+    assert gf.gf_tune_import("2 4 9 0 1 : 64 16 8 8\n") == gf.GF_OK
+    assert gf.gf_workspace_size(d, None, 1) > b8   # more deps partials
