@@ -1,21 +1,32 @@
 """Benchmark of the fused guided filtering layer on one MI355X.
 
-A step is one forward + one backward of the layer (every gradient: p_l, I_l,
-I_h, eps) over one batch of the FP32 workload 4 x 3 x 2048 x 3072 high-res
-(512 x 768 low-res, s = 4), r = 1, eps = 1e-4, dq ~ N(0, 1), with inputs
-already resident in HBM.  Prints ONE JSON line:
+A step is one forward + one backward of the layer over one batch, with the
+inputs already resident in HBM.  Workloads (--workload):
 
+  1 (default)  FP32, 4 x 3 x 2048 x 3072 high-res (512 x 768 low-res, s = 4),
+               r = 1, eps = 1e-4, dq ~ N(0, 1); gradients to p_l, I_l, I_h, eps
+  2            trainable guide (3 -> 15 -> 3, adaptive BN, leaky ReLU 0.2),
+               BF16 I/O, 8 x 3 x 1536 x 2048 (s = 4), r = 1, eps = 1e-8;
+               gradients to p_l, eps and every guide parameter
+  3            64 uneven images (H, W in [512, 3072], s in {2, 4, 8},
+               r in {1, 2, 4}, eps in [1e-8, 1e-2]), FP32, one batched plan
+               replayed as a HIP graph, launch shapes autotuned first
+  4            FP16 I/O precision stress: 2 x 3 x 2160 x 3840 (s = 4) with
+               near-constant regions, r = 8 (--radius 1 for the r = 1 run),
+               eps = 1e-8
+
+Prints ONE JSON line:
   value        high-res Mpixel/s of fwd+bwd (a 3-channel pixel counts once)
-  roofline     the dominant kernel's algorithmic bytes per launch / its
-               average duration (HIP events on the launch stream, timed
+  roofline     the dominant kernel: its algorithmic bytes per step / its time
+               per step (HIP events on the launch stream over the timed
                region), against the 8 TB/s HBM peak; `traffic` is the HBM
-               bytes per launch measured with rocprofv3 counters (from the
-               committed summary, null when the kernel changed since)
+               bytes per launch measured with rocprofv3 counters (workload 1,
+               from the committed summary; null when the kernel changed since)
   plain        the unfused PyTorch composition (autograd) on the same GPU
   cpu_baseline the FP64 CPU oracle on the host cores (bounded sample)
-  error        max error of this run's outputs against that oracle
+  error_vs_fp64_oracle  errors of this run's outputs on that sample
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload N]
 """
 import argparse
 import hashlib
@@ -30,6 +41,9 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 KERNEL_SRC = os.path.join(ROOT, "paper_1803_05619_amd", "csrc", "gf_kernels.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_fp32_4x3x2048x3072.txt")
+METRIC = "high-res Mpixel/s fwd+bwd, fused vs plain at stated max-abs error; % HBM peak"
+DATA = "synthetic (seeded photo-like images: smooth field + step edges + noise)"
+BYTES = {"f32": 4, "bf16": 2, "f16": 2}
 
 
 def log(msg):
@@ -40,19 +54,332 @@ def kernel_hash():
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
-def algorithmic_bytes(n, c, H, W, h, w, b=4):
-    """Compulsory bytes per launch of each kernel (every input read once and
-    every output written once): high-res b bytes per pixel-channel per
-    tensor, low-res likewise; gradients at low resolution are float32."""
+def identity_bytes(n, c, H, W, h, w, b, with_dI=True):
+    """Compulsory bytes of each identity-guide kernel per launch (every input
+    read once, every output written once; low-res gradients are float32)."""
     hi, lo = n * c * H * W, n * c * h * w
     return {
-        "gf_apply": 2 * b * hi,                 # I_h in, q out
-        "gf_bwd_hi": 3 * b * hi,                # dq, I_h in, dI_h out
-        "gf_coef": 2 * b * lo,                  # I_l, p_l in (its outputs are intermediates)
-        "gf_bwd_lo": 2 * b * lo + 8 * lo,       # I_l, p_l in; dI_l, dp_l out (float32)
-        "gf_eps_reduce": 0,
-        "step": (2 * b * hi + 2 * b * lo) + (3 * b * hi + 2 * b * lo + 8 * lo),
+        "apply": 2 * b * hi,                                  # I_h in, q out
+        "bwd_hi": (3 if with_dI else 2) * b * hi,             # dq, I_h in, dI_h out
+        "coef": 2 * b * lo,                                   # I_l, p_l in
+        "bwd_lo": 2 * b * lo + (8 if with_dI else 4) * lo,    # I_l, p_l in; dI_l, dp_l out
     }
+
+
+def oracle_errors(got, ref):
+    """Errors as in the parity tests: q absolute; gradients scaled by
+    max(1, max |ref|); deps and the guide parameters' gradients (sums over
+    pixels) by max(1, sum of the magnitudes of their terms)."""
+    import numpy as np
+    err = {}
+    if "q" in got:
+        err["q_max_abs"] = float(np.abs(got["q"] - ref["q"]).max())
+    if "dguide" in got:
+        err["dguide_scaled"] = float((np.abs(got["dguide"] - ref["dguide"]) /
+                                      np.maximum(1.0, ref["dguide_abs"])).max())
+    for k in ("dI_lo", "dp_lo", "dI_hi"):
+        if k in got and k in ref:
+            err[k + "_scaled"] = float(np.abs(got[k] - ref[k]).max() /
+                                       max(1.0, np.abs(ref[k]).max()))
+    if "deps" in got:
+        err["deps_scaled"] = float((np.abs(got["deps"] - ref["deps"]) /
+                                    np.maximum(1.0, ref["deps_abs"])).max())
+    return err
+
+
+def merge_max(acc, err):
+    for k, v in err.items():
+        acc[k] = max(acc.get(k, 0.0), v)
+    return acc
+
+
+# ------------------------------------------------------------------ workloads
+
+def workload_1(args, dev):
+    import torch
+
+    from paper_1803_05619_amd import datagen, gf, plain
+    log("generating workload 1 (FP32 4x3x2048x3072)")
+    prob = datagen.make_config(1)
+    return identity_workload(args, dev, prob, "f32",
+                             "guided filtering layer fwd+bwd, FP32, 4x3x2048x3072 high-res "
+                             "<- 512x768 low-res (s=4), r=1, eps=1e-4, window-mean of A,b, "
+                             "grads to p_l, I_l, I_h, eps")
+
+
+def workload_4(args, dev):
+    from paper_1803_05619_amd import datagen
+    r = args.radius if args.radius is not None else 8
+    log(f"generating workload 4 (FP16 2x3x2160x3840, near-constant regions, r={r})")
+    prob = datagen.make_config(4, r=r)
+    return identity_workload(args, dev, prob, "f16",
+                             f"precision stress fwd+bwd, FP16 I/O + FP32 accumulate, "
+                             f"2x3x2160x3840 <- 540x960 (s=4), r={r}, eps=1e-8, near-constant "
+                             f"regions 0.5+N(0,1e-4), grads to p_l, I_l, I_h, eps")
+
+
+def identity_workload(args, dev, prob, dt, name):
+    import torch
+
+    from paper_1803_05619_amd import gf, plain
+    n, c, H, W, h, w, r = (prob[k] for k in ("n", "c", "H", "W", "h", "w", "r"))
+    t = {k: prob[k].to(dev) for k in ("I_lo", "p_lo", "I_hi", "dq")}
+    eps = torch.tensor(prob["eps"], dtype=torch.float32, device=dev)
+    q = torch.empty_like(t["I_hi"])
+    outs = (torch.empty(t["I_lo"].shape, dtype=torch.float32, device=dev),
+            torch.empty(t["p_lo"].shape, dtype=torch.float32, device=dev),
+            torch.empty_like(t["I_hi"]),
+            torch.empty(1, dtype=torch.float32, device=dev))
+    desc = gf.make_desc(t["I_lo"], t["I_hi"], r)
+    ws = torch.empty(max(gf.gf_workspace_size(desc, None, 0), gf.gf_workspace_size(desc, None, 1)),
+                     dtype=torch.uint8, device=dev)
+
+    def step():
+        gf.forward(t["I_lo"], t["p_lo"], t["I_hi"], eps, r, out=q, ws=ws)
+        gf.backward(t["I_lo"], t["p_lo"], t["I_hi"], eps, t["dq"], r, ws=ws, outs=outs)
+
+    kb = identity_bytes(n, c, H, W, h, w, BYTES[dt])
+    per_step = {"gf_apply": kb["apply"], "gf_bwd_hi": kb["bwd_hi"], "gf_coef": 2 * kb["coef"],
+                "gf_bwd_lo": kb["bwd_lo"], "gf_eps_reduce": 0}
+    step_bytes = kb["apply"] + kb["coef"] + kb["bwd_hi"] + kb["bwd_lo"]
+
+    I_lo = t["I_lo"].clone().requires_grad_(True)
+    p_lo = t["p_lo"].clone().requires_grad_(True)
+    I_hi = t["I_hi"].clone().requires_grad_(True)
+    eps_p = eps.clone().requires_grad_(True)
+
+    def plain_step():
+        for x in (I_lo, p_lo, I_hi, eps_p):
+            x.grad = None
+        plain.guided_filter(I_lo, p_lo, I_hi, r, eps_p).backward(t["dq"].float())
+
+    def cpu_sample():
+        import oracle
+        args_np = [prob[k].double().numpy() for k in ("I_lo", "p_lo", "I_hi")]
+        dq_np = prob["dq"].double().numpy()
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            ref = {"q": oracle.forward(*args_np, r, prob["eps"])}
+            ref.update(oracle.backward(*args_np, r, prob["eps"], dq_np))
+            reps += 1
+            el = time.perf_counter() - t0
+            if el >= args.cpu_seconds or reps >= 20:
+                break
+        torch.cuda.synchronize()
+        got = {"q": q.double().cpu().numpy(), "dI_lo": outs[0].double().cpu().numpy(),
+               "dp_lo": outs[1].double().cpu().numpy(), "dI_hi": outs[2].double().cpu().numpy(),
+               "deps": outs[3].double().cpu().numpy()}
+        return (n * H * W / 1e6 * reps, el,
+                f"the full {n}-image batch, fwd+bwd, repeated {reps}x ({el:.1f} s); parallel "
+                f"over the {n * c} image planes", n * c, oracle_errors(got, ref))
+
+    return dict(step=step, plain_step=plain_step, cpu_sample=cpu_sample, mpx=n * H * W / 1e6,
+                per_step=per_step, step_bytes=step_bytes, dtype=dt,
+                config={"workload": name, "n": n, "c": c, "H": H, "W": W, "s": prob["s"], "r": r,
+                        "eps": float(prob["eps"][0])},
+                traffic_ok=(dt == "f32" and n == 4 and H == 2048 and W == 3072))
+
+
+def workload_2(args, dev):
+    import numpy as np
+    import torch
+
+    from paper_1803_05619_amd import datagen, gf, plain
+    log("generating workload 2 (BF16 8x3x1536x2048, trainable guide)")
+    prob = datagen.make_config(2)
+    n, c, H, W, h, w, r = (prob[k] for k in ("n", "c", "H", "W", "h", "w", "r"))
+    gp = prob["guide"]
+    K = np.asarray(gp["w1"]).shape[0]
+    t = {k: prob[k].to(dev) for k in ("I_lo", "p_lo", "I_hi", "dq")}
+    eps = torch.tensor(prob["eps"], dtype=torch.float32, device=dev)
+    params = gf.pack_transform_params(gp["w1"], gp["w2"], gp["b2"], gp["lam"], gp["mu"],
+                                      gp["gamma"], gp["beta"], device=dev)
+    stats = torch.empty(gf.gf_guide_stats_count(3), dtype=torch.float32, device=dev)
+    g_fwd = gf.Guide(gf.GF_GUIDE_TRANSFORM, 3, K, params, gp["bn_eps"], gp["slope"], stats, False)
+    g_bwd = gf.Guide(gf.GF_GUIDE_TRANSFORM, 3, K, params, gp["bn_eps"], gp["slope"], stats, True)
+    q = torch.empty_like(t["I_hi"])
+    f32 = dict(dtype=torch.float32, device=dev)
+    dp_lo = torch.empty(t["p_lo"].shape, **f32)
+    deps = torch.empty(1, **f32)
+    dparams = torch.empty(gf.gf_guide_param_count(3, 3, K), **f32)
+    desc = gf.make_desc(t["I_lo"], t["I_hi"], r)
+    ws = torch.empty(max(gf.gf_workspace_size(desc, g_fwd.struct(), 0),
+                         gf.gf_workspace_size(desc, g_fwd.struct(), 1)), dtype=torch.uint8,
+                     device=dev)
+
+    def step():
+        gf.forward(t["I_lo"], t["p_lo"], t["I_hi"], eps, r, out=q, ws=ws, guide=g_fwd)
+        gf.backward(t["I_lo"], t["p_lo"], t["I_hi"], eps, t["dq"], r, ws=ws, guide=g_bwd,
+                    outs=(None, dp_lo, None, deps, dparams))
+
+    b = 2
+    hi, lo = n * c * H * W, n * c * h * w
+    hpx, lpx = n * H * W, n * h * w
+    # each kernel's own compulsory I/O per step (G planes are float32)
+    per_step = {
+        "gf_guide_moments": 3 * b * (hpx + lpx),                 # fwd only (bwd reads saved)
+        "gf_guide_map": 2 * (3 * b + 12) * (hpx + lpx),          # fwd and bwd
+        "gf_coef": 2 * (4 + b) * lo,
+        "gf_apply": (4 + b) * hi,
+        "gf_bwd_hi": (4 + b + 4) * hi,
+        "gf_bwd_lo": (4 + b + 4 + 4) * lo,
+        "gf_guide_bwd": (3 * b + 12) * (hpx + lpx),
+    }
+    # the step's compulsory bytes: inputs read once per pass, outputs once
+    step_bytes = 2 * b * hi + 2 * b * lo + 2 * b * hi + 2 * b * lo + 4 * lo
+
+    w1, w2, b2, gam, bet = (torch.tensor(np.asarray(gp[k]), **f32)
+                            for k in ("w1", "w2", "b2", "gamma", "beta"))
+    leaves = [x.clone().requires_grad_(True) for x in (w1, w2, b2, gam, bet)]
+    lam_t = torch.tensor(float(gp["lam"]), **f32).requires_grad_(True)
+    mu_t = torch.tensor(float(gp["mu"]), **f32).requires_grad_(True)
+    p_lo = t["p_lo"].clone().requires_grad_(True)
+    eps_p = eps.clone().requires_grad_(True)
+
+    def plain_step():
+        for x in leaves + [lam_t, mu_t, p_lo, eps_p]:
+            x.grad = None
+        G_lo = plain.guide_transform(t["I_lo"], leaves[0], leaves[1], leaves[2], lam_t, mu_t,
+                                     leaves[3], leaves[4], gp["bn_eps"], gp["slope"])
+        G_hi = plain.guide_transform(t["I_hi"], leaves[0], leaves[1], leaves[2], lam_t, mu_t,
+                                     leaves[3], leaves[4], gp["bn_eps"], gp["slope"])
+        plain.guided_filter(G_lo, p_lo, G_hi, r, eps_p).backward(t["dq"].float())
+
+    def cpu_sample():
+        import oracle
+        args_np = [prob[k].double().numpy() for k in ("I_lo", "p_lo", "I_hi")]
+        dq_np = prob["dq"].double().numpy()
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            ref = {"q": oracle.forward(*args_np, r, prob["eps"], guide=gp)}
+            ref.update(oracle.backward(*args_np, r, prob["eps"], dq_np, guide=gp))
+            reps += 1
+            el = time.perf_counter() - t0
+            if el >= args.cpu_seconds or reps >= 20:
+                break
+        torch.cuda.synchronize()
+        got = {"q": q.double().cpu().numpy(), "dp_lo": dp_lo.double().cpu().numpy(),
+               "deps": deps.double().cpu().numpy(), "dguide": dparams.double().cpu().numpy()}
+        return (n * H * W / 1e6 * reps, el,
+                f"the full {n}-image batch, fwd+bwd with the guide, repeated {reps}x "
+                f"({el:.1f} s); parallel over the {n * c} image planes", n * c,
+                oracle_errors(got, ref))
+
+    return dict(step=step, plain_step=plain_step, cpu_sample=cpu_sample, mpx=n * H * W / 1e6,
+                per_step=per_step, step_bytes=step_bytes, dtype="bf16",
+                config={"workload": "trainable-guide guided filtering fwd+bwd, BF16 I/O + FP32 "
+                                    "accumulate, 8x3x1536x2048 <- 384x512 (s=4), r=1, eps=1e-8, "
+                                    "guide 3->15->3 with adaptive BN and leaky ReLU 0.2, grads "
+                                    "to p_l, eps and the guide parameters",
+                        "n": n, "c": c, "H": H, "W": W, "s": prob["s"], "r": r, "eps": 1e-8,
+                        "hidden": K},
+                traffic_ok=False)
+
+
+def _gen_item(spec):
+    from paper_1803_05619_amd import datagen
+    return datagen.batched_item(spec)
+
+
+def workload_3(args, dev):
+    import multiprocessing as mp
+
+    import torch
+
+    from paper_1803_05619_amd import datagen, gf, plain
+    specs = datagen.batched_specs(args.items)
+    log(f"generating workload 3 ({len(specs)} uneven images)")
+    probs = [None] * len(specs)
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    with mp.get_context("spawn").Pool(workers) as pool:
+        for k, p in enumerate(pool.imap(_gen_item, specs)):
+            probs[k] = p
+            if (k + 1) % 8 == 0:
+                log(f"  {k + 1}/{len(specs)} images")
+    items = []
+    f32 = dict(dtype=torch.float32, device=dev)
+    for p in probs:
+        it = {k: p[k].to(dev) for k in ("I_lo", "p_lo", "I_hi", "dq")}
+        it.update(r=p["r"], eps=float(p["eps"][0]), mean_ab=True)
+        it["q"] = torch.empty_like(it["I_hi"])
+        it["dI_hi"] = torch.empty_like(it["I_hi"])
+        it["dI_lo"] = torch.empty(it["I_lo"].shape, **f32)
+        it["dp_lo"] = torch.empty(it["p_lo"].shape, **f32)
+        it["deps"] = torch.empty(1, **f32)
+        items.append(it)
+    # autotune once per (s, r) key on its largest image
+    keys = {}
+    for p, it in zip(probs, items):
+        key = (p["s"], p["r"])
+        if key not in keys or p["H"] * p["W"] > keys[key][0]:
+            keys[key] = (p["H"] * p["W"], it)
+    log(f"autotuning {len(keys)} (s, r) keys")
+    for key, (_, it) in sorted(keys.items()):
+        gf.autotune(it["I_lo"], it["p_lo"], it["I_hi"], it["eps"], it["dq"], r=it["r"], iters=3)
+    log("tuned shapes: " + gf.gf_tune_export().strip().replace("\n", "; "))
+    plan = gf.BatchPlan(items)
+
+    def step():
+        plan.run(gf.GF_RUN_FORWARD | gf.GF_RUN_BACKWARD, graph=True)
+
+    per_step = {"gf_coef_multi": 0, "gf_apply_multi": 0, "gf_bwd_hi_multi": 0,
+                "gf_bwd_lo_multi": 0, "gf_eps_multi": 0}
+    step_bytes = 0
+    mpx = 0.0
+    for p in probs:
+        kb = identity_bytes(1, 3, p["H"], p["W"], p["h"], p["w"], 4)
+        per_step["gf_coef_multi"] += kb["coef"]
+        per_step["gf_apply_multi"] += kb["apply"]
+        per_step["gf_bwd_hi_multi"] += kb["bwd_hi"]
+        per_step["gf_bwd_lo_multi"] += kb["bwd_lo"]
+        step_bytes += kb["apply"] + kb["coef"] + kb["bwd_hi"] + kb["bwd_lo"] - kb["coef"]
+        mpx += p["H"] * p["W"] / 1e6
+    step_bytes += sum(2 * 4 * 3 * p["h"] * p["w"] for p in probs)  # the one coef pass
+
+    leaves = [{k: it[k].clone().requires_grad_(True) for k in ("I_lo", "p_lo", "I_hi")}
+              for it in items]
+    eps_t = [torch.tensor([it["eps"]], **f32).requires_grad_(True) for it in items]
+
+    def plain_step():
+        for lv, e, it in zip(leaves, eps_t, items):
+            for x in list(lv.values()) + [e]:
+                x.grad = None
+            plain.guided_filter(lv["I_lo"], lv["p_lo"], lv["I_hi"], it["r"], e).backward(it["dq"])
+
+    def cpu_sample():
+        import oracle
+        err, done, t0, k = {}, 0.0, time.perf_counter(), 0
+        torch.cuda.synchronize()
+        while k < len(probs):
+            p, it = probs[k], items[k]
+            args_np = [p[x].double().numpy() for x in ("I_lo", "p_lo", "I_hi")]
+            ref = {"q": oracle.forward(*args_np, p["r"], p["eps"])}
+            ref.update(oracle.backward(*args_np, p["r"], p["eps"], p["dq"].double().numpy()))
+            got = {x: it[x].double().cpu().numpy() for x in ("q", "dI_lo", "dp_lo", "dI_hi",
+                                                             "deps")}
+            merge_max(err, oracle_errors(got, ref))
+            done += p["H"] * p["W"] / 1e6
+            k += 1
+            if time.perf_counter() - t0 >= args.cpu_seconds:
+                break
+        el = time.perf_counter() - t0
+        return (done, el, f"the first {k} of the {len(probs)} images, fwd+bwd each once "
+                          f"({el:.1f} s); parallel over each image's 3 planes", 3, err)
+
+    def eager_step():
+        plan.run(gf.GF_RUN_FORWARD | gf.GF_RUN_BACKWARD, graph=False)
+
+    return dict(step=step, eager_step=eager_step, plain_step=plain_step, cpu_sample=cpu_sample,
+                mpx=mpx, per_step=per_step, step_bytes=step_bytes, dtype="f32",
+                config={"workload": f"batched uneven guided filtering fwd+bwd, FP32, "
+                                    f"{len(probs)} images H,W in [512,3072], s in {{2,4,8}}, "
+                                    f"r in {{1,2,4}}, eps in [1e-8,1e-2]; one plan replayed as "
+                                    f"a HIP graph, autotuned launch shapes",
+                        "images": len(probs), "Mpx_per_step": round(mpx, 2)},
+                traffic_ok=False, keep=plan)
+
+
+WORKLOADS = {1: workload_1, 2: workload_2, 3: workload_3, 4: workload_4}
 
 
 def main():
@@ -60,6 +387,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", type=int, default=1, choices=sorted(WORKLOADS))
+    ap.add_argument("--radius", type=int, default=None, help="workload 4: radius (default 8)")
+    ap.add_argument("--items", type=int, default=64, help="workload 3: images")
     ap.add_argument("--plain-steps", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
@@ -75,7 +405,7 @@ def main():
 
     import torch
 
-    from paper_1803_05619_amd import datagen, gf
+    from paper_1803_05619_amd import gf
 
     dev = torch.device("cuda:0")
     if args.copy_probe:
@@ -85,24 +415,8 @@ def main():
         torch.cuda.synchronize()
         log("copy probe: 1 GiB read + 1 GiB written")
         del src, dst
-    log("generating the synthetic workload")
-    prob = datagen.make_config(1)
-    n, c, H, W, h, w, r = (prob[k] for k in ("n", "c", "H", "W", "h", "w", "r"))
-    eps_host = prob["eps"]
-    t = {k: prob[k].to(dev) for k in ("I_lo", "p_lo", "I_hi", "dq")}
-    eps = torch.tensor(eps_host, dtype=torch.float32, device=dev)
-    q = torch.empty_like(t["I_hi"])
-    outs = (torch.empty(t["I_lo"].shape, dtype=torch.float32, device=dev),
-            torch.empty(t["p_lo"].shape, dtype=torch.float32, device=dev),
-            torch.empty_like(t["I_hi"]),
-            torch.empty(1, dtype=torch.float32, device=dev))
-    desc = gf.make_desc(t["I_lo"], t["I_hi"], r)
-    ws = torch.empty(max(gf.gf_workspace_size(desc, None, 0), gf.gf_workspace_size(desc, None, 1)),
-                     dtype=torch.uint8, device=dev)
-
-    def step():
-        gf.forward(t["I_lo"], t["p_lo"], t["I_hi"], eps, r, out=q, ws=ws)
-        gf.backward(t["I_lo"], t["p_lo"], t["I_hi"], eps, t["dq"], r, ws=ws, outs=outs)
+    wl = WORKLOADS[args.workload](args, dev)
+    step = wl["step"]
 
     log(f"warmup {args.warmup} steps")
     for _ in range(args.warmup):
@@ -116,122 +430,93 @@ def main():
         step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    prof = gf.gf_profile_read()
+    prof = gf.gf_profile_read(64)
     gf.gf_profile_enable(False)
     sec = t1 - t0
-    mpx = n * H * W / 1e6
-    value = mpx * args.steps / sec
+    value = wl["mpx"] * args.steps / sec
     ms_per_step = 1e3 * sec / args.steps
     log(f"fused: {ms_per_step:.4f} ms/step, {value:.1f} Mpx/s")
 
-    algo = algorithmic_bytes(n, c, H, W, h, w)
+    prof_steps = args.steps
+    if not prof and "eager_step" in wl:
+        # graph replays record no per-kernel events: a separate eager pass
+        # (same launches, not timed as the step) gives the kernel breakdown
+        prof_steps = min(args.steps, 10)
+        gf.gf_profile_enable(True)
+        for _ in range(prof_steps):
+            wl["eager_step"]()
+        torch.cuda.synchronize()
+        prof = gf.gf_profile_read(64)
+        gf.gf_profile_enable(False)
     kernels = {}
     for name, (ms, cnt) in prof.items():
-        avg = ms / max(cnt, 1)
-        b = algo.get(name, 0)
-        kernels[name] = {"avg_us": round(1e3 * avg, 3), "launches": cnt,
-                         "algo_bytes": b, "algo_GBs": round(b / (avg * 1e-3) / 1e9, 1)}
-    dom = max(prof.items(), key=lambda kv: kv[1][0])[0]
-    dom_avg_s = prof[dom][0] / prof[dom][1] * 1e-3
-    achieved = algo[dom] / dom_avg_s / 1e9
+        b = wl["per_step"].get(name, 0)
+        step_s = ms / prof_steps * 1e-3
+        kernels[name] = {"avg_us": round(1e3 * ms / max(cnt, 1), 3), "launches": cnt,
+                         "us_per_step": round(1e6 * step_s, 3), "algo_bytes_per_step": b,
+                         "algo_GBs": round(b / step_s / 1e9, 1) if step_s > 0 else None}
+    # graph replays record no per-kernel events: fall back to the whole step
+    if prof:
+        dom = max(prof.items(), key=lambda kv: kv[1][0])[0]
+        dom_s = prof[dom][0] / prof_steps * 1e-3
+        dom_bytes = wl["per_step"].get(dom, 0)
+    else:
+        dom, dom_s, dom_bytes = "step (graph replay)", ms_per_step * 1e-3, wl["step_bytes"]
+    achieved = dom_bytes / dom_s / 1e9
     traffic = None
-    if os.path.exists(TRAFFIC_FILE):
+    if wl.get("traffic_ok") and os.path.exists(TRAFFIC_FILE):
         rec = json.load(open(TRAFFIC_FILE))
         if rec.get("kernel_src_sha256_16") == kernel_hash() and dom in rec.get("kernels", {}):
             traffic = rec["kernels"][dom]["hbm_bytes_per_launch"]
+    launches = prof[dom][1] / prof_steps if prof else 1
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "algo_bytes_per_launch": algo[dom]}
-    step_gbs = algo["step"] / (ms_per_step * 1e-3) / 1e9
+                "traffic": traffic,
+                "algo_bytes_per_launch": int(dom_bytes / max(launches, 1))}
+    step_gbs = wl["step_bytes"] / (ms_per_step * 1e-3) / 1e9
 
     out = {
-        "metric": "high-res Mpixel/s fwd+bwd, fused vs plain at stated max-abs error; % HBM peak",
-        "value": round(value, 1), "unit": "Mpixel/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic (seeded photo-like images: smooth field + step edges + noise)",
-        "config": {"workload": "guided filtering layer fwd+bwd, FP32, 4x3x2048x3072 high-res "
-                               "<- 512x768 low-res (s=4), r=1, eps=1e-4, window-mean of A,b, "
-                               "grads to p_l, I_l, I_h, eps",
-                   "n": n, "c": c, "H": H, "W": W, "s": prob["s"], "r": r, "eps": 1e-4},
-        "roofline": roofline,
-        "step_algo_GBs": round(step_gbs, 1),
-        "kernels": kernels,
+        "metric": METRIC, "value": round(value, 1), "unit": "Mpixel/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": wl["dtype"],
+        "data": DATA, "config": wl["config"], "roofline": roofline,
+        "step_algo_GBs": round(step_gbs, 1), "kernels": kernels,
     }
     if not args.no_plain:
-        out["plain"] = plain_leg(args, t, eps, r, mpx, value)
+        out["plain"] = plain_leg(args, wl, value)
     if not args.no_cpu:
-        out["cpu_baseline"], out["error_vs_fp64_oracle"] = cpu_leg(args, prob, q, outs, mpx)
+        out["cpu_baseline"], out["error_vs_fp64_oracle"] = cpu_leg(args, wl)
     print(json.dumps(out), flush=True)
 
 
-def plain_leg(args, t, eps, r, mpx, value):
+def plain_leg(args, wl, value):
     """The unfused PyTorch composition (autograd) on the same GPU and inputs."""
     import torch
-
-    from paper_1803_05619_amd import plain
     log(f"timing the plain PyTorch composition ({args.plain_steps} steps)")
-    I_lo = t["I_lo"].clone().requires_grad_(True)
-    p_lo = t["p_lo"].clone().requires_grad_(True)
-    I_hi = t["I_hi"].clone().requires_grad_(True)
-    eps_p = eps.clone().requires_grad_(True)
-
-    def plain_step():
-        for x in (I_lo, p_lo, I_hi, eps_p):
-            x.grad = None
-        qq = plain.guided_filter(I_lo, p_lo, I_hi, r, eps_p)
-        qq.backward(t["dq"])
-
     for _ in range(2):
-        plain_step()
+        wl["plain_step"]()
     torch.cuda.synchronize()
     p0 = time.perf_counter()
     for _ in range(args.plain_steps):
-        plain_step()
+        wl["plain_step"]()
     torch.cuda.synchronize()
     plain_ms = 1e3 * (time.perf_counter() - p0) / args.plain_steps
-    plain_val = mpx / (plain_ms * 1e-3)
-    del I_lo, p_lo, I_hi, eps_p
+    plain_val = wl["mpx"] / (plain_ms * 1e-3)
     torch.cuda.empty_cache()
     log(f"plain: {plain_ms:.3f} ms/step, {plain_val:.1f} Mpx/s")
     return {"value": round(plain_val, 1), "unit": "Mpixel/s", "ms_per_step": round(plain_ms, 3),
             "speedup_fused_vs_plain": round(value / plain_val, 2)}
 
 
-def cpu_leg(args, prob, q, outs, mpx):
-    """The FP64 oracle on the host cores (a bounded sample: the same batch,
-    repeated for about --cpu-seconds), and the error of the timed run's final
-    outputs against it."""
-    import numpy as np
-    import torch
-
-    import oracle
+def cpu_leg(args, wl):
+    """The FP64 oracle on the host cores over a bounded sample, and the
+    error of the timed run's final outputs on that sample."""
     log("CPU oracle leg (FP64, host cores)")
-    n, c, r, eps_host = prob["n"], prob["c"], prob["r"], prob["eps"]
-    args_np = [prob[k].double().numpy() for k in ("I_lo", "p_lo", "I_hi")]
-    dq_np = prob["dq"].double().numpy()
-    reps, tc0 = 0, time.perf_counter()
-    while True:
-        q_ref = oracle.forward(*args_np, r, eps_host)
-        g_ref = oracle.backward(*args_np, r, eps_host, dq_np)
-        reps += 1
-        el = time.perf_counter() - tc0
-        if el >= args.cpu_seconds or reps >= 20:
-            break
+    mpx, el, sample, planes, err = wl["cpu_sample"]()
     threads = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
-    cpu = {"value": round(mpx * reps / el, 3), "unit": "Mpixel/s",
-           "cores": min(threads, n * c), "kind": "oracle",
-           "sample": f"the full 4-image batch, fwd+bwd, repeated {reps}x ({el:.1f} s); "
-                     f"parallel over the {n * c} image planes with OpenMP "
-                     f"({threads} threads available)"}
-    torch.cuda.synchronize()
-    err = {"q_max_abs": float(np.abs(q.double().cpu().numpy() - q_ref).max())}
-    for name, got in (("dI_lo", outs[0]), ("dp_lo", outs[1]), ("dI_hi", outs[2])):
-        ref = g_ref[name]
-        err[name + "_scaled"] = float(np.abs(got.double().cpu().numpy() - ref).max() /
-                                      max(1.0, np.abs(ref).max()))
-    err["deps_scaled"] = float(abs(outs[3].item() - g_ref["deps"][0]) /
-                               max(1.0, g_ref["deps_abs"][0]))
+    cores = min(threads, planes)
+    cpu = {"value": round(mpx / el, 3), "unit": "Mpixel/s", "cores": cores, "kind": "oracle",
+           "sample": f"{sample}; OpenMP over planes ({threads} threads available)"}
     log(f"cpu oracle: {cpu['value']} Mpx/s; errors {err}")
     return cpu, {k: float(f"{v:.3e}") for k, v in err.items()}
 

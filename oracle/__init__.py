@@ -64,7 +64,7 @@ def _load():
         lib.gfo_forward.argtypes = [ci] * 11 + [ctypes.POINTER(_Guide), dp, dp, dp, dp, ci, dp]
         lib.gfo_forward.restype = ci
         lib.gfo_backward.argtypes = ([ci] * 11 + [ctypes.POINTER(_Guide), dp, dp, dp, dp, ci]
-                                     + [dp] * 7)
+                                     + [dp] * 8)
         lib.gfo_backward.restype = ci
         lib.gfo_guide_apply.argtypes = [ci, ctypes.POINTER(_Guide), ci, ci, ci, ctypes.c_long, dp, dp]
         lib.gfo_guide_apply.restype = ci
@@ -140,7 +140,9 @@ def backward(I_lo, p_lo, I_hi, r, eps, dq, *, align_corners=False, mean_ab=True,
 
     Returns a dict with dI_lo, dp_lo, dI_hi, deps (one entry per eps entry),
     deps_abs (sum of the magnitudes of the terms of deps, an error scale)
-    and, for the transform guide, dguide (flat, see guide_grad_split).
+    and, for the transform guide, dguide (flat, see guide_grad_split) and
+    dguide_abs (per entry, the sum of the magnitudes of the per-pixel terms
+    that entry adds up: the error scale of a sum, as deps_abs for deps).
     """
     lib = _load()
     I_lo, p_lo, I_hi, e, (n, c, h, w, H, W, cin) = _common(I_lo, p_lo, I_hi, eps)
@@ -155,20 +157,22 @@ def backward(I_lo, p_lo, I_hi, r, eps, dq, *, align_corners=False, mean_ab=True,
     dI_hi = np.empty_like(I_hi)
     deps = np.empty(e.size, np.float64)
     deps_abs = np.empty(e.size, np.float64)
-    dguide = None
+    dguide = dguide_abs = None
     if mode == GUIDE_MODES["transform"]:
         dguide = np.zeros(lib.gfo_guide_grad_size(cin, c, g.hidden), np.float64)
+        dguide_abs = np.zeros_like(dguide)
     rc = lib.gfo_backward(n, c, h, w, H, W, int(r), int(bool(align_corners)),
                           int(bool(mean_ab)), mode, cin,
                           ctypes.byref(g) if g is not None else None,
                           _ptr(I_lo), _ptr(p_lo), _ptr(I_hi), _ptr(e), e.size, _ptr(dq),
                           _ptr(dI_lo), _ptr(dp_lo), _ptr(dI_hi), _ptr(deps), _ptr(deps_abs),
-                          _ptr(dguide))
+                          _ptr(dguide), _ptr(dguide_abs))
     if rc != 0:
         raise RuntimeError(f"gfo_backward failed ({rc})")
     out = {"dI_lo": dI_lo, "dp_lo": dp_lo, "dI_hi": dI_hi, "deps": deps, "deps_abs": deps_abs}
     if dguide is not None:
         out["dguide"] = dguide
+        out["dguide_abs"] = dguide_abs
     return out
 
 

@@ -170,11 +170,14 @@ static int guide_forward(int mode, const gfo_guide_t *g, int n, int cin,
 }
 
 /* Adjoint of guide_forward.  dX[n, cin, P] is overwritten; parameter
- * gradients are ADDED into dparam (layout of gfo_guide_grad_size). */
+ * gradients are ADDED into dparam (layout of gfo_guide_grad_size), and, when
+ * dabs is not NULL, the magnitudes of the per-pixel terms each parameter
+ * gradient sums are ADDED into dabs (same layout): the scale of the
+ * rounding error any summation order of those terms can make. */
 static int guide_backward(int mode, const gfo_guide_t *g, int n, int cin,
                           int cout, long P, const double *X,
                           const guide_state_t *st, const double *dG,
-                          double *dX, double *dparam) {
+                          double *dX, double *dparam, double *dabs) {
   if (mode == GFO_GUIDE_IDENTITY) {
     memcpy(dX, dG, sizeof(double) * (size_t)n * cin * P);
     return 0;
@@ -204,6 +207,23 @@ static int guide_backward(int mode, const gfo_guide_t *g, int n, int cin,
   double *dgam = dmu + 1;
   double *dbet = dgam + K;
   const double cnt = (double)n * (double)P;
+  const long nparam = gfo_guide_grad_size(cin, cout, K);
+  double *abs_scratch = NULL;
+  if (dabs == NULL) {
+    abs_scratch = (double *)calloc((size_t)nparam, sizeof(double));
+    if (!abs_scratch) {
+      free(scratch_param);
+      return -2;
+    }
+    dabs = abs_scratch;
+  }
+  double *aw1 = dabs;
+  double *aw2 = aw1 + K * cin;
+  double *ab2 = aw2 + cout * K;
+  double *alam = ab2 + cout;
+  double *amu = alam + 1;
+  double *agam = amu + 1;
+  double *abet = agam + K;
 
   /* pass 1: everything up to d(hn); keep dy and dhn per pixel */
   double *dy = (double *)malloc(sizeof(double) * (size_t)n * K * P);
@@ -212,11 +232,15 @@ static int guide_backward(int mode, const gfo_guide_t *g, int n, int cin,
     free(dy);
     free(dhn);
     free(scratch_param);
+    free(abs_scratch);
     return -2;
   }
   for (int b = 0; b < n; ++b)
     for (long p = 0; p < P; ++p) {
-      for (int co = 0; co < cout; ++co) db2[co] += dG[((long)b * cout + co) * P + p];
+      for (int co = 0; co < cout; ++co) {
+        db2[co] += dG[((long)b * cout + co) * P + p];
+        ab2[co] += fabs(dG[((long)b * cout + co) * P + p]);
+      }
       for (int k = 0; k < K; ++k) {
         long idx = ((long)b * K + k) * P + p;
         double h = st->hpre[idx];
@@ -228,6 +252,7 @@ static int guide_backward(int mode, const gfo_guide_t *g, int n, int cin,
         for (int co = 0; co < cout; ++co) {
           double dg = dG[((long)b * cout + co) * P + p];
           dw2[co * K + k] += dg * z;
+          aw2[co * K + k] += fabs(dg * z);
           dz += g->w2[co * K + k] * dg;
         }
         double dyv = (y > 0.0) ? dz : g->slope * dz;
@@ -236,6 +261,10 @@ static int guide_backward(int mode, const gfo_guide_t *g, int n, int cin,
         double dbn = g->mu * dyv;
         dgam[k] += dbn * hn;
         dbet[k] += dbn;
+        *alam += fabs(dyv * h);
+        *amu += fabs(dyv * bn);
+        agam[k] += fabs(dbn * hn);
+        abet[k] += fabs(dbn);
         dy[idx] = dyv;
         dhn[idx] = g->gamma[k] * dbn;
       }
@@ -270,15 +299,20 @@ static int guide_backward(int mode, const gfo_guide_t *g, int n, int cin,
       }
   for (int k = 0; k < K; ++k)
     for (int ci = 0; ci < cin; ++ci) {
-      double s = 0.0;
+      double s = 0.0, sa = 0.0;
       for (int b = 0; b < n; ++b)
-        for (long p = 0; p < P; ++p)
-          s += dy[((long)b * K + k) * P + p] * X[((long)b * cin + ci) * P + p];
+        for (long p = 0; p < P; ++p) {
+          double t = dy[((long)b * K + k) * P + p] * X[((long)b * cin + ci) * P + p];
+          s += t;
+          sa += fabs(t);
+        }
       dw1[k * cin + ci] += s;
+      aw1[k * cin + ci] += sa;
     }
   free(dy);
   free(dhn);
   free(scratch_param);
+  free(abs_scratch);
   return 0;
 }
 
@@ -462,7 +496,7 @@ int gfo_backward(int n, int c, int h, int w, int H, int W, int r,
                  const double *p_lo, const double *I_hi, const double *eps,
                  int eps_count, const double *dq, double *dI_lo,
                  double *dp_lo, double *dI_hi, double *deps,
-                 double *deps_abs, double *dguide) {
+                 double *deps_abs, double *dguide, double *dguide_abs) {
   if (check_args(n, c, h, w, H, W, r, eps_count)) return -1;
   if (!guide_cout_ok(guide_mode, cin, c, gd)) return -1;
   const long Pl = (long)h * w, Ph = (long)H * W;
@@ -621,12 +655,15 @@ int gfo_backward(int n, int c, int h, int w, int H, int W, int r,
   /* through the guidance transform (shared by both resolutions) */
   if (!fail && dguide && guide_mode == GFO_GUIDE_TRANSFORM)
     memset(dguide, 0, sizeof(double) * (size_t)gfo_guide_grad_size(cin, c, gd->hidden));
+  if (!fail && dguide_abs && guide_mode == GFO_GUIDE_TRANSFORM)
+    memset(dguide_abs, 0, sizeof(double) * (size_t)gfo_guide_grad_size(cin, c, gd->hidden));
   if (!fail) {
     double *tmp = dI_lo;
     double *own = NULL;
     if (!tmp) tmp = own = (double *)malloc(sizeof(double) * (size_t)n * cin * Pl);
     if (!tmp) fail = 1;
-    else if (guide_backward(guide_mode, gd, n, cin, c, Pl, I_lo, &sl, dGl, tmp, dguide))
+    else if (guide_backward(guide_mode, gd, n, cin, c, Pl, I_lo, &sl, dGl, tmp, dguide,
+                            dguide_abs))
       fail = 1;
     free(own);
   }
@@ -635,7 +672,8 @@ int gfo_backward(int n, int c, int h, int w, int H, int W, int r,
     double *own = NULL;
     if (!tmp) tmp = own = (double *)malloc(sizeof(double) * (size_t)n * cin * Ph);
     if (!tmp) fail = 1;
-    else if (guide_backward(guide_mode, gd, n, cin, c, Ph, I_hi, &sh, dGh, tmp, dguide))
+    else if (guide_backward(guide_mode, gd, n, cin, c, Ph, I_hi, &sh, dGh, tmp, dguide,
+                            dguide_abs))
       fail = 1;
     free(own);
   }

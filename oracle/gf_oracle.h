@@ -59,7 +59,7 @@ int gfo_backward(int n, int c, int h, int w, int H, int W, int r,
                  const double *p_lo, const double *I_hi, const double *eps,
                  int eps_count, const double *dq, double *dI_lo,
                  double *dp_lo, double *dI_hi, double *deps, double *deps_abs,
-                 double *dguide);
+                 double *dguide, double *dguide_abs);
 
 #ifdef __cplusplus
 }

@@ -173,7 +173,9 @@ int make_plan(const gf_desc_t* d, const gf_guide_t* g, Plan* p, const char** why
     // identity layout (a superset is allocated for both directions)
     const size_t lo = (size_t)q.planes * q.h * q.w * sizeof(float);
     const size_t hi = (size_t)q.planes * q.H * q.W * sizeof(float);
-    auto chunks = [](long long P) { return (int)std::min<long long>(64, (P + 16383) / 16384); };
+    // reduction chunks per image: about 8 K pixels each (enough workgroups
+    // to fill the chip), at most 256
+    auto chunks = [](long long P) { return (int)std::min<long long>(256, (P + 8191) / 8192); };
     q.g_chunks_lo = chunks((long long)q.h * q.w);
     q.g_chunks_hi = chunks((long long)q.H * q.W);
     size_t o = align_up(std::max(q.ws_fwd, q.ws_bwd), 256);

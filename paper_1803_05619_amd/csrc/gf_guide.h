@@ -10,7 +10,7 @@
 //   guide_fold_kernel    batch mean/covariance -> BN statistics of h = W1 x
 //                        (mean W1 m, variance W1 C W1^T) -> per-call folded
 //                        constants y_k = w1f_k . x + bf_k
-//   guide_map_kernel     G = F(x) per pixel
+//   guide_map_*_kernel   G = F(x) per pixel
 //   guide_bwd_kernel     grey: dx directly; transform: per-chunk sums of
 //                        dG, dG z^T, dy, dy x^T (the only pixel sums the
 //                        parameter gradients need)
@@ -119,33 +119,53 @@ __device__ __forceinline__ float load_any(const void* x, int dtype, long long i)
   return to_f(reinterpret_cast<const bf16*>(x)[i]);
 }
 
-// One workgroup (thread 0 does the arithmetic; the data is tiny).
-__global__ __launch_bounds__(64) void guide_fold_kernel(FoldArgs a) {
-  if (threadIdx.x != 0) return;
-  float mean[3], cov[9];
-  if (a.stats_in) {
-    for (int i = 0; i < 3; ++i) mean[i] = a.stats_in[i];
-    for (int i = 0; i < 9; ++i) cov[i] = a.stats_in[3 + i];
-  } else {
-    float S[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    for (int q = 0; q < a.npart; ++q)
-      for (int k = 0; k < 9; ++k) S[k] += a.part[(size_t)q * kMomFloats + k];
-    const float inv = 1.f / a.count;
-    const float sh[3] = {load_any(a.x, a.dtype, 0), load_any(a.x, a.dtype, a.P),
-                         load_any(a.x, a.dtype, 2 * a.P)};
-    float d[3];
-    for (int i = 0; i < 3; ++i) {
-      d[i] = S[i] * inv;  // mean of the shifted values
-      mean[i] = sh[i] + d[i];
+// One workgroup: the partials are summed by all 256 threads in a fixed
+// order (strided, then a tree), the tiny fold arithmetic runs on thread 0.
+__global__ __launch_bounds__(256) void guide_fold_kernel(FoldArgs a) {
+  __shared__ float red[9][256];
+  const int tid = threadIdx.x;
+  if (!a.stats_in) {
+    float acc[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int q = tid; q < a.npart; q += 256)
+#pragma unroll
+      for (int k = 0; k < 9; ++k) acc[k] += a.part[(size_t)q * kMomFloats + k];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) red[k][tid] = acc[k];
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+      if (tid < st)
+#pragma unroll
+        for (int k = 0; k < 9; ++k) red[k][tid] += red[k][tid + st];
+      __syncthreads();
     }
-    const int idx[3][3] = {{3, 4, 5}, {4, 6, 7}, {5, 7, 8}};
-    for (int i = 0; i < 3; ++i)
-      for (int j = 0; j < 3; ++j) cov[i * 3 + j] = S[idx[i][j]] * inv - d[i] * d[j];
   }
-  if (a.stats_out) {
-    for (int i = 0; i < 3; ++i) a.stats_out[i] = mean[i];
-    for (int i = 0; i < 9; ++i) a.stats_out[3 + i] = cov[i];
+  __shared__ float st[12];  // batch mean (3) and covariance (9) of x
+  if (tid == 0) {
+    float mean[3], cov[9];
+    if (a.stats_in) {
+      for (int i = 0; i < 3; ++i) mean[i] = a.stats_in[i];
+      for (int i = 0; i < 9; ++i) cov[i] = a.stats_in[3 + i];
+    } else {
+      float S[9];
+      for (int k = 0; k < 9; ++k) S[k] = red[k][0];
+      const float inv = 1.f / a.count;
+      const float sh[3] = {load_any(a.x, a.dtype, 0), load_any(a.x, a.dtype, a.P),
+                           load_any(a.x, a.dtype, 2 * a.P)};
+      float d[3];
+      for (int i = 0; i < 3; ++i) {
+        d[i] = S[i] * inv;  // mean of the shifted values
+        mean[i] = sh[i] + d[i];
+      }
+      const int idx[3][3] = {{3, 4, 5}, {4, 6, 7}, {5, 7, 8}};
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) cov[i * 3 + j] = S[idx[i][j]] * inv - d[i] * d[j];
+    }
+    for (int i = 0; i < 3; ++i) st[i] = mean[i];
+    for (int i = 0; i < 9; ++i) st[3 + i] = cov[i];
+    if (a.stats_out)
+      for (int i = 0; i < 12; ++i) a.stats_out[i] = st[i];
   }
+  __syncthreads();
   const int K = a.hidden;
   const float* W1 = a.params;
   const float* W2 = W1 + 3 * K;
@@ -154,37 +174,132 @@ __global__ __launch_bounds__(64) void guide_fold_kernel(FoldArgs a) {
   const float* gamma = b2 + 5;
   const float* beta = gamma + K;
   float* f = a.fold;
-  for (int i = 0; i < kFoldFloats; ++i) f[i] = 0.f;
-  for (int k = 0; k < K; ++k) {
-    float m = 0.f, v = 0.f;
-    for (int i = 0; i < 3; ++i) {
-      m += W1[k * 3 + i] * mean[i];
-      for (int j = 0; j < 3; ++j) v += W1[k * 3 + i] * W1[k * 3 + j] * cov[i * 3 + j];
+  // one thread per (padded) hidden channel; padding channels get zeros
+  if (tid < kKP) {
+    const int k = tid;
+    float m = 0.f, v = 0.f, w[3] = {0.f, 0.f, 0.f}, g = 0.f, be = 0.f, rstd = 0.f;
+    if (k < K) {
+      for (int i = 0; i < 3; ++i) w[i] = W1[k * 3 + i];
+      for (int i = 0; i < 3; ++i) {
+        m += w[i] * st[i];
+        for (int j = 0; j < 3; ++j) v += w[i] * w[j] * st[3 + i * 3 + j];
+      }
+      rstd = 1.f / sqrtf(fmaxf(v, 0.f) + a.bn_eps);
+      g = gamma[k];
+      be = beta[k];
     }
-    const float rstd = 1.f / sqrtf(fmaxf(v, 0.f) + a.bn_eps);
-    const float ak = lam + mu * gamma[k] * rstd;
+    const float ak = k < K ? lam + mu * g * rstd : 0.f;
     for (int i = 0; i < 3; ++i) {
-      f[FO_W1F + k * 3 + i] = ak * W1[k * 3 + i];
-      f[FO_W1 + k * 3 + i] = W1[k * 3 + i];
+      f[FO_W1F + k * 3 + i] = ak * w[i];
+      f[FO_W1 + k * 3 + i] = w[i];
     }
-    f[FO_BF + k] = mu * (beta[k] - gamma[k] * m * rstd);
-    for (int c = 0; c < 3; ++c) f[FO_W2 + c * kKP + k] = W2[c * K + k];
+    f[FO_BF + k] = k < K ? mu * (be - g * m * rstd) : 0.f;
+    for (int c = 0; c < 3; ++c) f[FO_W2 + c * kKP + k] = k < K ? W2[c * K + k] : 0.f;
     f[FO_M + k] = m;
     f[FO_RSTD + k] = rstd;
-    f[FO_CDH + k] = mu * gamma[k] * rstd;
-    f[FO_GAM + k] = gamma[k];
-    f[FO_BET + k] = beta[k];
+    f[FO_CDH + k] = mu * g * rstd;
+    f[FO_GAM + k] = g;
+    f[FO_BET + k] = be;
+    f[FO_MDY + k] = 0.f;
+    f[FO_MDYHN + k] = 0.f;
+  } else if (tid == kKP) {
+    for (int c = 0; c < 3; ++c) f[FO_B2 + c] = b2[c];
+    f[FO_SCAL + 0] = lam;
+    f[FO_SCAL + 1] = mu;
+    f[FO_SCAL + 2] = a.slope;
+    f[FO_SCAL + 3] = a.count;
+    for (int i = 0; i < 3; ++i) f[FO_MEAN + i] = st[i];
+    for (int i = 0; i < 9; ++i) f[FO_COV + i] = st[3 + i];
   }
-  for (int c = 0; c < 3; ++c) f[FO_B2 + c] = b2[c];
-  f[FO_SCAL + 0] = lam;
-  f[FO_SCAL + 1] = mu;
-  f[FO_SCAL + 2] = a.slope;
-  f[FO_SCAL + 3] = a.count;
-  for (int i = 0; i < 3; ++i) f[FO_MEAN + i] = mean[i];
-  for (int i = 0; i < 9; ++i) f[FO_COV + i] = cov[i];
 }
 
 // ------------------------------------------------------------ per-pixel map
+
+// The folded constants one pixel of the transform needs, copied into
+// registers before the pixel loop (uniform: the compiler keeps them in
+// scalar registers where it can).
+struct FoldRegs {
+  float w1f[kKP][3], bf[kKP], w2[3][kKP], b2[3], slope;
+};
+
+__device__ __forceinline__ void load_fold(const float* __restrict__ f, FoldRegs& c) {
+#pragma unroll
+  for (int k = 0; k < kKP; ++k) {
+    c.w1f[k][0] = f[FO_W1F + 3 * k];
+    c.w1f[k][1] = f[FO_W1F + 3 * k + 1];
+    c.w1f[k][2] = f[FO_W1F + 3 * k + 2];
+    c.bf[k] = f[FO_BF + k];
+    c.w2[0][k] = f[FO_W2 + k];
+    c.w2[1][k] = f[FO_W2 + kKP + k];
+    c.w2[2][k] = f[FO_W2 + 2 * kKP + k];
+  }
+  c.b2[0] = f[FO_B2];
+  c.b2[1] = f[FO_B2 + 1];
+  c.b2[2] = f[FO_B2 + 2];
+  c.slope = f[FO_SCAL + 2];
+}
+
+// G of PX pixels in FP64 (one rounding at the store): the filter amplifies
+// per-pixel noise in G by the inverse local spread of G, so G carries only
+// its own half-ulp rounding (the folded constants are FP32; their rounding
+// perturbs G smoothly across pixels, which the filter does not amplify).
+// The constants sit in LDS as FP64 (row k: w1f[k][0..2], bf[k], w2[0..2][k]);
+// PX pixels share each read.
+struct FoldF64 {
+  double k[kKP][8];
+  double b2[3], slope;
+};
+
+__device__ __forceinline__ void stage_fold_f64(const float* __restrict__ f, FoldF64& c) {
+  const int t = threadIdx.x;
+  if (t < kKP) {
+    c.k[t][0] = f[FO_W1F + 3 * t];
+    c.k[t][1] = f[FO_W1F + 3 * t + 1];
+    c.k[t][2] = f[FO_W1F + 3 * t + 2];
+    c.k[t][3] = f[FO_BF + t];
+    c.k[t][4] = f[FO_W2 + t];
+    c.k[t][5] = f[FO_W2 + kKP + t];
+    c.k[t][6] = f[FO_W2 + 2 * kKP + t];
+    c.k[t][7] = 0.0;
+  } else if (t == kKP) {
+    c.b2[0] = f[FO_B2];
+    c.b2[1] = f[FO_B2 + 1];
+    c.b2[2] = f[FO_B2 + 2];
+    c.slope = f[FO_SCAL + 2];
+  }
+  __syncthreads();
+}
+
+template <int PX>
+__device__ __forceinline__ void transform_px(const FoldF64& c, const float (&x)[3][PX],
+                                             float (&g)[3][PX]) {
+  double acc[3][PX], xd[3][PX];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int e = 0; e < PX; ++e) {
+      acc[i][e] = c.b2[i];
+      xd[i][e] = x[i][e];
+    }
+  const double slope = c.slope;
+#pragma unroll 2
+  for (int k = 0; k < kKP; ++k) {
+    const double a0 = c.k[k][0], a1 = c.k[k][1], a2 = c.k[k][2], bb = c.k[k][3];
+    const double v0 = c.k[k][4], v1 = c.k[k][5], v2 = c.k[k][6];
+#pragma unroll
+    for (int e = 0; e < PX; ++e) {
+      const double y = bb + a0 * xd[0][e] + a1 * xd[1][e] + a2 * xd[2][e];
+      const double z = y > 0.0 ? y : slope * y;
+      acc[0][e] += v0 * z;
+      acc[1][e] += v1 * z;
+      acc[2][e] += v2 * z;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int e = 0; e < PX; ++e) g[i][e] = (float)acc[i][e];
+}
 
 struct MapArgs {
   const void* x;   // [n][c_in][P]
@@ -194,44 +309,53 @@ struct MapArgs {
   const float* fold;
 };
 
-// MODE: GF_GUIDE_GREY or GF_GUIDE_TRANSFORM.
-template <typename TX, int MODE>
-__global__ __launch_bounds__(256) void guide_map_kernel(MapArgs a) {
+// Grey map: every output channel is the mean of the c_in input channels.
+template <typename TX>
+__global__ __launch_bounds__(256) void guide_map_grey_kernel(MapArgs a) {
   const TX* X = reinterpret_cast<const TX*>(a.x) + (size_t)blockIdx.y * a.c_in * a.P;
   float* G = a.G + (size_t)blockIdx.y * a.c * a.P;
   for (long long p = (long long)blockIdx.x * 256 + threadIdx.x; p < a.P;
        p += (long long)gridDim.x * 256) {
-    if (MODE == GF_GUIDE_GREY) {
-      float s = 0.f;
+    float s = 0.f;
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
-        if (i < a.c_in) s += to_f(X[i * a.P + p]);
-      s *= 1.f / (float)a.c_in;
+    for (int i = 0; i < 4; ++i)
+      if (i < a.c_in) s += to_f(X[i * a.P + p]);
+    s *= 1.f / (float)a.c_in;
 #pragma unroll
-      for (int c = 0; c < 4; ++c)
-        if (c < a.c) G[c * a.P + p] = s;
-    } else {
-      // FP64 arithmetic, one rounding at the store: the filter amplifies
-      // per-pixel noise in G by the inverse local spread of G, so G carries
-      // only its own half-ulp rounding (the folded constants are FP32; their
-      // rounding perturbs G smoothly across pixels, which the filter does
-      // not amplify).
-      const float* f = a.fold;
-      const double x0 = to_f(X[p]), x1 = to_f(X[a.P + p]), x2 = to_f(X[2 * a.P + p]);
-      double g0 = f[FO_B2], g1 = f[FO_B2 + 1], g2 = f[FO_B2 + 2];
-      const double slope = f[FO_SCAL + 2];
+    for (int c = 0; c < 4; ++c)
+      if (c < a.c) G[c * a.P + p] = s;
+  }
+}
+
+// Transform map: 4 adjacent pixels per thread (vector loads and stores)
+// when the plane size allows, else one.
+template <typename TX>
+__global__ __launch_bounds__(256) void guide_map_transform_kernel(MapArgs a) {
+  const TX* __restrict__ X = reinterpret_cast<const TX*>(a.x) + (size_t)blockIdx.y * 3 * a.P;
+  float* __restrict__ G = a.G + (size_t)blockIdx.y * 3 * a.P;
+  __shared__ FoldF64 c;
+  stage_fold_f64(a.fold, c);
+  const long long stride = (long long)gridDim.x * 256;
+  if ((a.P & 3) == 0) {
+    const long long P4 = a.P >> 2;
+    for (long long v = (long long)blockIdx.x * 256 + threadIdx.x; v < P4; v += stride) {
+      float x[3][4], g[3][4];
 #pragma unroll
-      for (int k = 0; k < kKP; ++k) {
-        const double y = (double)f[FO_BF + k] + (double)f[FO_W1F + 3 * k] * x0 +
-                         (double)f[FO_W1F + 3 * k + 1] * x1 + (double)f[FO_W1F + 3 * k + 2] * x2;
-        const double z = y > 0.0 ? y : slope * y;
-        g0 += (double)f[FO_W2 + k] * z;
-        g1 += (double)f[FO_W2 + kKP + k] * z;
-        g2 += (double)f[FO_W2 + 2 * kKP + k] * z;
-      }
-      G[p] = (float)g0;
-      G[a.P + p] = (float)g1;
-      G[2 * a.P + p] = (float)g2;
+      for (int i = 0; i < 3; ++i) load_vec<TX, 4>(X + i * a.P + 4 * v, x[i]);
+      transform_px<4>(c, x, g);
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+        *reinterpret_cast<float4*>(G + i * a.P + 4 * v) = make_float4(g[i][0], g[i][1], g[i][2],
+                                                                      g[i][3]);
+    }
+  } else {
+    for (long long p = (long long)blockIdx.x * 256 + threadIdx.x; p < a.P; p += stride) {
+      float x[3][1], g[3][1];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) x[i][0] = to_f(X[i * a.P + p]);
+      transform_px<1>(c, x, g);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) G[i * a.P + p] = g[i][0];
     }
   }
 }
@@ -267,8 +391,10 @@ __global__ __launch_bounds__(256) void guide_bwd_kernel(GBwdArgs a) {
     }
     return;
   }
-  const float* f = a.fold;
-  const float slope = f[FO_SCAL + 2];
+  const float* __restrict__ f = a.fold;
+  FoldRegs c;
+  load_fold(f, c);
+  const float slope = c.slope;
   const float mx0 = f[FO_MEAN], mx1 = f[FO_MEAN + 1], mx2 = f[FO_MEAN + 2];
   float acc[AC_N];
 #pragma unroll
@@ -281,14 +407,13 @@ __global__ __launch_bounds__(256) void guide_bwd_kernel(GBwdArgs a) {
     acc[AC_DG + 2] += d2;
 #pragma unroll
     for (int k = 0; k < kKP; ++k) {
-      const float y = f[FO_BF + k] + f[FO_W1F + 3 * k] * x0 + f[FO_W1F + 3 * k + 1] * x1 +
-                      f[FO_W1F + 3 * k + 2] * x2;
+      const float y = c.bf[k] + c.w1f[k][0] * x0 + c.w1f[k][1] * x1 + c.w1f[k][2] * x2;
       const bool pos = y > 0.f;
       const float z = pos ? y : slope * y;
       acc[AC_DGZ + k] += d0 * z;
       acc[AC_DGZ + kKP + k] += d1 * z;
       acc[AC_DGZ + 2 * kKP + k] += d2 * z;
-      const float dz = f[FO_W2 + k] * d0 + f[FO_W2 + kKP + k] * d1 + f[FO_W2 + 2 * kKP + k] * d2;
+      const float dz = c.w2[0][k] * d0 + c.w2[1][k] * d1 + c.w2[2][k] * d2;
       const float dy = pos ? dz : slope * dz;
       acc[AC_DY + k] += dy;
       acc[AC_DYX + 3 * k] += dy * (x0 - mx0);
@@ -313,13 +438,20 @@ __global__ __launch_bounds__(256) void guide_bwd_kernel(GBwdArgs a) {
         ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
 }
 
+// One workgroup per accumulator; fixed-order sum (strided, then a tree).
 __global__ __launch_bounds__(256) void guide_acc_reduce_kernel(const float* part, int npart,
                                                                 float* tot) {
-  for (int k = threadIdx.x; k < AC_N; k += 256) {
-    float s = 0.f;
-    for (int q = 0; q < npart; ++q) s += part[(size_t)q * kAccFloats + k];
-    tot[k] = s;
+  __shared__ float red[256];
+  const int k = blockIdx.x, tid = threadIdx.x;
+  float s = 0.f;
+  for (int q = tid; q < npart; q += 256) s += part[(size_t)q * kAccFloats + k];
+  red[tid] = s;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (tid < st) red[tid] += red[tid + st];
+    __syncthreads();
   }
+  if (tid == 0) tot[k] = red[0];
 }
 
 // Parameter gradients from the two calls' totals (I_lo call first, then
@@ -333,30 +465,29 @@ struct GradArgs {
 };
 
 __global__ __launch_bounds__(64) void guide_grad_kernel(GradArgs a) {
-  if (threadIdx.x != 0) return;
-  const int K = a.hidden;
+  // one thread per hidden channel; lam and mu sum the channels' shares in
+  // channel order afterwards
+  __shared__ float slam[kKP], smu[kKP];
+  const int K = a.hidden, k = threadIdx.x;
   float* d = a.dparams;
-  float* dW1 = d;
-  float* dW2 = d ? d + 3 * K : nullptr;
-  float* db2 = d ? dW2 + 3 * K : nullptr;
-  float* dlam = d ? db2 + 3 : nullptr;
-  float* dmu = d ? dlam + 1 : nullptr;
-  float* dgam = d ? dmu + 1 : nullptr;
-  float* dbet = d ? dgam + K : nullptr;
-  if (d)
-    for (int i = 0; i < 3 * K + 3 * K + 3 + 2 + 2 * K; ++i) d[i] = 0.f;
-  for (int call = 0; call < 2; ++call) {
-    const float* T = a.tot[call];
-    float* f = a.fold[call];
-    const float lam = f[FO_SCAL], mu = f[FO_SCAL + 1], P = f[FO_SCAL + 3];
-    const float* mean = f + FO_MEAN;
-    const float* cov = f + FO_COV;
-    // With e = x - mean(x) (the accumulators hold sums of dy e):
-    //   sum dy_k h_k        = W1_k . sum dy_k e + m_k sum dy_k
-    //   sum dy_k hn_k       = rstd_k W1_k . sum dy_k e
-    //   sum hn_k x_i        = rstd_k P (W1_k C)_i          (C: covariance of x)
-    //   sum dy_k x_i - mean(dy_k) sum x_i = sum dy_k e_i
-    for (int k = 0; k < K; ++k) {
+  if (k < kKP) {
+    slam[k] = 0.f;
+    smu[k] = 0.f;
+  }
+  if (k < K) {
+    float dw1[3] = {0.f, 0.f, 0.f}, dw2[3] = {0.f, 0.f, 0.f};
+    float dl = 0.f, dm = 0.f, dg = 0.f, db = 0.f;
+    for (int call = 0; call < 2; ++call) {
+      const float* T = a.tot[call];
+      float* f = a.fold[call];
+      const float lam = f[FO_SCAL], mu = f[FO_SCAL + 1], P = f[FO_SCAL + 3];
+      const float* mean = f + FO_MEAN;
+      const float* cov = f + FO_COV;
+      // With e = x - mean(x) (the accumulators hold sums of dy e):
+      //   sum dy_k h_k        = W1_k . sum dy_k e + m_k sum dy_k
+      //   sum dy_k hn_k       = rstd_k W1_k . sum dy_k e
+      //   sum hn_k x_i        = rstd_k P (W1_k C)_i          (C: covariance of x)
+      //   sum dy_k x_i - mean(dy_k) sum x_i = sum dy_k e_i
       const float* W1 = f + FO_W1 + 3 * k;
       const float* Se = T + AC_DYX + 3 * k;
       const float m = f[FO_M + k], rstd = f[FO_RSTD + k], cdh = f[FO_CDH + k];
@@ -365,21 +496,37 @@ __global__ __launch_bounds__(64) void guide_grad_kernel(GradArgs a) {
       const float sdyhn = rstd * sdye;
       f[FO_MDY + k] = sdy / P;
       f[FO_MDYHN + k] = sdyhn / P;
-      if (!d) continue;
       for (int i = 0; i < 3; ++i) {
         const float wc = W1[0] * cov[i] + W1[1] * cov[3 + i] + W1[2] * cov[6 + i];
         const float shnx = rstd * P * wc;
-        dW1[3 * k + i] += lam * (Se[i] + mean[i] * sdy) + cdh * (Se[i] - (sdyhn / P) * shnx);
+        dw1[i] += lam * (Se[i] + mean[i] * sdy) + cdh * (Se[i] - (sdyhn / P) * shnx);
       }
       const float gamma = f[FO_GAM + k], beta = f[FO_BET + k];
-      *dlam += sdye + m * sdy;
-      *dmu += gamma * sdyhn + beta * sdy;
-      dgam[k] += mu * sdyhn;
-      dbet[k] += mu * sdy;
-      for (int c = 0; c < 3; ++c) dW2[c * K + k] += T[AC_DGZ + c * kKP + k];
+      dl += sdye + m * sdy;
+      dm += gamma * sdyhn + beta * sdy;
+      dg += mu * sdyhn;
+      db += mu * sdy;
+      for (int c = 0; c < 3; ++c) dw2[c] += T[AC_DGZ + c * kKP + k];
     }
-    if (d)
-      for (int c = 0; c < 3; ++c) db2[c] += T[AC_DG + c];
+    if (d) {
+      for (int i = 0; i < 3; ++i) d[3 * k + i] = dw1[i];
+      for (int c = 0; c < 3; ++c) d[3 * K + c * K + k] = dw2[c];
+      d[6 * K + 5 + k] = dg;
+      d[7 * K + 5 + k] = db;
+    }
+    slam[k] = dl;
+    smu[k] = dm;
+  }
+  __syncthreads();
+  if (k == 0 && d) {
+    float dl = 0.f, dm = 0.f;
+    for (int j = 0; j < K; ++j) {
+      dl += slam[j];
+      dm += smu[j];
+    }
+    for (int c = 0; c < 3; ++c) d[6 * K + c] = a.tot[0][AC_DG + c] + a.tot[1][AC_DG + c];
+    d[6 * K + 3] = dl;
+    d[6 * K + 4] = dm;
   }
 }
 
@@ -388,11 +535,25 @@ __global__ __launch_bounds__(64) void guide_grad_kernel(GradArgs a) {
 template <typename TX, typename TDX>
 __global__ __launch_bounds__(256) void guide_dx_kernel(GBwdArgs a) {
   const int b = blockIdx.y;
-  const TX* X = reinterpret_cast<const TX*>(a.x) + (size_t)b * 3 * a.P;
-  const float* dG = a.dG + (size_t)b * 3 * a.P;
-  TDX* dX = reinterpret_cast<TDX*>(a.dx) + (size_t)b * 3 * a.P;
-  const float* f = a.fold;
-  const float lam = f[FO_SCAL], slope = f[FO_SCAL + 2];
+  const TX* __restrict__ X = reinterpret_cast<const TX*>(a.x) + (size_t)b * 3 * a.P;
+  const float* __restrict__ dG = a.dG + (size_t)b * 3 * a.P;
+  TDX* __restrict__ dX = reinterpret_cast<TDX*>(a.dx) + (size_t)b * 3 * a.P;
+  const float* __restrict__ f = a.fold;
+  FoldRegs c;
+  load_fold(f, c);
+  float w1[kKP][3], m[kKP], rstd[kKP], cdh[kKP], mdy[kKP], mdyhn[kKP];
+#pragma unroll
+  for (int k = 0; k < kKP; ++k) {
+    w1[k][0] = f[FO_W1 + 3 * k];
+    w1[k][1] = f[FO_W1 + 3 * k + 1];
+    w1[k][2] = f[FO_W1 + 3 * k + 2];
+    m[k] = f[FO_M + k];
+    rstd[k] = f[FO_RSTD + k];
+    cdh[k] = f[FO_CDH + k];
+    mdy[k] = f[FO_MDY + k];
+    mdyhn[k] = f[FO_MDYHN + k];
+  }
+  const float lam = f[FO_SCAL], slope = c.slope;
   for (long long p = (long long)blockIdx.x * 256 + threadIdx.x; p < a.P;
        p += (long long)gridDim.x * 256) {
     const float x0 = to_f(X[p]), x1 = to_f(X[a.P + p]), x2 = to_f(X[2 * a.P + p]);
@@ -400,17 +561,15 @@ __global__ __launch_bounds__(256) void guide_dx_kernel(GBwdArgs a) {
     float o0 = 0.f, o1 = 0.f, o2 = 0.f;
 #pragma unroll
     for (int k = 0; k < kKP; ++k) {
-      const float y = f[FO_BF + k] + f[FO_W1F + 3 * k] * x0 + f[FO_W1F + 3 * k + 1] * x1 +
-                      f[FO_W1F + 3 * k + 2] * x2;
-      const float dz = f[FO_W2 + k] * d0 + f[FO_W2 + kKP + k] * d1 + f[FO_W2 + 2 * kKP + k] * d2;
+      const float y = c.bf[k] + c.w1f[k][0] * x0 + c.w1f[k][1] * x1 + c.w1f[k][2] * x2;
+      const float dz = c.w2[0][k] * d0 + c.w2[1][k] * d1 + c.w2[2][k] * d2;
       const float dy = y > 0.f ? dz : slope * dz;
-      const float h = f[FO_W1 + 3 * k] * x0 + f[FO_W1 + 3 * k + 1] * x1 + f[FO_W1 + 3 * k + 2] * x2;
-      const float hn = (h - f[FO_M + k]) * f[FO_RSTD + k];
-      const float dh =
-          lam * dy + f[FO_CDH + k] * (dy - f[FO_MDY + k] - hn * f[FO_MDYHN + k]);
-      o0 += f[FO_W1 + 3 * k] * dh;
-      o1 += f[FO_W1 + 3 * k + 1] * dh;
-      o2 += f[FO_W1 + 3 * k + 2] * dh;
+      const float h = w1[k][0] * x0 + w1[k][1] * x1 + w1[k][2] * x2;
+      const float hn = (h - m[k]) * rstd[k];
+      const float dh = lam * dy + cdh[k] * (dy - mdy[k] - hn * mdyhn[k]);
+      o0 += w1[k][0] * dh;
+      o1 += w1[k][1] * dh;
+      o2 += w1[k][2] * dh;
     }
     dX[p] = from_f<TDX>(o0);
     dX[a.P + p] = from_f<TDX>(o1);
@@ -434,7 +593,7 @@ hipError_t guided_fold(const Plan& p, const void* x, long long P, int chunks, fl
   FoldArgs f{part, chunks * p.n, x, p.dtype, P, (float)((double)P * p.n), p.gparams,
              p.hidden, p.bn_eps, p.slope, stats_in, stats_out, fold};
   prof_begin("gf_guide_fold", s);
-  hipLaunchKernelGGL(guide_fold_kernel, dim3(1), dim3(64), 0, s, f);
+  hipLaunchKernelGGL(guide_fold_kernel, dim3(1), dim3(256), 0, s, f);
   prof_end(s);
   return hipGetLastError();
 }
@@ -445,10 +604,10 @@ hipError_t guided_map(const Plan& p, const void* x, float* G, long long P, int c
   MapArgs m{x, G, P, p.c_in, p.c, fold};
   prof_begin("gf_guide_map", s);
   if (p.gmode == GF_GUIDE_GREY)
-    hipLaunchKernelGGL((guide_map_kernel<T, GF_GUIDE_GREY>), dim3(chunks * 4, p.n), dim3(256), 0,
+    hipLaunchKernelGGL((guide_map_grey_kernel<T>), dim3(chunks * 4, p.n), dim3(256), 0,
                        s, m);
   else
-    hipLaunchKernelGGL((guide_map_kernel<T, GF_GUIDE_TRANSFORM>), dim3(chunks * 4, p.n),
+    hipLaunchKernelGGL((guide_map_transform_kernel<T>), dim3(chunks * 4, p.n),
                        dim3(256), 0, s, m);
   prof_end(s);
   return hipGetLastError();
@@ -561,7 +720,7 @@ hipError_t backward_guided_t(const Plan& p, const BwdArgs& b, hipStream_t s) {
       e = hipGetLastError();
       if (e != hipSuccess) return e;
       prof_begin("gf_guide_acc_reduce", s);
-      hipLaunchKernelGGL(guide_acc_reduce_kernel, dim3(1), dim3(256), 0, s,
+      hipLaunchKernelGGL(guide_acc_reduce_kernel, dim3(AC_N), dim3(256), 0, s,
                          part + (lo ? 0 : half), chunks * p.n, tot + call * kAccFloats);
       prof_end(s);
       e = hipGetLastError();

@@ -164,15 +164,12 @@ def make_config(i: int, *, div: int = 1, r: int | None = None, with_dq: bool = T
     return prob
 
 
-def batched_items(count: int = 64, *, div: int = 1, seed_config: int = 3,
-                  io_dtype: str = "f32") -> list:
-    """The uneven batch: per-image (H, W, s, r, eps) drawn from the stated ranges.
-
-    H, W = 8 * floor(U[512, 3072] / 8) (divided by `div`, kept a multiple of
-    8), s in {2, 4, 8}, r in {1, 2, 4}, eps = 10^U(-8, -2); 3 channels.
-    """
+def batched_specs(count: int = 64, *, div: int = 1, seed_config: int = 3) -> list:
+    """Per-image (H, W, s, r, eps) of the uneven batch, drawn from the stated
+    ranges: H, W = 8 * floor(U[512, 3072] / 8) (divided by `div`, kept a
+    multiple of 8), s in {2, 4, 8}, r in {1, 2, 4}, eps = 10^U(-8, -2)."""
     rng = rng_for(seed_config, 0, salt=2)
-    items = []
+    specs = []
     for k in range(count):
         H = 8 * int(rng.uniform(512, 3072) // 8)
         W = 8 * int(rng.uniform(512, 3072) // 8)
@@ -181,6 +178,18 @@ def batched_items(count: int = 64, *, div: int = 1, seed_config: int = 3,
         eps = float(10.0 ** rng.uniform(-8, -2))
         H = max(8, (H // div) // 8 * 8)
         W = max(8, (W // div) // 8 * 8)
-        items.append(make_problem(1, 3, H, W, s, r, eps, io_dtype, config=seed_config,
-                                  noise=0.02, image_offset=k))
-    return items
+        specs.append({"k": k, "H": H, "W": W, "s": s, "r": r, "eps": eps})
+    return specs
+
+
+def batched_item(spec: dict, io_dtype: str = "f32", seed_config: int = 3) -> dict:
+    """Image k of the uneven batch (3 channels, noise 0.02)."""
+    return make_problem(1, 3, spec["H"], spec["W"], spec["s"], spec["r"], spec["eps"], io_dtype,
+                        config=seed_config, noise=0.02, image_offset=spec["k"])
+
+
+def batched_items(count: int = 64, *, div: int = 1, seed_config: int = 3,
+                  io_dtype: str = "f32") -> list:
+    """The uneven batch (see batched_specs), one problem per image."""
+    return [batched_item(sp, io_dtype, seed_config)
+            for sp in batched_specs(count, div=div, seed_config=seed_config)]

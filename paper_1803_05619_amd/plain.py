@@ -30,3 +30,16 @@ def guided_filter(I_lo, p_lo, I_hi, r, eps, mean_ab=True):
     A_h = F.interpolate(A, size=size, mode="bilinear", align_corners=False)
     b_h = F.interpolate(b, size=size, mode="bilinear", align_corners=False)
     return A_h * I_hi + b_h
+
+
+def guide_transform(x, w1, w2, b2, lam, mu, gamma, beta, bn_eps=1e-5, slope=0.2):
+    """The trainable guidance map as framework operators (float32): 1x1
+    convolution, adaptive normalisation lam*h + mu*BN(h) with the batch
+    statistics of x (train-mode batch norm), leaky ReLU, 1x1 convolution."""
+    x = x.float()
+    h = F.conv2d(x, w1[:, :, None, None])
+    m = h.mean(dim=(0, 2, 3), keepdim=True)
+    v = ((h - m) ** 2).mean(dim=(0, 2, 3), keepdim=True)
+    bn = gamma.view(1, -1, 1, 1) * (h - m) / torch.sqrt(v + bn_eps) + beta.view(1, -1, 1, 1)
+    y = lam * h + mu * bn
+    return F.conv2d(F.leaky_relu(y, slope), w2[:, :, None, None], b2)

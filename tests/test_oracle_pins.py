@@ -320,7 +320,10 @@ def test_backward_matches_autograd(eps, mode):
                                           P["gamma"], P["beta"])
     else:
         Fn = lambda x: x
-    q = R.guided_filter(Fn(T["Il"]), T["p"], Fn(T["Ih"]), r, T["eps"])
+    G_lo, G_hi = Fn(T["Il"]), Fn(T["Ih"])
+    G_lo.retain_grad()
+    G_hi.retain_grad()
+    q = R.guided_filter(G_lo, T["p"], G_hi, r, T["eps"])
     (q * torch.from_numpy(dq)).sum().backward()
     scale = lambda a: max(1.0, float(np.abs(a).max()))
     for mine, ref in ((grads["dp_lo"], T["p"].grad), (grads["dI_lo"], T["Il"].grad),
@@ -332,6 +335,14 @@ def test_backward_matches_autograd(eps, mode):
         for k in ("w1", "w2", "b2", "lam", "mu", "gamma", "beta"):
             ref = P[k].grad.numpy()
             assert np.abs(split[k] - ref).max() <= 1e-9 * scale(ref), k
+        # the error scale of each summed entry bounds it (triangle
+        # inequality); for b2 the terms are the per-pixel guide gradients
+        # of both calls, taken here from autograd
+        absd = grads["dguide_abs"]
+        assert np.all(absd >= np.abs(grads["dguide"]) * (1 - 1e-12))
+        split_abs = oracle.guide_grad_split(absd, c, c, g["w1"].shape[0])
+        ref_b2 = (G_lo.grad.abs().sum(dim=(0, 2, 3)) + G_hi.grad.abs().sum(dim=(0, 2, 3))).numpy()
+        assert np.allclose(split_abs["b2"], ref_b2, rtol=1e-9, atol=0)
 
 
 def _alg1_grads(G, p, Gh, r, eps, dq):
