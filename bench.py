@@ -1,7 +1,10 @@
 """Benchmark of the fused guided filtering layer on one MI355X.
 
 A step is one forward + one backward of the layer over one batch, with the
-inputs already resident in HBM.  Workloads (--workload):
+inputs already resident in HBM: one gf_forward_backward call (the batched
+plan for workload 3), which computes the coefficients and guide maps once
+for both directions; `separate_calls` times the same step as gf_forward then
+gf_backward.  Workloads (--workload):
 
   1 (default)  FP32, 4 x 3 x 2048 x 3072 high-res (512 x 768 low-res, s = 4),
                r = 1, eps = 1e-4, dq ~ N(0, 1); gradients to p_l, I_l, I_h, eps
@@ -18,8 +21,10 @@ inputs already resident in HBM.  Workloads (--workload):
 Prints ONE JSON line:
   value        high-res Mpixel/s of fwd+bwd (a 3-channel pixel counts once)
   roofline     the dominant kernel: its algorithmic bytes per step / its time
-               per step (HIP events on the launch stream over the timed
-               region), against the 8 TB/s HBM peak; `traffic` is the HBM
+               per step (HIP events around every launch, on the launch
+               stream, over a second timed pass of the same steps: events
+               add time, so `value` comes from the first, event-free pass),
+               against the 8 TB/s HBM peak; `traffic` is the HBM
                bytes per launch measured with rocprofv3 counters (workload 1,
                from the committed summary; null when the kernel changed since)
   plain        the unfused PyTorch composition (autograd) on the same GPU
@@ -131,15 +136,18 @@ def identity_workload(args, dev, prob, dt, name):
             torch.empty_like(t["I_hi"]),
             torch.empty(1, dtype=torch.float32, device=dev))
     desc = gf.make_desc(t["I_lo"], t["I_hi"], r)
-    ws = torch.empty(max(gf.gf_workspace_size(desc, None, 0), gf.gf_workspace_size(desc, None, 1)),
-                     dtype=torch.uint8, device=dev)
+    ws = torch.empty(gf.gf_workspace_size(desc, None, 2), dtype=torch.uint8, device=dev)
 
     def step():
+        gf.forward_backward(t["I_lo"], t["p_lo"], t["I_hi"], eps, t["dq"], r, ws=ws,
+                            outs=(q,) + outs)
+
+    def separate_step():
         gf.forward(t["I_lo"], t["p_lo"], t["I_hi"], eps, r, out=q, ws=ws)
         gf.backward(t["I_lo"], t["p_lo"], t["I_hi"], eps, t["dq"], r, ws=ws, outs=outs)
 
     kb = identity_bytes(n, c, H, W, h, w, BYTES[dt])
-    per_step = {"gf_apply": kb["apply"], "gf_bwd_hi": kb["bwd_hi"], "gf_coef": 2 * kb["coef"],
+    per_step = {"gf_apply": kb["apply"], "gf_bwd_hi": kb["bwd_hi"], "gf_coef": kb["coef"],
                 "gf_bwd_lo": kb["bwd_lo"], "gf_eps_reduce": 0}
     step_bytes = kb["apply"] + kb["coef"] + kb["bwd_hi"] + kb["bwd_lo"]
 
@@ -173,7 +181,11 @@ def identity_workload(args, dev, prob, dt, name):
                 f"the full {n}-image batch, fwd+bwd, repeated {reps}x ({el:.1f} s); parallel "
                 f"over the {n * c} image planes", n * c, oracle_errors(got, ref))
 
-    return dict(step=step, plain_step=plain_step, cpu_sample=cpu_sample, mpx=n * H * W / 1e6,
+    def tune():
+        gf.autotune(t["I_lo"], t["p_lo"], t["I_hi"], eps, t["dq"], r=r, iters=5)
+
+    return dict(step=step, separate_step=separate_step, plain_step=plain_step,
+                cpu_sample=cpu_sample, mpx=n * H * W / 1e6, tune=tune,
                 per_step=per_step, step_bytes=step_bytes, dtype=dt,
                 config={"workload": name, "n": n, "c": c, "H": H, "W": W, "s": prob["s"], "r": r,
                         "eps": float(prob["eps"][0])},
@@ -203,11 +215,14 @@ def workload_2(args, dev):
     deps = torch.empty(1, **f32)
     dparams = torch.empty(gf.gf_guide_param_count(3, 3, K), **f32)
     desc = gf.make_desc(t["I_lo"], t["I_hi"], r)
-    ws = torch.empty(max(gf.gf_workspace_size(desc, g_fwd.struct(), 0),
-                         gf.gf_workspace_size(desc, g_fwd.struct(), 1)), dtype=torch.uint8,
+    ws = torch.empty(gf.gf_workspace_size(desc, g_fwd.struct(), 2), dtype=torch.uint8,
                      device=dev)
 
     def step():
+        gf.forward_backward(t["I_lo"], t["p_lo"], t["I_hi"], eps, t["dq"], r, ws=ws, guide=g_fwd,
+                            outs=(q, None, dp_lo, None, deps, dparams))
+
+    def separate_step():
         gf.forward(t["I_lo"], t["p_lo"], t["I_hi"], eps, r, out=q, ws=ws, guide=g_fwd)
         gf.backward(t["I_lo"], t["p_lo"], t["I_hi"], eps, t["dq"], r, ws=ws, guide=g_bwd,
                     outs=(None, dp_lo, None, deps, dparams))
@@ -217,9 +232,9 @@ def workload_2(args, dev):
     hpx, lpx = n * H * W, n * h * w
     # each kernel's own compulsory I/O per step (G planes are float32)
     per_step = {
-        "gf_guide_moments": 3 * b * (hpx + lpx),                 # fwd only (bwd reads saved)
-        "gf_guide_map": 2 * (3 * b + 12) * (hpx + lpx),          # fwd and bwd
-        "gf_coef": 2 * (4 + b) * lo,
+        "gf_guide_moments": 3 * b * (hpx + lpx),
+        "gf_guide_map": (3 * b + 12) * (hpx + lpx),
+        "gf_coef": (4 + b) * lo,
         "gf_apply": (4 + b) * hi,
         "gf_bwd_hi": (4 + b + 4) * hi,
         "gf_bwd_lo": (4 + b + 4 + 4) * lo,
@@ -265,7 +280,11 @@ def workload_2(args, dev):
                 f"({el:.1f} s); parallel over the {n * c} image planes", n * c,
                 oracle_errors(got, ref))
 
-    return dict(step=step, plain_step=plain_step, cpu_sample=cpu_sample, mpx=n * H * W / 1e6,
+    def tune():
+        gf.autotune(t["I_lo"], t["p_lo"], t["I_hi"], eps, t["dq"], r=r, iters=5, guide=g_fwd)
+
+    return dict(step=step, separate_step=separate_step, plain_step=plain_step,
+                cpu_sample=cpu_sample, mpx=n * H * W / 1e6, tune=tune,
                 per_step=per_step, step_bytes=step_bytes, dtype="bf16",
                 config={"workload": "trainable-guide guided filtering fwd+bwd, BF16 I/O + FP32 "
                                     "accumulate, 8x3x1536x2048 <- 384x512 (s=4), r=1, eps=1e-8, "
@@ -390,6 +409,8 @@ def main():
     ap.add_argument("--workload", type=int, default=1, choices=sorted(WORKLOADS))
     ap.add_argument("--radius", type=int, default=None, help="workload 4: radius (default 8)")
     ap.add_argument("--items", type=int, default=64, help="workload 3: images")
+    ap.add_argument("--autotune", type=int, default=1,
+                    help="1: run the autotuner on the workload before timing (untimed)")
     ap.add_argument("--plain-steps", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
@@ -417,25 +438,39 @@ def main():
         del src, dst
     wl = WORKLOADS[args.workload](args, dev)
     step = wl["step"]
+    if args.autotune and "tune" in wl:
+        log("autotuning the launch shapes (untimed)")
+        wl["tune"]()
+        log("tuned shapes: " + gf.gf_tune_export().strip().replace("\n", "; "))
 
     log(f"warmup {args.warmup} steps")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
     log(f"timing {args.steps} steps")
-    gf.gf_profile_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    prof = gf.gf_profile_read(64)
-    gf.gf_profile_enable(False)
     sec = t1 - t0
     value = wl["mpx"] * args.steps / sec
     ms_per_step = 1e3 * sec / args.steps
     log(f"fused: {ms_per_step:.4f} ms/step, {value:.1f} Mpx/s")
+    # the kernel breakdown: the same steps again with a HIP event pair
+    # around every launch (recording events adds host and device time, so
+    # this pass is not the one `value` comes from)
+    gf.gf_profile_enable(True)
+    torch.cuda.synchronize()
+    p0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    prof_ms_per_step = 1e3 * (time.perf_counter() - p0) / args.steps
+    prof = gf.gf_profile_read(64)
+    gf.gf_profile_enable(False)
+    log(f"profiled pass: {prof_ms_per_step:.4f} ms/step")
 
     prof_steps = args.steps
     if not prof and "eager_step" in wl:
@@ -481,7 +516,24 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": wl["dtype"],
         "data": DATA, "config": wl["config"], "roofline": roofline,
         "step_algo_GBs": round(step_gbs, 1), "kernels": kernels,
+        "profiled_pass_ms_per_step": round(prof_ms_per_step, 4),
     }
+    if "separate_step" in wl:
+        # the same step as separate gf_forward and gf_backward calls (the
+        # backward recomputing the coefficients), for comparison
+        sep = max(10, args.steps // 4)
+        for _ in range(3):
+            wl["separate_step"]()
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        for _ in range(sep):
+            wl["separate_step"]()
+        torch.cuda.synchronize()
+        sep_ms = 1e3 * (time.perf_counter() - s0) / sep
+        out["separate_calls"] = {"ms_per_step": round(sep_ms, 4),
+                                 "value": round(wl["mpx"] / (sep_ms * 1e-3), 1),
+                                 "steps": sep}
+        log(f"separate gf_forward + gf_backward: {sep_ms:.4f} ms/step")
     if not args.no_plain:
         out["plain"] = plain_leg(args, wl, value)
     if not args.no_cpu:

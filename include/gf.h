@@ -126,8 +126,9 @@ typedef struct {
 size_t gf_guide_param_count(int32_t c_in, int32_t c, int32_t hidden);
 size_t gf_guide_stats_count(int32_t c_in);
 
-/* Bytes of scratch memory gf_forward (backward = 0) or gf_backward
- * (backward = 1) needs for this problem; 0 for an invalid description. */
+/* Bytes of scratch memory gf_forward (backward = 0), gf_backward
+ * (backward = 1) or gf_forward_backward (backward = 2) needs for this
+ * problem; 0 for an invalid description. */
 size_t gf_workspace_size(const gf_desc_t *desc, const gf_guide_t *guide,
                          int32_t backward);
 
@@ -213,6 +214,20 @@ int32_t gf_autotune(const gf_desc_t *desc, const gf_guide_t *guide,
  * (GF_ERR_INVALID_ARG on a malformed line, nothing imported then). */
 size_t gf_tune_export(char *buf, size_t cap);
 int32_t gf_tune_import(const char *text);
+
+/* Forward and backward in one call: q_hi as gf_forward writes it and the
+ * gradients as gf_backward writes them, with the guidance maps, the batch
+ * statistics (saved to guide->stats if given) and the coefficients
+ * computed once for both.  For callers that have dq_hi when they run the
+ * forward (e.g. a fused training step or a benchmark of the whole layer).
+ * Arguments as for gf_backward plus q_hi (required). */
+int32_t gf_forward_backward(const gf_desc_t *desc, const gf_guide_t *guide,
+                            const void *I_lo, const void *p_lo,
+                            const void *I_hi, const float *eps,
+                            int32_t eps_count, const void *dq_hi, void *q_hi,
+                            float *dI_lo, float *dp_lo, void *dI_hi,
+                            float *deps, float *dparams, void *ws,
+                            size_t ws_bytes, void *stream);
 
 /* Human-readable name of a status code (static string). */
 const char *gf_status_string(int32_t status);

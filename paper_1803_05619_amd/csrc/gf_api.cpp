@@ -254,13 +254,27 @@ std::vector<Rec> g_recs;
 const char* g_pending_name = nullptr;
 hipEvent_t g_pending_ev = nullptr;
 
+// Recorded events go back to a pool (creating events costs far more host
+// time than recording them, and the records sit in the timed region).
+std::vector<hipEvent_t> g_ev_pool;
+
+hipEvent_t ev_get() {
+  if (!g_ev_pool.empty()) {
+    hipEvent_t e = g_ev_pool.back();
+    g_ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  return hipEventCreate(&e) == hipSuccess ? e : nullptr;
+}
+
 void prof_clear() {
   for (auto& r : g_recs) {
-    (void)hipEventDestroy(r.a);
-    (void)hipEventDestroy(r.b);
+    g_ev_pool.push_back(r.a);
+    g_ev_pool.push_back(r.b);
   }
   g_recs.clear();
-  if (g_pending_ev) (void)hipEventDestroy(g_pending_ev);
+  if (g_pending_ev) g_ev_pool.push_back(g_pending_ev);
   g_pending_ev = nullptr;
 }
 }  // namespace
@@ -272,8 +286,8 @@ void prof_begin(const char* name, hipStream_t s) {
   if (g_prof_muted) return;
   std::lock_guard<std::mutex> lk(g_prof_mu);
   if (!g_prof_on) return;
-  hipEvent_t ev;
-  if (hipEventCreate(&ev) != hipSuccess) return;
+  hipEvent_t ev = ev_get();
+  if (!ev) return;
   (void)hipEventRecord(ev, s);
   g_pending_name = name;
   g_pending_ev = ev;
@@ -283,8 +297,8 @@ void prof_end(hipStream_t s) {
   if (g_prof_muted) return;
   std::lock_guard<std::mutex> lk(g_prof_mu);
   if (!g_prof_on || !g_pending_ev) return;
-  hipEvent_t ev;
-  if (hipEventCreate(&ev) != hipSuccess) return;
+  hipEvent_t ev = ev_get();
+  if (!ev) return;
   (void)hipEventRecord(ev, s);
   g_recs.push_back({g_pending_name, g_pending_ev, ev});
   g_pending_ev = nullptr;
@@ -314,6 +328,7 @@ size_t gf_workspace_size(const gf_desc_t* desc, const gf_guide_t* guide, int32_t
   gf::Plan p;
   const char* why = nullptr;
   if (gf::make_plan(desc, guide, &p, &why) != GF_OK) return 0;
+  if (backward == 2) return std::max(p.ws_fwd, p.ws_bwd);
   return backward ? p.ws_bwd : p.ws_fwd;
 }
 
@@ -341,32 +356,59 @@ int32_t gf_forward(const gf_desc_t* desc, const gf_guide_t* guide, const void* I
   return GF_OK;
 }
 
-int32_t gf_backward(const gf_desc_t* desc, const gf_guide_t* guide, const void* I_lo,
-                    const void* p_lo, const void* I_hi, const float* eps, int32_t eps_count,
-                    const void* dq_hi, float* dI_lo, float* dp_lo, void* dI_hi, float* deps,
-                    float* dparams, void* ws, size_t ws_bytes, void* stream) {
+}  // extern "C"
+
+namespace {
+// gf_backward, and with q_hi set gf_forward_backward.
+int32_t run_backward(const gf_desc_t* desc, const gf_guide_t* guide, const void* I_lo,
+                     const void* p_lo, const void* I_hi, const float* eps, int32_t eps_count,
+                     const void* dq_hi, void* q_hi, float* dI_lo, float* dp_lo, void* dI_hi,
+                     float* deps, float* dparams, void* ws, size_t ws_bytes, void* stream,
+                     bool with_forward) {
   gf::g_detail.clear();
   gf::Plan p;
   const char* why = nullptr;
   int st = gf::make_plan(desc, guide, &p, &why);
   if (st != GF_OK) return fail(st, why);
-  if (!I_lo || !p_lo || !I_hi || !eps || !dq_hi)
+  if (!I_lo || !p_lo || !I_hi || !eps || !dq_hi || (with_forward && !q_hi))
     return fail(GF_ERR_INVALID_ARG, "a required pointer is NULL");
   if (eps_count != 1 && eps_count != desc->n)
     return fail(GF_ERR_INVALID_ARG, "eps_count must be 1 or n");
   if (dparams && p.gmode != GF_GUIDE_TRANSFORM)
     return fail(GF_ERR_INVALID_ARG, "dparams needs the transform guide");
   if (misaligned(I_lo) || misaligned(p_lo) || misaligned(I_hi) || misaligned(dq_hi) ||
-      misaligned(dI_lo) || misaligned(dp_lo) || misaligned(dI_hi) || misaligned(ws))
+      misaligned(dI_lo) || misaligned(dp_lo) || misaligned(dI_hi) || misaligned(q_hi) ||
+      misaligned(ws))
     return fail(GF_ERR_INVALID_ARG, "tensor pointers must be 16-byte aligned");
-  if (!ws || ws_bytes < p.ws_bwd)
-    return fail(GF_ERR_WORKSPACE, "workspace smaller than gf_workspace_size(desc, guide, 1) = " +
-                                      std::to_string(p.ws_bwd));
+  const size_t need = with_forward ? std::max(p.ws_fwd, p.ws_bwd) : p.ws_bwd;
+  if (!ws || ws_bytes < need)
+    return fail(GF_ERR_WORKSPACE, std::string("workspace smaller than gf_workspace_size(desc, guide, ") +
+                                      (with_forward ? "2" : "1") + ") = " + std::to_string(need));
   gf::BwdArgs a{I_lo, p_lo, I_hi, dq_hi, eps, eps_count, dI_lo, dp_lo, deps, dparams, dI_hi,
-                static_cast<char*>(ws)};
+                static_cast<char*>(ws), with_forward ? q_hi : nullptr};
   hipError_t e = gf::launch_backward(p, a, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return fail(GF_ERR_HIP, hipGetErrorString(e));
   return GF_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int32_t gf_backward(const gf_desc_t* desc, const gf_guide_t* guide, const void* I_lo,
+                    const void* p_lo, const void* I_hi, const float* eps, int32_t eps_count,
+                    const void* dq_hi, float* dI_lo, float* dp_lo, void* dI_hi, float* deps,
+                    float* dparams, void* ws, size_t ws_bytes, void* stream) {
+  return run_backward(desc, guide, I_lo, p_lo, I_hi, eps, eps_count, dq_hi, nullptr, dI_lo,
+                      dp_lo, dI_hi, deps, dparams, ws, ws_bytes, stream, false);
+}
+
+int32_t gf_forward_backward(const gf_desc_t* desc, const gf_guide_t* guide, const void* I_lo,
+                            const void* p_lo, const void* I_hi, const float* eps,
+                            int32_t eps_count, const void* dq_hi, void* q_hi, float* dI_lo,
+                            float* dp_lo, void* dI_hi, float* deps, float* dparams, void* ws,
+                            size_t ws_bytes, void* stream) {
+  return run_backward(desc, guide, I_lo, p_lo, I_hi, eps, eps_count, dq_hi, q_hi, dI_lo, dp_lo,
+                      dI_hi, deps, dparams, ws, ws_bytes, stream, true);
 }
 
 const char* gf_status_string(int32_t status) {
@@ -386,6 +428,12 @@ int32_t gf_profile_enable(int32_t on) {
   std::lock_guard<std::mutex> lk(gf::g_prof_mu);
   gf::prof_clear();
   gf::g_prof_on = on != 0;
+  // records of a few hundred launches without creating events on the way
+  while (gf::g_prof_on && gf::g_ev_pool.size() < 2048) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) break;
+    gf::g_ev_pool.push_back(e);
+  }
   return GF_OK;
 }
 

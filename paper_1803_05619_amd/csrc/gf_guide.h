@@ -674,9 +674,12 @@ hipError_t guided_input_grad(const Plan& p, const void* x, const float* dG, void
   return hipGetLastError();
 }
 
+// With b.q set, the forward runs first on the same guide maps and
+// coefficients (batch statistics computed, and saved if asked, as by the
+// forward).
 template <typename T>
 hipError_t backward_guided_t(const Plan& p, const BwdArgs& b, hipStream_t s) {
-  hipError_t e = guided_prepare<T>(p, b.I_lo, b.I_hi, b.ws, true, s);
+  hipError_t e = guided_prepare<T>(p, b.I_lo, b.I_hi, b.ws, b.q == nullptr, s);
   if (e != hipSuccess) return e;
   float* fold = reinterpret_cast<float*>(b.ws + p.off_fold);
   float* Gl = reinterpret_cast<float*>(b.ws + p.off_gl);
@@ -689,8 +692,10 @@ hipError_t backward_guided_t(const Plan& p, const BwdArgs& b, hipStream_t s) {
   if (e != hipSuccess) return e;
   float* abar = reinterpret_cast<float*>(b.ws + p.off_abar);
   float* U = reinterpret_cast<float*>(b.ws + p.off_u);
-  e = launch_coef<float, T>(p, Gl, b.p_lo, b.eps, b.eps_count, abar, nullptr, s);
+  float* bbar = b.q ? reinterpret_cast<float*>(b.ws + p.off_bbar) : nullptr;
+  e = launch_coef<float, T>(p, Gl, b.p_lo, b.eps, b.eps_count, abar, bbar, s);
   if (e != hipSuccess) return e;
+  if (b.q && (e = launch_apply<float, T>(p, Gh, b.q, abar, bbar, s)) != hipSuccess) return e;
   // dG_h = dq * A_h (the guide gradient at high resolution) and the
   // transposed-bilinear partial planes
   e = launch_bwd_hi<float, T, float>(p, Gh, b.dq, dGh, abar, U, s);

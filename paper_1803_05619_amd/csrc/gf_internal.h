@@ -85,6 +85,7 @@ struct BwdArgs {
   float *dI_lo, *dp_lo, *deps, *dparams;
   void* dI_hi;
   char* ws;
+  void* q;  // non-null: forward and backward in one pass (q written too)
 };
 
 // Kernel arguments of the four filter kernels (one problem each).

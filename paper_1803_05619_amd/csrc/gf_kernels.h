@@ -1328,12 +1328,16 @@ hipError_t forward_t(const Plan& p, const FwdArgs& f, hipStream_t s) {
   return launch_apply<T, T>(p, f.I_hi, f.q, abar, bbar, s);
 }
 
+// With b.q set, the forward runs first on the same coefficients (bbar is
+// consumed by the apply kernel before the partial planes reuse its space).
 template <typename T>
 hipError_t backward_t(const Plan& p, const BwdArgs& b, hipStream_t s) {
   float* abar = reinterpret_cast<float*>(b.ws + p.off_abar);
+  float* bbar = b.q ? reinterpret_cast<float*>(b.ws + p.off_bbar) : nullptr;
   float* U = reinterpret_cast<float*>(b.ws + p.off_u);
-  hipError_t err = launch_coef<T, T>(p, b.I_lo, b.p_lo, b.eps, b.eps_count, abar, nullptr, s);
+  hipError_t err = launch_coef<T, T>(p, b.I_lo, b.p_lo, b.eps, b.eps_count, abar, bbar, s);
   if (err != hipSuccess) return err;
+  if (b.q && (err = launch_apply<T, T>(p, b.I_hi, b.q, abar, bbar, s)) != hipSuccess) return err;
   err = launch_bwd_hi<T, T, T>(p, b.I_hi, b.dq, b.dI_hi, abar, U, s);
   if (err != hipSuccess) return err;
   if (!b.dI_lo && !b.dp_lo && !b.deps) return hipSuccess;

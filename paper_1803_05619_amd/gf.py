@@ -59,6 +59,9 @@ lib.gf_forward.restype = ctypes.c_int32
 lib.gf_backward.argtypes = [_dp, _gp, _vp, _vp, _vp, _fp, ctypes.c_int32, _vp, _fp, _fp, _vp,
                             _fp, _fp, _vp, ctypes.c_size_t, _vp]
 lib.gf_backward.restype = ctypes.c_int32
+lib.gf_forward_backward.argtypes = [_dp, _gp, _vp, _vp, _vp, _fp, ctypes.c_int32, _vp, _vp, _fp,
+                                    _fp, _vp, _fp, _fp, _vp, ctypes.c_size_t, _vp]
+lib.gf_forward_backward.restype = ctypes.c_int32
 GF_RUN_FORWARD, GF_RUN_BACKWARD, GF_RUN_GRAPH = 1, 2, 4
 
 
@@ -174,6 +177,13 @@ def gf_tune_export() -> str:
 
 def gf_tune_import(text: str) -> int:
     return int(lib.gf_tune_import(text.encode()))
+
+
+def gf_forward_backward(desc, guide, I_lo, p_lo, I_hi, eps, eps_count, dq_hi, q_hi, dI_lo, dp_lo,
+                        dI_hi, deps, dparams, ws, ws_bytes, stream) -> int:
+    return int(lib.gf_forward_backward(ctypes.byref(desc), _gref(guide), I_lo, p_lo, I_hi, eps,
+                                       eps_count, dq_hi, q_hi, dI_lo, dp_lo, dI_hi, deps,
+                                       dparams, ws, ws_bytes, stream))
 
 
 def gf_status_string(code: int) -> str:
@@ -359,6 +369,43 @@ def backward(I_lo, p_lo, I_hi, eps, dq, r=1, mean_ab=True, need_dI_lo=True, need
     if st != GF_OK:
         raise GFError(st)
     return dI_lo, dp_lo, dI_hi, deps, dparams
+
+
+def forward_backward(I_lo, p_lo, I_hi, eps, dq, r=1, mean_ab=True, ws=None, outs=None,
+                     guide=None, need_dI_lo=True, need_dp_lo=True, need_dI_hi=True,
+                     need_deps=True, need_dparams=None):
+    """q and the gradients (dI_lo, dp_lo, dI_hi, deps, dparams) in one call
+    (gf_forward_backward: coefficients and guide maps computed once)."""
+    dev = I_hi.device
+    _check(dict(I_lo=I_lo, p_lo=p_lo, I_hi=I_hi, dq=dq), I_hi.dtype, dev)
+    desc = make_desc(I_lo, I_hi, r, mean_ab, c=p_lo.shape[1])
+    g = None if guide is None else guide.struct()
+    transform = guide is not None and guide.mode == GF_GUIDE_TRANSFORM
+    if need_dparams is None:
+        need_dparams = transform
+    e = _eps_tensor(eps, desc.n, dev)
+    f32 = dict(dtype=torch.float32, device=dev)
+    if outs is not None:
+        q, dI_lo, dp_lo, dI_hi, deps = outs[:5]
+        dparams = outs[5] if len(outs) > 5 else None
+    else:
+        q = torch.empty((desc.n, desc.c, desc.h_hi, desc.w_hi), dtype=I_hi.dtype, device=dev)
+        dI_lo = torch.empty(I_lo.shape, **f32) if need_dI_lo else None
+        dp_lo = torch.empty(p_lo.shape, **f32) if need_dp_lo else None
+        dI_hi = torch.empty_like(I_hi) if need_dI_hi else None
+        deps = torch.empty(e.numel(), **f32) if need_deps else None
+        dparams = None
+        if need_dparams and transform:
+            dparams = torch.empty(gf_guide_param_count(guide.c_in, desc.c, guide.hidden), **f32)
+    _check(dict(dI_lo=dI_lo, dp_lo=dp_lo, deps=deps, dparams=dparams), torch.float32, dev)
+    _check(dict(q=q, dI_hi=dI_hi), I_hi.dtype, dev)
+    ws = _ws(gf_workspace_size(desc, g, 2), dev, ws)
+    st = gf_forward_backward(desc, g, _ptr(I_lo), _ptr(p_lo), _ptr(I_hi), _ptr(e), e.numel(),
+                             _ptr(dq), _ptr(q), _ptr(dI_lo), _ptr(dp_lo), _ptr(dI_hi), _ptr(deps),
+                             _ptr(dparams), _ptr(ws), ws.numel(), _stream(dev))
+    if st != GF_OK:
+        raise GFError(st)
+    return q, dI_lo, dp_lo, dI_hi, deps, dparams
 
 
 class GuidedFilterFn(torch.autograd.Function):

@@ -16,7 +16,8 @@ def desc(**kw):
 
 def test_exports_every_declared_symbol():
     names = gf.header_functions()
-    assert {"gf_forward", "gf_backward", "gf_workspace_size", "gf_status_string",
+    assert {"gf_forward", "gf_backward", "gf_forward_backward", "gf_workspace_size",
+            "gf_status_string",
             "gf_last_error_detail", "gf_profile_enable", "gf_profile_read"} <= set(names)
     for name in names:
         assert hasattr(gf.lib, name), name
@@ -211,3 +212,19 @@ def test_tuned_shapes_reach_the_planner():
     assert b8 < b2   # (8 + 2) / 8 < (2 + 2) / 2 partial rows per low-res row
     assert gf.gf_tune_import("2 4 9 0 1 : 64 16 8 8\n") == gf.GF_OK
     assert gf.gf_workspace_size(d, None, 1) > b8   # more deps partials
+
+
+def test_forward_backward_checks():
+    d = desc()
+    big = 1 << 40
+    both = gf.gf_workspace_size(d, None, 2)
+    assert both >= max(gf.gf_workspace_size(d, None, 0), gf.gf_workspace_size(d, None, 1))
+    # q_hi is required
+    assert gf.gf_forward_backward(d, None, FAKE, FAKE, FAKE, FAKE, 2, FAKE, None, FAKE, FAKE, FAKE,
+                                  FAKE, None, FAKE, big, None) == gf.GF_ERR_INVALID_ARG
+    assert gf.gf_forward_backward(d, None, FAKE, FAKE, FAKE, FAKE, 2, FAKE, FAKE + 4, FAKE, FAKE,
+                                  FAKE, FAKE, None, FAKE, big, None) == gf.GF_ERR_INVALID_ARG
+    assert gf.gf_forward_backward(d, None, FAKE, FAKE, FAKE, FAKE, 2, FAKE, FAKE, FAKE, FAKE, FAKE,
+                                  FAKE, None, FAKE, both - 1, None) == gf.GF_ERR_WORKSPACE
+    assert gf.gf_forward_backward(desc(r=-1), None, FAKE, FAKE, FAKE, FAKE, 2, FAKE, FAKE, FAKE,
+                                  FAKE, FAKE, FAKE, None, FAKE, big, None) == gf.GF_ERR_INVALID_ARG

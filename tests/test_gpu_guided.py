@@ -200,3 +200,31 @@ def test_guided_deterministic():
     torch.cuda.synchronize()
     for a, b in zip(*runs):
         assert (a is None and b is None) or torch.equal(a, b)
+
+
+@pytest.mark.parametrize("mode", ["grey", "transform"])
+def test_guided_forward_backward_equals_separate_calls(mode):
+    gf = _gf()
+    if mode == "grey":
+        prob = grey_problem(2, 3, 1, 96, 160, 4, 1, 1e-3, "f32", config=150)
+    else:
+        prob = datagen.make_config(2, div=16, n=2)
+    d = {k: prob[k].to(DEV) for k in ("I_lo", "p_lo", "I_hi", "dq")}
+    stats = None
+    if mode == "transform":
+        stats = torch.zeros(gf.gf_guide_stats_count(3), device=DEV)
+    guide = make_guide(gf, mode, prob, stats)
+    q = gf.forward(d["I_lo"], d["p_lo"], d["I_hi"], prob["eps"], 1, guide=guide)
+    g = gf.backward(d["I_lo"], d["p_lo"], d["I_hi"], prob["eps"], d["dq"], 1, guide=guide)
+    torch.cuda.synchronize()
+    saved = None if stats is None else stats.clone()
+    if stats is not None:
+        stats.zero_()
+    fb = gf.forward_backward(d["I_lo"], d["p_lo"], d["I_hi"], prob["eps"], d["dq"], 1,
+                             guide=guide)
+    torch.cuda.synchronize()
+    assert torch.equal(fb[0], q)
+    for a, b in zip(fb[1:], g):
+        assert (a is None and b is None) or torch.equal(a, b)
+    if stats is not None:
+        assert torch.equal(stats, saved)

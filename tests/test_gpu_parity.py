@@ -206,3 +206,20 @@ def test_config1_full_size():
     """4 x 3 x 2048 x 3072 FP32, r=1, eps=1e-4: the benchmarked launch shapes,
     every output compared with the full oracle."""
     check(datagen.make_config(1))
+
+
+@pytest.mark.parametrize("cfg, dt", [(1, "f32"), (2, "bf16"), (4, "f16")])
+def test_forward_backward_equals_separate_calls(cfg, dt):
+    """One gf_forward_backward call gives bit for bit what gf_forward then
+    gf_backward give (the backward recomputes the same coefficients)."""
+    gf = _gf()
+    prob = datagen.make_config(cfg, div=16, n=2)
+    d = to_dev(prob)
+    print(f"case config={cfg} dtype={dt}", flush=True)
+    q = gf.forward(d["I_lo"], d["p_lo"], d["I_hi"], prob["eps"], prob["r"])
+    g = gf.backward(d["I_lo"], d["p_lo"], d["I_hi"], prob["eps"], d["dq"], prob["r"])
+    fb = gf.forward_backward(d["I_lo"], d["p_lo"], d["I_hi"], prob["eps"], d["dq"], prob["r"])
+    torch.cuda.synchronize()
+    assert torch.equal(fb[0], q)
+    for a, b in zip(fb[1:5], g[:4]):
+        assert torch.equal(a, b)
