@@ -121,8 +121,6 @@ int make_plan(const gf_desc_t* d, const gf_guide_t* g, Plan* p, const char** why
   const int r = q.r;
   if (r > kMaxRadius) return bad(GF_ERR_UNSUPPORTED, "radius above 10 is not supported");
   const int hal = q.mean_ab ? 2 * r : r;  // halo of the coefficient walker
-  const size_t KRc = walker_ring_rows(r, kWalkBlock, kCoefRingPow2Max);
-  const size_t KRb = walker_ring_rows(r, kWalkBlock, kBwdLoRingPow2Max);
   // Launch shapes: the tuned entry for this key if the autotuner (or an
   // import) made one, else the defaults below; environment overrides win
   // (tuning experiments).
@@ -144,11 +142,11 @@ int make_plan(const gf_desc_t* d, const gf_guide_t* g, Plan* p, const char** why
   q.coTR = tv.coTR;
   q.co_nx = (q.w + (64 - 2 * hal) - 1) / (64 - 2 * hal);
   q.co_ny = (q.h + q.coTR - 1) / q.coTR;
-  q.coLDS = 64 * (16 * KRc + 24 * kWalkBlock);  // (g,p), (A,b) rings + row buffers
+  q.coLDS = coef_lds_bytes(r);  // row buffers (+ (g,p), (A,b) rings for large r)
   q.loTR = tv.loTR;
   q.lo_nx = (q.w + (64 - 4 * r) - 1) / (64 - 4 * r);
   q.lo_ny = (q.h + q.loTR - 1) / q.loTR;
-  q.loLDS = 64 * (32 * KRb + 40 * kWalkBlock);  // input and X rings + row buffers
+  q.loLDS = bwd_lo_lds_bytes(r);  // row buffers (+ input and X rings for large r)
 
   q.RB = ((tv.RB + S - 1) / S) * S;  // whole low-res row blocks
   q.nrb = (q.H + q.RB - 1) / q.RB;

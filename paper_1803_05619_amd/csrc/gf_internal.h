@@ -67,6 +67,23 @@ constexpr int kWalkBlock = 4;        // rows per block of the low-res walkers
 constexpr int kCoefRingPow2Max = 32;  // coef: 64 * (16 KR + 24 * 4) bytes
 constexpr int kBwdLoRingPow2Max = 16;  // bwd_lo: 64 * (32 KR + 40 * 4) bytes
 
+// Small radii keep each lane's vertical windows (2R + block rows) in
+// registers instead of LDS rings: the LDS footprint per wave then shrinks to
+// the row buffers of the horizontal windows, which lifts occupancy.  The
+// coefficient walker holds 2 x 2 floats per window row, the backward walker
+// 2 x 4.
+constexpr bool coef_reg_window(int R) { return 4 * (2 * R + kWalkBlock) <= 64; }
+constexpr bool bwd_lo_reg_window(int R) { return 8 * (2 * R + kWalkBlock) <= 64; }
+constexpr size_t coef_lds_bytes(int R) {
+  return 64 * (24 * kWalkBlock +
+               (coef_reg_window(R) ? 0 : 16 * walker_ring_rows(R, kWalkBlock, kCoefRingPow2Max)));
+}
+constexpr size_t bwd_lo_lds_bytes(int R) {
+  return 64 * (40 * kWalkBlock +
+               (bwd_lo_reg_window(R) ? 0
+                                     : 32 * walker_ring_rows(R, kWalkBlock, kBwdLoRingPow2Max)));
+}
+
 // Returns GF_OK and fills `p`, or an error code with a message in `why`.
 int make_plan(const gf_desc_t* d, const gf_guide_t* g, Plan* p, const char** why);
 

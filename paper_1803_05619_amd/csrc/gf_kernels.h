@@ -195,20 +195,51 @@ struct WinStats {
 
 __device__ __forceinline__ bool row_ok(int t, int h) { return (unsigned)t < (unsigned)h; }
 
-// Column statistics of the K = 2R+1 rows centred on rc, read from a ring of
-// (g, p) pairs; rows outside the image hold zeros and are masked out.
-template <int R, int KR>
-__device__ __forceinline__ float4 column_stats(const float2* ring, int rc, int x0, int h,
-                                               int lane) {
+// Vertical window of one lane (its own column) for the walkers: NW rows,
+// row xb + OFF + t at index t while the block starting at row xb is
+// processed.  In registers (index t must be a compile-time constant after
+// unrolling; advance() shifts by one block) or in a per-wave LDS ring of KR
+// rows indexed by absolute row (advance() is a no-op).
+template <typename V, int NW, int OFF, int KR, bool REG>
+struct VWin;
+
+template <typename V, int NW, int OFF, int KR>
+struct VWin<V, NW, OFF, KR, true> {
+  V v[NW];
+  __device__ __forceinline__ void init(V* /*ring*/, int /*x0*/, int /*lane*/, V zero) {
+#pragma unroll
+    for (int t = 0; t < NW; ++t) v[t] = zero;
+  }
+  __device__ __forceinline__ V& at(int /*xb*/, int t) { return v[t]; }
+  __device__ __forceinline__ void advance() {
+#pragma unroll
+    for (int t = 0; t + kWalkBlock < NW; ++t) v[t] = v[t + kWalkBlock];
+  }
+};
+
+template <typename V, int NW, int OFF, int KR>
+struct VWin<V, NW, OFF, KR, false> {
+  V* ring;
+  int x0, lane;
+  __device__ __forceinline__ void init(V* r, int x, int l, V /*zero*/) {
+    ring = r;
+    x0 = x;
+    lane = l;
+  }
+  __device__ __forceinline__ V& at(int xb, int t) {
+    return ring[(int)((unsigned)(xb + OFF + t - x0) % (unsigned)KR) * 64 + lane];
+  }
+  __device__ __forceinline__ void advance() {}
+};
+
+// Column statistics of the K = 2R+1 rows rc-R .. rc+R given in v (rows
+// outside the image hold zeros and are masked out).
+template <int R>
+__device__ __forceinline__ float4 column_stats_v(const float2 (&v)[2 * R + 1], int rc, int h) {
   constexpr int K = 2 * R + 1;
-  float2 v[K];
   int nrow = 0;
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int t = rc - R + k;
-    v[k] = ring[(int)((unsigned)(t - x0) % (unsigned)KR) * 64 + lane];
-    nrow += row_ok(t, h) ? 1 : 0;
-  }
+  for (int k = 0; k < K; ++k) nrow += row_ok(rc - R + k, h) ? 1 : 0;
   float s0 = 0.f, s1 = 0.f;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
@@ -279,11 +310,15 @@ __device__ __forceinline__ void coef_body(const CoefArgs& a, const int bx, const
   constexpr int HAL = R + HB;
   constexpr int TWo = 64 - 2 * HAL;
   constexpr int KR = walker_ring_rows(R, kPF, kCoefRingPow2Max);
+  constexpr bool REG = coef_reg_window(R);
+  constexpr int NW = 2 * R + kPF;
   extern __shared__ float4 lds4[];
-  float2* gp = reinterpret_cast<float2*>(lds4);  // [KR][64] recentred (g, p)
-  float4* cs = reinterpret_cast<float4*>(gp + KR * 64);  // [kPF][64] column statistics
-  float2* ab = reinterpret_cast<float2*>(cs + kPF * 64);  // [KR][64] (A, b)
-  float2* vs = ab + KR * 64;                               // [kPF][64] column sums of (A, b)
+  float4* cs = lds4;                                       // [kPF][64] column statistics
+  float2* vs = reinterpret_cast<float2*>(cs + kPF * 64);  // [kPF][64] column sums of (A, b)
+  float2* rings = vs + kPF * 64;                           // LDS rings (large R only)
+  // vertical windows: recentred (g, p) rows xb-2R.., (A, b) rows xb-3R..
+  VWin<float2, NW, -2 * R, KR, REG> gp;
+  VWin<float2, NW, -3 * R, KR, REG> ab;
   const int lane = threadIdx.x;
   const float e = a.eps[a.eps_count == 1 ? 0 : plane / a.c];
   const int h = a.h, w = a.w;
@@ -311,9 +346,8 @@ __device__ __forceinline__ void coef_body(const CoefArgs& a, const int bx, const
   const bool a_lane = colin && lane >= R && lane < 64 - R;  // lanes that form (A, b)
   const bool out_lane = colin && lane >= HAL && lane < HAL + TWo;
   const int x0 = i0 - HAL, xend = i1 + HAL;  // input rows walked
-  auto ring = [&](int x) __attribute__((always_inline)) {
-    return (int)((unsigned)(x - x0) % (unsigned)KR) * 64 + lane;
-  };
+  gp.init(rings, x0, lane, make_float2(0.f, 0.f));
+  ab.init(rings + KR * 64, x0, lane, make_float2(0.f, 0.f));
 
   // Loads are unconditional (clamped address) and the queue holds the raw
   // values: a load inside a divergent branch, or arithmetic right after it,
@@ -331,7 +365,8 @@ __device__ __forceinline__ void coef_body(const CoefArgs& a, const int bx, const
       const int x = xb + d;
       const bool ok = colin && row_ok(x, h);
       if (x < xend)
-        gp[ring(x)] = make_float2(ok ? to_f(gq[d]) - cg : 0.f, ok ? to_f(pq[d]) - cp : 0.f);
+        gp.at(xb, 2 * R + d) =
+            make_float2(ok ? to_f(gq[d]) - cg : 0.f, ok ? to_f(pq[d]) - cp : 0.f);
     }
     // rows rc = x - R whose windows are complete with this block
 #pragma unroll
@@ -339,7 +374,12 @@ __device__ __forceinline__ void coef_body(const CoefArgs& a, const int bx, const
       const int rc = xb + d - R;
       if (xb + d < xend && rc - R >= x0 && rc >= i0 - HB && rc < i1 + HB) {
         float4 st = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (colin && row_ok(rc, h)) st = column_stats<R, KR>(gp, rc, x0, h, lane);
+        if (colin && row_ok(rc, h)) {
+          float2 v[K];
+#pragma unroll
+          for (int k = 0; k < K; ++k) v[k] = gp.at(xb, d + k);  // rows rc-R .. rc+R
+          st = column_stats_v<R>(v, rc, h);
+        }
         cs[d * 64 + lane] = st;
       }
     }
@@ -363,7 +403,7 @@ __device__ __forceinline__ void coef_body(const CoefArgs& a, const int bx, const
             if (Bb) Bb[(size_t)rc * w + j] = B;
           }
         } else {
-          ab[ring(rc)] = make_float2(A, B);
+          ab.at(xb, 2 * R + d) = make_float2(A, B);  // row rc
         }
       }
     }
@@ -375,7 +415,7 @@ __device__ __forceinline__ void coef_body(const CoefArgs& a, const int bx, const
           float sa = 0.f, sb = 0.f;
 #pragma unroll
           for (int k = 0; k < K; ++k) {
-            const float2 v = ab[ring(ra - R + k)];  // rows outside the image hold zeros
+            const float2 v = ab.at(xb, d + k);  // row ra-R+k; outside the image: zeros
             sa += v.x;
             sb += v.y;
           }
@@ -414,6 +454,8 @@ __device__ __forceinline__ void coef_body(const CoefArgs& a, const int bx, const
 #pragma unroll
     for (int d = 0; d < kPF; ++d) load(base + kPF + d, gn[d], pn[d]);
     block(base, gq, pq);
+    gp.advance();
+    ab.advance();
 #pragma unroll
     for (int d = 0; d < kPF; ++d) {
       gq[d] = gn[d];
@@ -866,12 +908,16 @@ __device__ __forceinline__ void bwd_lo_body(const BwdLoArgs& a, const int bx, co
   constexpr int K = 2 * R + 1;
   constexpr int TWo = 64 - 4 * R;
   constexpr int KR = walker_ring_rows(R, kPF, kBwdLoRingPow2Max);
+  constexpr bool REG = bwd_lo_reg_window(R);
+  constexpr int NW = 2 * R + kPF;
   extern __shared__ float4 lds4[];
-  float4* in = lds4;              // [KR][64] (g', p', dAbar, dbbar)
-  float4* cs = in + KR * 64;      // [kPF][64] column statistics
+  float4* cs = lds4;              // [kPF][64] column statistics
   float2* cu = reinterpret_cast<float2*>(cs + kPF * 64);  // [kPF][64] column sums of dAbar, dbbar
-  float4* xr = reinterpret_cast<float4*>(cu + kPF * 64);  // [KR][64] X
-  float4* vs = xr + KR * 64;      // [kPF][64] column sums of X
+  float4* vs = reinterpret_cast<float4*>(cu + kPF * 64);  // [kPF][64] column sums of X
+  float4* rings = vs + kPF * 64;  // LDS rings (large R only)
+  // vertical windows: (g', p', dAbar, dbbar) rows xb-2R.., X rows xb-3R..
+  VWin<float4, NW, -2 * R, KR, REG> in;
+  VWin<float4, NW, -3 * R, KR, REG> xr;
   const int lane = threadIdx.x;
   const float e = a.eps[a.eps_count == 1 ? 0 : plane / a.c];
   const int h = a.h, w = a.w;
@@ -897,9 +943,8 @@ __device__ __forceinline__ void bwd_lo_body(const BwdLoArgs& a, const int bx, co
   const bool x_lane = colin && lane >= R && lane < 64 - R;  // lanes that form X
   const bool out_col = colin && lane >= 2 * R && lane < 2 * R + TWo;
   const int x0 = i0 - 2 * R, xend = i1 + 2 * R;
-  auto ring = [&](int x) __attribute__((always_inline)) {
-    return (int)((unsigned)(x - x0) % (unsigned)KR) * 64 + lane;
-  };
+  in.init(rings, x0, lane, make_float4(0.f, 0.f, 0.f, 0.f));
+  xr.init(rings + KR * 64, x0, lane, make_float4(0.f, 0.f, 0.f, 0.f));
   float deps_acc = 0.f;
 
   // Loads are unconditional (clamped address) and the queue holds the raw
@@ -940,7 +985,7 @@ __device__ __forceinline__ void bwd_lo_body(const BwdLoArgs& a, const int bx, co
         }
         v = make_float4(to_f(q[d].g) - cg, to_f(q[d].p) - cp, u, vv);
       }
-      in[ring(x)] = v;
+      in.at(xb, 2 * R + d) = v;  // row x
     }
     // rows rc = x - R whose windows are complete with this block
 #pragma unroll
@@ -954,7 +999,7 @@ __device__ __forceinline__ void bwd_lo_body(const BwdLoArgs& a, const int bx, co
         int nrow = 0;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-          v[k] = in[ring(rc - R + k)];
+          v[k] = in.at(xb, d + k);  // row rc-R+k
           nrow += row_ok(rc - R + k, h) ? 1 : 0;
         }
         float s0 = 0.f, s1 = 0.f;
@@ -1001,7 +1046,7 @@ __device__ __forceinline__ void bwd_lo_body(const BwdLoArgs& a, const int bx, co
             db += c.y;
           }
         } else {
-          const float4 v = in[ring(rc)];
+          const float4 v = in.at(xb, d + R);  // row rc
           dA = v.z;
           db = v.w;
         }
@@ -1018,7 +1063,7 @@ __device__ __forceinline__ void bwd_lo_body(const BwdLoArgs& a, const int bx, co
         X = make_float4(dmI * invN, dmP * invN, dcov * invN, dvar * invN);
         if (rc >= i0 && rc < i1 && out_col) deps_acc += dvar;
       }
-      xr[ring(rc)] = X;
+      xr.at(xb, 2 * R + d) = X;  // row rc
     }
     // rows rx = x - 2R whose X windows are complete
 #pragma unroll
@@ -1028,7 +1073,7 @@ __device__ __forceinline__ void bwd_lo_body(const BwdLoArgs& a, const int bx, co
       float4 sum = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
       for (int k = 0; k < K; ++k) {  // rows outside the image hold zeros
-        const float4 v = xr[ring(rx - R + k)];
+        const float4 v = xr.at(xb, d + k);  // row rx-R+k
         sum.x += v.x;
         sum.y += v.y;
         sum.z += v.z;
@@ -1050,7 +1095,7 @@ __device__ __forceinline__ void bwd_lo_body(const BwdLoArgs& a, const int bx, co
         B.z += v.z;
         B.w += v.w;
       }
-      const float4 gpv = in[ring(rx)];
+      const float4 gpv = in.at(xb, d);  // row rx
       const size_t go = pofs + (size_t)rx * w + j;
       if (a.dI_lo) a.dI_lo[go] = B.x + 2.f * B.w * gpv.x + B.z * gpv.y;
       if (a.dp_lo) a.dp_lo[go] = B.y + B.z * gpv.x;
@@ -1066,6 +1111,8 @@ __device__ __forceinline__ void bwd_lo_body(const BwdLoArgs& a, const int bx, co
 #pragma unroll
     for (int d = 0; d < kPF; ++d) nq[d] = load(base + kPF + d);
     block(base, q);
+    in.advance();
+    xr.advance();
 #pragma unroll
     for (int d = 0; d < kPF; ++d) q[d] = nq[d];
   }
