@@ -124,14 +124,16 @@ int make_plan(const gf_desc_t* d, const gf_guide_t* g, Plan* p, const char** why
   // Launch shapes: the tuned entry for this key if the autotuner (or an
   // import) made one, else the defaults below; environment overrides win
   // (tuning experiments).
-  //  - rows per low-res walker wave: long enough to amortise the 2*halo
-  //    warm-up rows
+  //  - rows per low-res walker wave: 16 for r <= 2 (enough waves to fill
+  //    the chip; the register windows make the 2*halo warm-up rows cheap),
+  //    longer for larger radii to amortise their warm-up
   //  - high-res rows per apply thread: short walks keep DRAM streams
   //    sequential (8 measured best on MI355X for the 4 x 3 x 2048 x 3072
   //    workload): two low-res row blocks at S = 4, one at S = 8
   //  - low-res rows per backward high-res block: 2 (short walks stream
   //    best; the partial planes' extra border rows cost less)
-  TuneVal tv{r <= 2 ? 32 : 64, r <= 2 ? 32 : 64, S >= 8 ? S : 8, 2};
+  const int walk = r <= 2 ? 16 : r <= 4 ? 32 : 64;
+  TuneVal tv{walk, walk, S >= 8 ? S : 8, 2};
   TuneVal tuned;
   if (tune_lookup(TuneKey{d->io_dtype, S, r, gmode, d->mean_ab}, &tuned)) tv = tuned;
   if (env_int("GF_LO_ROWS", 0) > 0) tv.coTR = tv.loTR = env_int("GF_LO_ROWS", 0);
