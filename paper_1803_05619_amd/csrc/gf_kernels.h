@@ -1300,12 +1300,14 @@ hipError_t launch_bwd_hi_t(const Plan& p, const void* G_hi, const void* dq, void
   return hipGetLastError();
 }
 
-// High-res launch shapes: VEC is 16 bytes of the guide type, raised to S
-// when S is larger (so that a lane always covers whole low-res columns), or
-// 1 when the width is not a multiple of it.
+// High-res launch shapes: VEC = 4 elements per lane-load (16 bytes of
+// float, 8 of a half type: 8 half elements per lane would double the
+// double-buffered rows in registers and cut occupancy), raised to S when S
+// is larger (so that a lane always covers whole low-res columns), or 1 when
+// the width is not a multiple of it.
 template <typename TG, int S>
 constexpr int vec_for() {
-  return (int)(16 / sizeof(TG)) >= S ? (int)(16 / sizeof(TG)) : S;
+  return 4 >= S ? 4 : S;
 }
 
 template <typename TG, typename TQ>
