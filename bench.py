@@ -326,31 +326,39 @@ def workload_3(args, dev):
         it["dp_lo"] = torch.empty(it["p_lo"].shape, **f32)
         it["deps"] = torch.empty(1, **f32)
         items.append(it)
-    # autotune once per (s, r) key on its largest image
+    # autotune once per (s, r) key, on that key's largest image repeated as
+    # many times as the key has images (the launch sees about that much work
+    # in the batch, which decides between short and long walks)
     keys = {}
     for p, it in zip(probs, items):
         key = (p["s"], p["r"])
-        if key not in keys or p["H"] * p["W"] > keys[key][0]:
-            keys[key] = (p["H"] * p["W"], it)
+        big, cnt = keys.get(key, (None, 0))
+        if big is None or p["H"] * p["W"] > big[0]:
+            big = (p["H"] * p["W"], it)
+        keys[key] = (big, cnt + 1)
     log(f"autotuning {len(keys)} (s, r) keys")
-    for key, (_, it) in sorted(keys.items()):
-        gf.autotune(it["I_lo"], it["p_lo"], it["I_hi"], it["eps"], it["dq"], r=it["r"], iters=3)
+    for key, ((_, it), cnt) in sorted(keys.items()):
+        rep = lambda x: x.expand(cnt, *x.shape[1:]).contiguous()
+        gf.autotune(rep(it["I_lo"]), rep(it["p_lo"]), rep(it["I_hi"]), it["eps"], rep(it["dq"]),
+                    r=it["r"], iters=3)
+        torch.cuda.empty_cache()
     log("tuned shapes: " + gf.gf_tune_export().strip().replace("\n", "; "))
     plan = gf.BatchPlan(items)
 
     def step():
         plan.run(gf.GF_RUN_FORWARD | gf.GF_RUN_BACKWARD, graph=True)
 
-    per_step = {"gf_coef_multi": 0, "gf_apply_multi": 0, "gf_bwd_hi_multi": 0,
-                "gf_bwd_lo_multi": 0, "gf_eps_multi": 0}
+    # kernel records are per launch class: radius (low-res) or factor (high-res)
+    per_step = {"gf_eps_multi": 0}
     step_bytes = 0
     mpx = 0.0
     for p in probs:
         kb = identity_bytes(1, 3, p["H"], p["W"], p["h"], p["w"], 4)
-        per_step["gf_coef_multi"] += kb["coef"]
-        per_step["gf_apply_multi"] += kb["apply"]
-        per_step["gf_bwd_hi_multi"] += kb["bwd_hi"]
-        per_step["gf_bwd_lo_multi"] += kb["bwd_lo"]
+        for name, key in ((f"gf_coef_multi_r{p['r']}", "coef"),
+                          (f"gf_apply_multi_s{p['s']}", "apply"),
+                          (f"gf_bwd_hi_multi_s{p['s']}", "bwd_hi"),
+                          (f"gf_bwd_lo_multi_r{p['r']}", "bwd_lo")):
+            per_step[name] = per_step.get(name, 0) + kb[key]
         step_bytes += kb["apply"] + kb["coef"] + kb["bwd_hi"] + kb["bwd_lo"] - kb["coef"]
         mpx += p["H"] * p["W"] / 1e6
     step_bytes += sum(2 * 4 * 3 * p["h"] * p["w"] for p in probs)  # the one coef pass

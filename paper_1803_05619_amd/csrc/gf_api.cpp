@@ -112,10 +112,8 @@ int make_plan(const gf_desc_t* d, const gf_guide_t* g, Plan* p, const char** why
   q.xcd = env_int("GF_XCD", 0) != 0 ? 1 : 0;  // measured slower on MI355X: off by default
   q.planes = d->n * d->c;
   // elements per lane-load on the high-res side: 4 (16 bytes of float, 8 of
-  // a half type), at least S (a lane then covers whole low-res columns), 1
-  // when W is not a multiple
+  // a half type), 1 when W is not a multiple
   int V = 4;
-  if (V < S) V = S;
   q.VEC = (q.W % V == 0) ? V : 1;
 
   const int r = q.r;

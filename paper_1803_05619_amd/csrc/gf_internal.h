@@ -69,11 +69,12 @@ constexpr int kBwdLoRingPow2Max = 16;  // bwd_lo: 64 * (32 KR + 40 * 4) bytes
 
 // Small radii keep each lane's vertical windows (2R + block rows) in
 // registers instead of LDS rings: the LDS footprint per wave then shrinks to
-// the row buffers of the horizontal windows, which lifts occupancy.  The
-// coefficient walker holds 2 x 2 floats per window row, the backward walker
-// 2 x 4.
+// the row buffers of the horizontal windows, which lifts occupancy (at r = 4
+// the backward walker's rings would take 43 KB per wave: three waves per
+// CU).  The coefficient walker holds 2 x 2 floats per window row, the
+// backward walker 2 x 4.
 constexpr bool coef_reg_window(int R) { return 4 * (2 * R + kWalkBlock) <= 64; }
-constexpr bool bwd_lo_reg_window(int R) { return 8 * (2 * R + kWalkBlock) <= 64; }
+constexpr bool bwd_lo_reg_window(int R) { return 8 * (2 * R + kWalkBlock) <= 96; }
 constexpr size_t coef_lds_bytes(int R) {
   return 64 * (24 * kWalkBlock +
                (coef_reg_window(R) ? 0 : 16 * walker_ring_rows(R, kWalkBlock, kCoefRingPow2Max)));

@@ -1301,13 +1301,14 @@ hipError_t launch_bwd_hi_t(const Plan& p, const void* G_hi, const void* dq, void
 }
 
 // High-res launch shapes: VEC = 4 elements per lane-load (16 bytes of
-// float, 8 of a half type: 8 half elements per lane would double the
-// double-buffered rows in registers and cut occupancy), raised to S when S
-// is larger (so that a lane always covers whole low-res columns), or 1 when
-// the width is not a multiple of it.
+// float, 8 of a half type), or 1 when the width is not a multiple of 4.
+// Wider lanes (8 half elements, or VEC = S = 8 so that a lane covers a whole
+// low-res column) double the double-buffered rows held in registers and cut
+// occupancy to one or two waves per SIMD; at S = 8 a lane covers half a
+// low-res column and the backward flushes its row sums through LDS.
 template <typename TG, int S>
 constexpr int vec_for() {
-  return 4 >= S ? 4 : S;
+  return 4;
 }
 
 template <typename TG, typename TQ>
@@ -1398,11 +1399,31 @@ hipError_t backward_t(const Plan& p, const BwdArgs& b, hipStream_t s) {
 
 // ------------------------------------------------------------ batched launchers
 
+// Per-class kernel names for the timing records (radius or factor).
+#define GF_R_NAMES(base)                                                                    \
+  {base "_r0", base "_r1", base "_r2", base "_r3", base "_r4", base "_r5", base "_r6",      \
+   base "_r7", base "_r8", base "_r9", base "_r10"}
+__host__ inline const char* class_name_r(int kind, int R) {
+  static const char* coef[] = GF_R_NAMES("gf_coef_multi");
+  static const char* lo[] = GF_R_NAMES("gf_bwd_lo_multi");
+  if (R < 0 || R > 10) return kind == kClassCoef ? "gf_coef_multi" : "gf_bwd_lo_multi";
+  return kind == kClassCoef ? coef[R] : lo[R];
+}
+#undef GF_R_NAMES
+__host__ inline const char* class_name_s(int kind, int S) {
+  const int k = S == 1 ? 0 : S == 2 ? 1 : S == 4 ? 2 : 3;
+  static const char* apply[] = {"gf_apply_multi_s1", "gf_apply_multi_s2", "gf_apply_multi_s4",
+                                "gf_apply_multi_s8"};
+  static const char* hi[] = {"gf_bwd_hi_multi_s1", "gf_bwd_hi_multi_s2", "gf_bwd_hi_multi_s4",
+                             "gf_bwd_hi_multi_s8"};
+  return kind == kClassApply ? apply[k] : hi[k];
+}
+
 template <typename TG, typename TP>
 hipError_t launch_coef_multi(const BatchClass& c, char* ws, hipStream_t s) {
   MultiLaunch m = c.m;
   m.ws = ws;
-  prof_begin("gf_coef_multi", s);
+  prof_begin(class_name_r(kClassCoef, c.R), s);
   hipError_t err = with_radius(c.R, [&](auto rc) {
     constexpr int R = decltype(rc)::value;
     if (c.MAB)
@@ -1420,7 +1441,7 @@ template <typename TG, typename TP>
 hipError_t launch_bwd_lo_multi(const BatchClass& c, char* ws, hipStream_t s) {
   MultiLaunch m = c.m;
   m.ws = ws;
-  prof_begin("gf_bwd_lo_multi", s);
+  prof_begin(class_name_r(kClassBwdLo, c.R), s);
   hipError_t err = with_radius(c.R, [&](auto rc) {
     constexpr int R = decltype(rc)::value;
     if (c.MAB)
@@ -1439,7 +1460,7 @@ template <typename TG, typename TQ>
 hipError_t launch_apply_multi(const BatchClass& c, char* ws, hipStream_t s) {
   MultiLaunch m = c.m;
   m.ws = ws;
-  prof_begin("gf_apply_multi", s);
+  prof_begin(class_name_s(kClassApply, c.S), s);
   switch (c.S) {
 #define GF_CASE(SS)                                                                            \
   case SS:                                                                                     \
@@ -1463,7 +1484,7 @@ template <typename TG, typename TD, typename TO>
 hipError_t launch_bwd_hi_multi(const BatchClass& c, char* ws, hipStream_t s) {
   MultiLaunch m = c.m;
   m.ws = ws;
-  prof_begin("gf_bwd_hi_multi", s);
+  prof_begin(class_name_s(kClassBwdHi, c.S), s);
   switch (c.S) {
 #define GF_CASE(SS)                                                                             \
   case SS:                                                                                      \
