@@ -20,6 +20,7 @@
  *                                A, b themselves (mean_ab = 0, the form of
  *                                Algorithm 1)
  *   A_h, b_h                     bilinear upsampling f_up, half-pixel centres
+ *                                (or corner-aligned, desc.align_corners)
  *   q = A_h * G_h + b_h          Eq. (2)
  *
  * gf_backward is the adjoint (Algorithm 1, extended by the window mean of
@@ -80,6 +81,8 @@ typedef struct {
   int32_t r;        /* box radius, >= 0 (window side 2r + 1)              */
   int32_t mean_ab;  /* 1: window-mean A and b before upsampling; 0: not   */
   int32_t io_dtype; /* gf_dtype_t of I_lo, p_lo, I_hi, q_hi, dq_hi, dI_hi */
+  int32_t align_corners; /* 0: half-pixel centres (default); 1: corner   */
+                         /* alignment, source y (h_lo-1)/(h_hi-1)        */
 } gf_desc_t;
 
 /* Guidance map G = F(I) (Sec. III-D).  Pass NULL for the identity.

@@ -65,6 +65,8 @@ int make_plan(const gf_desc_t* d, const gf_guide_t* g, Plan* p, const char** why
     return bad(GF_ERR_INVALID_ARG, "low-res size must not exceed high-res size");
   if (d->r < 0) return bad(GF_ERR_INVALID_ARG, "radius r must be >= 0");
   if (d->mean_ab != 0 && d->mean_ab != 1) return bad(GF_ERR_INVALID_ARG, "mean_ab must be 0 or 1");
+  if (d->align_corners != 0 && d->align_corners != 1)
+    return bad(GF_ERR_INVALID_ARG, "align_corners must be 0 or 1");
   if (dtype_size(d->io_dtype) == 0) return bad(GF_ERR_INVALID_ARG, "unknown io_dtype");
   if (d->h_hi % d->h_lo || d->w_hi % d->w_lo || d->h_hi / d->h_lo != d->w_hi / d->w_lo)
     return bad(GF_ERR_UNSUPPORTED, "high/low size ratio must be one integer factor for both axes");
@@ -107,6 +109,7 @@ int make_plan(const gf_desc_t* d, const gf_guide_t* g, Plan* p, const char** why
   q.W = d->w_hi;
   q.r = d->r;
   q.mean_ab = d->mean_ab;
+  q.ac = d->align_corners;
   q.dtype = d->io_dtype;
   q.S = S;
   q.xcd = env_int("GF_XCD", 0) != 0 ? 1 : 0;  // measured slower on MI355X: off by default

@@ -100,9 +100,10 @@ void build_classes(const ClassMap& cm, int kind, std::vector<char>& host, size_t
     if (kind == kClassCoef || kind == kClassBwdLo) {
       c.R = kv.first.first;
       c.MAB = kv.first.second;
-    } else {
+    } else {  // high-res key: (S, 2 VEC + corner alignment)
       c.S = kv.first.first;
-      c.VEC = kv.first.second;
+      c.VEC = kv.first.second / 2;
+      c.AC = kv.first.second % 2;
     }
     c.lds = lds ? lds(geo[mem[0].item]) : 0;
     c.m.base = reinterpret_cast<const long long*>(dmem + base_off);
@@ -166,11 +167,12 @@ int create(const gf_item_t* items, int count, gf_plan** out) {
     const Plan& p = geo[k].p;
     cm_coef[{p.r, p.mean_ab}].push_back({k, geo[k].t_coef});
     cm_lo[{p.r, p.mean_ab}].push_back({k, geo[k].t_bwd_lo});
-    cm_hi[{p.S, p.VEC}].push_back({k, geo[k].t_bwd_hi});
+    cm_hi[{p.S, 2 * p.VEC + p.ac}].push_back({k, geo[k].t_bwd_hi});
     if (items[k].deps) ++n_eps;
   }
   ClassMap cm_apply;
-  for (int k = 0; k < count; ++k) cm_apply[{geo[k].p.S, geo[k].p.VEC}].push_back({k, geo[k].t_apply});
+  for (int k = 0; k < count; ++k)
+    cm_apply[{geo[k].p.S, 2 * geo[k].p.VEC + geo[k].p.ac}].push_back({k, geo[k].t_apply});
 
   // device table layout: eps values, four class families, eps items
   size_t total = align_up((size_t)count * sizeof(float), 256);

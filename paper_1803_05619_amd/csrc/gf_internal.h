@@ -16,6 +16,7 @@ namespace gf {
 // Geometry and launch shapes derived from a gf_desc_t on the host.
 struct Plan {
   int n, c, h, w, H, W, r, mean_ab, dtype;
+  int ac;       // corner-aligned bilinear (align_corners)
   int S;        // integer upsampling factor (H = S h, W = S w)
   int xcd;      // XCD-aware workgroup order for the high-res kernels
   int VEC;      // high-res elements per thread-load (16 bytes, or 1)
@@ -185,7 +186,7 @@ enum { kClassCoef = 0, kClassApply = 1, kClassBwdHi = 2, kClassBwdLo = 3 };
 
 struct BatchClass {
   int kind;
-  int S, VEC;     // high-res classes
+  int S, VEC, AC; // high-res classes (AC: corner alignment)
   int R, MAB;     // low-res classes
   size_t lds;     // dynamic LDS bytes (low-res classes)
   MultiLaunch m;

@@ -166,6 +166,57 @@ __device__ __forceinline__ Tap tap(int y, int S, int n) {
   return t;
 }
 
+// Corner-aligned taps (align_corners): source s = y (n - 1) / (N - 1) on a
+// low-res axis of length n (high-res N = S n); exact integer quotient and
+// remainder, so floor(s) is exact.
+__device__ __forceinline__ Tap tap_ac(int y, int n, int N) {
+  Tap t;
+  if (N <= 1) {
+    t.i0 = t.i1 = 0;
+    t.w = 0.f;
+    return t;
+  }
+  const long long num = (long long)y * (n - 1);
+  const int den = N - 1;
+  t.i0 = (int)(num / den);
+  t.w = (float)(num - (long long)t.i0 * den) / (float)den;
+  t.i1 = min(t.i0 + 1, n - 1);
+  return t;
+}
+
+template <bool AC>
+__device__ __forceinline__ Tap tap_t(int y, int S, int n, int N) {
+  if constexpr (AC)
+    return tap_ac(y, n, N);
+  else
+    return tap(y, S, n);
+}
+
+// Weights of high-res row y (in low-res row block i) on the low-res rows
+// i-1, i, i+1 under corner alignment (its taps are (i-1, i) or (i, i+1),
+// clamped at the last row).
+struct RowW {
+  float m, c, p;
+};
+__device__ __forceinline__ RowW row_weights_ac(int y, int i, int h, int H) {
+  const Tap t = tap_ac(y, h, H);
+  RowW r;
+  if (t.i0 < i) {
+    r.m = 1.f - t.w;
+    r.c = t.w;
+    r.p = 0.f;
+  } else if (t.i1 == t.i0) {
+    r.m = 0.f;
+    r.c = 1.f;
+    r.p = 0.f;
+  } else {
+    r.m = 0.f;
+    r.c = 1.f - t.w;
+    r.p = t.w;
+  }
+  return r;
+}
+
 // ------------------------------------------------------------ low-res column walkers
 //
 // The low-res kernels run one wave per strip of 64 adjacent columns (one
@@ -495,7 +546,7 @@ __device__ __forceinline__ void hrow(const float* L, int i, int h, int w, const 
 // register buffers alternate: while block i is computed, block i+1 is in
 // flight (its loads are issued after the low-res tap loads of block i, so
 // waiting for those does not wait for it).
-template <typename TG, typename TQ, int S, int VEC>
+template <typename TG, typename TQ, int S, int VEC, bool AC>
 __device__ __forceinline__ void apply_body(const ApplyArgs& a, const long long blk) {
   const long long t = blk * 256 + threadIdx.x;
   if (t >= a.total) return;
@@ -509,7 +560,7 @@ __device__ __forceinline__ void apply_body(const ApplyArgs& a, const long long b
   float wx[VEC];
 #pragma unroll
   for (int e = 0; e < VEC; ++e) {
-    const Tap tx = tap(x0 + e, S, w);
+    const Tap tx = tap_t<AC>(x0 + e, S, w, W);
     j0[e] = tx.i0;
     j1[e] = tx.i1;
     wx[e] = tx.w;
@@ -539,7 +590,15 @@ __device__ __forceinline__ void apply_body(const ApplyArgs& a, const long long b
     for (int t2 = 0; t2 < S; ++t2) {
       const int num = 2 * t2 + 1 - S;
       float q[VEC];
-      if (num < 0) {
+      if constexpr (AC) {
+        const RowW rw = row_weights_ac(S * i + t2, i, h, a.H);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+          const float A = rw.m * am[e] + rw.c * ac[e] + rw.p * ap[e];
+          const float B = rw.m * bm[e] + rw.c * bc[e] + rw.p * bp[e];
+          q[e] = A * g[t2][e] + B;
+        }
+      } else if (num < 0) {
         const float wy = (float)(num + 2 * S) / (float)(2 * S);
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
@@ -574,9 +633,9 @@ __device__ __forceinline__ void apply_body(const ApplyArgs& a, const long long b
   }
 }
 
-template <typename TG, typename TQ, int S, int VEC>
+template <typename TG, typename TQ, int S, int VEC, bool AC>
 __global__ __launch_bounds__(256) void apply_kernel(ApplyArgs a) {
-  apply_body<TG, TQ, S, VEC>(a, xcd_order(blockIdx.x, gridDim.x, a.xcd));
+  apply_body<TG, TQ, S, VEC, AC>(a, xcd_order(blockIdx.x, gridDim.x, a.xcd));
 }
 
 // ------------------------------------------------------------ backward: high-res
@@ -598,11 +657,13 @@ __global__ __launch_bounds__(256) void apply_kernel(ApplyArgs a) {
 // contributions that cross into the neighbouring lanes' columns move with
 // one lane shuffle each; otherwise (VEC = 1 fallback) through LDS.
 // Loads of row block i+1 are issued before block i is computed.
-template <typename TG, typename TD, typename TO, int S, int VEC>
+template <typename TG, typename TD, typename TO, int S, int VEC, bool AC>
 __device__ __forceinline__ void bwd_hi_body(const BwdHiArgs& a, const int bx, const int by,
                                             const int plane) {
   constexpr int TWH = 64 * VEC;  // high-res columns per block
-  constexpr bool REG = (VEC % S) == 0;
+  // register flush: compile-time half-pixel weights over whole low-res
+  // columns per lane; otherwise (corner alignment, VEC < S) through LDS
+  constexpr bool REG = (VEC % S) == 0 && !AC;
   constexpr int NB = REG ? VEC / S : 1;  // low-res columns per lane
   __shared__ float sR[REG ? 1 : 2][REG ? 1 : TWH];
   const int lane = threadIdx.x;
@@ -617,7 +678,7 @@ __device__ __forceinline__ void bwd_hi_body(const BwdHiArgs& a, const int bx, co
   float wx[VEC];
 #pragma unroll
   for (int e = 0; e < VEC; ++e) {
-    const Tap tx = tap(valid ? x0 + e : 0, S, w);
+    const Tap tx = tap_t<AC>(valid ? x0 + e : 0, S, w, W);
     j0[e] = tx.i0;
     j1[e] = tx.i1;
     wx[e] = tx.w;
@@ -725,7 +786,7 @@ __device__ __forceinline__ void bwd_hi_body(const BwdHiArgs& a, const int bx, co
           const int xlo = max(max(S * (j - 1), X_a), 0);
           const int xhi = min(min(S * (j + 2), X_a + TWH), W);
           for (int x = xlo; x < xhi; ++x) {
-            const Tap tx = tap(x, S, w);
+            const Tap tx = tap_t<AC>(x, S, w, W);
             const float wt = (tx.i0 == j ? 1.f - tx.w : 0.f) + (tx.i1 == j ? tx.w : 0.f);
             sa += wt * sR[0][x - X_a];
             sb += wt * sR[1][x - X_a];
@@ -766,7 +827,21 @@ __device__ __forceinline__ void bwd_hi_body(const BwdHiArgs& a, const int bx, co
       // weights of this row on the low-res rows i-1, i, i+1; at the image's
       // first/last row block the source row is clamped and all weight goes
       // to row i (selected as weights, not as branches over accumulators)
-      if (num < 0) {
+      if constexpr (AC) {
+        const RowW rw = row_weights_ac(S * i + t2, i, h, a.H);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+          const float dv = valid ? d[t2][e] : 0.f;
+          o[e] = dv * (rw.m * am[e] + rw.c * ac[e] + rw.p * ap[e]);
+          const float vA = dv * g[t2][e], vB = dv;
+          pA[e] += rw.m * vA;
+          cA[e] += rw.c * vA;
+          nA[e] += rw.p * vA;
+          pB[e] += rw.m * vB;
+          cB[e] += rw.c * vB;
+          nB[e] += rw.p * vB;
+        }
+      } else if (num < 0) {
         const float wy = (float)(num + 2 * S) / (float)(2 * S);
         const float wp = top ? 0.f : 1.f - wy, wc = top ? 1.f : wy;
 #pragma unroll
@@ -818,13 +893,14 @@ __device__ __forceinline__ void bwd_hi_body(const BwdHiArgs& a, const int bx, co
   flush(cA, cB, i_b - i_a + 1);  // row i_b (contributions of the last rows)
 }
 
-template <typename TG, typename TD, typename TO, int S, int VEC>
+template <typename TG, typename TD, typename TO, int S, int VEC, bool AC>
 __global__ __launch_bounds__(64) void bwd_hi_kernel(BwdHiArgs a) {
   const long long nwg = (long long)gridDim.x * gridDim.y * gridDim.z;
   const long long lin = xcd_order(
       blockIdx.x + (long long)gridDim.x * (blockIdx.y + (long long)gridDim.y * blockIdx.z), nwg,
       a.xcd);
-  bwd_hi_body<TG, TD, TO, S, VEC>(a, (int)(lin % gridDim.x), (int)((lin / gridDim.x) % gridDim.y),
+  bwd_hi_body<TG, TD, TO, S, VEC, AC>(a, (int)(lin % gridDim.x),
+                                      (int)((lin / gridDim.x) % gridDim.y),
                                   (int)(lin / ((long long)gridDim.x * gridDim.y)));
 }
 
@@ -1190,7 +1266,7 @@ __global__ __launch_bounds__(64) void coef_multi_kernel(MultiLaunch m) {
   }
 }
 
-template <typename TG, typename TQ, int S, int VEC>
+template <typename TG, typename TQ, int S, int VEC, bool AC>
 __global__ __launch_bounds__(256) void apply_multi_kernel(MultiLaunch m) {
   for (long long t = blockIdx.x; t < m.total; t += gridDim.x) {
     long long l;
@@ -1198,11 +1274,11 @@ __global__ __launch_bounds__(256) void apply_multi_kernel(MultiLaunch m) {
     ApplyArgs a = it.a;
     a.abar = rebase(m.ws, a.abar);
     a.bbar = rebase(m.ws, a.bbar);
-    apply_body<TG, TQ, S, VEC>(a, l);
+    apply_body<TG, TQ, S, VEC, AC>(a, l);
   }
 }
 
-template <typename TG, typename TD, typename TO, int S, int VEC>
+template <typename TG, typename TD, typename TO, int S, int VEC, bool AC>
 __global__ __launch_bounds__(64) void bwd_hi_multi_kernel(MultiLaunch m) {
   for (long long t = blockIdx.x; t < m.total; t += gridDim.x) {
     long long l;
@@ -1211,7 +1287,7 @@ __global__ __launch_bounds__(64) void bwd_hi_multi_kernel(MultiLaunch m) {
     a.abar = rebase(m.ws, a.abar);
     a.U = rebase(m.ws, a.U);
     const long long xy = (long long)it.nx * it.ny;
-    bwd_hi_body<TG, TD, TO, S, VEC>(a, (int)(l % it.nx), (int)((l / it.nx) % it.ny),
+    bwd_hi_body<TG, TD, TO, S, VEC, AC>(a, (int)(l % it.nx), (int)((l / it.nx) % it.ny),
                                     (int)(l / xy));
   }
 }
@@ -1277,25 +1353,25 @@ hipError_t launch_coef(const Plan& p, const void* I_lo, const void* p_lo, const 
   return err;
 }
 
-template <typename TG, typename TQ, int S, int VEC>
+template <typename TG, typename TQ, int S, int VEC, bool AC>
 hipError_t launch_apply_t(const Plan& p, const void* G_hi, void* q, const float* abar,
                           const float* bbar, hipStream_t s) {
   ApplyArgs a{G_hi, q, abar, bbar, p.h, p.w, p.H, p.W, p.RB,
               p.nrb, p.nxv, (long long)p.planes * p.nrb * p.nxv, p.xcd};
   const unsigned blocks = (unsigned)((a.total + 255) / 256);
   prof_begin("gf_apply", s);
-  hipLaunchKernelGGL((apply_kernel<TG, TQ, S, VEC>), dim3(blocks), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((apply_kernel<TG, TQ, S, VEC, AC>), dim3(blocks), dim3(256), 0, s, a);
   prof_end(s);
   return hipGetLastError();
 }
 
-template <typename TG, typename TD, typename TO, int S, int VEC>
+template <typename TG, typename TD, typename TO, int S, int VEC, bool AC>
 hipError_t launch_bwd_hi_t(const Plan& p, const void* G_hi, const void* dq, void* out,
                            const float* abar, float* U, hipStream_t s) {
   BwdHiArgs a{G_hi, dq, out, abar, U, p.h, p.w, p.H, p.W, p.bh, p.tw, p.nby, p.nbx, p.xcd};
   prof_begin("gf_bwd_hi", s);
-  hipLaunchKernelGGL((bwd_hi_kernel<TG, TD, TO, S, VEC>), dim3(p.nbx, p.nby, p.planes), dim3(64),
-                     0, s, a);
+  hipLaunchKernelGGL((bwd_hi_kernel<TG, TD, TO, S, VEC, AC>), dim3(p.nbx, p.nby, p.planes),
+                     dim3(64), 0, s, a);
   prof_end(s);
   return hipGetLastError();
 }
@@ -1306,38 +1382,45 @@ hipError_t launch_bwd_hi_t(const Plan& p, const void* G_hi, const void* dq, void
 // low-res column) double the double-buffered rows held in registers and cut
 // occupancy to one or two waves per SIMD; at S = 8 a lane covers half a
 // low-res column and the backward flushes its row sums through LDS.
-template <typename TG, int S>
-constexpr int vec_for() {
-  return 4;
+constexpr int kVec = 4;
+
+// Calls f(integral_constant S, integral_constant VEC, integral_constant AC)
+// for the plan's factor, vector width and alignment.
+template <typename F>
+hipError_t with_hires_shape(int S, int VEC, int ac, F&& f) {
+  auto by_vec = [&](auto sc) -> hipError_t {
+    auto by_ac = [&](auto vc) -> hipError_t {
+      if (ac) return f(sc, vc, std::integral_constant<bool, true>{});
+      return f(sc, vc, std::integral_constant<bool, false>{});
+    };
+    if (VEC == 1) return by_ac(std::integral_constant<int, 1>{});
+    return by_ac(std::integral_constant<int, kVec>{});
+  };
+  switch (S) {
+    case 1: return by_vec(std::integral_constant<int, 1>{});
+    case 2: return by_vec(std::integral_constant<int, 2>{});
+    case 4: return by_vec(std::integral_constant<int, 4>{});
+    case 8: return by_vec(std::integral_constant<int, 8>{});
+  }
+  return hipErrorInvalidValue;
 }
 
 template <typename TG, typename TQ>
 hipError_t launch_apply(const Plan& p, const void* G_hi, void* q, const float* abar,
                         const float* bbar, hipStream_t s) {
-  switch (p.S) {
-#define GF_CASE(SS)                                                                        \
-  case SS:                                                                                 \
-    return p.VEC == 1 ? launch_apply_t<TG, TQ, SS, 1>(p, G_hi, q, abar, bbar, s)          \
-                      : launch_apply_t<TG, TQ, SS, vec_for<TG, SS>()>(p, G_hi, q, abar, bbar, s);
-    GF_CASE(1) GF_CASE(2) GF_CASE(4) GF_CASE(8)
-#undef GF_CASE
-  }
-  return hipErrorInvalidValue;
+  return with_hires_shape(p.S, p.VEC, p.ac, [&](auto sc, auto vc, auto acc) {
+    return launch_apply_t<TG, TQ, decltype(sc)::value, decltype(vc)::value, decltype(acc)::value>(
+        p, G_hi, q, abar, bbar, s);
+  });
 }
 
 template <typename TG, typename TD, typename TO>
 hipError_t launch_bwd_hi(const Plan& p, const void* G_hi, const void* dq, void* out,
                          const float* abar, float* U, hipStream_t s) {
-  switch (p.S) {
-#define GF_CASE(SS)                                                                         \
-  case SS:                                                                                  \
-    return p.VEC == 1                                                                       \
-               ? launch_bwd_hi_t<TG, TD, TO, SS, 1>(p, G_hi, dq, out, abar, U, s)           \
-               : launch_bwd_hi_t<TG, TD, TO, SS, vec_for<TG, SS>()>(p, G_hi, dq, out, abar, U, s);
-    GF_CASE(1) GF_CASE(2) GF_CASE(4) GF_CASE(8)
-#undef GF_CASE
-  }
-  return hipErrorInvalidValue;
+  return with_hires_shape(p.S, p.VEC, p.ac, [&](auto sc, auto vc, auto acc) {
+    return launch_bwd_hi_t<TG, TD, TO, decltype(sc)::value, decltype(vc)::value,
+                           decltype(acc)::value>(p, G_hi, dq, out, abar, U, s);
+  });
 }
 
 template <typename TG, typename TP>
@@ -1461,23 +1544,14 @@ hipError_t launch_apply_multi(const BatchClass& c, char* ws, hipStream_t s) {
   MultiLaunch m = c.m;
   m.ws = ws;
   prof_begin(class_name_s(kClassApply, c.S), s);
-  switch (c.S) {
-#define GF_CASE(SS)                                                                            \
-  case SS:                                                                                     \
-    if (c.VEC == 1)                                                                            \
-      hipLaunchKernelGGL((apply_multi_kernel<TG, TQ, SS, 1>), dim3(m.grid), dim3(256), 0, s, m); \
-    else                                                                                       \
-      hipLaunchKernelGGL((apply_multi_kernel<TG, TQ, SS, vec_for<TG, SS>()>), dim3(m.grid),    \
-                         dim3(256), 0, s, m);                                                  \
-    break;
-    GF_CASE(1) GF_CASE(2) GF_CASE(4) GF_CASE(8)
-#undef GF_CASE
-    default:
-      prof_end(s);
-      return hipErrorInvalidValue;
-  }
+  const hipError_t e = with_hires_shape(c.S, c.VEC, c.AC, [&](auto sc, auto vc, auto acc) {
+    hipLaunchKernelGGL((apply_multi_kernel<TG, TQ, decltype(sc)::value, decltype(vc)::value,
+                                           decltype(acc)::value>),
+                       dim3(m.grid), dim3(256), 0, s, m);
+    return hipGetLastError();
+  });
   prof_end(s);
-  return hipGetLastError();
+  return e;
 }
 
 template <typename TG, typename TD, typename TO>
@@ -1485,24 +1559,14 @@ hipError_t launch_bwd_hi_multi(const BatchClass& c, char* ws, hipStream_t s) {
   MultiLaunch m = c.m;
   m.ws = ws;
   prof_begin(class_name_s(kClassBwdHi, c.S), s);
-  switch (c.S) {
-#define GF_CASE(SS)                                                                             \
-  case SS:                                                                                      \
-    if (c.VEC == 1)                                                                             \
-      hipLaunchKernelGGL((bwd_hi_multi_kernel<TG, TD, TO, SS, 1>), dim3(m.grid), dim3(64), 0, s, \
-                         m);                                                                    \
-    else                                                                                        \
-      hipLaunchKernelGGL((bwd_hi_multi_kernel<TG, TD, TO, SS, vec_for<TG, SS>()>), dim3(m.grid), \
-                         dim3(64), 0, s, m);                                                    \
-    break;
-    GF_CASE(1) GF_CASE(2) GF_CASE(4) GF_CASE(8)
-#undef GF_CASE
-    default:
-      prof_end(s);
-      return hipErrorInvalidValue;
-  }
+  const hipError_t e = with_hires_shape(c.S, c.VEC, c.AC, [&](auto sc, auto vc, auto acc) {
+    hipLaunchKernelGGL((bwd_hi_multi_kernel<TG, TD, TO, decltype(sc)::value, decltype(vc)::value,
+                                            decltype(acc)::value>),
+                       dim3(m.grid), dim3(64), 0, s, m);
+    return hipGetLastError();
+  });
   prof_end(s);
-  return hipGetLastError();
+  return e;
 }
 
 // Forward (mode bit 1) and/or backward (bit 2) of every item; with both,

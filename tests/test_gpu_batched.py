@@ -35,8 +35,10 @@ def uneven_items(count, div, io_dtype="f32", extra=True):
         e2 = datagen.make_problem(1, 3, 4 * 30, 4 * 44, 4, 2, 1e-2, io_dtype, config=141)
         e3 = datagen.make_problem(1, 3, 96, 64, 1, 3, 1e-4, io_dtype, config=142)
         e4 = datagen.make_problem(2, 3, 8 * 16, 8 * 20, 8, 1, 1e-3, io_dtype, config=143)
+        e5 = datagen.make_problem(1, 3, 4 * 24, 4 * 36, 4, 1, 1e-3, io_dtype, config=144)
         e1["mean_ab"], e2["mean_ab"], e3["mean_ab"], e4["mean_ab"] = True, False, True, True
-        probs += [e1, e2, e3, e4]
+        e5["mean_ab"], e5["align_corners"] = True, True
+        probs += [e1, e2, e3, e4, e5]
     return probs
 
 
@@ -44,7 +46,8 @@ def device_items(probs):
     items = []
     for p in probs:
         it = {k: p[k].to(DEV) for k in ("I_lo", "p_lo", "I_hi", "dq")}
-        it.update(r=p["r"], eps=float(np.atleast_1d(p["eps"])[0]), mean_ab=p["mean_ab"])
+        it.update(r=p["r"], eps=float(np.atleast_1d(p["eps"])[0]), mean_ab=p["mean_ab"],
+                  align_corners=p.get("align_corners", False))
         it["q"] = torch.empty_like(it["I_hi"])
         it["dI_hi"] = torch.empty_like(it["I_hi"])
         it["dI_lo"] = torch.empty(it["I_lo"].shape, dtype=torch.float32, device=DEV)
@@ -55,9 +58,11 @@ def device_items(probs):
 
 
 def singles(gf, it):
-    q = gf.forward(it["I_lo"], it["p_lo"], it["I_hi"], it["eps"], it["r"], it["mean_ab"])
+    ac = it.get("align_corners", False)
+    q = gf.forward(it["I_lo"], it["p_lo"], it["I_hi"], it["eps"], it["r"], it["mean_ab"],
+                   align_corners=ac)
     g = gf.backward(it["I_lo"], it["p_lo"], it["I_hi"], it["eps"], it["dq"], it["r"],
-                    it["mean_ab"])
+                    it["mean_ab"], align_corners=ac)
     return {"q": q, "dI_lo": g[0], "dp_lo": g[1], "dI_hi": g[2], "deps": g[3]}
 
 
@@ -149,8 +154,10 @@ def test_batched_against_oracle(dt):
     for p, it in zip(probs, items):
         args = [p[k].double().numpy() for k in ("I_lo", "p_lo", "I_hi")]
         eps = float(np.atleast_1d(p["eps"])[0])
-        q = oracle.forward(*args, p["r"], eps, mean_ab=p["mean_ab"])
-        g = oracle.backward(*args, p["r"], eps, p["dq"].double().numpy(), mean_ab=p["mean_ab"])
+        ac = p.get("align_corners", False)
+        q = oracle.forward(*args, p["r"], eps, mean_ab=p["mean_ab"], align_corners=ac)
+        g = oracle.backward(*args, p["r"], eps, p["dq"].double().numpy(), mean_ab=p["mean_ab"],
+                            align_corners=ac)
         err = {"q": float(np.abs(it["q"].double().cpu().numpy() - q).max())}
         for k in ("dI_lo", "dp_lo", "dI_hi"):
             ref = g[k]

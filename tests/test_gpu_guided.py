@@ -228,3 +228,29 @@ def test_guided_forward_backward_equals_separate_calls(mode):
         assert (a is None and b is None) or torch.equal(a, b)
     if stats is not None:
         assert torch.equal(stats, saved)
+
+
+@pytest.mark.parametrize("mode", ["grey", "transform"])
+def test_guided_align_corners(mode):
+    gf = _gf()
+    if mode == "grey":
+        prob = grey_problem(2, 3, 2, 4 * 24, 4 * 40, 4, 1, 1e-3, "f32", config=151)
+    else:
+        prob = datagen.make_config(2, div=16, n=2)
+    d = {k: prob[k].to(DEV) for k in ("I_lo", "p_lo", "I_hi", "dq")}
+    guide = make_guide(gf, mode, prob)
+    out = gf.forward_backward(d["I_lo"], d["p_lo"], d["I_hi"], prob["eps"], d["dq"], prob["r"],
+                              guide=guide, align_corners=True)
+    torch.cuda.synchronize()
+    got = {k: v.double().cpu().numpy() for k, v in zip(
+        ("q", "dI_lo", "dp_lo", "dI_hi", "deps", "dparams"), out) if v is not None}
+    args = [prob[k].double().numpy() for k in ("I_lo", "p_lo", "I_hi")]
+    gkw = dict(guide=prob.get("guide") if mode == "transform" else None, guide_mode=mode,
+               align_corners=True)
+    ref = {"q": oracle.forward(*args, prob["r"], prob["eps"], **gkw)}
+    ref.update(oracle.backward(*args, prob["r"], prob["eps"], prob["dq"].double().numpy(), **gkw))
+    hidden = np.asarray(prob["guide"]["w1"]).shape[0] if mode == "transform" else None
+    err = errors(got, ref, hidden)
+    print("errors:", {k: f"{v:.3e}" for k, v in err.items()}, flush=True)
+    for k, v in err.items():
+        assert v <= TOL[prob["io_dtype"]], (k, v, err)

@@ -34,25 +34,29 @@ def to_dev(prob):
             for k in ("I_lo", "p_lo", "I_hi", "dq")}
 
 
-def run_both(prob, mean_ab=True, eps=None, backward=True):
+def run_both(prob, mean_ab=True, eps=None, backward=True, align_corners=False):
     gf = _gf()
     d = to_dev(prob)
     eps = prob["eps"] if eps is None else eps
     print(f"case n={prob['n']} c={prob['c']} H={prob['H']} W={prob['W']} s={prob['s']} "
-          f"r={prob['r']} dtype={prob['io_dtype']} mean_ab={mean_ab}", flush=True)
-    q = gf.forward(d["I_lo"], d["p_lo"], d["I_hi"], eps, prob["r"], mean_ab)
+          f"r={prob['r']} dtype={prob['io_dtype']} mean_ab={mean_ab} ac={align_corners}",
+          flush=True)
+    q = gf.forward(d["I_lo"], d["p_lo"], d["I_hi"], eps, prob["r"], mean_ab,
+                   align_corners=align_corners)
     out = {"q": q}
     if backward:
         dI_lo, dp_lo, dI_hi, deps, _ = gf.backward(d["I_lo"], d["p_lo"], d["I_hi"], eps, d["dq"],
-                                                prob["r"], mean_ab)
+                                                   prob["r"], mean_ab,
+                                                   align_corners=align_corners)
         out.update(dI_lo=dI_lo, dp_lo=dp_lo, dI_hi=dI_hi, deps=deps)
     torch.cuda.synchronize()
     out = {k: v.double().cpu().numpy() for k, v in out.items()}
     args = [prob[k].double().numpy() for k in ("I_lo", "p_lo", "I_hi")]
-    ref = {"q": oracle.forward(*args, prob["r"], eps, mean_ab=mean_ab)}
+    ref = {"q": oracle.forward(*args, prob["r"], eps, mean_ab=mean_ab,
+                               align_corners=align_corners)}
     if backward:
         ref.update(oracle.backward(*args, prob["r"], eps, prob["dq"].double().numpy(),
-                                   mean_ab=mean_ab))
+                                   mean_ab=mean_ab, align_corners=align_corners))
     return out, ref
 
 
@@ -223,3 +227,27 @@ def test_forward_backward_equals_separate_calls(cfg, dt):
     assert torch.equal(fb[0], q)
     for a, b in zip(fb[1:5], g[:4]):
         assert torch.equal(a, b)
+
+
+# ------------------------------------------------------------ corner alignment
+
+@pytest.mark.parametrize("s, r, mean_ab", [(1, 1, True), (2, 2, True), (4, 1, True), (4, 3, False),
+                                           (8, 1, True), (8, 2, False)])
+def test_align_corners(s, r, mean_ab):
+    """Corner-aligned bilinear (align_corners = 1): per-column and per-row
+    taps at run time, the backward's row sums flushed through LDS."""
+    prob = datagen.make_problem(2, 3, 16 * s + 8 * s, 24 * s + 8 * s, s, r, 1e-3, "f32",
+                                config=160 + s, noise=0.02)
+    check(prob, mean_ab=mean_ab, align_corners=True)
+
+
+@pytest.mark.parametrize("dt", ["bf16", "f16"])
+def test_align_corners_half_io(dt):
+    prob = datagen.make_problem(2, 3, 4 * 40, 4 * 52, 4, 2, 1e-4, dt, config=170, noise=0.02)
+    check(prob, align_corners=True)
+
+
+def test_align_corners_scalar_width():
+    """A width that is not a multiple of 4 (one column per lane)."""
+    prob = datagen.make_problem(1, 3, 2 * 30, 2 * 37, 2, 1, 1e-3, "f32", config=171, noise=0.02)
+    check(prob, align_corners=True)
