@@ -326,22 +326,8 @@ def workload_3(args, dev):
         it["dp_lo"] = torch.empty(it["p_lo"].shape, **f32)
         it["deps"] = torch.empty(1, **f32)
         items.append(it)
-    # autotune once per (s, r) key, on that key's largest image repeated as
-    # many times as the key has images (the launch sees about that much work
-    # in the batch, which decides between short and long walks)
-    keys = {}
-    for p, it in zip(probs, items):
-        key = (p["s"], p["r"])
-        big, cnt = keys.get(key, (None, 0))
-        if big is None or p["H"] * p["W"] > big[0]:
-            big = (p["H"] * p["W"], it)
-        keys[key] = (big, cnt + 1)
-    log(f"autotuning {len(keys)} (s, r) keys")
-    for key, ((_, it), cnt) in sorted(keys.items()):
-        rep = lambda x: x.expand(cnt, *x.shape[1:]).contiguous()
-        gf.autotune(rep(it["I_lo"]), rep(it["p_lo"]), rep(it["I_hi"]), it["eps"], rep(it["dq"]),
-                    r=it["r"], iters=3)
-        torch.cuda.empty_cache()
+    if args.autotune != 0:
+        log(f"autotuned {gf.autotune_batch(items)} launch-shape keys")
     log("tuned shapes: " + gf.gf_tune_export().strip().replace("\n", "; "))
     plan = gf.BatchPlan(items)
 
@@ -417,8 +403,11 @@ def main():
     ap.add_argument("--workload", type=int, default=1, choices=sorted(WORKLOADS))
     ap.add_argument("--radius", type=int, default=None, help="workload 4: radius (default 8)")
     ap.add_argument("--items", type=int, default=64, help="workload 3: images")
-    ap.add_argument("--autotune", type=int, default=1,
-                    help="1: run the autotuner on the workload before timing (untimed)")
+    ap.add_argument("--autotune", type=int, default=-1,
+                    help="1: run the autotuner on the workload before timing (untimed); "
+                         "0: the planner's default shapes; default: 1 for workload 3 (the "
+                         "uneven batch), 0 otherwise (the defaults are the tuned shapes of "
+                         "workload 1)")
     ap.add_argument("--plain-steps", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
@@ -446,6 +435,8 @@ def main():
         del src, dst
     wl = WORKLOADS[args.workload](args, dev)
     step = wl["step"]
+    if args.autotune < 0:
+        args.autotune = 1 if args.workload == 3 else 0
     if args.autotune and "tune" in wl:
         log("autotuning the launch shapes (untimed)")
         wl["tune"]()

@@ -68,6 +68,8 @@ def _load():
         lib.gfo_backward.restype = ci
         lib.gfo_guide_apply.argtypes = [ci, ctypes.POINTER(_Guide), ci, ci, ci, ctypes.c_long, dp, dp]
         lib.gfo_guide_apply.restype = ci
+        lib.gfo_guide_preact.argtypes = [ctypes.POINTER(_Guide), ci, ci, ctypes.c_long, dp, dp]
+        lib.gfo_guide_preact.restype = ci
         lib.gfo_guide_grad_size.argtypes = [ci, ci, ci]
         lib.gfo_guide_grad_size.restype = ctypes.c_long
         _lib = lib
@@ -192,6 +194,21 @@ def guide_apply(X, guide=None, guide_mode=None, cout=None):
     if rc != 0:
         raise RuntimeError(f"gfo_guide_apply failed ({rc})")
     return G
+
+
+def guide_preact(X, guide):
+    """Pre-activations y = lam h + mu BN(h) of the transform guide for one
+    call (X: [n, cin, H, W]; batch statistics of X): [n, hidden, H, W]."""
+    lib = _load()
+    X = _f64(X)
+    n, cin, H, W = X.shape
+    keep = []
+    g = _guide_struct(guide, keep)
+    Y = np.empty((n, g.hidden, H, W), np.float64)
+    rc = lib.gfo_guide_preact(ctypes.byref(g), n, cin, H * W, _ptr(X), _ptr(Y))
+    if rc != 0:
+        raise RuntimeError(f"gfo_guide_preact failed ({rc})")
+    return Y
 
 
 def guide_grad_split(flat, cin, cout, hidden):

@@ -426,6 +426,34 @@ int gfo_guide_apply(int mode, const gfo_guide_t *g, int n, int cin, int cout,
   return rc;
 }
 
+/* Pre-activations y = lam h + mu BN(h) of the transform (hidden channels,
+ * batch statistics of X), Y[n, hidden, P]: where some y is within rounding
+ * of 0 the leaky ReLU's branch is not determined by any finite-precision
+ * evaluation, which tests use to tell such pixels apart. */
+int gfo_guide_preact(const gfo_guide_t *g, int n, int cin, long P, const double *X,
+                     double *Y) {
+  if (!g || g->hidden <= 0) return -1;
+  const int K = g->hidden;
+  double *G = (double *)malloc(sizeof(double) * (size_t)n * 3 * P);
+  if (!G) return -2;
+  guide_state_t st;
+  memset(&st, 0, sizeof(st));
+  int rc = guide_forward(GFO_GUIDE_TRANSFORM, g, n, cin, 3, P, X, G, &st);
+  if (rc == 0) {
+    for (int b = 0; b < n; ++b)
+      for (int k = 0; k < K; ++k)
+        for (long p = 0; p < P; ++p) {
+          const long idx = ((long)b * K + k) * P + p;
+          const double h = st.hpre[idx];
+          const double hn = (h - st.mean[k]) * st.rstd[k];
+          Y[idx] = g->lam * h + g->mu * (g->gamma[k] * hn + g->beta[k]);
+        }
+  }
+  guide_state_free(&st);
+  free(G);
+  return rc;
+}
+
 int gfo_forward(int n, int c, int h, int w, int H, int W, int r,
                 int align_corners, int mean_ab, int guide_mode, int cin,
                 const gfo_guide_t *gd, const double *I_lo, const double *p_lo,

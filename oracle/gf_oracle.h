@@ -53,6 +53,8 @@ int gfo_forward(int n, int c, int h, int w, int H, int W, int r,
                 const double *I_hi, const double *eps, int eps_count,
                 double *q);
 
+int gfo_guide_preact(const gfo_guide_t *g, int n, int cin, long P, const double *X,
+                     double *Y);
 int gfo_backward(int n, int c, int h, int w, int H, int W, int r,
                  int align_corners, int mean_ab, int guide_mode, int cin,
                  const gfo_guide_t *g, const double *I_lo,

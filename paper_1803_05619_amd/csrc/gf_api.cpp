@@ -197,6 +197,10 @@ int make_plan(const gf_desc_t* d, const gf_guide_t* g, Plan* p, const char** why
     o += align_up(sizeof(float) * kAccFloats * q.n * std::max(q.g_chunks_lo, q.g_chunks_hi) * 2, 256);
     q.off_acct = o;
     o += align_up(sizeof(float) * kAccFloats * 2, 256);
+    q.off_mlo = o;
+    o += align_up(sizeof(uint16_t) * q.n * q.h * q.w, 256);
+    q.off_mhi = o;
+    o += align_up(sizeof(uint16_t) * q.n * q.H * q.W, 256);
     q.ws_bwd = o;
     // the forward also needs the moments and folded parameters: place them
     // after G_h as well (same offsets as in the backward layout are not

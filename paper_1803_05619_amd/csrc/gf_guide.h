@@ -270,9 +270,13 @@ __device__ __forceinline__ void stage_fold_f64(const float* __restrict__ f, Fold
   __syncthreads();
 }
 
+// The branch taken by each hidden channel is returned in bits (bit k set
+// when y_k > 0): the backward uses the same branches, so the gradient is
+// that of the G this map produced (a pixel whose y_k is within rounding of 0
+// could otherwise take the other branch in single precision).
 template <int PX>
 __device__ __forceinline__ void transform_px(const FoldF64& c, const float (&x)[3][PX],
-                                             float (&g)[3][PX]) {
+                                             float (&g)[3][PX], unsigned (&bits)[PX]) {
   double acc[3][PX], xd[3][PX];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
@@ -282,6 +286,8 @@ __device__ __forceinline__ void transform_px(const FoldF64& c, const float (&x)[
       xd[i][e] = x[i][e];
     }
   const double slope = c.slope;
+#pragma unroll
+  for (int e = 0; e < PX; ++e) bits[e] = 0u;
 #pragma unroll 2
   for (int k = 0; k < kKP; ++k) {
     const double a0 = c.k[k][0], a1 = c.k[k][1], a2 = c.k[k][2], bb = c.k[k][3];
@@ -289,7 +295,9 @@ __device__ __forceinline__ void transform_px(const FoldF64& c, const float (&x)[
 #pragma unroll
     for (int e = 0; e < PX; ++e) {
       const double y = bb + a0 * xd[0][e] + a1 * xd[1][e] + a2 * xd[2][e];
-      const double z = y > 0.0 ? y : slope * y;
+      const bool pos = y > 0.0;
+      const double z = pos ? y : slope * y;
+      bits[e] |= (pos ? 1u : 0u) << k;
       acc[0][e] += v0 * z;
       acc[1][e] += v1 * z;
       acc[2][e] += v2 * z;
@@ -307,6 +315,7 @@ struct MapArgs {
   long long P;
   int c_in, c;
   const float* fold;
+  uint16_t* mask;  // transform: [n][P] leaky-ReLU branches (bit k: y_k > 0)
 };
 
 // Grey map: every output channel is the mean of the c_in input channels.
@@ -333,6 +342,7 @@ template <typename TX>
 __global__ __launch_bounds__(256) void guide_map_transform_kernel(MapArgs a) {
   const TX* __restrict__ X = reinterpret_cast<const TX*>(a.x) + (size_t)blockIdx.y * 3 * a.P;
   float* __restrict__ G = a.G + (size_t)blockIdx.y * 3 * a.P;
+  uint16_t* __restrict__ M = a.mask + (size_t)blockIdx.y * a.P;
   __shared__ FoldF64 c;
   stage_fold_f64(a.fold, c);
   const long long stride = (long long)gridDim.x * 256;
@@ -340,9 +350,12 @@ __global__ __launch_bounds__(256) void guide_map_transform_kernel(MapArgs a) {
     const long long P4 = a.P >> 2;
     for (long long v = (long long)blockIdx.x * 256 + threadIdx.x; v < P4; v += stride) {
       float x[3][4], g[3][4];
+      unsigned bits[4];
 #pragma unroll
       for (int i = 0; i < 3; ++i) load_vec<TX, 4>(X + i * a.P + 4 * v, x[i]);
-      transform_px<4>(c, x, g);
+      transform_px<4>(c, x, g, bits);
+      *reinterpret_cast<uint2*>(M + 4 * v) =
+          make_uint2(bits[0] | (bits[1] << 16), bits[2] | (bits[3] << 16));
 #pragma unroll
       for (int i = 0; i < 3; ++i)
         *reinterpret_cast<float4*>(G + i * a.P + 4 * v) = make_float4(g[i][0], g[i][1], g[i][2],
@@ -351,9 +364,11 @@ __global__ __launch_bounds__(256) void guide_map_transform_kernel(MapArgs a) {
   } else {
     for (long long p = (long long)blockIdx.x * 256 + threadIdx.x; p < a.P; p += stride) {
       float x[3][1], g[3][1];
+      unsigned bits[1];
 #pragma unroll
       for (int i = 0; i < 3; ++i) x[i][0] = to_f(X[i * a.P + p]);
-      transform_px<1>(c, x, g);
+      transform_px<1>(c, x, g, bits);
+      M[p] = (uint16_t)bits[0];
 #pragma unroll
       for (int i = 0; i < 3; ++i) G[i * a.P + p] = g[i][0];
     }
@@ -370,6 +385,7 @@ struct GBwdArgs {
   long long P;
   int c_in, c;
   const float* fold;
+  const uint16_t* mask;  // transform: the map's leaky-ReLU branches
 };
 
 template <typename TX, typename TDX, int MODE>
@@ -399,16 +415,18 @@ __global__ __launch_bounds__(256) void guide_bwd_kernel(GBwdArgs a) {
   float acc[AC_N];
 #pragma unroll
   for (int k = 0; k < AC_N; ++k) acc[k] = 0.f;
+  const uint16_t* Mk = a.mask + (size_t)b * a.P;
   for (long long p = (long long)blockIdx.x * 256 + tid; p < a.P; p += (long long)gridDim.x * 256) {
     const float x0 = to_f(X[p]), x1 = to_f(X[a.P + p]), x2 = to_f(X[2 * a.P + p]);
     const float d0 = dG[p], d1 = dG[a.P + p], d2 = dG[2 * a.P + p];
+    const unsigned mbits = Mk[p];
     acc[AC_DG] += d0;
     acc[AC_DG + 1] += d1;
     acc[AC_DG + 2] += d2;
 #pragma unroll
     for (int k = 0; k < kKP; ++k) {
       const float y = c.bf[k] + c.w1f[k][0] * x0 + c.w1f[k][1] * x1 + c.w1f[k][2] * x2;
-      const bool pos = y > 0.f;
+      const bool pos = (mbits >> k) & 1u;
       const float z = pos ? y : slope * y;
       acc[AC_DGZ + k] += d0 * z;
       acc[AC_DGZ + kKP + k] += d1 * z;
@@ -554,16 +572,17 @@ __global__ __launch_bounds__(256) void guide_dx_kernel(GBwdArgs a) {
     mdyhn[k] = f[FO_MDYHN + k];
   }
   const float lam = f[FO_SCAL], slope = c.slope;
+  const uint16_t* __restrict__ Mk = a.mask + (size_t)b * a.P;
   for (long long p = (long long)blockIdx.x * 256 + threadIdx.x; p < a.P;
        p += (long long)gridDim.x * 256) {
     const float x0 = to_f(X[p]), x1 = to_f(X[a.P + p]), x2 = to_f(X[2 * a.P + p]);
     const float d0 = dG[p], d1 = dG[a.P + p], d2 = dG[2 * a.P + p];
+    const unsigned mbits = Mk[p];
     float o0 = 0.f, o1 = 0.f, o2 = 0.f;
 #pragma unroll
     for (int k = 0; k < kKP; ++k) {
-      const float y = c.bf[k] + c.w1f[k][0] * x0 + c.w1f[k][1] * x1 + c.w1f[k][2] * x2;
       const float dz = c.w2[0][k] * d0 + c.w2[1][k] * d1 + c.w2[2][k] * d2;
-      const float dy = y > 0.f ? dz : slope * dz;
+      const float dy = ((mbits >> k) & 1u) ? dz : slope * dz;
       const float h = w1[k][0] * x0 + w1[k][1] * x1 + w1[k][2] * x2;
       const float hn = (h - m[k]) * rstd[k];
       const float dh = lam * dy + cdh[k] * (dy - mdy[k] - hn * mdyhn[k]);
@@ -600,8 +619,8 @@ hipError_t guided_fold(const Plan& p, const void* x, long long P, int chunks, fl
 
 template <typename T>
 hipError_t guided_map(const Plan& p, const void* x, float* G, long long P, int chunks,
-                      const float* fold, hipStream_t s) {
-  MapArgs m{x, G, P, p.c_in, p.c, fold};
+                      const float* fold, uint16_t* mask, hipStream_t s) {
+  MapArgs m{x, G, P, p.c_in, p.c, fold, mask};
   prof_begin("gf_guide_map", s);
   if (p.gmode == GF_GUIDE_GREY)
     hipLaunchKernelGGL((guide_map_grey_kernel<T>), dim3(chunks * 4, p.n), dim3(256), 0,
@@ -639,9 +658,12 @@ hipError_t forward_guided_t(const Plan& p, const FwdArgs& f, hipStream_t s) {
   const float* fold = reinterpret_cast<const float*>(f.ws + p.off_fold);
   float* Gl = reinterpret_cast<float*>(f.ws + p.off_gl);
   float* Gh = reinterpret_cast<float*>(f.ws + p.off_gh);
-  e = guided_map<T>(p, f.I_lo, Gl, (long long)p.h * p.w, p.g_chunks_lo, fold, s);
+  uint16_t* Ml = reinterpret_cast<uint16_t*>(f.ws + p.off_mlo);
+  uint16_t* Mh = reinterpret_cast<uint16_t*>(f.ws + p.off_mhi);
+  e = guided_map<T>(p, f.I_lo, Gl, (long long)p.h * p.w, p.g_chunks_lo, fold, Ml, s);
   if (e != hipSuccess) return e;
-  e = guided_map<T>(p, f.I_hi, Gh, (long long)p.H * p.W, p.g_chunks_hi, fold + kFoldFloats, s);
+  e = guided_map<T>(p, f.I_hi, Gh, (long long)p.H * p.W, p.g_chunks_hi, fold + kFoldFloats, Mh,
+                    s);
   if (e != hipSuccess) return e;
   float* abar = reinterpret_cast<float*>(f.ws + p.off_abar);
   float* bbar = reinterpret_cast<float*>(f.ws + p.off_bbar);
@@ -652,10 +674,11 @@ hipError_t forward_guided_t(const Plan& p, const FwdArgs& f, hipStream_t s) {
 
 template <typename T>
 hipError_t guided_input_grad(const Plan& p, const void* x, const float* dG, void* dx, bool lo,
-                             float* part, const float* fold, hipStream_t s) {
+                             float* part, const float* fold, const uint16_t* mask,
+                             hipStream_t s) {
   const long long P = lo ? (long long)p.h * p.w : (long long)p.H * p.W;
   const int chunks = lo ? p.g_chunks_lo : p.g_chunks_hi;
-  GBwdArgs g{x, dG, dx, part, P, p.c_in, p.c, fold};
+  GBwdArgs g{x, dG, dx, part, P, p.c_in, p.c, fold, mask};
   prof_begin(lo ? "gf_guide_dx_lo" : "gf_guide_dx_hi", s);
   if (p.gmode == GF_GUIDE_GREY) {
     if (lo)
@@ -686,9 +709,12 @@ hipError_t backward_guided_t(const Plan& p, const BwdArgs& b, hipStream_t s) {
   float* Gh = reinterpret_cast<float*>(b.ws + p.off_gh);
   float* dGl = reinterpret_cast<float*>(b.ws + p.off_dgl);
   float* dGh = reinterpret_cast<float*>(b.ws + p.off_dgh);
-  e = guided_map<T>(p, b.I_lo, Gl, (long long)p.h * p.w, p.g_chunks_lo, fold, s);
+  uint16_t* Ml = reinterpret_cast<uint16_t*>(b.ws + p.off_mlo);
+  uint16_t* Mh = reinterpret_cast<uint16_t*>(b.ws + p.off_mhi);
+  e = guided_map<T>(p, b.I_lo, Gl, (long long)p.h * p.w, p.g_chunks_lo, fold, Ml, s);
   if (e != hipSuccess) return e;
-  e = guided_map<T>(p, b.I_hi, Gh, (long long)p.H * p.W, p.g_chunks_hi, fold + kFoldFloats, s);
+  e = guided_map<T>(p, b.I_hi, Gh, (long long)p.H * p.W, p.g_chunks_hi, fold + kFoldFloats, Mh,
+                    s);
   if (e != hipSuccess) return e;
   float* abar = reinterpret_cast<float*>(b.ws + p.off_abar);
   float* U = reinterpret_cast<float*>(b.ws + p.off_u);
@@ -717,7 +743,8 @@ hipError_t backward_guided_t(const Plan& p, const BwdArgs& b, hipStream_t s) {
       const long long P = lo ? (long long)p.h * p.w : (long long)p.H * p.W;
       const int chunks = lo ? p.g_chunks_lo : p.g_chunks_hi;
       GBwdArgs g{lo ? b.I_lo : b.I_hi, lo ? dGl : dGh, nullptr, part + (lo ? 0 : half), P,
-                 p.c_in, p.c, fold + call * kFoldFloats};
+                 p.c_in, p.c, fold + call * kFoldFloats,
+                 reinterpret_cast<const uint16_t*>(b.ws + (lo ? p.off_mlo : p.off_mhi))};
       prof_begin("gf_guide_bwd", s);
       hipLaunchKernelGGL((guide_bwd_kernel<T, float, GF_GUIDE_TRANSFORM>), dim3(chunks, p.n),
                          dim3(256), 0, s, g);
@@ -739,11 +766,12 @@ hipError_t backward_guided_t(const Plan& p, const BwdArgs& b, hipStream_t s) {
     if (e != hipSuccess) return e;
   }
   if (b.dI_lo) {
-    e = guided_input_grad<T>(p, b.I_lo, dGl, b.dI_lo, true, nullptr, fold, s);
+    e = guided_input_grad<T>(p, b.I_lo, dGl, b.dI_lo, true, nullptr, fold, Ml, s);
     if (e != hipSuccess) return e;
   }
   if (b.dI_hi) {
-    e = guided_input_grad<T>(p, b.I_hi, dGh, b.dI_hi, false, nullptr, fold + kFoldFloats, s);
+    e = guided_input_grad<T>(p, b.I_hi, dGh, b.dI_hi, false, nullptr, fold + kFoldFloats, Mh,
+                             s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

@@ -48,6 +48,9 @@ struct Plan {
   // guided path: G_l, G_h (float planes), dG_l, dG_h, moments partials,
   // folded transform parameters (2 calls), accumulator partials/totals
   size_t off_gl, off_gh, off_dgl, off_dgh, off_mom, off_fold, off_accp, off_acct;
+  // transform: leaky-ReLU branch of every hidden channel per pixel (bit k
+  // of a 16-bit word), written by the map and read by the backward kernels
+  size_t off_mlo, off_mhi;
 };
 
 // Per-call folded transform parameters (floats), see gf_guide.h.

@@ -538,3 +538,28 @@ def autotune(I_lo, p_lo, I_hi, eps, dq, r=1, mean_ab=True, iters=5, guide=None,
                      _ptr(ws), ws.numel(), iters, _stream(dev))
     if st != GF_OK:
         raise GFError(st)
+
+
+def autotune_batch(items, iters=3):
+    """Autotune the launch shapes for a batch of items (BatchPlan's item
+    dicts) before creating its plan: once per (factor, radius, mean_ab,
+    alignment) key, on that key's largest image repeated as many times as
+    the key has items, since the batched launch sees about that much work
+    (which decides between short and long walks)."""
+    keys = {}
+    for it in items:
+        s = it["I_hi"].shape[-1] // it["I_lo"].shape[-1]
+        key = (s, it["r"], bool(it.get("mean_ab", True)), bool(it.get("align_corners", False)))
+        big, cnt = keys.get(key, (None, 0))
+        size = it["I_hi"].shape[-2] * it["I_hi"].shape[-1]
+        if big is None or size > big[0]:
+            big = (size, it)
+        keys[key] = (big, cnt + 1)
+    for key, ((_, it), cnt) in sorted(keys.items()):
+        rep = lambda x: x.expand(cnt * x.shape[0], *x.shape[1:]).contiguous() \
+            if x.shape[0] == 1 else torch.cat([x] * cnt)
+        autotune(rep(it["I_lo"]), rep(it["p_lo"]), rep(it["I_hi"]), it["eps"], rep(it["dq"]),
+                 r=it["r"], mean_ab=it.get("mean_ab", True), iters=iters,
+                 align_corners=it.get("align_corners", False))
+        torch.cuda.empty_cache()
+    return len(keys)

@@ -8,8 +8,23 @@ Errors as in test_gpu_parity.py; in addition
                every pixel of both calls, judged like deps (b2's gradient,
                for one, is zero up to rounding: the output does not change
                when the same constant is added to G at both resolutions)
+  dI_lo, dI_hi  with the transform guide, pixels where some hidden
+               pre-activation y is within 2e-6 of 0 are left out (checked
+               finite only): there the leaky ReLU's branch is not fixed by a
+               finite-precision evaluation of y (the kernels' folded FP32
+               constants move y by ~1e-7), and the two branches give
+               gradients that differ by O(1) at that pixel; both are valid.
 Bars: 1e-4 for FP32 I/O, 2e-2 for BF16/FP16 I/O.
 """
+
+BRANCH_DELTA = 2e-6
+
+
+def branch_ambiguous(X, guide):
+    """[n, 1, H, W]: pixels whose transform pre-activations include one
+    within BRANCH_DELTA of 0 (from the oracle)."""
+    Y = oracle.guide_preact(X, guide)
+    return (np.abs(Y) < BRANCH_DELTA).any(axis=1, keepdims=True)
 import numpy as np
 import pytest
 import torch
@@ -81,11 +96,16 @@ def run_both(prob, mode, mean_ab=True, backward=True, use_stats=False):
     return out, ref
 
 
-def errors(out, ref, hidden=None):
+def errors(out, ref, hidden=None, amb=None):
+    """amb: optional {"dI_lo": mask, "dI_hi": mask} of branch-ambiguous pixels."""
     err = {"q": float(np.abs(out["q"] - ref["q"]).max())}
     for k in ("dI_lo", "dp_lo", "dI_hi"):
         if k in out:
-            err[k] = float(np.abs(out[k] - ref[k]).max() / max(1.0, np.abs(ref[k]).max()))
+            diff = np.abs(out[k] - ref[k])
+            if amb is not None and k in amb:
+                assert np.isfinite(out[k]).all()
+                diff = np.where(amb[k], 0.0, diff)
+            err[k] = float(diff.max() / max(1.0, np.abs(ref[k]).max()))
     if "deps" in out:
         err["deps"] = float((np.abs(out["deps"] - ref["deps"]) /
                              np.maximum(1.0, ref["deps_abs"])).max())
@@ -96,10 +116,19 @@ def errors(out, ref, hidden=None):
     return err
 
 
+def ambiguous(prob, mode):
+    if mode != "transform":
+        return None
+    amb = {"dI_lo": branch_ambiguous(prob["I_lo"].double().numpy(), prob["guide"]),
+           "dI_hi": branch_ambiguous(prob["I_hi"].double().numpy(), prob["guide"])}
+    print("branch-ambiguous pixels:", {k: int(v.sum()) for k, v in amb.items()}, flush=True)
+    return amb
+
+
 def check(prob, mode, tol=None, **kw):
     out, ref = run_both(prob, mode, **kw)
     hidden = np.asarray(prob["guide"]["w1"]).shape[0] if mode == "transform" else None
-    err = errors(out, ref, hidden)
+    err = errors(out, ref, hidden, ambiguous(prob, mode))
     print("errors:", {k: f"{v:.3e}" for k, v in err.items()}, flush=True)
     tol = TOL[prob["io_dtype"]] if tol is None else tol
     for k, v in err.items():
@@ -250,7 +279,7 @@ def test_guided_align_corners(mode):
     ref = {"q": oracle.forward(*args, prob["r"], prob["eps"], **gkw)}
     ref.update(oracle.backward(*args, prob["r"], prob["eps"], prob["dq"].double().numpy(), **gkw))
     hidden = np.asarray(prob["guide"]["w1"]).shape[0] if mode == "transform" else None
-    err = errors(got, ref, hidden)
+    err = errors(got, ref, hidden, ambiguous(prob, mode))
     print("errors:", {k: f"{v:.3e}" for k, v in err.items()}, flush=True)
     for k, v in err.items():
         assert v <= TOL[prob["io_dtype"]], (k, v, err)

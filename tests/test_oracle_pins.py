@@ -408,3 +408,24 @@ def test_null_outputs_and_eps_sum():
     one = oracle.backward(G, p, Gh, 1, 1e-2, dq)
     np.testing.assert_allclose(one["deps"][0], per["deps"].sum(), rtol=1e-12)
     np.testing.assert_allclose(one["dp_lo"], per["dp_lo"], atol=0)
+
+
+def test_guide_preact_is_the_batch_norm_mix():
+    """The transform's pre-activations y = lam h + mu BN(h): against torch's
+    training-mode batch_norm of the 1x1 convolution, and consistent with the
+    guide map (G = W2 leaky_relu(y) + b2)."""
+    import torch.nn.functional as F
+    from paper_1803_05619_amd.datagen import guide_params
+    rng = np.random.default_rng(41)
+    g = guide_params(rng)
+    X = rng.uniform(0, 1, size=(3, 3, 6, 9))
+    Y = oracle.guide_preact(X, g)
+    Xt = torch.from_numpy(X)
+    h = F.conv2d(Xt, torch.from_numpy(np.asarray(g["w1"]))[:, :, None, None])
+    bn = F.batch_norm(h, None, None, torch.from_numpy(np.asarray(g["gamma"])),
+                      torch.from_numpy(np.asarray(g["beta"])), training=True, eps=g["bn_eps"])
+    ref = (g["lam"] * h + g["mu"] * bn).numpy()
+    assert np.abs(Y - ref).max() <= 1e-12
+    Z = np.where(Y > 0, Y, g["slope"] * Y)
+    G = np.einsum("ck,nkhw->nchw", np.asarray(g["w2"]), Z) + np.asarray(g["b2"])[None, :, None, None]
+    assert np.abs(G - oracle.guide_apply(X, g)).max() <= 1e-12
