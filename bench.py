@@ -18,6 +18,9 @@ gf_backward.  Workloads (--workload):
                near-constant regions, r = 8 (--radius 1 for the r = 1 run),
                eps = 1e-8
 
+  0            the plain forward only, FP32, 1 x 3 x 256 x 256 from 64 x 64
+               (s = 4), r = 1, eps = 1e-2 (latency-bound: reported per call)
+
 Prints ONE JSON line:
   value        high-res Mpixel/s of fwd+bwd (a 3-channel pixel counts once)
   roofline     the dominant kernel: its algorithmic bytes per step / its time
@@ -392,7 +395,54 @@ def workload_3(args, dev):
                 traffic_ok=False, keep=plan)
 
 
-WORKLOADS = {1: workload_1, 2: workload_2, 3: workload_3, 4: workload_4}
+def workload_0(args, dev):
+    """Forward only, 1 x 3 x 256 x 256 from 64 x 64: one gf_forward call per
+    step (a few microseconds: launch-latency bound)."""
+    import torch
+
+    from paper_1803_05619_amd import datagen, gf, plain
+    prob = datagen.make_config(0, with_dq=False)
+    n, c, H, W, h, w, r = (prob[k] for k in ("n", "c", "H", "W", "h", "w", "r"))
+    t = {k: prob[k].to(dev) for k in ("I_lo", "p_lo", "I_hi")}
+    eps = torch.tensor(prob["eps"], dtype=torch.float32, device=dev)
+    q = torch.empty_like(t["I_hi"])
+    desc = gf.make_desc(t["I_lo"], t["I_hi"], r)
+    ws = torch.empty(gf.gf_workspace_size(desc, None, 0), dtype=torch.uint8, device=dev)
+
+    def step():
+        gf.forward(t["I_lo"], t["p_lo"], t["I_hi"], eps, r, out=q, ws=ws)
+
+    kb = identity_bytes(n, c, H, W, h, w, 4)
+
+    def plain_step():
+        with torch.no_grad():
+            plain.guided_filter(t["I_lo"], t["p_lo"], t["I_hi"], r, eps)
+
+    def cpu_sample():
+        import oracle
+        args_np = [prob[k].double().numpy() for k in ("I_lo", "p_lo", "I_hi")]
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            ref = {"q": oracle.forward(*args_np, r, prob["eps"])}
+            reps += 1
+            el = time.perf_counter() - t0
+            if el >= min(args.cpu_seconds, 2.0) or reps >= 200:
+                break
+        torch.cuda.synchronize()
+        return (n * H * W / 1e6 * reps, el,
+                f"the 1-image forward repeated {reps}x ({el:.2f} s)", n * c,
+                oracle_errors({"q": q.double().cpu().numpy()}, ref))
+
+    return dict(step=step, plain_step=plain_step, cpu_sample=cpu_sample, mpx=n * H * W / 1e6,
+                per_step={"gf_coef": kb["coef"], "gf_apply": kb["apply"]},
+                step_bytes=kb["coef"] + kb["apply"], dtype="f32",
+                config={"workload": "guided filtering layer forward only, FP32, 1x3x256x256 <- "
+                                    "64x64 (s=4), r=1, eps=1e-2 (launch-latency bound)",
+                        "n": n, "c": c, "H": H, "W": W, "s": prob["s"], "r": r, "eps": 1e-2},
+                traffic_ok=False)
+
+
+WORKLOADS = {0: workload_0, 1: workload_1, 2: workload_2, 3: workload_3, 4: workload_4}
 
 
 def main():
@@ -457,6 +507,8 @@ def main():
     value = wl["mpx"] * args.steps / sec
     ms_per_step = 1e3 * sec / args.steps
     log(f"fused: {ms_per_step:.4f} ms/step, {value:.1f} Mpx/s")
+    # a step is its own launch sequence; per call in microseconds as well
+    us_per_step = 1e3 * ms_per_step
     # the kernel breakdown: the same steps again with a HIP event pair
     # around every launch (recording events adds host and device time, so
     # this pass is not the one `value` comes from)
@@ -513,6 +565,7 @@ def main():
         "metric": METRIC, "value": round(value, 1), "unit": "Mpixel/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": wl["dtype"],
+        "us_per_step": round(us_per_step, 2),
         "data": DATA, "config": wl["config"], "roofline": roofline,
         "step_algo_GBs": round(step_gbs, 1), "kernels": kernels,
         "profiled_pass_ms_per_step": round(prof_ms_per_step, 4),

@@ -165,7 +165,9 @@ int make_plan(const gf_desc_t* d, const gf_guide_t* g, Plan* p, const char** why
   q.off_abar = 0;
   q.off_bbar = align_up(lo_plane, 256);
   q.ws_fwd = q.off_bbar + align_up(lo_plane, 256);
-  q.off_u = align_up(lo_plane, 256);
+  // the partial planes follow bbar (not aliasing it: the fused forward +
+  // backward pass reads bbar while it writes them)
+  q.off_u = q.off_bbar + align_up(lo_plane, 256);
   const size_t ubytes = (size_t)q.planes * q.nby * q.nbx * q.ublk_floats * sizeof(float);
   q.off_eps = q.off_u + align_up(ubytes, 256);
   q.ws_bwd = q.off_eps + align_up((size_t)q.planes * q.lo_nx * q.lo_ny * sizeof(float), 256);

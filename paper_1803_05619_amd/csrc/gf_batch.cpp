@@ -231,7 +231,8 @@ int create(const gf_item_t* items, int count, gf_plan** out) {
         const Plan& p = geo[k].p;
         return BwdHiArgs{items[k].I_hi, items[k].dq_hi, items[k].dI_hi,
                          ws_rel<float>(geo[k].off_abar), ws_rel<float>(geo[k].off_u), p.h, p.w,
-                         p.H, p.W, p.bh, p.tw, p.nby, p.nbx, 0};
+                         p.H, p.W, p.bh, p.tw, p.nby, p.nbx, 0,
+                         ws_rel<float>(geo[k].off_bbar), items[k].q_hi};
       },
       [](const Geo& g, int& nx, int& ny) {
         nx = g.p.nbx;

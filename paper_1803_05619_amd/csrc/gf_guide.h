@@ -721,10 +721,10 @@ hipError_t backward_guided_t(const Plan& p, const BwdArgs& b, hipStream_t s) {
   float* bbar = b.q ? reinterpret_cast<float*>(b.ws + p.off_bbar) : nullptr;
   e = launch_coef<float, T>(p, Gl, b.p_lo, b.eps, b.eps_count, abar, bbar, s);
   if (e != hipSuccess) return e;
-  if (b.q && (e = launch_apply<float, T>(p, Gh, b.q, abar, bbar, s)) != hipSuccess) return e;
   // dG_h = dq * A_h (the guide gradient at high resolution) and the
-  // transposed-bilinear partial planes
-  e = launch_bwd_hi<float, T, float>(p, Gh, b.dq, dGh, abar, U, s);
+  // transposed-bilinear partial planes (and q, in the same pass, with the
+  // forward)
+  e = launch_bwd_hi<float, T, float, T>(p, Gh, b.dq, dGh, abar, U, s, bbar, b.q);
   if (e != hipSuccess) return e;
   float* epart = reinterpret_cast<float*>(b.ws + p.off_eps);
   e = launch_bwd_lo<float, T>(p, Gl, b.p_lo, b.eps, b.eps_count, U, dGl, b.dp_lo, epart, s);

@@ -138,6 +138,9 @@ struct BwdHiArgs {
   float* U;     // per-block partial planes
   int h, w, H, W, bh, tw, nby, nbx;
   int xcd;  // 1: XCD-aware workgroup order
+  // forward in the same pass (fused kernel only): q = A_h G_h + b_h
+  const float* bbar;
+  void* q;
 };
 
 struct BwdLoArgs {

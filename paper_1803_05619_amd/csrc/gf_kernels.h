@@ -657,7 +657,10 @@ __global__ __launch_bounds__(256) void apply_kernel(ApplyArgs a) {
 // contributions that cross into the neighbouring lanes' columns move with
 // one lane shuffle each; otherwise (VEC = 1 fallback) through LDS.
 // Loads of row block i+1 are issued before block i is computed.
-template <typename TG, typename TD, typename TO, int S, int VEC, bool AC>
+// FWD: the same pass also writes the forward output q = A_h G_h + b_h
+// (type TQ), reading the bbar rows alongside Abar's: one read of G_h and dq
+// for both directions.
+template <typename TG, typename TD, typename TO, typename TQ, int S, int VEC, bool AC, bool FWD>
 __device__ __forceinline__ void bwd_hi_body(const BwdHiArgs& a, const int bx, const int by,
                                             const int plane) {
   constexpr int TWH = 64 * VEC;  // high-res columns per block
@@ -688,6 +691,8 @@ __device__ __forceinline__ void bwd_hi_body(const BwdHiArgs& a, const int bx, co
   const TG* Gp = reinterpret_cast<const TG*>(a.I_hi) + hofs;
   const TD* Dp = reinterpret_cast<const TD*>(a.dq) + hofs;
   TO* Op = a.dI_hi ? reinterpret_cast<TO*>(a.dI_hi) + hofs : nullptr;
+  const float* Bb = FWD ? a.bbar + (size_t)plane * h * w : nullptr;
+  TQ* Qp = FWD ? reinterpret_cast<TQ*>(a.q) + hofs : nullptr;
   const int UW = tw + 2;
   const size_t UP = (size_t)(bh + 2) * UW;
   float* Ub = a.U + (((size_t)plane * a.nby + by) * a.nbx + bx) * 2 * UP;
@@ -800,11 +805,16 @@ __device__ __forceinline__ void bwd_hi_body(const BwdHiArgs& a, const int bx, co
   };
 
   float am[VEC], ac[VEC], ap[VEC];
+  float bm[FWD ? VEC : 1], bc[FWD ? VEC : 1], bp[FWD ? VEC : 1];
   float pA[VEC], cA[VEC], nA[VEC], pB[VEC], cB[VEC], nB[VEC];
 #pragma unroll
   for (int e = 0; e < VEC; ++e) pA[e] = cA[e] = nA[e] = pB[e] = cB[e] = nB[e] = 0.f;
   hrow<VEC>(Ab, i_a - 1, h, w, j0, j1, wx, am);
   hrow<VEC>(Ab, i_a, h, w, j0, j1, wx, ac);
+  if constexpr (FWD) {
+    hrow<VEC>(Bb, i_a - 1, h, w, j0, j1, wx, bm);
+    hrow<VEC>(Bb, i_a, h, w, j0, j1, wx, bc);
+  }
 
   // unconditional loads (lanes past the image edge re-read column 0 and
   // are zeroed), so that no load sits in a divergent branch
@@ -818,12 +828,13 @@ __device__ __forceinline__ void bwd_hi_body(const BwdHiArgs& a, const int bx, co
   auto body = [&](int i, float (&d)[S][VEC], float (&g)[S][VEC], float (&dn)[S][VEC],
                   float (&gn)[S][VEC]) __attribute__((always_inline)) {
     hrow<VEC>(Ab, i + 1, h, w, j0, j1, wx, ap);
+    if constexpr (FWD) hrow<VEC>(Bb, i + 1, h, w, j0, j1, wx, bp);
     if (i + 1 < i_b) load_block(i + 1, dn, gn);
     const bool top = (i == 0), bot = (i == h - 1);
 #pragma unroll
     for (int t2 = 0; t2 < S; ++t2) {
       const int num = 2 * t2 + 1 - S;
-      float o[VEC];
+      float o[VEC], qo[FWD ? VEC : 1];
       // weights of this row on the low-res rows i-1, i, i+1; at the image's
       // first/last row block the source row is clamped and all weight goes
       // to row i (selected as weights, not as branches over accumulators)
@@ -832,7 +843,10 @@ __device__ __forceinline__ void bwd_hi_body(const BwdHiArgs& a, const int bx, co
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
           const float dv = valid ? d[t2][e] : 0.f;
-          o[e] = dv * (rw.m * am[e] + rw.c * ac[e] + rw.p * ap[e]);
+          const float Av = rw.m * am[e] + rw.c * ac[e] + rw.p * ap[e];
+          if constexpr (FWD)
+            qo[e] = Av * g[t2][e] + (rw.m * bm[e] + rw.c * bc[e] + rw.p * bp[e]);
+          o[e] = dv * Av;
           const float vA = dv * g[t2][e], vB = dv;
           pA[e] += rw.m * vA;
           cA[e] += rw.c * vA;
@@ -847,7 +861,9 @@ __device__ __forceinline__ void bwd_hi_body(const BwdHiArgs& a, const int bx, co
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
           const float dv = valid ? d[t2][e] : 0.f;
-          o[e] = dv * (am[e] + wy * (ac[e] - am[e]));
+          const float Av = am[e] + wy * (ac[e] - am[e]);
+          if constexpr (FWD) qo[e] = Av * g[t2][e] + (bm[e] + wy * (bc[e] - bm[e]));
+          o[e] = dv * Av;
           const float vA = dv * g[t2][e], vB = dv;
           pA[e] += wp * vA;
           cA[e] += wc * vA;
@@ -860,7 +876,9 @@ __device__ __forceinline__ void bwd_hi_body(const BwdHiArgs& a, const int bx, co
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
           const float dv = valid ? d[t2][e] : 0.f;
-          o[e] = dv * (ac[e] + wy * (ap[e] - ac[e]));
+          const float Av = ac[e] + wy * (ap[e] - ac[e]);
+          if constexpr (FWD) qo[e] = Av * g[t2][e] + (bc[e] + wy * (bp[e] - bc[e]));
+          o[e] = dv * Av;
           const float vA = dv * g[t2][e], vB = dv;
           cA[e] += wc * vA;
           nA[e] += wn * vA;
@@ -869,6 +887,8 @@ __device__ __forceinline__ void bwd_hi_body(const BwdHiArgs& a, const int bx, co
         }
       }
       if (Op && valid) store_vec_nt<TO, VEC>(Op + (size_t)(S * i + t2) * W, o);
+      if constexpr (FWD)
+        if (valid) store_vec_nt<TQ, VEC>(Qp + (size_t)(S * i + t2) * W, qo);
     }
     flush(pA, pB, i - i_a);  // low-res row i-1 is complete
 #pragma unroll
@@ -881,6 +901,10 @@ __device__ __forceinline__ void bwd_hi_body(const BwdHiArgs& a, const int bx, co
       nB[e] = 0.f;
       am[e] = ac[e];
       ac[e] = ap[e];
+      if constexpr (FWD) {
+        bm[e] = bc[e];
+        bc[e] = bp[e];
+      }
     }
   };
   float da[S][VEC], ga[S][VEC], db[S][VEC], gb[S][VEC];
@@ -893,13 +917,13 @@ __device__ __forceinline__ void bwd_hi_body(const BwdHiArgs& a, const int bx, co
   flush(cA, cB, i_b - i_a + 1);  // row i_b (contributions of the last rows)
 }
 
-template <typename TG, typename TD, typename TO, int S, int VEC, bool AC>
+template <typename TG, typename TD, typename TO, typename TQ, int S, int VEC, bool AC, bool FWD>
 __global__ __launch_bounds__(64) void bwd_hi_kernel(BwdHiArgs a) {
   const long long nwg = (long long)gridDim.x * gridDim.y * gridDim.z;
   const long long lin = xcd_order(
       blockIdx.x + (long long)gridDim.x * (blockIdx.y + (long long)gridDim.y * blockIdx.z), nwg,
       a.xcd);
-  bwd_hi_body<TG, TD, TO, S, VEC, AC>(a, (int)(lin % gridDim.x),
+  bwd_hi_body<TG, TD, TO, TQ, S, VEC, AC, FWD>(a, (int)(lin % gridDim.x),
                                       (int)((lin / gridDim.x) % gridDim.y),
                                   (int)(lin / ((long long)gridDim.x * gridDim.y)));
 }
@@ -1278,7 +1302,7 @@ __global__ __launch_bounds__(256) void apply_multi_kernel(MultiLaunch m) {
   }
 }
 
-template <typename TG, typename TD, typename TO, int S, int VEC, bool AC>
+template <typename TG, typename TD, typename TO, typename TQ, int S, int VEC, bool AC, bool FWD>
 __global__ __launch_bounds__(64) void bwd_hi_multi_kernel(MultiLaunch m) {
   for (long long t = blockIdx.x; t < m.total; t += gridDim.x) {
     long long l;
@@ -1286,8 +1310,9 @@ __global__ __launch_bounds__(64) void bwd_hi_multi_kernel(MultiLaunch m) {
     BwdHiArgs a = it.a;
     a.abar = rebase(m.ws, a.abar);
     a.U = rebase(m.ws, a.U);
+    a.bbar = rebase(m.ws, a.bbar);
     const long long xy = (long long)it.nx * it.ny;
-    bwd_hi_body<TG, TD, TO, S, VEC, AC>(a, (int)(l % it.nx), (int)((l / it.nx) % it.ny),
+    bwd_hi_body<TG, TD, TO, TQ, S, VEC, AC, FWD>(a, (int)(l % it.nx), (int)((l / it.nx) % it.ny),
                                     (int)(l / xy));
   }
 }
@@ -1365,13 +1390,15 @@ hipError_t launch_apply_t(const Plan& p, const void* G_hi, void* q, const float*
   return hipGetLastError();
 }
 
-template <typename TG, typename TD, typename TO, int S, int VEC, bool AC>
+template <typename TG, typename TD, typename TO, typename TQ, int S, int VEC, bool AC, bool FWD>
 hipError_t launch_bwd_hi_t(const Plan& p, const void* G_hi, const void* dq, void* out,
-                           const float* abar, float* U, hipStream_t s) {
-  BwdHiArgs a{G_hi, dq, out, abar, U, p.h, p.w, p.H, p.W, p.bh, p.tw, p.nby, p.nbx, p.xcd};
-  prof_begin("gf_bwd_hi", s);
-  hipLaunchKernelGGL((bwd_hi_kernel<TG, TD, TO, S, VEC, AC>), dim3(p.nbx, p.nby, p.planes),
-                     dim3(64), 0, s, a);
+                           const float* abar, float* U, const float* bbar, void* q,
+                           hipStream_t s) {
+  BwdHiArgs a{G_hi, dq, out, abar, U, p.h, p.w, p.H, p.W, p.bh, p.tw, p.nby, p.nbx, p.xcd,
+              bbar, q};
+  prof_begin(FWD ? "gf_fwd_bwd_hi" : "gf_bwd_hi", s);
+  hipLaunchKernelGGL((bwd_hi_kernel<TG, TD, TO, TQ, S, VEC, AC, FWD>),
+                     dim3(p.nbx, p.nby, p.planes), dim3(64), 0, s, a);
   prof_end(s);
   return hipGetLastError();
 }
@@ -1414,12 +1441,20 @@ hipError_t launch_apply(const Plan& p, const void* G_hi, void* q, const float* a
   });
 }
 
-template <typename TG, typename TD, typename TO>
+// With q set, the fused pass: forward output and backward in one read of
+// G_h and dq (bbar needed then).
+template <typename TG, typename TD, typename TO, typename TQ = TD>
 hipError_t launch_bwd_hi(const Plan& p, const void* G_hi, const void* dq, void* out,
-                         const float* abar, float* U, hipStream_t s) {
+                         const float* abar, float* U, hipStream_t s,
+                         const float* bbar = nullptr, void* q = nullptr) {
   return with_hires_shape(p.S, p.VEC, p.ac, [&](auto sc, auto vc, auto acc) {
-    return launch_bwd_hi_t<TG, TD, TO, decltype(sc)::value, decltype(vc)::value,
-                           decltype(acc)::value>(p, G_hi, dq, out, abar, U, s);
+    constexpr int SS = decltype(sc)::value, VV = decltype(vc)::value;
+    constexpr bool AA = decltype(acc)::value;
+    if (q)
+      return launch_bwd_hi_t<TG, TD, TO, TQ, SS, VV, AA, true>(p, G_hi, dq, out, abar, U, bbar,
+                                                               q, s);
+    return launch_bwd_hi_t<TG, TD, TO, TQ, SS, VV, AA, false>(p, G_hi, dq, out, abar, U,
+                                                              nullptr, nullptr, s);
   });
 }
 
@@ -1461,8 +1496,8 @@ hipError_t forward_t(const Plan& p, const FwdArgs& f, hipStream_t s) {
   return launch_apply<T, T>(p, f.I_hi, f.q, abar, bbar, s);
 }
 
-// With b.q set, the forward runs first on the same coefficients (bbar is
-// consumed by the apply kernel before the partial planes reuse its space).
+// With b.q set, the forward runs in the same passes: the coefficient kernel
+// writes bbar too and the high-res pass also writes q.
 template <typename T>
 hipError_t backward_t(const Plan& p, const BwdArgs& b, hipStream_t s) {
   float* abar = reinterpret_cast<float*>(b.ws + p.off_abar);
@@ -1470,8 +1505,8 @@ hipError_t backward_t(const Plan& p, const BwdArgs& b, hipStream_t s) {
   float* U = reinterpret_cast<float*>(b.ws + p.off_u);
   hipError_t err = launch_coef<T, T>(p, b.I_lo, b.p_lo, b.eps, b.eps_count, abar, bbar, s);
   if (err != hipSuccess) return err;
-  if (b.q && (err = launch_apply<T, T>(p, b.I_hi, b.q, abar, bbar, s)) != hipSuccess) return err;
-  err = launch_bwd_hi<T, T, T>(p, b.I_hi, b.dq, b.dI_hi, abar, U, s);
+  // with the forward: one high-res pass writes q, dI_h and the partial planes
+  err = launch_bwd_hi<T, T, T, T>(p, b.I_hi, b.dq, b.dI_hi, abar, U, s, bbar, b.q);
   if (err != hipSuccess) return err;
   if (!b.dI_lo && !b.dp_lo && !b.deps) return hipSuccess;
   float* part = reinterpret_cast<float*>(b.ws + p.off_eps);
@@ -1555,14 +1590,19 @@ hipError_t launch_apply_multi(const BatchClass& c, char* ws, hipStream_t s) {
 }
 
 template <typename TG, typename TD, typename TO>
-hipError_t launch_bwd_hi_multi(const BatchClass& c, char* ws, hipStream_t s) {
+hipError_t launch_bwd_hi_multi(const BatchClass& c, char* ws, hipStream_t s, bool fwd) {
   MultiLaunch m = c.m;
   m.ws = ws;
   prof_begin(class_name_s(kClassBwdHi, c.S), s);
   const hipError_t e = with_hires_shape(c.S, c.VEC, c.AC, [&](auto sc, auto vc, auto acc) {
-    hipLaunchKernelGGL((bwd_hi_multi_kernel<TG, TD, TO, decltype(sc)::value, decltype(vc)::value,
-                                            decltype(acc)::value>),
-                       dim3(m.grid), dim3(64), 0, s, m);
+    constexpr int SS = decltype(sc)::value, VV = decltype(vc)::value;
+    constexpr bool AA = decltype(acc)::value;
+    if (fwd)
+      hipLaunchKernelGGL((bwd_hi_multi_kernel<TG, TD, TO, TD, SS, VV, AA, true>), dim3(m.grid),
+                         dim3(64), 0, s, m);
+    else
+      hipLaunchKernelGGL((bwd_hi_multi_kernel<TG, TD, TO, TD, SS, VV, AA, false>), dim3(m.grid),
+                         dim3(64), 0, s, m);
     return hipGetLastError();
   });
   prof_end(s);
@@ -1576,12 +1616,14 @@ hipError_t batched_t(const BatchLaunch& b, int mode, char* ws, hipStream_t s) {
   hipError_t e = hipSuccess;
   for (const BatchClass& c : b.coef)
     if ((e = launch_coef_multi<T, T>(c, ws, s)) != hipSuccess) return e;
-  if (mode & GF_RUN_FORWARD)
+  // forward and backward: one high-res pass writes q, dI_h and the partials
+  const bool fused = (mode & GF_RUN_FORWARD) && (mode & GF_RUN_BACKWARD);
+  if ((mode & GF_RUN_FORWARD) && !fused)
     for (const BatchClass& c : b.apply)
       if ((e = launch_apply_multi<T, T>(c, ws, s)) != hipSuccess) return e;
   if (mode & GF_RUN_BACKWARD) {
     for (const BatchClass& c : b.bwd_hi)
-      if ((e = launch_bwd_hi_multi<T, T, T>(c, ws, s)) != hipSuccess) return e;
+      if ((e = launch_bwd_hi_multi<T, T, T>(c, ws, s, fused)) != hipSuccess) return e;
     for (const BatchClass& c : b.bwd_lo)
       if ((e = launch_bwd_lo_multi<T, T>(c, ws, s)) != hipSuccess) return e;
     if (b.eps_count > 0) {
