@@ -150,9 +150,11 @@ def identity_workload(args, dev, prob, dt, name):
         gf.backward(t["I_lo"], t["p_lo"], t["I_hi"], eps, t["dq"], r, ws=ws, outs=outs)
 
     kb = identity_bytes(n, c, H, W, h, w, BYTES[dt])
-    per_step = {"gf_apply": kb["apply"], "gf_bwd_hi": kb["bwd_hi"], "gf_coef": kb["coef"],
-                "gf_bwd_lo": kb["bwd_lo"], "gf_eps_reduce": 0}
-    step_bytes = kb["apply"] + kb["coef"] + kb["bwd_hi"] + kb["bwd_lo"]
+    # one gf_forward_backward call: the coefficient pass, one fused high-res
+    # pass (I_h, dq in; q, dI_h out), the low-res backward, the eps sum
+    per_step = {"gf_fwd_bwd_hi": kb["apply"] + kb["bwd_hi"] - BYTES[dt] * n * c * H * W,
+                "gf_coef": kb["coef"], "gf_bwd_lo": kb["bwd_lo"], "gf_eps_reduce": 0}
+    step_bytes = per_step["gf_fwd_bwd_hi"] + kb["coef"] + kb["bwd_lo"]
 
     I_lo = t["I_lo"].clone().requires_grad_(True)
     p_lo = t["p_lo"].clone().requires_grad_(True)
@@ -238,8 +240,7 @@ def workload_2(args, dev):
         "gf_guide_moments": 3 * b * (hpx + lpx),
         "gf_guide_map": (3 * b + 12) * (hpx + lpx),
         "gf_coef": (4 + b) * lo,
-        "gf_apply": (4 + b) * hi,
-        "gf_bwd_hi": (4 + b + 4) * hi,
+        "gf_fwd_bwd_hi": (4 + b + b + 4) * hi,     # G_h, dq in; q, dG_h out
         "gf_bwd_lo": (4 + b + 4 + 4) * lo,
         "gf_guide_bwd": (3 * b + 12) * (hpx + lpx),
     }
@@ -343,14 +344,15 @@ def workload_3(args, dev):
     mpx = 0.0
     for p in probs:
         kb = identity_bytes(1, 3, p["H"], p["W"], p["h"], p["w"], 4)
-        for name, key in ((f"gf_coef_multi_r{p['r']}", "coef"),
-                          (f"gf_apply_multi_s{p['s']}", "apply"),
-                          (f"gf_bwd_hi_multi_s{p['s']}", "bwd_hi"),
-                          (f"gf_bwd_lo_multi_r{p['r']}", "bwd_lo")):
-            per_step[name] = per_step.get(name, 0) + kb[key]
-        step_bytes += kb["apply"] + kb["coef"] + kb["bwd_hi"] + kb["bwd_lo"] - kb["coef"]
+        # forward+backward plan: the high-res pass is fused (I_h, dq in; q,
+        # dI_h out)
+        fused_hi = kb["apply"] + kb["bwd_hi"] - 4 * 3 * p["H"] * p["W"]
+        for name, nbytes in ((f"gf_coef_multi_r{p['r']}", kb["coef"]),
+                             (f"gf_bwd_hi_multi_s{p['s']}", fused_hi),
+                             (f"gf_bwd_lo_multi_r{p['r']}", kb["bwd_lo"])):
+            per_step[name] = per_step.get(name, 0) + nbytes
+        step_bytes += fused_hi + kb["coef"] + kb["bwd_lo"]
         mpx += p["H"] * p["W"] / 1e6
-    step_bytes += sum(2 * 4 * 3 * p["h"] * p["w"] for p in probs)  # the one coef pass
 
     leaves = [{k: it[k].clone().requires_grad_(True) for k in ("I_lo", "p_lo", "I_hi")}
               for it in items]
