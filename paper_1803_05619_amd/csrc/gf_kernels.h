@@ -818,21 +818,35 @@ __device__ __forceinline__ void bwd_hi_body(const BwdHiArgs& a, const int bx, co
 
   // unconditional loads (lanes past the image edge re-read column 0 and
   // are zeroed), so that no load sits in a divergent branch
-  auto load_block = [&](int i, float (&d)[S][VEC], float (&g)[S][VEC]) __attribute__((always_inline)) {
+  // Rows are loaded in units of SR rows (a low-res row block at S <= 4,
+  // half of one at S = 8: the two register buffers then hold 2 x 4 rows of
+  // G and dq, not 2 x 8) while the previous unit is computed.
+  constexpr int SR = S >= 8 ? S / 2 : S;
+  constexpr int NH = S / SR;
+  auto load_unit = [&](int i, int u, float (&d)[SR][VEC], float (&g)[SR][VEC])
+                       __attribute__((always_inline)) {
 #pragma unroll
-    for (int t2 = 0; t2 < S; ++t2) {
-      load_vec<TD, VEC>(Dp + (size_t)(S * i + t2) * W, d[t2]);
-      load_vec<TG, VEC>(Gp + (size_t)(S * i + t2) * W, g[t2]);
+    for (int t = 0; t < SR; ++t) {
+      load_vec<TD, VEC>(Dp + (size_t)(S * i + SR * u + t) * W, d[t]);
+      load_vec<TG, VEC>(Gp + (size_t)(S * i + SR * u + t) * W, g[t]);
     }
   };
-  auto body = [&](int i, float (&d)[S][VEC], float (&g)[S][VEC], float (&dn)[S][VEC],
-                  float (&gn)[S][VEC]) __attribute__((always_inline)) {
-    hrow<VEC>(Ab, i + 1, h, w, j0, j1, wx, ap);
-    if constexpr (FWD) hrow<VEC>(Bb, i + 1, h, w, j0, j1, wx, bp);
-    if (i + 1 < i_b) load_block(i + 1, dn, gn);
+  // unit U of low-res row block i
+  auto part = [&](auto uc, int i, float (&d)[SR][VEC], float (&g)[SR][VEC],
+                  float (&dn)[SR][VEC], float (&gn)[SR][VEC]) __attribute__((always_inline)) {
+    constexpr int U = decltype(uc)::value;
+    if constexpr (U == 0) {
+      hrow<VEC>(Ab, i + 1, h, w, j0, j1, wx, ap);
+      if constexpr (FWD) hrow<VEC>(Bb, i + 1, h, w, j0, j1, wx, bp);
+    }
+    if constexpr (U + 1 < NH)
+      load_unit(i, U + 1, dn, gn);
+    else if (i + 1 < i_b)
+      load_unit(i + 1, 0, dn, gn);
     const bool top = (i == 0), bot = (i == h - 1);
 #pragma unroll
-    for (int t2 = 0; t2 < S; ++t2) {
+    for (int t = 0; t < SR; ++t) {
+      const int t2 = SR * U + t;  // row within the block
       const int num = 2 * t2 + 1 - S;
       float o[VEC], qo[FWD ? VEC : 1];
       // weights of this row on the low-res rows i-1, i, i+1; at the image's
@@ -842,12 +856,12 @@ __device__ __forceinline__ void bwd_hi_body(const BwdHiArgs& a, const int bx, co
         const RowW rw = row_weights_ac(S * i + t2, i, h, a.H);
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
-          const float dv = valid ? d[t2][e] : 0.f;
+          const float dv = valid ? d[t][e] : 0.f;
           const float Av = rw.m * am[e] + rw.c * ac[e] + rw.p * ap[e];
           if constexpr (FWD)
-            qo[e] = Av * g[t2][e] + (rw.m * bm[e] + rw.c * bc[e] + rw.p * bp[e]);
+            qo[e] = Av * g[t][e] + (rw.m * bm[e] + rw.c * bc[e] + rw.p * bp[e]);
           o[e] = dv * Av;
-          const float vA = dv * g[t2][e], vB = dv;
+          const float vA = dv * g[t][e], vB = dv;
           pA[e] += rw.m * vA;
           cA[e] += rw.c * vA;
           nA[e] += rw.p * vA;
@@ -860,11 +874,11 @@ __device__ __forceinline__ void bwd_hi_body(const BwdHiArgs& a, const int bx, co
         const float wp = top ? 0.f : 1.f - wy, wc = top ? 1.f : wy;
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
-          const float dv = valid ? d[t2][e] : 0.f;
+          const float dv = valid ? d[t][e] : 0.f;
           const float Av = am[e] + wy * (ac[e] - am[e]);
-          if constexpr (FWD) qo[e] = Av * g[t2][e] + (bm[e] + wy * (bc[e] - bm[e]));
+          if constexpr (FWD) qo[e] = Av * g[t][e] + (bm[e] + wy * (bc[e] - bm[e]));
           o[e] = dv * Av;
-          const float vA = dv * g[t2][e], vB = dv;
+          const float vA = dv * g[t][e], vB = dv;
           pA[e] += wp * vA;
           cA[e] += wc * vA;
           pB[e] += wp * vB;
@@ -875,11 +889,11 @@ __device__ __forceinline__ void bwd_hi_body(const BwdHiArgs& a, const int bx, co
         const float wc = bot ? 1.f : 1.f - wy, wn = bot ? 0.f : wy;
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
-          const float dv = valid ? d[t2][e] : 0.f;
+          const float dv = valid ? d[t][e] : 0.f;
           const float Av = ac[e] + wy * (ap[e] - ac[e]);
-          if constexpr (FWD) qo[e] = Av * g[t2][e] + (bc[e] + wy * (bp[e] - bc[e]));
+          if constexpr (FWD) qo[e] = Av * g[t][e] + (bc[e] + wy * (bp[e] - bc[e]));
           o[e] = dv * Av;
-          const float vA = dv * g[t2][e], vB = dv;
+          const float vA = dv * g[t][e], vB = dv;
           cA[e] += wc * vA;
           nA[e] += wn * vA;
           cB[e] += wc * vB;
@@ -890,6 +904,7 @@ __device__ __forceinline__ void bwd_hi_body(const BwdHiArgs& a, const int bx, co
       if constexpr (FWD)
         if (valid) store_vec_nt<TQ, VEC>(Qp + (size_t)(S * i + t2) * W, qo);
     }
+    if constexpr (U + 1 < NH) return;
     flush(pA, pB, i - i_a);  // low-res row i-1 is complete
 #pragma unroll
     for (int e = 0; e < VEC; ++e) {
@@ -907,11 +922,18 @@ __device__ __forceinline__ void bwd_hi_body(const BwdHiArgs& a, const int bx, co
       }
     }
   };
-  float da[S][VEC], ga[S][VEC], db[S][VEC], gb[S][VEC];
-  load_block(i_a, da, ga);
-  for (int i = i_a; i < i_b; i += 2) {
-    body(i, da, ga, db, gb);
-    if (i + 1 < i_b) body(i + 1, db, gb, da, ga);
+  float da[SR][VEC], ga[SR][VEC], db[SR][VEC], gb[SR][VEC];
+  load_unit(i_a, 0, da, ga);
+  if constexpr (NH == 1) {
+    for (int i = i_a; i < i_b; i += 2) {
+      part(std::integral_constant<int, 0>{}, i, da, ga, db, gb);
+      if (i + 1 < i_b) part(std::integral_constant<int, 0>{}, i + 1, db, gb, da, ga);
+    }
+  } else {
+    for (int i = i_a; i < i_b; ++i) {
+      part(std::integral_constant<int, 0>{}, i, da, ga, db, gb);
+      part(std::integral_constant<int, 1>{}, i, db, gb, da, ga);
+    }
   }
   flush(pA, pB, i_b - i_a);      // row i_b - 1
   flush(cA, cB, i_b - i_a + 1);  // row i_b (contributions of the last rows)
