@@ -251,3 +251,35 @@ def test_align_corners_scalar_width():
     """A width that is not a multiple of 4 (one column per lane)."""
     prob = datagen.make_problem(1, 3, 2 * 30, 2 * 37, 2, 1, 1e-3, "f32", config=171, noise=0.02)
     check(prob, align_corners=True)
+
+
+# ------------------------------------------------------------ degenerate cases
+
+def _const_guide(prob, value=0.375):
+    """The same problem with a constant guide (exactly representable)."""
+    out = dict(prob)
+    out["I_lo"] = torch.full_like(prob["I_lo"], value)
+    out["I_hi"] = torch.full_like(prob["I_hi"], value)
+    return out
+
+
+@pytest.mark.parametrize("eps", [0.0, 1e-3])
+def test_constant_guide(eps):
+    """var = 0 in every window: with eps = 0 the rule A := 0 applies (q is
+    the upsampled window mean of p); with eps > 0 A = 0 / eps = 0."""
+    prob = _const_guide(datagen.make_problem(2, 3, 4 * 20, 4 * 28, 4, 1, eps, "f32", config=180))
+    check(prob)
+
+
+def test_zero_eps_textured_guide():
+    """eps = 0 with a textured guide (noise keeps every window's variance
+    positive)."""
+    prob = datagen.make_problem(1, 3, 4 * 24, 4 * 24, 4, 1, 0.0, "f32", config=181, noise=0.05)
+    check(prob)
+
+
+@pytest.mark.parametrize("h, w, s", [(1, 1, 4), (1, 17, 2), (13, 1, 8), (2, 3, 1)])
+def test_degenerate_shapes(h, w, s):
+    """One-pixel, one-row and one-column low-res images."""
+    prob = datagen.make_problem(2, 3, s * h, s * w, s, 1, 1e-2, "f32", config=182, noise=0.02)
+    check(prob)
