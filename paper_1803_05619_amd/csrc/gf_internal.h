@@ -1,5 +1,7 @@
 // Internal interface between the C-ABI layer (gf_api.cpp) and the HIP
-// kernels (gf_kernels.hip).  Not part of the public ABI.
+// kernels (gf_kernels.h, gf_guide.h, instantiated per I/O type in
+// gf_f32.hip, gf_f16.hip, gf_bf16.hip) and the batched planner
+// (gf_batch.cpp).  Not part of the public ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>

@@ -655,8 +655,9 @@ __global__ __launch_bounds__(256) void apply_kernel(ApplyArgs a) {
 // Horizontal: when the lane's VEC columns are whole low-res blocks
 // (VEC % S == 0) the weights are compile-time constants and the two
 // contributions that cross into the neighbouring lanes' columns move with
-// one lane shuffle each; otherwise (VEC = 1 fallback) through LDS.
-// Loads of row block i+1 are issued before block i is computed.
+// one lane shuffle each; otherwise (S = 8 with 4 columns per lane, the
+// VEC = 1 fallback, corner alignment) through an LDS row.
+// Loads of the next rows are issued before the current ones are computed.
 // FWD: the same pass also writes the forward output q = A_h G_h + b_h
 // (type TQ), reading the bbar rows alongside Abar's: one read of G_h and dq
 // for both directions.
