@@ -160,6 +160,11 @@ int make_plan(const gf_desc_t* d, const gf_guide_t* g, Plan* p, const char** why
   q.nby = (q.h + q.bh - 1) / q.bh;
   q.nbx = (q.W + 64 * q.VEC - 1) / (64 * q.VEC);
   q.ublk_floats = (size_t)2 * (q.bh + 2) * (q.tw + 2);
+  // the low-res walkers address a plane, and its partial planes, with
+  // 32-bit byte offsets
+  if ((double)q.h * q.w * 4.0 > 2147483647.0 ||
+      (double)q.nby * q.nbx * q.ublk_floats * 4.0 > 2147483647.0)
+    return bad(GF_ERR_UNSUPPORTED, "low-res plane too large");
 
   const size_t lo_plane = (size_t)q.planes * q.h * q.w * sizeof(float);
   q.off_abar = 0;

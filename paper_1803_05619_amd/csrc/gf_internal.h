@@ -81,12 +81,16 @@ constexpr int kBwdLoRingPow2Max = 16;  // bwd_lo: 64 * (32 KR + 40 * 4) bytes
 // backward walker 2 x 4.
 constexpr bool coef_reg_window(int R) { return 4 * (2 * R + kWalkBlock) <= 64; }
 constexpr bool bwd_lo_reg_window(int R) { return 8 * (2 * R + kWalkBlock) <= 96; }
+// Radii whose horizontal windows are formed by whole-wave DPP lane shifts
+// (R shifts each way) rather than through LDS row buffers: with vertical
+// windows in registers as well, such walkers use no LDS at all.
+constexpr bool lane_dpp(int R) { return R <= 2; }
 constexpr size_t coef_lds_bytes(int R) {
-  return 64 * (24 * kWalkBlock +
+  return 64 * ((lane_dpp(R) ? 0 : 24 * kWalkBlock) +
                (coef_reg_window(R) ? 0 : 16 * walker_ring_rows(R, kWalkBlock, kCoefRingPow2Max)));
 }
 constexpr size_t bwd_lo_lds_bytes(int R) {
-  return 64 * (40 * kWalkBlock +
+  return 64 * ((lane_dpp(R) ? 0 : 40 * kWalkBlock) +
                (bwd_lo_reg_window(R) ? 0
                                      : 32 * walker_ring_rows(R, kWalkBlock, kBwdLoRingPow2Max)));
 }

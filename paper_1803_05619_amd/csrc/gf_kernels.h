@@ -124,6 +124,58 @@ __device__ __forceinline__ void wave_sync() {
 // kernels use it for window counts and variance denominators.
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// Whole-wave lane shifts by DPP (wave_shl:1, wave_shr:1); bound_ctrl makes
+// the lane shifted in from beyond the wave read 0.  The walkers call them
+// with every lane of the wave active (outside divergent branches).
+__device__ __forceinline__ float lane_next(float v) {  // the value of lane + 1
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float lane_prev(float v) {  // the value of lane - 1
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x138, 0xF, 0xF, true));
+}
+// The values of lanes lane - R .. lane + R (index k holds lane + k - R).
+template <int R>
+__device__ __forceinline__ void lane_window(float v, float (&o)[2 * R + 1]) {
+  o[R] = v;
+#pragma unroll
+  for (int m = 1; m <= R; ++m) {
+    o[R + m] = lane_next(o[R + m - 1]);
+    o[R - m] = lane_prev(o[R - m + 1]);
+  }
+}
+template <int R>
+__device__ __forceinline__ float lane_sum(float v) {
+  float o[2 * R + 1];
+  lane_window<R>(v, o);
+  float s = o[0];
+#pragma unroll
+  for (int k = 1; k < 2 * R + 1; ++k) s += o[k];
+  return s;
+}
+
+// Raw buffer accesses for the low-res walkers: a resource over one plane
+// (base and byte size in scalar registers), a per-lane byte offset (fixed
+// for a wave: its column) and a wave-uniform byte offset (the row).  The
+// address arithmetic stays scalar, and accesses beyond the resource's size
+// read 0 / are dropped by the hardware.  Word 3 is the gfx9-family default
+// (32-bit data format, untyped).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, size_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0,
+                                           (int)(unsigned)bytes, 0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T buf_ld(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  static_assert(sizeof(T) == 4 || sizeof(T) == 2, "32- or 16-bit elements");
+  if constexpr (sizeof(T) == 4)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+  else
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
+}
+__device__ __forceinline__ void buf_st(float v, __amdgpu_buffer_rsrc_t r, unsigned voff,
+                                       unsigned soff) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, 0);
+}
+
 // XCD-aware workgroup order.  The dispatcher hands consecutive workgroups
 // to the 8 XCDs in turn, each XCD with its own L2; remapping the linear
 // workgroup id so that XCD k runs the contiguous k-th eighth of the work
@@ -285,12 +337,12 @@ struct VWin<V, NW, OFF, KR, false> {
 
 // Column statistics of the K = 2R+1 rows rc-R .. rc+R given in v (rows
 // outside the image hold zeros and are masked out).
-template <int R>
+template <int R, bool IN = false>
 __device__ __forceinline__ float4 column_stats_v(const float2 (&v)[2 * R + 1], int rc, int h) {
   constexpr int K = 2 * R + 1;
   int nrow = 0;
 #pragma unroll
-  for (int k = 0; k < K; ++k) nrow += row_ok(rc - R + k, h) ? 1 : 0;
+  for (int k = 0; k < K; ++k) nrow += (IN || row_ok(rc - R + k, h)) ? 1 : 0;
   float s0 = 0.f, s1 = 0.f;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
@@ -302,7 +354,7 @@ __device__ __forceinline__ float4 column_stats_v(const float2 (&v)[2 * R + 1], i
   float vv = 0.f, vp = 0.f;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const bool ok = row_ok(rc - R + k, h);
+    const bool ok = IN || row_ok(rc - R + k, h);
     const float dg = ok ? v[k].x - cg : 0.f;
     const float dp = ok ? v[k].y - cp : 0.f;
     vv += dg * dg;
@@ -311,23 +363,20 @@ __device__ __forceinline__ float4 column_stats_v(const float2 (&v)[2 * R + 1], i
   return make_float4(cg, cp, vv, vp);
 }
 
-// Window statistics at this lane from the column-statistics row cs (entries
-// of lanes lane-R .. lane+R); cmask[k] = 1 for in-image columns.
+// Window statistics from the column statistics of the window's columns
+// (lanes lane-R .. lane+R): cx, cy their column means, wv, wp the sums of
+// their cvv, cvp; cmask[k] = 1 for in-image columns.
 template <int R>
-__device__ __forceinline__ WinStats window_stats(const float4* cs, int lane,
-                                                 const float (&cmask)[2 * R + 1], float inv_ncol,
-                                                 float invN) {
+__device__ __forceinline__ WinStats window_stats_c(const float (&cx)[2 * R + 1],
+                                                   const float (&cy)[2 * R + 1], float wv,
+                                                   float wp, const float (&cmask)[2 * R + 1],
+                                                   float inv_ncol, float invN) {
   constexpr int K = 2 * R + 1;
-  float4 c[K];
+  float s0 = cx[0], s1 = cy[0];
 #pragma unroll
-  for (int k = 0; k < K; ++k) c[k] = cs[lane + k - R];
-  float s0 = 0.f, s1 = 0.f, wv = 0.f, wp = 0.f;
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    s0 += c[k].x;
-    s1 += c[k].y;
-    wv += c[k].z;
-    wp += c[k].w;
+  for (int k = 1; k < K; ++k) {
+    s0 += cx[k];
+    s1 += cy[k];
   }
   WinStats st;
   st.mI = s0 * inv_ncol;
@@ -335,14 +384,44 @@ __device__ __forceinline__ WinStats window_stats(const float4* cs, int lane,
   float bv = 0.f, bp = 0.f;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const float dg = cmask[k] * (c[k].x - st.mI);
-    const float dp = c[k].y - st.mP;
+    const float dg = cmask[k] * (cx[k] - st.mI);
+    const float dp = cy[k] - st.mP;
     bv += dg * dg;
     bp += dg * dp;
   }
   st.var = wv * invN + bv * inv_ncol;
   st.cov = wp * invN + bp * inv_ncol;
   return st;
+}
+
+// The same from an LDS row of column statistics (entries of lanes
+// lane-R .. lane+R).
+template <int R>
+__device__ __forceinline__ WinStats window_stats(const float4* cs, int lane,
+                                                 const float (&cmask)[2 * R + 1], float inv_ncol,
+                                                 float invN) {
+  constexpr int K = 2 * R + 1;
+  float cx[K], cy[K], wv = 0.f, wp = 0.f;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const float4 c = cs[lane + k - R];
+    cx[k] = c.x;
+    cy[k] = c.y;
+    wv += c.z;
+    wp += c.w;
+  }
+  return window_stats_c<R>(cx, cy, wv, wp, cmask, inv_ncol, invN);
+}
+
+// The same from this lane's own column statistics, the neighbours' by DPP.
+template <int R>
+__device__ __forceinline__ WinStats window_stats_dpp(float4 c, const float (&cmask)[2 * R + 1],
+                                                     float inv_ncol, float invN) {
+  constexpr int K = 2 * R + 1;
+  float cx[K], cy[K];
+  lane_window<R>(c.x, cx);
+  lane_window<R>(c.y, cy);
+  return window_stats_c<R>(cx, cy, lane_sum<R>(c.z), lane_sum<R>(c.w), cmask, inv_ncol, invN);
 }
 
 // ------------------------------------------------------------ forward: low-res
@@ -352,7 +431,10 @@ __device__ __forceinline__ WinStats window_stats(const float4* cs, int lane,
 // Abar, bbar (A, b when MAB is false) of a strip of 64 - 2(R + R_ab) output
 // columns x TR output rows.  The guide and input are recentred by their
 // values at the segment centre (variance and covariance are shift
-// invariant; b is formed from the actual means).
+// invariant; b is formed from the actual means).  Blocks whose rows and
+// windows all lie inside the image and the segment run without row checks.
+// Lanes without a result compute one anyway and select zero, so that each
+// phase is one basic block (the DPP shifts then fold into the adds).
 template <typename TG, typename TP, int R, bool MAB>
 __device__ __forceinline__ void coef_body(const CoefArgs& a, const int bx, const int by,
                                           const int plane) {
@@ -362,11 +444,14 @@ __device__ __forceinline__ void coef_body(const CoefArgs& a, const int bx, const
   constexpr int TWo = 64 - 2 * HAL;
   constexpr int KR = walker_ring_rows(R, kPF, kCoefRingPow2Max);
   constexpr bool REG = coef_reg_window(R);
+  constexpr bool DPP = lane_dpp(R);
   constexpr int NW = 2 * R + kPF;
   extern __shared__ float4 lds4[];
-  float4* cs = lds4;                                       // [kPF][64] column statistics
-  float2* vs = reinterpret_cast<float2*>(cs + kPF * 64);  // [kPF][64] column sums of (A, b)
-  float2* rings = vs + kPF * 64;                           // LDS rings (large R only)
+  // LDS when the horizontal windows do not use DPP: [kPF][64] column
+  // statistics, [kPF][64] column sums of (A, b); then the rings (large R)
+  float4* cs = lds4;
+  float2* vs = reinterpret_cast<float2*>(cs + kPF * 64);
+  float2* rings = DPP ? reinterpret_cast<float2*>(lds4) : vs + kPF * 64;
   // vertical windows: recentred (g, p) rows xb-2R.., (A, b) rows xb-3R..
   VWin<float2, NW, -2 * R, KR, REG> gp;
   VWin<float2, NW, -3 * R, KR, REG> ab;
@@ -381,8 +466,11 @@ __device__ __forceinline__ void coef_body(const CoefArgs& a, const int bx, const
   const size_t pofs = (size_t)plane * h * w;
   const TG* G = reinterpret_cast<const TG*>(a.I_lo) + pofs;
   const TP* P = reinterpret_cast<const TP*>(a.p_lo) + pofs;
-  float* Ab = a.abar + pofs;
-  float* Bb = a.bbar ? a.bbar + pofs : nullptr;
+  const size_t hw = (size_t)h * w;
+  const __amdgpu_buffer_rsrc_t gR = buf_rsrc(G, hw * sizeof(TG));
+  const __amdgpu_buffer_rsrc_t pR = buf_rsrc(P, hw * sizeof(TP));
+  const __amdgpu_buffer_rsrc_t aR = buf_rsrc(a.abar + pofs, hw * 4);
+  const __amdgpu_buffer_rsrc_t bR = buf_rsrc(a.bbar ? a.bbar + pofs : a.abar, a.bbar ? hw * 4 : 0);
   const int ic = min(i0 + a.TR / 2, h - 1), jc = min(max(j0 + TWo / 2, 0), w - 1);
   const float cg = to_f(G[(size_t)ic * w + jc]);
   const float cp = to_f(P[(size_t)ic * w + jc]);
@@ -396,122 +484,162 @@ __device__ __forceinline__ void coef_body(const CoefArgs& a, const int bx, const
   const float inv_ncol = rcp(fmaxf(ncol, 1.f));
   const bool a_lane = colin && lane >= R && lane < 64 - R;  // lanes that form (A, b)
   const bool out_lane = colin && lane >= HAL && lane < HAL + TWo;
+  const unsigned jo = (unsigned)(colin ? j : 0) * 4u;  // output byte offset in a row
   const int x0 = i0 - HAL, xend = i1 + HAL;  // input rows walked
   gp.init(rings, x0, lane, make_float2(0.f, 0.f));
   ab.init(rings + KR * 64, x0, lane, make_float2(0.f, 0.f));
 
-  // Loads are unconditional (clamped address) and the queue holds the raw
+  // Loads are unconditional (clamped row) and the queue holds the raw
   // values: a load inside a divergent branch, or arithmetic right after it,
   // would make the wave wait for it there instead of a block later.
   const int jcl = min(max(j, 0), w - 1);
+  const unsigned jg = (unsigned)jcl * sizeof(TG), jp = (unsigned)jcl * sizeof(TP);
   auto load = [&](int x, TG& g, TP& p) __attribute__((always_inline)) {
-    const size_t o = (size_t)min(max(x, 0), h - 1) * w + jcl;
-    g = G[o];
-    p = P[o];
+    const unsigned o = (unsigned)(min(max(x, 0), h - 1) * w);
+    g = buf_ld<TG>(gR, jg, o * (unsigned)sizeof(TG));
+    p = buf_ld<TP>(pR, jp, o * (unsigned)sizeof(TP));
+  };
+  // 1 / N for the window of row t (interior rows: K rows)
+  auto inv_count = [&](auto tag, int t) __attribute__((always_inline)) {
+    constexpr bool IN = decltype(tag)::value;
+    const int nrow = IN ? K : min(t + R, h - 1) - max(t - R, 0) + 1;
+    return inv_ncol * rcp((float)nrow);
+  };
+  // (A, b) from the window statistics; zero where the lane forms none
+  auto coef_of = [&](const WinStats& st, bool ok) __attribute__((always_inline)) {
+    const float den = st.var + e;
+    const float A = den > 0.f ? st.cov * rcp(den) : 0.f;
+    const float B = (st.mP + cp) - A * (st.mI + cg);
+    return ok ? make_float2(A, B) : make_float2(0.f, 0.f);
+  };
+  auto put_ab = [&](int xb, int d, int rc, float2 v) __attribute__((always_inline)) {
+    if (!MAB) {
+      if (rc >= i0 && rc < i1 && out_lane) {
+        const unsigned ro = (unsigned)(rc * w) * 4u;
+        buf_st(v.x, aR, jo, ro);
+        if (a.bbar) buf_st(v.y, bR, jo, ro);
+      }
+    } else {
+      ab.at(xb, 2 * R + d) = v;  // row rc
+    }
+  };
+  auto put_bar = [&](auto tag, int ra, float sa, float sb) __attribute__((always_inline)) {
+    const float invN = inv_count(tag, ra);
+    if (out_lane) {
+      const unsigned ro = (unsigned)(ra * w) * 4u;
+      buf_st(sa * invN, aR, jo, ro);
+      if (a.bbar) buf_st(sb * invN, bR, jo, ro);
+    }
   };
 
-  auto block = [&](int xb, const TG (&gq)[kPF], const TP (&pq)[kPF]) __attribute__((always_inline)) {
+  auto block = [&](auto tag, int xb, TG (&gq)[kPF], TP (&pq)[kPF]) __attribute__((always_inline)) {
+    constexpr bool IN = decltype(tag)::value;
 #pragma unroll
     for (int d = 0; d < kPF; ++d) {
       const int x = xb + d;
-      const bool ok = colin && row_ok(x, h);
-      if (x < xend)
+      const bool ok = colin && (IN || row_ok(x, h));
+      if (IN || x < xend)
         gp.at(xb, 2 * R + d) =
-            make_float2(ok ? to_f(gq[d]) - cg : 0.f, ok ? to_f(pq[d]) - cp : 0.f);
+            ok ? make_float2(to_f(gq[d]) - cg, to_f(pq[d]) - cp) : make_float2(0.f, 0.f);
     }
+    // the queue's rows are consumed: fetch the next block's
+#pragma unroll
+    for (int d = 0; d < kPF; ++d) load(xb + kPF + d, gq[d], pq[d]);
     // rows rc = x - R whose windows are complete with this block
 #pragma unroll
     for (int d = 0; d < kPF; ++d) {
       const int rc = xb + d - R;
-      if (xb + d < xend && rc - R >= x0 && rc >= i0 - HB && rc < i1 + HB) {
-        float4 st = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (colin && row_ok(rc, h)) {
-          float2 v[K];
+      if (!(IN || (xb + d >= i0 + R - HB && xb + d < xend))) continue;
+      float2 v[K];
 #pragma unroll
-          for (int k = 0; k < K; ++k) v[k] = gp.at(xb, d + k);  // rows rc-R .. rc+R
-          st = column_stats_v<R>(v, rc, h);
-        }
+      for (int k = 0; k < K; ++k) v[k] = gp.at(xb, d + k);  // rows rc-R .. rc+R
+      const bool rok = IN || row_ok(rc, h);
+      float4 st = column_stats_v<R, IN>(v, rc, h);
+      if (!(colin && rok)) st = make_float4(0.f, 0.f, 0.f, 0.f);
+      if constexpr (DPP) {
+        const WinStats ws = window_stats_dpp<R>(st, cmask, inv_ncol, inv_count(tag, rc));
+        put_ab(xb, d, rc, coef_of(ws, a_lane && rok));
+      } else {
         cs[d * 64 + lane] = st;
       }
     }
-    wave_sync();
-#pragma unroll
-    for (int d = 0; d < kPF; ++d) {
-      const int rc = xb + d - R;
-      if (xb + d < xend && rc - R >= x0 && rc >= i0 - HB && rc < i1 + HB) {
-        float A = 0.f, B = 0.f;
-        if (a_lane && row_ok(rc, h)) {
-          const int nrow = min(rc + R, h - 1) - max(rc - R, 0) + 1;
-          const float invN = inv_ncol * rcp((float)nrow);
-          const WinStats st = window_stats<R>(cs + d * 64, lane, cmask, inv_ncol, invN);
-          const float den = st.var + e;
-          A = den > 0.f ? st.cov * rcp(den) : 0.f;
-          B = (st.mP + cp) - A * (st.mI + cg);
-        }
-        if (!MAB) {
-          if (rc >= i0 && rc < i1 && out_lane) {
-            Ab[(size_t)rc * w + j] = A;
-            if (Bb) Bb[(size_t)rc * w + j] = B;
-          }
-        } else {
-          ab.at(xb, 2 * R + d) = make_float2(A, B);  // row rc
-        }
-      }
-    }
-    if (MAB) {
-#pragma unroll
-      for (int d = 0; d < kPF; ++d) {
-        const int ra = xb + d - 2 * R;  // row whose (A, b) window is complete
-        if (xb + d < xend && ra >= i0 && ra < i1) {
-          float sa = 0.f, sb = 0.f;
-#pragma unroll
-          for (int k = 0; k < K; ++k) {
-            const float2 v = ab.at(xb, d + k);  // row ra-R+k; outside the image: zeros
-            sa += v.x;
-            sb += v.y;
-          }
-          vs[d * 64 + lane] = make_float2(sa, sb);
-        }
-      }
+    if constexpr (!DPP) {
       wave_sync();
 #pragma unroll
       for (int d = 0; d < kPF; ++d) {
+        const int rc = xb + d - R;
+        if (!(IN || (xb + d >= i0 + R - HB && xb + d < xend))) continue;
+        // lanes 0 .. R-1 and 64-R .. 63 form no (A, b): their window would leave the row
+        const int lc = min(max(lane, R), 63 - R);
+        const WinStats ws = window_stats<R>(cs + d * 64, lc, cmask, inv_ncol, inv_count(tag, rc));
+        put_ab(xb, d, rc, coef_of(ws, a_lane && (IN || row_ok(rc, h))));
+      }
+    }
+    if (MAB) {
+      // rows ra = x - 2R whose (A, b) windows are complete
+#pragma unroll
+      for (int d = 0; d < kPF; ++d) {
         const int ra = xb + d - 2 * R;
-        if (xb + d < xend && ra >= i0 && ra < i1 && out_lane) {
+        if (!(IN || (xb + d >= i0 + 2 * R && xb + d < xend))) continue;
+        float2 v = ab.at(xb, d);  // row ra-R; outside the image: zeros
+#pragma unroll
+        for (int k = 1; k < K; ++k) {
+          const float2 u = ab.at(xb, d + k);
+          v.x += u.x;
+          v.y += u.y;
+        }
+        if constexpr (DPP) {
+          put_bar(tag, ra, lane_sum<R>(v.x), lane_sum<R>(v.y));
+        } else {
+          vs[d * 64 + lane] = v;
+        }
+      }
+      if constexpr (!DPP) {
+        wave_sync();
+#pragma unroll
+        for (int d = 0; d < kPF; ++d) {
+          const int ra = xb + d - 2 * R;
+          if (!(IN || (xb + d >= i0 + 2 * R && xb + d < xend)) || !out_lane) continue;
           float sa = 0.f, sb = 0.f;
 #pragma unroll
           for (int k = 0; k < K; ++k) {  // columns outside the image hold zeros
-            const float2 v = vs[d * 64 + lane + k - R];
-            sa += v.x;
-            sb += v.y;
+            const float2 u = vs[d * 64 + lane + k - R];
+            sa += u.x;
+            sb += u.y;
           }
-          const int nrow = min(ra + R, h - 1) - max(ra - R, 0) + 1;
-          const float invN = inv_ncol * rcp((float)nrow);
-          Ab[(size_t)ra * w + j] = sa * invN;
-          if (Bb) Bb[(size_t)ra * w + j] = sb * invN;
+          put_bar(tag, ra, sa, sb);
         }
       }
     }
-    wave_sync();
+    if constexpr (!DPP) wave_sync();
   };
 
   TG gq[kPF];
   TP pq[kPF];
 #pragma unroll
   for (int d = 0; d < kPF; ++d) load(x0 + d, gq[d], pq[d]);
-  for (int base = x0; base < xend; base += kPF) {
-    TG gn[kPF];
-    TP pn[kPF];
-#pragma unroll
-    for (int d = 0; d < kPF; ++d) load(base + kPF + d, gn[d], pn[d]);
-    block(base, gq, pq);
+  // blocks before, inside and after the interior range (xin <= xb <= xlim);
+  // three loops rather than a branch per block keep the register
+  // allocation of the loop-carried windows simple
+  // (interior: the block's rows, the windows of its statistics rows
+  // rc = x - R and of its (A, b) rows ra = x - 2R lie inside the image, every
+  // phase's row is live)
+  const int xin = max(x0 + 2 * HAL, 3 * R), xlim = min(xend, h) - kPF;
+  int base = x0;
+  for (; base < xend && (base < xin || base > xlim); base += kPF) {
+    block(std::false_type{}, base, gq, pq);
     gp.advance();
     ab.advance();
-#pragma unroll
-    for (int d = 0; d < kPF; ++d) {
-      gq[d] = gn[d];
-      pq[d] = pn[d];
-    }
+  }
+  for (; base <= xlim; base += kPF) {
+    block(std::true_type{}, base, gq, pq);
+    gp.advance();
+    ab.advance();
+  }
+  for (; base < xend; base += kPF) {
+    block(std::false_type{}, base, gq, pq);
+    gp.advance();
+    ab.advance();
   }
 }
 
@@ -964,15 +1092,17 @@ struct URaw {
   float a00, a01, a10, a11, v00, v01, v10, v11;
 };
 
-// Per-lane (column) part of the partial-plane addressing: block column c0
-// that owns column j and, on a block border, its neighbour c1 (weight wc).
+// Per-lane (column) part of the partial-plane addressing: byte offsets
+// (block column, column within the block) of the block column c0 that owns
+// column j and, on a block border, of its neighbour c1 (weight wc).
 struct UCol {
-  int o0, o1;  // offsets of (block column, column within block) for c0, c1
+  unsigned o0, o1;
   float wc;
 };
-// Per-row part: block row b0 owning row i and neighbour b1 (weight wb).
+// Per-row part: byte offsets (block row, row within the block) of the block
+// row b0 owning row i and of the neighbour b1 (weight wb).
 struct URow {
-  int o0, o1;  // offsets of (block row, row within block) for b0, b1
+  unsigned o0, o1;
   float wb;
 };
 
@@ -988,12 +1118,15 @@ __device__ __forceinline__ UCol u_col(const BwdLoArgs& a, int j) {
     c1 = c0 + 1;
     wc = 1.f;
   }
-  return UCol{c0 * UP2 + (j - (c0 * tw - 1)), c1 * UP2 + (j - (c1 * tw - 1)), wc};
+  return UCol{4u * (unsigned)(c0 * UP2 + (j - (c0 * tw - 1))),
+              4u * (unsigned)(c1 * UP2 + (j - (c1 * tw - 1))), wc};
 }
 
-__device__ __forceinline__ URow u_row(const BwdLoArgs& a, int i) {
+// Row i's block row b0 = i / bh as a multiply-high by bmul = ceil(2^32 / bh),
+// exact while i * bh < 2^32.
+__device__ __forceinline__ URow u_row(const BwdLoArgs& a, unsigned bmul, int i) {
   const int bh = a.bh, UW = a.tw + 2, UP2 = 2 * (bh + 2) * UW;
-  const int b0 = i / bh, ri = i - b0 * bh;
+  const int b0 = (int)__umulhi((unsigned)i, bmul), ri = i - b0 * bh;
   int b1 = b0;
   float wb = 0.f;
   if (ri == 0 && b0 > 0) {
@@ -1003,28 +1136,29 @@ __device__ __forceinline__ URow u_row(const BwdLoArgs& a, int i) {
     b1 = b0 + 1;
     wb = 1.f;
   }
-  return URow{b0 * a.nbx * UP2 + (i - (b0 * bh - 1)) * UW,
-              b1 * a.nbx * UP2 + (i - (b1 * bh - 1)) * UW, wb};
+  return URow{4u * (unsigned)(b0 * a.nbx * UP2 + (i - (b0 * bh - 1)) * UW),
+              4u * (unsigned)(b1 * a.nbx * UP2 + (i - (b1 * bh - 1)) * UW), wb};
 }
 
-// The four partial-plane reads per plane (absent neighbours re-read the
-// owner, with weight 0, so that no load sits in a divergent branch).
-__device__ __forceinline__ URaw gather_u_raw(const float* base, size_t UP, const URow& ro,
+// The four partial-plane reads per plane (ub: UP * 4, the byte offset of the
+// second plane of a block's partials).
+__device__ __forceinline__ URaw gather_u_raw(__amdgpu_buffer_rsrc_t r, unsigned ub, const URow& ro,
                                              const UCol& co) {
-  const float* p00 = base + ro.o0 + co.o0;
-  const float* p01 = base + ro.o0 + co.o1;
-  const float* p10 = base + ro.o1 + co.o0;
-  const float* p11 = base + ro.o1 + co.o1;
-  return URaw{p00[0], p01[0], p10[0], p11[0], p00[UP], p01[UP], p10[UP], p11[UP]};
+  return URaw{buf_ld<float>(r, co.o0, ro.o0),      buf_ld<float>(r, co.o1, ro.o0),
+              buf_ld<float>(r, co.o0, ro.o1),      buf_ld<float>(r, co.o1, ro.o1),
+              buf_ld<float>(r, co.o0, ro.o0 + ub), buf_ld<float>(r, co.o1, ro.o0 + ub),
+              buf_ld<float>(r, co.o0, ro.o1 + ub), buf_ld<float>(r, co.o1, ro.o1 + ub)};
 }
 
-// Adjoint of the low-res part (Algorithm 1 with the adjoint of the A/b window
-// mean): one wave per strip of 64 - 4R output columns x TR output rows.
-// Per input row: ring the recentred guide/input and the gathered upstream
+// Adjoint of the low-res part (Algorithm 1, plus the adjoint of the A/b
+// window mean): one wave per strip of 64 - 4R output columns x TR output
+// rows.  Per input row: the recentred guide/input and the gathered upstream
 // planes dAbar, dbbar (divided by the window count N when MAB, so that
 // f_mu^T(y) = box sum of y/N); per row whose window is complete: statistics,
 // A, and the adjoint quantities X = (dmean_I, dmean_p, dcov, dvar) / N; per
-// row whose X window is complete: box sums of X give dG and dp.
+// row whose X window is complete: box sums of X give dG and dp.  Blocks
+// whose rows and windows all lie inside the image and the segment run
+// without row checks.
 template <typename TG, typename TP, int R, bool MAB>
 __device__ __forceinline__ void bwd_lo_body(const BwdLoArgs& a, const int bx, const int by,
                                             const int plane) {
@@ -1032,12 +1166,16 @@ __device__ __forceinline__ void bwd_lo_body(const BwdLoArgs& a, const int bx, co
   constexpr int TWo = 64 - 4 * R;
   constexpr int KR = walker_ring_rows(R, kPF, kBwdLoRingPow2Max);
   constexpr bool REG = bwd_lo_reg_window(R);
+  constexpr bool DPP = lane_dpp(R);
   constexpr int NW = 2 * R + kPF;
   extern __shared__ float4 lds4[];
-  float4* cs = lds4;              // [kPF][64] column statistics
-  float2* cu = reinterpret_cast<float2*>(cs + kPF * 64);  // [kPF][64] column sums of dAbar, dbbar
-  float4* vs = reinterpret_cast<float4*>(cu + kPF * 64);  // [kPF][64] column sums of X
-  float4* rings = vs + kPF * 64;  // LDS rings (large R only)
+  // LDS when the horizontal windows do not use DPP: [kPF][64] column
+  // statistics, column sums of (dAbar, dbbar), column sums of X; then the
+  // rings (large R)
+  float4* cs = lds4;
+  float2* cu = reinterpret_cast<float2*>(cs + kPF * 64);
+  float4* vs = reinterpret_cast<float4*>(cu + kPF * 64);
+  float4* rings = DPP ? lds4 : vs + kPF * 64;
   // vertical windows: (g', p', dAbar, dbbar) rows xb-2R.., X rows xb-3R..
   VWin<float4, NW, -2 * R, KR, REG> in;
   VWin<float4, NW, -3 * R, KR, REG> xr;
@@ -1050,8 +1188,13 @@ __device__ __forceinline__ void bwd_lo_body(const BwdLoArgs& a, const int bx, co
   const bool colin = (unsigned)j < (unsigned)w;
   const int i0 = by * a.TR, i1 = min(i0 + a.TR, h);
   const size_t pofs = (size_t)plane * h * w;
+  const size_t hw = (size_t)h * w;
   const TG* G = reinterpret_cast<const TG*>(a.I_lo) + pofs;
   const TP* P = reinterpret_cast<const TP*>(a.p_lo) + pofs;
+  const __amdgpu_buffer_rsrc_t gR = buf_rsrc(G, hw * sizeof(TG));
+  const __amdgpu_buffer_rsrc_t pR = buf_rsrc(P, hw * sizeof(TP));
+  const __amdgpu_buffer_rsrc_t dgR = buf_rsrc(a.dI_lo ? a.dI_lo + pofs : nullptr, a.dI_lo ? hw * 4 : 0);
+  const __amdgpu_buffer_rsrc_t dpR = buf_rsrc(a.dp_lo ? a.dp_lo + pofs : nullptr, a.dp_lo ? hw * 4 : 0);
   const int ic = min(i0 + a.TR / 2, h - 1), jc = min(max(j0 + TWo / 2, 0), w - 1);
   const float cg = to_f(G[(size_t)ic * w + jc]);
   const float cp = to_f(P[(size_t)ic * w + jc]);
@@ -1065,179 +1208,246 @@ __device__ __forceinline__ void bwd_lo_body(const BwdLoArgs& a, const int bx, co
   const float inv_ncol = rcp(fmaxf(ncol, 1.f));
   const bool x_lane = colin && lane >= R && lane < 64 - R;  // lanes that form X
   const bool out_col = colin && lane >= 2 * R && lane < 2 * R + TWo;
+  const unsigned jo = (unsigned)(colin ? j : 0) * 4u;  // output byte offset in a row
   const int x0 = i0 - 2 * R, xend = i1 + 2 * R;
   in.init(rings, x0, lane, make_float4(0.f, 0.f, 0.f, 0.f));
   xr.init(rings + KR * 64, x0, lane, make_float4(0.f, 0.f, 0.f, 0.f));
   float deps_acc = 0.f;
 
-  // Loads are unconditional (clamped address) and the queue holds the raw
+  // Loads are unconditional (clamped row) and the queue holds the raw
   // values: a load inside a divergent branch, or arithmetic right after it,
   // would make the wave wait for it there instead of a block later.
   const int jcl = min(max(j, 0), w - 1);
+  const unsigned jg = (unsigned)jcl * sizeof(TG), jp = (unsigned)jcl * sizeof(TP);
   struct Raw {
     TG g;
     TP p;
     URaw u;
+    float wb;
   };
   const size_t UP = (size_t)(a.bh + 2) * (a.tw + 2);
-  const float* ubase = a.U + (size_t)plane * a.nby * a.nbx * 2 * UP;
+  const size_t uplane = (size_t)a.nby * a.nbx * 2 * UP;  // floats per plane
+  const __amdgpu_buffer_rsrc_t uR = buf_rsrc(a.U + (size_t)plane * uplane, uplane * 4);
+  const unsigned ub = (unsigned)UP * 4u;
   const UCol ucol = u_col(a, jcl);
+  const unsigned bmul = 0xffffffffu / (unsigned)a.bh + 1u;
   auto load = [&](int x) __attribute__((always_inline)) {
     const int xc = min(max(x, 0), h - 1);
-    const size_t o = (size_t)xc * w + jcl;
-    return Raw{G[o], P[o], gather_u_raw(ubase, UP, u_row(a, xc), ucol)};
+    const unsigned o = (unsigned)(xc * w);
+    const URow ro = u_row(a, bmul, xc);
+    return Raw{buf_ld<TG>(gR, jg, o * (unsigned)sizeof(TG)),
+               buf_ld<TP>(pR, jp, o * (unsigned)sizeof(TP)), gather_u_raw(uR, ub, ro, ucol),
+               ro.wb};
+  };
+  // 1 / N for the window of row t (interior rows: K rows)
+  auto inv_count = [&](auto tag, int t) __attribute__((always_inline)) {
+    constexpr bool IN = decltype(tag)::value;
+    const int nrow = IN ? K : min(t + R, h - 1) - max(t - R, 0) + 1;
+    return inv_ncol * rcp((float)nrow);
+  };
+  // X of row rc from its window statistics and upstream dA, db (zero where
+  // the lane forms none); adds dvar to the lane's deps where it is an output
+  auto adjoint = [&](int rc, bool ok, const WinStats& st, float dA, float db, float invN)
+                     __attribute__((always_inline)) {
+    const float den = st.var + e;
+    const float rden = den > 0.f ? rcp(den) : 0.f;  // A := 0 when var + eps == 0
+    const float A = st.cov * rden;
+    // b = mean_p - A mean_I (actual means), A = cov / (var + eps)
+    const float dAt = dA - db * (st.mI + cg);
+    const float dcov = dAt * rden;
+    const float dvar = -dAt * A * rden;
+    // var = E[g'^2] - mI'^2, cov = E[g'p'] - mI' mP' (recentred g', p')
+    const float dmI = -db * A - dcov * st.mP - 2.f * dvar * st.mI;
+    const float dmP = db - dcov * st.mI;
+    if (rc >= i0 && rc < i1) deps_acc += out_col ? dvar : 0.f;
+    return ok ? make_float4(dmI * invN, dmP * invN, dcov * invN, dvar * invN)
+              : make_float4(0.f, 0.f, 0.f, 0.f);
+  };
+  auto put_out = [&](int rx, float4 B, float4 gpv) __attribute__((always_inline)) {
+    const unsigned ro = (unsigned)(rx * w) * 4u;
+    if (a.dI_lo) buf_st(B.x + 2.f * B.w * gpv.x + B.z * gpv.y, dgR, jo, ro);
+    if (a.dp_lo) buf_st(B.y + B.z * gpv.x, dpR, jo, ro);
   };
 
-  auto block = [&](int xb, const Raw (&q)[kPF]) __attribute__((always_inline)) {
+  auto block = [&](auto tag, int xb, Raw (&q)[kPF]) __attribute__((always_inline)) {
+    constexpr bool IN = decltype(tag)::value;
 #pragma unroll
     for (int d = 0; d < kPF; ++d) {
       const int x = xb + d;
-      if (x >= xend) continue;
-      const bool ok = colin && row_ok(x, h);
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (ok) {
-        const float wb = u_row(a, x).wb, wc = ucol.wc;
-        const URaw& z = q[d].u;
-        float u = (z.a00 + wc * z.a01) + wb * (z.a10 + wc * z.a11);
-        float vv = (z.v00 + wc * z.v01) + wb * (z.v10 + wc * z.v11);
-        if (MAB) {  // f_mu^T(y) = box sum of y / N: divide by N here
-          const int nrow = min(x + R, h - 1) - max(x - R, 0) + 1;
-          const float invN = inv_ncol * rcp((float)nrow);
-          u *= invN;
-          vv *= invN;
-        }
-        v = make_float4(to_f(q[d].g) - cg, to_f(q[d].p) - cp, u, vv);
+      if (!IN && x >= xend) continue;
+      const bool ok = colin && (IN || row_ok(x, h));
+      const float wb = q[d].wb, wc = ucol.wc;
+      const URaw& z = q[d].u;
+      float u = (z.a00 + wc * z.a01) + wb * (z.a10 + wc * z.a11);
+      float vv = (z.v00 + wc * z.v01) + wb * (z.v10 + wc * z.v11);
+      if (MAB) {  // f_mu^T(y) = box sum of y / N: divide by N here
+        const float invN = inv_count(tag, x);
+        u *= invN;
+        vv *= invN;
       }
-      in.at(xb, 2 * R + d) = v;  // row x
+      in.at(xb, 2 * R + d) = ok ? make_float4(to_f(q[d].g) - cg, to_f(q[d].p) - cp, u, vv)
+                                : make_float4(0.f, 0.f, 0.f, 0.f);  // row x
     }
+    // the queue's rows are consumed: fetch the next block's
+#pragma unroll
+    for (int d = 0; d < kPF; ++d) q[d] = load(xb + kPF + d);
     // rows rc = x - R whose windows are complete with this block
 #pragma unroll
     for (int d = 0; d < kPF; ++d) {
       const int rc = xb + d - R;
-      if (!(xb + d < xend && rc - R >= x0 && rc >= i0 - R && rc < i1 + R)) continue;
-      float4 st = make_float4(0.f, 0.f, 0.f, 0.f);
-      float2 su = make_float2(0.f, 0.f);
-      if (colin && row_ok(rc, h)) {
-        float4 v[K];
-        int nrow = 0;
+      if (!(IN || (xb + d >= i0 && xb + d < xend))) continue;
+      const bool rok = IN || row_ok(rc, h);
+      float4 v[K];
+      int nrow = 0;
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-          v[k] = in.at(xb, d + k);  // row rc-R+k
-          nrow += row_ok(rc - R + k, h) ? 1 : 0;
-        }
-        float s0 = 0.f, s1 = 0.f;
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-          s0 += v[k].x;
-          s1 += v[k].y;
-          su.x += v[k].z;
-          su.y += v[k].w;
-        }
-        const float inv = rcp((float)nrow);
-        st.x = s0 * inv;
-        st.y = s1 * inv;
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-          const bool ok = row_ok(rc - R + k, h);
-          const float dg = ok ? v[k].x - st.x : 0.f;
-          const float dp = ok ? v[k].y - st.y : 0.f;
-          st.z += dg * dg;
-          st.w += dg * dp;
-        }
+      for (int k = 0; k < K; ++k) {
+        v[k] = in.at(xb, d + k);  // row rc-R+k
+        nrow += (IN || row_ok(rc - R + k, h)) ? 1 : 0;
       }
-      cs[d * 64 + lane] = st;
-      cu[d * 64 + lane] = su;
-    }
-    wave_sync();
+      float4 st;
+      float2 su;
+      st.x = v[0].x;
+      st.y = v[0].y;
+      su.x = v[0].z;
+      su.y = v[0].w;
 #pragma unroll
-    for (int d = 0; d < kPF; ++d) {
-      const int rc = xb + d - R;
-      if (!(xb + d < xend && rc - R >= x0 && rc >= i0 - R && rc < i1 + R)) continue;
-      float4 X = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (x_lane && row_ok(rc, h)) {
-        const int nrow = min(rc + R, h - 1) - max(rc - R, 0) + 1;
-        const float invN = inv_ncol * rcp((float)nrow);
-        const WinStats st = window_stats<R>(cs + d * 64, lane, cmask, inv_ncol, invN);
+      for (int k = 1; k < K; ++k) {
+        st.x += v[k].x;
+        st.y += v[k].y;
+        su.x += v[k].z;
+        su.y += v[k].w;
+      }
+      const float inv = rcp((float)max(nrow, 1));
+      st.x *= inv;
+      st.y *= inv;
+      st.z = 0.f;
+      st.w = 0.f;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const bool ok = IN || row_ok(rc - R + k, h);
+        const float dg = ok ? v[k].x - st.x : 0.f;
+        const float dp = ok ? v[k].y - st.y : 0.f;
+        st.z += dg * dg;
+        st.w += dg * dp;
+      }
+      if (!(colin && rok)) {
+        st = make_float4(0.f, 0.f, 0.f, 0.f);
+        su = make_float2(0.f, 0.f);
+      }
+      if constexpr (DPP) {
+        const float invN = inv_count(tag, rc);
+        const WinStats ws = window_stats_dpp<R>(st, cmask, inv_ncol, invN);
+        float dA, db;
+        if (MAB) {  // f_mu^T of the upstream planes: box sums of dAbar/N, dbbar/N
+          dA = lane_sum<R>(su.x);
+          db = lane_sum<R>(su.y);
+        } else {
+          const float4 c = in.at(xb, d + R);  // row rc
+          dA = c.z;
+          db = c.w;
+        }
+        xr.at(xb, 2 * R + d) = adjoint(rc, x_lane && rok, ws, dA, db, invN);  // row rc
+      } else {
+        cs[d * 64 + lane] = st;
+        cu[d * 64 + lane] = su;
+      }
+    }
+    if constexpr (!DPP) {
+      wave_sync();
+#pragma unroll
+      for (int d = 0; d < kPF; ++d) {
+        const int rc = xb + d - R;
+        if (!(IN || (xb + d >= i0 && xb + d < xend))) continue;
+        const bool ok = x_lane && (IN || row_ok(rc, h));
+        const float invN = inv_count(tag, rc);
+        // lanes 0 .. R-1 and 64-R .. 63 form no X: their window would leave the row
+        const int lc = min(max(lane, R), 63 - R);
+        const WinStats st = window_stats<R>(cs + d * 64, lc, cmask, inv_ncol, invN);
         float dA, db;
         if (MAB) {  // f_mu^T of the upstream planes: box sums of dAbar/N, dbbar/N
           dA = 0.f;
           db = 0.f;
 #pragma unroll
           for (int k = 0; k < K; ++k) {
-            const float2 c = cu[d * 64 + lane + k - R];
+            const float2 c = cu[d * 64 + lc + k - R];
             dA += c.x;
             db += c.y;
           }
         } else {
-          const float4 v = in.at(xb, d + R);  // row rc
-          dA = v.z;
-          db = v.w;
+          const float4 c = in.at(xb, d + R);  // row rc
+          dA = c.z;
+          db = c.w;
         }
-        const float den = st.var + e;
-        const float rden = den > 0.f ? rcp(den) : 0.f;  // A := 0 when var + eps == 0
-        const float A = st.cov * rden;
-        // b = mean_p - A mean_I (actual means), A = cov / (var + eps)
-        const float dAt = dA - db * (st.mI + cg);
-        const float dcov = dAt * rden;
-        const float dvar = -dAt * A * rden;
-        // var = E[g'^2] - mI'^2, cov = E[g'p'] - mI' mP' (recentred g', p')
-        const float dmI = -db * A - dcov * st.mP - 2.f * dvar * st.mI;
-        const float dmP = db - dcov * st.mI;
-        X = make_float4(dmI * invN, dmP * invN, dcov * invN, dvar * invN);
-        if (rc >= i0 && rc < i1 && out_col) deps_acc += dvar;
+        xr.at(xb, 2 * R + d) = adjoint(rc, ok, st, dA, db, invN);  // row rc
       }
-      xr.at(xb, 2 * R + d) = X;  // row rc
     }
     // rows rx = x - 2R whose X windows are complete
 #pragma unroll
     for (int d = 0; d < kPF; ++d) {
       const int rx = xb + d - 2 * R;
-      if (!(xb + d < xend && rx >= i0 && rx < i1)) continue;
-      float4 sum = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (!(IN || (xb + d >= i0 + 2 * R && xb + d < xend))) continue;
+      float4 sum = xr.at(xb, d);  // rows rx-R .. rx+R; outside the image: zeros
 #pragma unroll
-      for (int k = 0; k < K; ++k) {  // rows outside the image hold zeros
-        const float4 v = xr.at(xb, d + k);  // row rx-R+k
+      for (int k = 1; k < K; ++k) {
+        const float4 v = xr.at(xb, d + k);
         sum.x += v.x;
         sum.y += v.y;
         sum.z += v.z;
         sum.w += v.w;
       }
-      vs[d * 64 + lane] = sum;
-    }
-    wave_sync();
-#pragma unroll
-    for (int d = 0; d < kPF; ++d) {
-      const int rx = xb + d - 2 * R;
-      if (!(xb + d < xend && rx >= i0 && rx < i1 && out_col)) continue;
-      float4 B = make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-      for (int k = 0; k < K; ++k) {  // columns outside the image hold zeros
-        const float4 v = vs[d * 64 + lane + k - R];
-        B.x += v.x;
-        B.y += v.y;
-        B.z += v.z;
-        B.w += v.w;
+      if constexpr (DPP) {
+        const float4 B = make_float4(lane_sum<R>(sum.x), lane_sum<R>(sum.y), lane_sum<R>(sum.z),
+                                     lane_sum<R>(sum.w));
+        if (out_col) put_out(rx, B, in.at(xb, d));  // in.at(xb, d): row rx
+      } else {
+        vs[d * 64 + lane] = sum;
       }
-      const float4 gpv = in.at(xb, d);  // row rx
-      const size_t go = pofs + (size_t)rx * w + j;
-      if (a.dI_lo) a.dI_lo[go] = B.x + 2.f * B.w * gpv.x + B.z * gpv.y;
-      if (a.dp_lo) a.dp_lo[go] = B.y + B.z * gpv.x;
     }
-    wave_sync();
+    if constexpr (!DPP) {
+      wave_sync();
+#pragma unroll
+      for (int d = 0; d < kPF; ++d) {
+        const int rx = xb + d - 2 * R;
+        if (!(IN || (xb + d >= i0 + 2 * R && xb + d < xend)) || !out_col) continue;
+        float4 B = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {  // columns outside the image hold zeros
+          const float4 v = vs[d * 64 + lane + k - R];
+          B.x += v.x;
+          B.y += v.y;
+          B.z += v.z;
+          B.w += v.w;
+        }
+        put_out(rx, B, in.at(xb, d));  // in.at(xb, d): row rx
+      }
+      wave_sync();
+    }
   };
 
   Raw q[kPF];
 #pragma unroll
   for (int d = 0; d < kPF; ++d) q[d] = load(x0 + d);
-  for (int base = x0; base < xend; base += kPF) {
-    Raw nq[kPF];
-#pragma unroll
-    for (int d = 0; d < kPF; ++d) nq[d] = load(base + kPF + d);
-    block(base, q);
+  // blocks before, inside and after the interior range (xin <= xb <= xlim);
+  // three loops rather than a branch per block keep the register
+  // allocation of the loop-carried windows simple
+  // (interior: the block's rows, their windows and those of the statistics
+  // rows rc = x - R lie inside the image, every phase's row is live)
+  const int xin = max(x0 + 4 * R, 2 * R), xlim = min(xend, h - R) - kPF;
+  int base = x0;
+  for (; base < xend && (base < xin || base > xlim); base += kPF) {
+    block(std::false_type{}, base, q);
     in.advance();
     xr.advance();
-#pragma unroll
-    for (int d = 0; d < kPF; ++d) q[d] = nq[d];
+  }
+  for (; base <= xlim; base += kPF) {
+    block(std::true_type{}, base, q);
+    in.advance();
+    xr.advance();
+  }
+  for (; base < xend; base += kPF) {
+    block(std::false_type{}, base, q);
+    in.advance();
+    xr.advance();
   }
   // fixed-order wave reduction of this strip's deps contribution
 #pragma unroll
