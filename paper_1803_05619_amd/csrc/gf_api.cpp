@@ -155,11 +155,15 @@ int make_plan(const gf_desc_t* d, const gf_guide_t* g, Plan* p, const char** why
   q.nrb = (q.H + q.RB - 1) / q.RB;
   q.nxv = q.W / q.VEC;
 
-  q.bh = tv.bh;
   q.tw = 64 * q.VEC / S;
-  q.nby = (q.h + q.bh - 1) / q.bh;
+  q.hw = hi_merge(d->io_dtype == GF_F32, S) ? kHiWaves : 1;  // waves per high-res workgroup
+  q.bh = tv.bh;  // rows per wave; fewer when the workgroup's merge buffers would exceed 64 KB
+  while (q.bh > 2 && bwd_hi_lds_bytes(q.hw * q.bh, q.tw) > kHiLdsMax) --q.bh;
+  q.ubh = q.hw * q.bh;
+  q.hiLDS = bwd_hi_lds_bytes(q.ubh, q.tw);
+  q.nby = (q.h + q.ubh - 1) / q.ubh;
   q.nbx = (q.W + 64 * q.VEC - 1) / (64 * q.VEC);
-  q.ublk_floats = (size_t)2 * (q.bh + 2) * (q.tw + 2);
+  q.ublk_floats = (size_t)2 * (q.ubh + 2) * (q.tw + 2);
   // the low-res walkers address a plane, and its partial planes, with
   // 32-bit byte offsets
   if ((double)q.h * q.w * 4.0 > 2147483647.0 ||

@@ -105,7 +105,10 @@ void build_classes(const ClassMap& cm, int kind, std::vector<char>& host, size_t
       c.VEC = kv.first.second / 2;
       c.AC = kv.first.second % 2;
     }
-    c.lds = lds ? lds(geo[mem[0].item]) : 0;
+    c.hw = geo[mem[0].item].p.hw;  // high-res classes: one dtype and factor, one value
+    c.lds = 0;  // the largest of the class's items
+    if (lds)
+      for (const Member& m : mem) c.lds = std::max(c.lds, lds(geo[m.item]));
     c.m.base = reinterpret_cast<const long long*>(dmem + base_off);
     c.m.items = dmem + items_off;
     c.m.count = (int)n;
@@ -231,20 +234,20 @@ int create(const gf_item_t* items, int count, gf_plan** out) {
         const Plan& p = geo[k].p;
         return BwdHiArgs{items[k].I_hi, items[k].dq_hi, items[k].dI_hi,
                          ws_rel<float>(geo[k].off_abar), ws_rel<float>(geo[k].off_u), p.h, p.w,
-                         p.H, p.W, p.bh, p.tw, p.nby, p.nbx, 0,
+                         p.H, p.W, p.bh, p.tw, p.nby, p.nbx, p.hw, 0,
                          ws_rel<float>(geo[k].off_bbar), items[k].q_hi};
       },
       [](const Geo& g, int& nx, int& ny) {
         nx = g.p.nbx;
         ny = g.p.nby;
       },
-      nullptr, geo, pl->launch.bwd_hi);
+      [](const Geo& g) { return g.p.hiLDS; }, geo, pl->launch.bwd_hi);
   build_classes<BwdLoArgs>(
       cm_lo, kClassBwdLo, host, off, pl->dmem,
       [&](int k) {
         const Plan& p = geo[k].p;
         return BwdLoArgs{items[k].I_lo, items[k].p_lo, eps_dev + k, 1, p.c,
-                         ws_rel<float>(geo[k].off_u), p.bh, p.tw, p.nby, p.nbx, p.h, p.w, p.loTR,
+                         ws_rel<float>(geo[k].off_u), p.ubh, p.tw, p.nby, p.nbx, p.h, p.w, p.loTR,
                          items[k].dI_lo, items[k].dp_lo, ws_rel<float>(geo[k].off_eps), p.lo_nx,
                          p.lo_ny};
       },

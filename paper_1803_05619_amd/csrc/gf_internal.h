@@ -29,10 +29,13 @@ struct Plan {
   size_t coLDS;
   // high-res apply: rows per thread
   int RB, nrb, nxv;
-  // backward high-res blocks (one wave each): bh low-res rows x tw low-res
-  // columns (64 * VEC high-res columns)
-  int bh, tw, nby, nbx;
-  size_t ublk_floats;  // floats per block (2 * (bh + 2) * (tw + 2))
+  // backward high-res blocks: a workgroup of hw waves (1 .. kHiWaves), each
+  // wave bh low-res rows (stacked) x tw low-res columns (64 * VEC high-res
+  // columns); the workgroup writes one merged partial block of ubh = hw * bh
+  // rows (nby x nbx blocks per plane)
+  int bh, hw, ubh, tw, nby, nbx;
+  size_t ublk_floats;  // floats per partial block (2 * (ubh + 2) * (tw + 2))
+  size_t hiLDS;        // the workgroup's LDS for merging its waves' partial rows
   // backward low-res kernel: same walker shape
   int loTR, lo_nx, lo_ny;
   size_t loLDS;
@@ -70,6 +73,24 @@ constexpr int walker_ring_rows(int R, int block, int pow2_max) {
   return p2 <= pow2_max ? p2 : need;
 }
 constexpr int kWalkBlock = 4;        // rows per block of the low-res walkers
+// Waves per workgroup of the high-res backward (at most): vertically
+// stacked row bands whose overlapping partial rows are summed in LDS, so one
+// partial block of hw * bh + 2 rows is written per workgroup (rather than
+// bh + 2 rows per wave), and the bands' shared low-res coefficient rows are
+// read by one CU.
+constexpr int kHiWaves = 4;
+// Stacking pays for its barrier where the partial planes and coefficient
+// halos are a large share of the traffic: FP32 gradients at S >= 4
+// (measured slower for the half types and for S <= 2 on MI355X).  The same
+// rule, on the gradient element type, selects the kernel variant.
+constexpr bool hi_merge(bool f32_grad, int S) { return f32_grad && S >= 4; }
+// LDS of that merge: two buffers (waves of even / odd index, whose row
+// ranges do not overlap within a buffer) x two quantities x (ubh + 2) rows
+// x (tw + 2) columns.
+constexpr size_t bwd_hi_lds_bytes(int ubh, int tw) {
+  return (size_t)2 * 2 * (ubh + 2) * (tw + 2) * sizeof(float);
+}
+constexpr size_t kHiLdsMax = 65536;
 constexpr int kCoefRingPow2Max = 32;  // coef: 64 * (16 KR + 24 * 4) bytes
 constexpr int kBwdLoRingPow2Max = 16;  // bwd_lo: 64 * (32 KR + 40 * 4) bytes
 
@@ -142,7 +163,8 @@ struct BwdHiArgs {
   void* dI_hi;  // may be null
   const float* abar;
   float* U;     // per-block partial planes
-  int h, w, H, W, bh, tw, nby, nbx;
+  int h, w, H, W, bh, tw, nby, nbx;  // bh: rows per wave; nby: partial blocks (hw * bh rows)
+  int hw;                            // waves per workgroup
   int xcd;  // 1: XCD-aware workgroup order
   // forward in the same pass (fused kernel only): q = A_h G_h + b_h
   const float* bbar;
@@ -200,7 +222,8 @@ struct BatchClass {
   int kind;
   int S, VEC, AC; // high-res classes (AC: corner alignment)
   int R, MAB;     // low-res classes
-  size_t lds;     // dynamic LDS bytes (low-res classes)
+  size_t lds;     // dynamic LDS bytes
+  int hw;         // high-res backward: waves per workgroup
   MultiLaunch m;
 };
 

@@ -770,12 +770,15 @@ __global__ __launch_bounds__(256) void apply_kernel(ApplyArgs a) {
 
 
 
-// One wave per block of bh low-res rows (S*bh high-res rows) x 64*VEC
-// high-res columns.  The block writes the transposed-bilinear contributions
-// of its own pixels to low-res rows i_a-1 .. i_a+bh and columns
-// j_a-1 .. j_a+tw: a (bh+2) x (tw+2) partial plane for dA_bar (from dq*G_h)
-// and one for db_bar (from dq).  The border rows/columns overlap the
-// neighbouring blocks' and are summed by the low-res kernel.
+// One wave per band of bh low-res rows (S*bh high-res rows) x 64*VEC
+// high-res columns; hw bands stacked vertically form a workgroup.  A
+// band's transposed-bilinear contributions reach low-res rows i_a-1 ..
+// i_a+bh and columns j_a-1 .. j_a+tw: (bh+2) x (tw+2) partial rows for
+// dA_bar (from dq*G_h) and for db_bar (from dq).  The waves write them into
+// LDS (even and odd waves into separate buffers, so that no two waves of a
+// buffer share a row) and the workgroup writes the sums of the two buffers
+// as one (hw*bh+2) x (tw+2) partial block; the border rows/columns
+// overlap the neighbouring blocks' and are summed by the low-res kernel.
 //
 // Vertical: per high-res row, each lane adds its VEC values, weighted, into
 // accumulators of the low-res rows i-1, i, i+1 of the current row block;
@@ -790,16 +793,25 @@ __global__ __launch_bounds__(256) void apply_kernel(ApplyArgs a) {
 // (type TQ), reading the bbar rows alongside Abar's: one read of G_h and dq
 // for both directions.
 template <typename TG, typename TD, typename TO, typename TQ, int S, int VEC, bool AC, bool FWD>
-__device__ __forceinline__ void bwd_hi_body(const BwdHiArgs& a, const int bx, const int by,
+__device__ __forceinline__ void bwd_hi_body(const BwdHiArgs& a, const int bx, const int byg,
                                             const int plane) {
   constexpr int TWH = 64 * VEC;  // high-res columns per block
   // register flush: compile-time half-pixel weights over whole low-res
   // columns per lane; otherwise (corner alignment, VEC < S) through LDS
   constexpr bool REG = (VEC % S) == 0 && !AC;
   constexpr int NB = REG ? VEC / S : 1;  // low-res columns per lane
-  __shared__ float sR[REG ? 1 : 2][REG ? 1 : TWH];
-  const int lane = threadIdx.x;
-  const int h = a.h, w = a.w, W = a.W, bh = a.bh, tw = a.tw;
+  constexpr int UW = TWH / S + 2;        // partial-row width (tw + 2)
+  __shared__ float sR[REG ? 1 : kHiWaves][2][REG ? 1 : TWH];
+  extern __shared__ float ush[];  // [even, odd waves][dA_bar, db_bar][ubh + 2][UW]
+  // stacked bands (merge) or one wave per workgroup (the same indexing, constant-folded)
+  constexpr bool merge = hi_merge(std::is_same<TD, float>::value, S);
+  const int lane = merge ? threadIdx.x & 63 : threadIdx.x;
+  const int wave = merge ? threadIdx.x >> 6 : 0;
+  const int hw = merge ? a.hw : 1;
+  const int by = byg * hw + wave;  // this wave's band
+  const int h = a.h, w = a.w, W = a.W, bh = a.bh;
+  const int URW = hw * bh + 2;          // rows of the merged partial block
+  const int UPm = URW * UW;             // floats per quantity
   const int X_a = bx * TWH;
   const int x0 = X_a + lane * VEC;
   const bool valid = x0 < W;
@@ -822,9 +834,41 @@ __device__ __forceinline__ void bwd_hi_body(const BwdHiArgs& a, const int bx, co
   TO* Op = a.dI_hi ? reinterpret_cast<TO*>(a.dI_hi) + hofs : nullptr;
   const float* Bb = FWD ? a.bbar + (size_t)plane * h * w : nullptr;
   TQ* Qp = FWD ? reinterpret_cast<TQ*>(a.q) + hofs : nullptr;
-  const int UW = tw + 2;
-  const size_t UP = (size_t)(bh + 2) * UW;
-  float* Ub = a.U + (((size_t)plane * a.nby + by) * a.nbx + bx) * 2 * UP;
+  // this wave's rows of the merge buffers (row lr of the band: merged row
+  // wave * bh + lr); single-wave workgroups (the variant without merge, the
+  // same layout) write their partial block straight to global memory
+  float* Ub = ush + (wave & 1) * 2 * UPm + wave * bh * UW;
+  float* Ug = a.U + (((size_t)plane * a.nby + byg) * a.nbx + bx) * 2 * (size_t)UPm;
+  auto put = [&](int k, float v) __attribute__((always_inline)) {
+    if constexpr (merge)
+      Ub[k] = v;
+    else
+      Ug[k] = v;
+  };
+  // the image's last workgroup may hold empty bands (never without merge:
+  // there nby = ceil(h / bh))
+  const bool active = !merge || i_a < h;
+  if constexpr (merge) {
+    // Rows of the merge buffers that no wave writes must read as zero: in
+    // this wave's buffer the gap before the next wave of the same parity
+    // (its own rows too when its band is empty), and, from wave 0, the odd
+    // buffer's rows above wave 1's.  No other wave touches these rows, so no
+    // barrier is needed before the bands are computed.  (Rows that only a
+    // partial last band leaves unwritten lie below the image and are never
+    // read.)
+    float* own = ush + (wave & 1) * 2 * UPm;
+    const int z0 = active ? wave * bh + bh + 2 : wave * bh;
+    const int z1 = wave + 2 < hw ? (wave + 2) * bh : URW;
+    for (int k = z0 * UW + lane; k < z1 * UW; k += 64) {
+      own[k] = 0.f;
+      own[UPm + k] = 0.f;
+    }
+    if (wave == 0)
+      for (int k = lane; k < bh * UW; k += 64) {
+        ush[2 * UPm + k] = 0.f;
+        ush[3 * UPm + k] = 0.f;
+      }
+  }
   // this lane's first low-res column (register path) and the image-edge clamps
   const int jb = x0 / S;
   const bool left_edge = (x0 == 0);
@@ -891,26 +935,25 @@ __device__ __forceinline__ void bwd_hi_body(const BwdHiArgs& a, const int bx, co
         oA[NB - 1] += fromA;
         oB[NB - 1] += fromB;
       }
-      float* rowA = Ub + (size_t)lr * UW;
-      float* rowB = Ub + UP + (size_t)lr * UW;
+      const int rowA = lr * UW, rowB = UPm + lr * UW;
 #pragma unroll
       for (int m = 0; m < NB; ++m) {
-        rowA[1 + lane * NB + m] = oA[m];
-        rowB[1 + lane * NB + m] = oB[m];
+        put(rowA + 1 + lane * NB + m, oA[m]);
+        put(rowB + 1 + lane * NB + m, oB[m]);
       }
       if (lane == 0) {
-        rowA[0] = lA;
-        rowB[0] = lB;
+        put(rowA, lA);
+        put(rowB, lB);
       }
       if (lane == 63) {
-        rowA[UW - 1] = rA;
-        rowB[UW - 1] = rB;
+        put(rowA + UW - 1, rA);
+        put(rowB + UW - 1, rB);
       }
     } else {
 #pragma unroll
       for (int e = 0; e < VEC; ++e) {
-        sR[0][lane * VEC + e] = uA[e];
-        sR[1][lane * VEC + e] = uB[e];
+        sR[wave][0][lane * VEC + e] = uA[e];
+        sR[wave][1][lane * VEC + e] = uB[e];
       }
       wave_sync();
       for (int k = lane; k < UW; k += 64) {
@@ -922,12 +965,12 @@ __device__ __forceinline__ void bwd_hi_body(const BwdHiArgs& a, const int bx, co
           for (int x = xlo; x < xhi; ++x) {
             const Tap tx = tap_t<AC>(x, S, w, W);
             const float wt = (tx.i0 == j ? 1.f - tx.w : 0.f) + (tx.i1 == j ? tx.w : 0.f);
-            sa += wt * sR[0][x - X_a];
-            sb += wt * sR[1][x - X_a];
+            sa += wt * sR[wave][0][x - X_a];
+            sb += wt * sR[wave][1][x - X_a];
           }
         }
-        Ub[(size_t)lr * UW + k] = sa;
-        Ub[UP + (size_t)lr * UW + k] = sb;
+        put(lr * UW + k, sa);
+        put(UPm + lr * UW + k, sb);
       }
       wave_sync();
     }
@@ -936,14 +979,6 @@ __device__ __forceinline__ void bwd_hi_body(const BwdHiArgs& a, const int bx, co
   float am[VEC], ac[VEC], ap[VEC];
   float bm[FWD ? VEC : 1], bc[FWD ? VEC : 1], bp[FWD ? VEC : 1];
   float pA[VEC], cA[VEC], nA[VEC], pB[VEC], cB[VEC], nB[VEC];
-#pragma unroll
-  for (int e = 0; e < VEC; ++e) pA[e] = cA[e] = nA[e] = pB[e] = cB[e] = nB[e] = 0.f;
-  hrow<VEC>(Ab, i_a - 1, h, w, j0, j1, wx, am);
-  hrow<VEC>(Ab, i_a, h, w, j0, j1, wx, ac);
-  if constexpr (FWD) {
-    hrow<VEC>(Bb, i_a - 1, h, w, j0, j1, wx, bm);
-    hrow<VEC>(Bb, i_a, h, w, j0, j1, wx, bc);
-  }
 
   // unconditional loads (lanes past the image edge re-read column 0 and
   // are zeroed), so that no load sits in a divergent branch
@@ -1051,25 +1086,40 @@ __device__ __forceinline__ void bwd_hi_body(const BwdHiArgs& a, const int bx, co
       }
     }
   };
-  float da[SR][VEC], ga[SR][VEC], db[SR][VEC], gb[SR][VEC];
-  load_unit(i_a, 0, da, ga);
-  if constexpr (NH == 1) {
-    for (int i = i_a; i < i_b; i += 2) {
-      part(std::integral_constant<int, 0>{}, i, da, ga, db, gb);
-      if (i + 1 < i_b) part(std::integral_constant<int, 0>{}, i + 1, db, gb, da, ga);
+  if (active) {
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) pA[e] = cA[e] = nA[e] = pB[e] = cB[e] = nB[e] = 0.f;
+    hrow<VEC>(Ab, i_a - 1, h, w, j0, j1, wx, am);
+    hrow<VEC>(Ab, i_a, h, w, j0, j1, wx, ac);
+    if constexpr (FWD) {
+      hrow<VEC>(Bb, i_a - 1, h, w, j0, j1, wx, bm);
+      hrow<VEC>(Bb, i_a, h, w, j0, j1, wx, bc);
     }
-  } else {
-    for (int i = i_a; i < i_b; ++i) {
-      part(std::integral_constant<int, 0>{}, i, da, ga, db, gb);
-      part(std::integral_constant<int, 1>{}, i, db, gb, da, ga);
+    float da[SR][VEC], ga[SR][VEC], db[SR][VEC], gb[SR][VEC];
+    load_unit(i_a, 0, da, ga);
+    if constexpr (NH == 1) {
+      for (int i = i_a; i < i_b; i += 2) {
+        part(std::integral_constant<int, 0>{}, i, da, ga, db, gb);
+        if (i + 1 < i_b) part(std::integral_constant<int, 0>{}, i + 1, db, gb, da, ga);
+      }
+    } else {
+      for (int i = i_a; i < i_b; ++i) {
+        part(std::integral_constant<int, 0>{}, i, da, ga, db, gb);
+        part(std::integral_constant<int, 1>{}, i, db, gb, da, ga);
+      }
     }
+    flush(pA, pB, i_b - i_a);      // row i_b - 1
+    flush(cA, cB, i_b - i_a + 1);  // row i_b (contributions of the last rows)
   }
-  flush(pA, pB, i_b - i_a);      // row i_b - 1
-  flush(cA, cB, i_b - i_a + 1);  // row i_b (contributions of the last rows)
+  if constexpr (merge) {
+    __syncthreads();
+    // the merged partial block: sum of the even and odd waves' buffers
+    for (int k = threadIdx.x; k < 2 * UPm; k += 64 * hw) Ug[k] = ush[k] + ush[2 * UPm + k];
+  }
 }
 
 template <typename TG, typename TD, typename TO, typename TQ, int S, int VEC, bool AC, bool FWD>
-__global__ __launch_bounds__(64) void bwd_hi_kernel(BwdHiArgs a) {
+__global__ __launch_bounds__(64 * kHiWaves) void bwd_hi_kernel(BwdHiArgs a) {
   const long long nwg = (long long)gridDim.x * gridDim.y * gridDim.z;
   const long long lin = xcd_order(
       blockIdx.x + (long long)gridDim.x * (blockIdx.y + (long long)gridDim.y * blockIdx.z), nwg,
@@ -1536,7 +1586,7 @@ __global__ __launch_bounds__(256) void apply_multi_kernel(MultiLaunch m) {
 }
 
 template <typename TG, typename TD, typename TO, typename TQ, int S, int VEC, bool AC, bool FWD>
-__global__ __launch_bounds__(64) void bwd_hi_multi_kernel(MultiLaunch m) {
+__global__ __launch_bounds__(64 * kHiWaves) void bwd_hi_multi_kernel(MultiLaunch m) {
   for (long long t = blockIdx.x; t < m.total; t += gridDim.x) {
     long long l;
     const MultiItem<BwdHiArgs>& it = item_of<BwdHiArgs>(m, t, l);
@@ -1547,6 +1597,8 @@ __global__ __launch_bounds__(64) void bwd_hi_multi_kernel(MultiLaunch m) {
     const long long xy = (long long)it.nx * it.ny;
     bwd_hi_body<TG, TD, TO, TQ, S, VEC, AC, FWD>(a, (int)(l % it.nx), (int)((l / it.nx) % it.ny),
                                     (int)(l / xy));
+    if constexpr (hi_merge(std::is_same<TD, float>::value, S))
+      __syncthreads();  // the next tile clears the LDS this one's write-out reads
   }
 }
 
@@ -1627,11 +1679,12 @@ template <typename TG, typename TD, typename TO, typename TQ, int S, int VEC, bo
 hipError_t launch_bwd_hi_t(const Plan& p, const void* G_hi, const void* dq, void* out,
                            const float* abar, float* U, const float* bbar, void* q,
                            hipStream_t s) {
-  BwdHiArgs a{G_hi, dq, out, abar, U, p.h, p.w, p.H, p.W, p.bh, p.tw, p.nby, p.nbx, p.xcd,
-              bbar, q};
+  if ((p.hw > 1) != hi_merge(std::is_same<TD, float>::value, S)) return hipErrorInvalidValue;
+  BwdHiArgs a{G_hi, dq, out, abar, U, p.h, p.w, p.H, p.W, p.bh, p.tw, p.nby, p.nbx, p.hw,
+              p.xcd, bbar, q};
   prof_begin(FWD ? "gf_fwd_bwd_hi" : "gf_bwd_hi", s);
   hipLaunchKernelGGL((bwd_hi_kernel<TG, TD, TO, TQ, S, VEC, AC, FWD>),
-                     dim3(p.nbx, p.nby, p.planes), dim3(64), 0, s, a);
+                     dim3(p.nbx, p.nby, p.planes), dim3(64 * p.hw), p.hiLDS, s, a);
   prof_end(s);
   return hipGetLastError();
 }
@@ -1695,7 +1748,7 @@ template <typename TG, typename TP>
 hipError_t launch_bwd_lo(const Plan& p, const void* G_lo, const void* p_lo, const float* eps,
                          int eps_count, const float* U, float* dG_lo, float* dp_lo,
                          float* part, hipStream_t s) {
-  BwdLoArgs a{G_lo, p_lo, eps, eps_count, p.c, U, p.bh, p.tw, p.nby, p.nbx,
+  BwdLoArgs a{G_lo, p_lo, eps, eps_count, p.c, U, p.ubh, p.tw, p.nby, p.nbx,
               p.h, p.w, p.loTR, dG_lo, dp_lo, part, p.lo_nx, p.lo_ny};
   const dim3 grid(p.lo_nx, p.lo_ny, p.planes);
   prof_begin("gf_bwd_lo", s);
@@ -1830,12 +1883,13 @@ hipError_t launch_bwd_hi_multi(const BatchClass& c, char* ws, hipStream_t s, boo
   const hipError_t e = with_hires_shape(c.S, c.VEC, c.AC, [&](auto sc, auto vc, auto acc) {
     constexpr int SS = decltype(sc)::value, VV = decltype(vc)::value;
     constexpr bool AA = decltype(acc)::value;
+    if ((c.hw > 1) != hi_merge(std::is_same<TD, float>::value, SS)) return hipErrorInvalidValue;
     if (fwd)
       hipLaunchKernelGGL((bwd_hi_multi_kernel<TG, TD, TO, TD, SS, VV, AA, true>), dim3(m.grid),
-                         dim3(64), 0, s, m);
+                         dim3(64 * c.hw), c.lds, s, m);
     else
       hipLaunchKernelGGL((bwd_hi_multi_kernel<TG, TD, TO, TD, SS, VV, AA, false>), dim3(m.grid),
-                         dim3(64), 0, s, m);
+                         dim3(64 * c.hw), c.lds, s, m);
     return hipGetLastError();
   });
   prof_end(s);
