@@ -112,7 +112,7 @@ int make_plan(const gf_desc_t* d, const gf_guide_t* g, Plan* p, const char** why
   q.ac = d->align_corners;
   q.dtype = d->io_dtype;
   q.S = S;
-  q.xcd = env_int("GF_XCD", 0) != 0 ? 1 : 0;  // measured slower on MI355X: off by default
+  q.xcd = std::max(0, env_int("GF_XCD", 0));  // workgroup order run; see xcd_order
   q.planes = d->n * d->c;
   // elements per lane-load on the high-res side: 4 (16 bytes of float, 8 of
   // a half type), 1 when W is not a multiple
@@ -125,19 +125,23 @@ int make_plan(const gf_desc_t* d, const gf_guide_t* g, Plan* p, const char** why
   // Launch shapes: the tuned entry for this key if the autotuner (or an
   // import) made one, else the defaults below; environment overrides win
   // (tuning experiments).
-  //  - rows per low-res walker wave: 16 for r <= 2 (enough waves to fill
-  //    the chip; the register windows make the 2*halo warm-up rows cheap),
-  //    longer for larger radii to amortise their warm-up
+  //  - rows per low-res walker wave: 16 (coefficients) / 24 (backward) for
+  //    r <= 2 (enough waves to fill the chip in one round; the register
+  //    windows make the 2*halo warm-up rows cheap), longer for larger radii
+  //    to amortise their warm-up
   //  - high-res rows per apply thread: short walks keep DRAM streams
   //    sequential (8 measured best on MI355X for the 4 x 3 x 2048 x 3072
   //    workload): two low-res row blocks at S = 4, one at S = 8
   //  - low-res rows per backward high-res block: 2 (short walks stream
   //    best; the partial planes' extra border rows cost less)
   const int walk = r <= 2 ? 16 : r <= 4 ? 32 : 64;
-  TuneVal tv{walk, walk, S >= 8 ? S : 8, 2};
+  // the backward walker at small radii: 24 rows (4 waves per SIMD; 16-row
+  // segments leave a second, mostly empty round of waves)
+  TuneVal tv{walk, r <= 2 ? 24 : walk, S >= 8 ? S : 8, 2};
   TuneVal tuned;
   if (tune_lookup(TuneKey{d->io_dtype, S, r, gmode, d->mean_ab}, &tuned)) tv = tuned;
   if (env_int("GF_LO_ROWS", 0) > 0) tv.coTR = tv.loTR = env_int("GF_LO_ROWS", 0);
+  if (env_int("GF_BWD_LO_ROWS", 0) > 0) tv.loTR = env_int("GF_BWD_LO_ROWS", 0);
   if (env_int("GF_APPLY_ROWS", 0) > 0) tv.RB = env_int("GF_APPLY_ROWS", 0);
   if (env_int("GF_BWD_BH", 0) >= 2) tv.bh = env_int("GF_BWD_BH", 0);
   if (tv.coTR < 1 || tv.loTR < 1 || tv.RB < 1 || tv.bh < 2)

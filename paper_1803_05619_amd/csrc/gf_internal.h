@@ -20,7 +20,7 @@ struct Plan {
   int n, c, h, w, H, W, r, mean_ab, dtype;
   int ac;       // corner-aligned bilinear (align_corners)
   int S;        // integer upsampling factor (H = S h, W = S w)
-  int xcd;      // XCD-aware workgroup order for the high-res kernels
+  int xcd;      // XCD-aware workgroup order for the high-res kernels (0: off; see xcd_order)
   int VEC;      // high-res elements per thread-load (16 bytes, or 1)
   int planes;   // n * c
   // low-res coefficient kernel: one wave per strip of 64 lanes (columns)
@@ -154,7 +154,7 @@ struct ApplyArgs {
   const float* bbar;
   int h, w, H, W, RB, nrb, nxv;
   long long total;
-  int xcd;  // 1: XCD-aware workgroup order
+  int xcd;  // XCD-aware workgroup order (0: off; see xcd_order)
 };
 
 struct BwdHiArgs {
@@ -165,7 +165,7 @@ struct BwdHiArgs {
   float* U;     // per-block partial planes
   int h, w, H, W, bh, tw, nby, nbx;  // bh: rows per wave; nby: partial blocks (hw * bh rows)
   int hw;                            // waves per workgroup
-  int xcd;  // 1: XCD-aware workgroup order
+  int xcd;  // XCD-aware workgroup order (0: off; see xcd_order)
   // forward in the same pass (fused kernel only): q = A_h G_h + b_h
   const float* bbar;
   void* q;

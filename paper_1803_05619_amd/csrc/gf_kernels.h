@@ -177,15 +177,19 @@ __device__ __forceinline__ void buf_st(float v, __amdgpu_buffer_rsrc_t r, unsign
 }
 
 // XCD-aware workgroup order.  The dispatcher hands consecutive workgroups
-// to the 8 XCDs in turn, each XCD with its own L2; remapping the linear
-// workgroup id so that XCD k runs the contiguous k-th eighth of the work
-// keeps neighbouring row blocks (which share low-res taps) in one L2 and
-// each XCD's DRAM stream sequential.  A bijection on [0, n).
-__device__ __forceinline__ long long xcd_order(long long p, long long n, bool on) {
-  if (!on) return p;
-  const long long q = n / 8;
-  if (p >= 8 * q) return p;
-  return (p % 8) * q + p / 8;
+// to the 8 XCDs in turn, each XCD with its own L2.  With run = m > 1 the
+// linear workgroup id is remapped so that, within every 8m consecutive
+// workgroups, XCD k runs the contiguous m of them starting at k m
+// (neighbouring blocks, which share low-res taps, then meet in one L2 while
+// the whole chip still works on one region of the image); run = 1 gives
+// XCD k the contiguous k-th eighth of all the work.  A bijection on [0, n).
+__device__ __forceinline__ long long xcd_order(long long p, long long n, int run) {
+  if (run <= 0) return p;
+  const long long m = run == 1 ? n / 8 : run;
+  const long long chunk = 8 * m;
+  if (m == 0 || p >= n / chunk * chunk) return p;
+  const long long q = p % chunk;
+  return p - q + (q % 8) * m + q / 8;
 }
 
 // ------------------------------------------------------------ geometry

@@ -211,4 +211,4 @@ def test_autotune_then_parity():
         assert np.abs(v.double().cpu().numpy() - gr[k]).max() / max(1.0, np.abs(gr[k]).max()) \
             <= 1e-4
     # leave the default shapes for later tests in this process
-    assert gf.gf_tune_import("0 4 1 0 1 : 16 16 8 2\n") == gf.GF_OK
+    assert gf.gf_tune_import("0 4 1 0 1 : 16 24 8 2\n") == gf.GF_OK
