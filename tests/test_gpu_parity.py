@@ -229,6 +229,26 @@ def test_forward_backward_equals_separate_calls(cfg, dt):
         assert torch.equal(a, b)
 
 
+def test_forward_backward_five_images():
+    """Five images with per-image eps, twice in a row: the fused call gives
+    bit for bit the separate calls' results, and the oracle's."""
+    gf = _gf()
+    prob = datagen.make_problem(5, 3, 4 * 40, 4 * 56, 4, 1, [1e-4, 1e-3, 1e-2, 1e-5, 1e-6], "f32",
+                                config=170, noise=0.02)
+    print("case 5 images, per-image eps, fused call", flush=True)
+    d = to_dev(prob)
+    q = gf.forward(d["I_lo"], d["p_lo"], d["I_hi"], prob["eps"], prob["r"])
+    g = gf.backward(d["I_lo"], d["p_lo"], d["I_hi"], prob["eps"], d["dq"], prob["r"])
+    for _ in range(2):
+        fb = gf.forward_backward(d["I_lo"], d["p_lo"], d["I_hi"], prob["eps"], d["dq"],
+                                 prob["r"])
+        torch.cuda.synchronize()
+        assert torch.equal(fb[0], q)
+        for a, b in zip(fb[1:5], g[:4]):
+            assert torch.equal(a, b)
+    check(prob)
+
+
 # ------------------------------------------------------------ corner alignment
 
 @pytest.mark.parametrize("s, r, mean_ab", [(1, 1, True), (2, 2, True), (4, 1, True), (4, 3, False),
