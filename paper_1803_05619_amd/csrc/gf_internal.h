@@ -98,9 +98,10 @@ constexpr int kBwdLoRingPow2Max = 16;  // bwd_lo: 64 * (32 KR + 40 * 4) bytes
 // registers instead of LDS rings: the LDS footprint per wave then shrinks to
 // the row buffers of the horizontal windows, which lifts occupancy (at r = 4
 // the backward walker's rings would take 43 KB per wave: three waves per
-// CU).  The coefficient walker holds 2 x 2 floats per window row, the
-// backward walker 2 x 4.
-constexpr bool coef_reg_window(int R) { return 4 * (2 * R + kWalkBlock) <= 64; }
+// CU).  The coefficient walker holds 2 x 2 floats per window row (up to
+// r = 8: 188 VGPRs, two waves per SIMD, against four waves per CU with
+// 39 KB of rings), the backward walker 2 x 4.
+constexpr bool coef_reg_window(int R) { return 4 * (2 * R + kWalkBlock) <= 80; }
 constexpr bool bwd_lo_reg_window(int R) { return 8 * (2 * R + kWalkBlock) <= 96; }
 // Radii whose horizontal windows are formed by whole-wave DPP lane shifts
 // (R shifts each way) rather than through LDS row buffers: with vertical
