@@ -102,7 +102,7 @@ constexpr int kBwdLoRingPow2Max = 16;  // bwd_lo: 64 * (32 KR + 40 * 4) bytes
 // r = 8: 188 VGPRs, two waves per SIMD, against four waves per CU with
 // 39 KB of rings), the backward walker 2 x 4.
 constexpr bool coef_reg_window(int R) { return 4 * (2 * R + kWalkBlock) <= 80; }
-constexpr bool bwd_lo_reg_window(int R) { return 8 * (2 * R + kWalkBlock) <= 96; }
+constexpr bool bwd_lo_reg_window(int R) { return 8 * (2 * R + kWalkBlock) <= 160; }
 // Radii whose horizontal windows are formed by whole-wave DPP lane shifts
 // (R shifts each way) rather than through LDS row buffers: with vertical
 // windows in registers as well, such walkers use no LDS at all.
