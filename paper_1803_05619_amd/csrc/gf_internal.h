@@ -94,13 +94,13 @@ constexpr size_t kHiLdsMax = 65536;
 constexpr int kCoefRingPow2Max = 32;  // coef: 64 * (16 KR + 24 * 4) bytes
 constexpr int kBwdLoRingPow2Max = 16;  // bwd_lo: 64 * (32 KR + 40 * 4) bytes
 
-// Small radii keep each lane's vertical windows (2R + block rows) in
+// Radii up to 8 keep each lane's vertical windows (2R + block rows) in
 // registers instead of LDS rings: the LDS footprint per wave then shrinks to
-// the row buffers of the horizontal windows, which lifts occupancy (at r = 4
-// the backward walker's rings would take 43 KB per wave: three waves per
-// CU).  The coefficient walker holds 2 x 2 floats per window row (up to
-// r = 8: 188 VGPRs, two waves per SIMD, against four waves per CU with
-// 39 KB of rings), the backward walker 2 x 4.
+// the row buffers of the horizontal windows, which lifts occupancy.  The
+// coefficient walker holds 2 x 2 floats per window row (at r = 8: 188
+// VGPRs, two waves per SIMD, against four waves per CU with 39 KB of
+// rings), the backward walker 2 x 4 (at r = 8 one wave per SIMD, against
+// three waves per CU with 51 KB of rings).
 constexpr bool coef_reg_window(int R) { return 4 * (2 * R + kWalkBlock) <= 80; }
 constexpr bool bwd_lo_reg_window(int R) { return 8 * (2 * R + kWalkBlock) <= 160; }
 // Radii whose horizontal windows are formed by whole-wave DPP lane shifts
