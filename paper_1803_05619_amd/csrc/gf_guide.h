@@ -408,35 +408,75 @@ __global__ __launch_bounds__(256) void guide_bwd_kernel(GBwdArgs a) {
     return;
   }
   const float* __restrict__ f = a.fold;
-  FoldRegs c;
-  load_fold(f, c);
-  const float slope = c.slope;
+  const float slope = f[FO_SCAL + 2];
   const float mx0 = f[FO_MEAN], mx1 = f[FO_MEAN + 1], mx2 = f[FO_MEAN + 2];
+  // The 112 folded constants are read from LDS inside the pixel loop
+  // (broadcast reads): held across the loop they exceed the scalar
+  // registers and were spilled to vector-register lanes, costing about 90
+  // lane reads per pixel.  Unit k: (w1f[k][0..2], bf[k]), (w2[0..2][k], 0).
+  __shared__ float4 cst[2 * kKP];
+  if (tid < kKP)
+    cst[2 * tid] = make_float4(f[FO_W1F + 3 * tid], f[FO_W1F + 3 * tid + 1],
+                               f[FO_W1F + 3 * tid + 2], f[FO_BF + tid]);
+  else if (tid < 2 * kKP)
+    cst[2 * (tid - kKP) + 1] = make_float4(f[FO_W2 + tid - kKP], f[FO_W2 + tid],
+                                           f[FO_W2 + kKP + tid], 0.f);
+  __syncthreads();
   float acc[AC_N];
 #pragma unroll
   for (int k = 0; k < AC_N; ++k) acc[k] = 0.f;
   const uint16_t* Mk = a.mask + (size_t)b * a.P;
-  for (long long p = (long long)blockIdx.x * 256 + tid; p < a.P; p += (long long)gridDim.x * 256) {
-    const float x0 = to_f(X[p]), x1 = to_f(X[a.P + p]), x2 = to_f(X[2 * a.P + p]);
-    const float d0 = dG[p], d1 = dG[a.P + p], d2 = dG[2 * a.P + p];
-    const unsigned mbits = Mk[p];
-    acc[AC_DG] += d0;
-    acc[AC_DG + 1] += d1;
-    acc[AC_DG + 2] += d2;
+  // two pixels per iteration (p and p + T), so that each constant read
+  // serves both; a missing second pixel contributes zero (dG := 0)
+  const long long T = (long long)gridDim.x * 256;
+  for (long long p = (long long)blockIdx.x * 256 + tid; p < a.P; p += 2 * T) {
+    const bool two = p + T < a.P;
+    const long long q = two ? p + T : p;
+    float x[2][3], d[2][3];
+    unsigned mb[2];
+    x[0][0] = to_f(X[p]);
+    x[0][1] = to_f(X[a.P + p]);
+    x[0][2] = to_f(X[2 * a.P + p]);
+    x[1][0] = to_f(X[q]);
+    x[1][1] = to_f(X[a.P + q]);
+    x[1][2] = to_f(X[2 * a.P + q]);
+    d[0][0] = dG[p];
+    d[0][1] = dG[a.P + p];
+    d[0][2] = dG[2 * a.P + p];
+    d[1][0] = two ? dG[q] : 0.f;
+    d[1][1] = two ? dG[a.P + q] : 0.f;
+    d[1][2] = two ? dG[2 * a.P + q] : 0.f;
+    mb[0] = Mk[p];
+    mb[1] = Mk[q];
+    // an offset the compiler cannot see through keeps the constant reads in
+    // the loop (hoisted, they would be held in registers again)
+    int coff = 0;
+    asm volatile("" : "+v"(coff));
+    const float4* cc = cst + coff;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      acc[AC_DG] += d[j][0];
+      acc[AC_DG + 1] += d[j][1];
+      acc[AC_DG + 2] += d[j][2];
+    }
 #pragma unroll
     for (int k = 0; k < kKP; ++k) {
-      const float y = c.bf[k] + c.w1f[k][0] * x0 + c.w1f[k][1] * x1 + c.w1f[k][2] * x2;
-      const bool pos = (mbits >> k) & 1u;
-      const float z = pos ? y : slope * y;
-      acc[AC_DGZ + k] += d0 * z;
-      acc[AC_DGZ + kKP + k] += d1 * z;
-      acc[AC_DGZ + 2 * kKP + k] += d2 * z;
-      const float dz = c.w2[0][k] * d0 + c.w2[1][k] * d1 + c.w2[2][k] * d2;
-      const float dy = pos ? dz : slope * dz;
-      acc[AC_DY + k] += dy;
-      acc[AC_DYX + 3 * k] += dy * (x0 - mx0);
-      acc[AC_DYX + 3 * k + 1] += dy * (x1 - mx1);
-      acc[AC_DYX + 3 * k + 2] += dy * (x2 - mx2);
+      const float4 u = cc[2 * k], v = cc[2 * k + 1];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const float y = u.w + u.x * x[j][0] + u.y * x[j][1] + u.z * x[j][2];
+        const bool pos = (mb[j] >> k) & 1u;
+        const float z = pos ? y : slope * y;
+        acc[AC_DGZ + k] += d[j][0] * z;
+        acc[AC_DGZ + kKP + k] += d[j][1] * z;
+        acc[AC_DGZ + 2 * kKP + k] += d[j][2] * z;
+        const float dz = v.x * d[j][0] + v.y * d[j][1] + v.z * d[j][2];
+        const float dy = pos ? dz : slope * dz;
+        acc[AC_DY + k] += dy;
+        acc[AC_DYX + 3 * k] += dy * (x[j][0] - mx0);
+        acc[AC_DYX + 3 * k + 1] += dy * (x[j][1] - mx1);
+        acc[AC_DYX + 3 * k + 2] += dy * (x[j][2] - mx2);
+      }
     }
   }
   // fixed-order reduction: within each wave by shuffles, then across the
