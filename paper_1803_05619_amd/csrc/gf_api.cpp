@@ -132,12 +132,13 @@ int make_plan(const gf_desc_t* d, const gf_guide_t* g, Plan* p, const char** why
   //  - high-res rows per apply thread: short walks keep DRAM streams
   //    sequential (8 measured best on MI355X for the 4 x 3 x 2048 x 3072
   //    workload): two low-res row blocks at S = 4, one at S = 8
-  //  - low-res rows per backward high-res block: 2 (short walks stream
-  //    best; the partial planes' extra border rows cost less)
+  //  - low-res rows per backward high-res wave: 2 for FP32 (short walks
+  //    stream best; at S >= 4 four waves stack into one partial block), 4
+  //    for the half types (one wave per workgroup: fewer partial rows)
   const int walk = r <= 2 ? 16 : r <= 4 ? 32 : 64;
   // the backward walker at small radii: 24 rows (4 waves per SIMD; 16-row
   // segments leave a second, mostly empty round of waves)
-  TuneVal tv{walk, r <= 2 ? 24 : walk, S >= 8 ? S : 8, 2};
+  TuneVal tv{walk, r <= 2 ? 24 : walk, S >= 8 ? S : 8, d->io_dtype == GF_F32 ? 2 : 4};
   TuneVal tuned;
   if (tune_lookup(TuneKey{d->io_dtype, S, r, gmode, d->mean_ab}, &tuned)) tv = tuned;
   if (env_int("GF_LO_ROWS", 0) > 0) tv.coTR = tv.loTR = env_int("GF_LO_ROWS", 0);

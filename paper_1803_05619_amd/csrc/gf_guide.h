@@ -352,7 +352,7 @@ __global__ __launch_bounds__(256) void guide_map_transform_kernel(MapArgs a) {
       float x[3][4], g[3][4];
       unsigned bits[4];
 #pragma unroll
-      for (int i = 0; i < 3; ++i) load_vec<TX, 4>(X + i * a.P + 4 * v, x[i]);
+      for (int i = 0; i < 3; ++i) load_vec_nt<TX, 4>(X + i * a.P + 4 * v, x[i]);
       transform_px<4>(c, x, g, bits);
       *reinterpret_cast<uint2*>(M + 4 * v) =
           make_uint2(bits[0] | (bits[1] << 16), bits[2] | (bits[3] << 16));
