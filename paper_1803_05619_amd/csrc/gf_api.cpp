@@ -140,7 +140,26 @@ int make_plan(const gf_desc_t* d, const gf_guide_t* g, Plan* p, const char** why
   // segments leave a second, mostly empty round of waves)
   TuneVal tv{walk, r <= 2 ? 24 : walk, S >= 8 ? S : 8, d->io_dtype == GF_F32 ? 2 : 4};
   TuneVal tuned;
-  if (tune_lookup(TuneKey{d->io_dtype, S, r, gmode, d->mean_ab}, &tuned)) tv = tuned;
+  if (tune_lookup(TuneKey{d->io_dtype, S, r, gmode, d->mean_ab}, &tuned)) {
+    tv = tuned;
+  } else if (r <= 2) {
+    // small problems (latency-bound launches): shorter walks spread the
+    // low-res walkers and the apply threads over more of the chip, down to
+    // 4 rows (a quarter of the default) while fewer than 1024 waves or 256
+    // apply workgroups would run
+    const long long planes = (long long)d->n * d->c;
+    const int hal_c = d->mean_ab ? 2 * r : r;
+    const long long nx_c = (d->w_lo + (64 - 2 * hal_c) - 1) / (64 - 2 * hal_c);
+    const long long nx_l = (d->w_lo + (64 - 4 * r) - 1) / (64 - 4 * r);
+    auto waves = [&](long long nx, int tr) { return nx * ((d->h_lo + tr - 1) / tr) * planes; };
+    while (tv.coTR > 4 && waves(nx_c, tv.coTR) < 1024) tv.coTR /= 2;
+    while (tv.loTR > 6 && waves(nx_l, tv.loTR) < 1024) tv.loTR /= 2;
+    const long long vec = d->w_hi % 4 == 0 ? 4 : 1;
+    auto apply_wgs = [&](int rb) {
+      return planes * ((d->h_hi + rb - 1) / rb) * (d->w_hi / vec) / 256;
+    };
+    while (tv.RB > S && apply_wgs(tv.RB) < 256) tv.RB /= 2;
+  }
   if (env_int("GF_LO_ROWS", 0) > 0) tv.coTR = tv.loTR = env_int("GF_LO_ROWS", 0);
   if (env_int("GF_BWD_LO_ROWS", 0) > 0) tv.loTR = env_int("GF_BWD_LO_ROWS", 0);
   if (env_int("GF_APPLY_ROWS", 0) > 0) tv.RB = env_int("GF_APPLY_ROWS", 0);
