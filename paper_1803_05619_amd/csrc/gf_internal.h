@@ -105,14 +105,19 @@ constexpr bool coef_reg_window(int R) { return 4 * (2 * R + kWalkBlock) <= 80; }
 constexpr bool bwd_lo_reg_window(int R) { return 8 * (2 * R + kWalkBlock) <= 160; }
 // Radii whose horizontal windows are formed by whole-wave DPP lane shifts
 // (R shifts each way) rather than through LDS row buffers: with vertical
-// windows in registers as well, such walkers use no LDS at all.
-constexpr bool lane_dpp(int R) { return R <= 2; }
+// windows in registers as well, such walkers use no LDS at all.  Measured
+// on the uneven batch's r = 4 class: the backward 1,054 -> 966 us with DPP,
+// the coefficients 373 -> 468 us (their horizontal work is mostly the
+// statistics' deviations, which need every neighbour value), so the
+// coefficient walker keeps LDS rows above r = 2.
+constexpr bool coef_lane_dpp(int R) { return R <= 2; }
+constexpr bool bwd_lo_lane_dpp(int R) { return R <= 4; }
 constexpr size_t coef_lds_bytes(int R) {
-  return 64 * ((lane_dpp(R) ? 0 : 24 * kWalkBlock) +
+  return 64 * ((coef_lane_dpp(R) ? 0 : 24 * kWalkBlock) +
                (coef_reg_window(R) ? 0 : 16 * walker_ring_rows(R, kWalkBlock, kCoefRingPow2Max)));
 }
 constexpr size_t bwd_lo_lds_bytes(int R) {
-  return 64 * ((lane_dpp(R) ? 0 : 40 * kWalkBlock) +
+  return 64 * ((bwd_lo_lane_dpp(R) ? 0 : 40 * kWalkBlock) +
                (bwd_lo_reg_window(R) ? 0
                                      : 32 * walker_ring_rows(R, kWalkBlock, kBwdLoRingPow2Max)));
 }

@@ -452,7 +452,7 @@ __device__ __forceinline__ void coef_body(const CoefArgs& a, const int bx, const
   constexpr int TWo = 64 - 2 * HAL;
   constexpr int KR = walker_ring_rows(R, kPF, kCoefRingPow2Max);
   constexpr bool REG = coef_reg_window(R);
-  constexpr bool DPP = lane_dpp(R);
+  constexpr bool DPP = coef_lane_dpp(R);
   constexpr int NW = 2 * R + kPF;
   extern __shared__ float4 lds4[];
   // LDS when the horizontal windows do not use DPP: [kPF][64] column
@@ -1224,7 +1224,7 @@ __device__ __forceinline__ void bwd_lo_body(const BwdLoArgs& a, const int bx, co
   constexpr int TWo = 64 - 4 * R;
   constexpr int KR = walker_ring_rows(R, kPF, kBwdLoRingPow2Max);
   constexpr bool REG = bwd_lo_reg_window(R);
-  constexpr bool DPP = lane_dpp(R);
+  constexpr bool DPP = bwd_lo_lane_dpp(R);
   constexpr int NW = 2 * R + kPF;
   extern __shared__ float4 lds4[];
   // LDS when the horizontal windows do not use DPP: [kPF][64] column
