@@ -57,6 +57,8 @@ FAKE = 0x10000  # aligned, never dereferenced: every case below fails validation
     (dict(h_hi=192, w_hi=288), gf.GF_ERR_UNSUPPORTED),    # factor 3
     (dict(h_hi=128), gf.GF_ERR_UNSUPPORTED),              # different factors per axis
     (dict(r=40), gf.GF_ERR_UNSUPPORTED),
+    # a low-res plane above 2^31 bytes (the walkers' 32-bit buffer offsets)
+    (dict(h_lo=24000, w_lo=24000, h_hi=24000, w_hi=24000), gf.GF_ERR_UNSUPPORTED),
 ])
 def test_invalid_descriptions(kw, code):
     d = desc(**kw)
