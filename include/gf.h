@@ -196,7 +196,7 @@ void gf_plan_destroy(gf_plan_t *plan);
 /* ------------------------------------------------------------- autotuner
  * Times the candidate launch shapes of the four filter kernels (rows per
  * low-res walker wave, high-res rows per apply thread, low-res rows per
- * backward high-res block) on the caller's buffers, `iters` launches each,
+ * backward high-res wave) on the caller's buffers, `iters` launches each,
  * and keeps the fastest per kernel in a process-wide table keyed by
  * (io_dtype, factor, radius, guide mode, mean_ab).  Later plans for that
  * key (gf_forward, gf_backward, gf_plan_create) use the table.  Arguments
