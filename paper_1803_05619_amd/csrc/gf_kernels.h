@@ -1522,19 +1522,19 @@ __global__ __launch_bounds__(64) void bwd_lo_kernel(BwdLoArgs a) {
 __global__ __launch_bounds__(256) void eps_reduce_kernel(const float* part, int per_plane,
                                                           int c, int n, int eps_count,
                                                           float* deps) {
-  __shared__ float red[256];
+  // fixed order: strided per-thread sums, a shuffle tree per wave, then the
+  // four waves' sums in wave order
+  __shared__ float red[4];
   const int k = blockIdx.x;
   const size_t lo = (size_t)(eps_count == 1 ? 0 : k * c) * per_plane;
   const size_t hi = (size_t)(eps_count == 1 ? n * c : (k + 1) * c) * per_plane;
   float s = 0.f;
   for (size_t q = lo + threadIdx.x; q < hi; q += 256) s += part[q];
-  red[threadIdx.x] = s;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
-  for (int st = 128; st > 0; st >>= 1) {
-    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) deps[k] = red[0];
+  if (threadIdx.x == 0) deps[k] = ((red[0] + red[1]) + red[2]) + red[3];
 }
 
 // ------------------------------------------------------------ batched (multi-problem) kernels
@@ -1625,18 +1625,16 @@ __global__ __launch_bounds__(64) void bwd_lo_multi_kernel(MultiLaunch m) {
 
 // One workgroup per item with a deps output: fixed-order sum of its partials.
 __global__ __launch_bounds__(256) void eps_multi_kernel(const EpsItem* items, char* ws) {
-  __shared__ float red[256];
+  __shared__ float red[4];  // same order as eps_reduce_kernel
   const EpsItem it = items[blockIdx.x];
   const float* part = rebase(ws, it.part);
   float s = 0.f;
   for (long long q = threadIdx.x; q < it.count; q += 256) s += part[q];
-  red[threadIdx.x] = s;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
-  for (int st = 128; st > 0; st >>= 1) {
-    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) *it.deps = red[0];
+  if (threadIdx.x == 0) *it.deps = ((red[0] + red[1]) + red[2]) + red[3];
 }
 
 // ------------------------------------------------------------ dispatch
