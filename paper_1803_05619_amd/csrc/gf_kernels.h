@@ -4,21 +4,24 @@
 // gf_bf16.hip, which instantiate the launchers for that type.
 //
 // Forward (Sec. III-B/C, Eq. (1)-(2)):
-//   coef_kernel   low-res tile in LDS: box statistics of the recentred guide
-//                 and input, A = cov/(var+eps), b = mean_p - A mean_I, then
-//                 their window means; writes Abar, bbar (low-res, fp32).
+//   coef_kernel   low-res column walker: box statistics of the recentred
+//                 guide and input, A = cov/(var+eps), b = mean_p - A mean_I,
+//                 then their window means; writes Abar, bbar (low-res, fp32).
 //   apply_kernel  streams the high-res guide: bilinear Abar/bbar taps are
 //                 blended in registers (never stored at high resolution) and
-//                 q = A_h G_h + b_h is written with non-temporal stores.
+//                 q = A_h G_h + b_h is written; non-temporal loads and stores.
 // Backward (Algorithm 1, plus the adjoint of the A/b window mean):
-//   coef_kernel   recomputes Abar.
-//   bwd_hi_kernel one wave per high-res block: dI_h = dq A_h, and the
-//                 transposed bilinear of dq G_h and dq accumulated first
-//                 vertically in registers, then horizontally through LDS,
-//                 into per-block partial low-res planes (no atomics).
-//   bwd_lo_kernel low-res tile: gathers the partial planes, recomputes the
-//                 box statistics and runs the adjoint chain; f_mu^T(y) is the
-//                 box SUM of y/N.  Writes dI_l, dp_l and per-tile deps partials.
+//   coef_kernel   recomputes Abar (and bbar when the forward runs too).
+//   bwd_hi_kernel one wave per band of high-res rows (stacked four to a
+//                 workgroup for FP32 at S >= 4): dI_h = dq A_h (and q in the
+//                 fused pass), and the transposed bilinear of dq G_h and dq
+//                 accumulated vertically in registers, then horizontally by
+//                 lane shuffles or through LDS, into partial low-res planes
+//                 per block (no atomics).
+//   bwd_lo_kernel low-res column walker: gathers the partial planes,
+//                 recomputes the box statistics and runs the adjoint chain;
+//                 f_mu^T(y) is the box SUM of y/N.  Writes dI_l, dp_l and
+//                 per-segment deps partials.
 //   eps_reduce_kernel  fixed-order sum of the deps partials.
 // All reductions run in a fixed order, so results are bitwise reproducible.
 
@@ -281,13 +284,14 @@ __device__ __forceinline__ RowW row_weights_ac(int y, int i, int h, int H) {
 //
 // The low-res kernels run one wave per strip of 64 adjacent columns (one
 // lane per column) and walk down a segment of rows, kPF rows per block.
-// Vertical windows live in per-wave LDS ring buffers (each lane only touches
-// its own column); horizontal windows read the neighbouring lanes' entries
-// of a row buffer after a wave-level sync.  Global rows are fetched one block
-// ahead.  Everything that depends on the radius is a compile-time constant,
-// so the window loops unroll and LDS reads use immediate offsets.  Pixels
-// outside the image are stored as zeros and excluded from every window by
-// explicit row/column masks (window sums run over the in-image part only).
+// Vertical windows live in registers (radii up to 8) or in per-wave LDS
+// ring buffers (each lane only touches its own column); horizontal windows
+// take the neighbouring lanes' values by DPP lane shifts (small radii) or
+// from a row buffer in LDS after a wave-level sync.  Global rows are fetched
+// one block ahead.  Everything that depends on the radius is a compile-time
+// constant, so the window loops unroll.  Pixels outside the image are stored
+// as zeros and excluded from every window by explicit row/column masks
+// (window sums run over the in-image part only).
 //
 // Window statistics are computed in two levels so that no step subtracts two
 // large, nearly equal numbers (the law of total variance over the window's
