@@ -469,8 +469,8 @@ def main():
                          "reference for hardware byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the layer's "
-              "multi-GPU split is a design note, not part of this build.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the layer "
+              "has no multi-GPU path.", file=sys.stderr)
         sys.exit(2)
 
     import torch
