@@ -133,12 +133,14 @@ int make_plan(const gf_desc_t* d, const gf_guide_t* g, Plan* p, const char** why
   //    sequential (8 measured best on MI355X for the 4 x 3 x 2048 x 3072
   //    workload): two low-res row blocks at S = 4, one at S = 8
   //  - low-res rows per backward high-res wave: 2 for FP32 (short walks
-  //    stream best; at S >= 4 four waves stack into one partial block), 4
+  //    stream best; at S >= 4 four waves stack into one partial block), 8
   //    for the half types (one wave per workgroup: fewer partial rows)
+  //  - the backward walker at r > 4: 128 rows (its 4r-row warm-up)
   const int walk = r <= 2 ? 16 : r <= 4 ? 32 : 64;
   // the backward walker at small radii: 24 rows (4 waves per SIMD; 16-row
   // segments leave a second, mostly empty round of waves)
-  TuneVal tv{walk, r <= 2 ? 24 : walk, S >= 8 ? S : 8, d->io_dtype == GF_F32 ? 2 : 4};
+  TuneVal tv{walk, r <= 2 ? 24 : r <= 4 ? walk : 128, S >= 8 ? S : 8,
+             d->io_dtype == GF_F32 ? 2 : 8};
   TuneVal tuned;
   if (tune_lookup(TuneKey{d->io_dtype, S, r, gmode, d->mean_ab}, &tuned)) {
     tv = tuned;
