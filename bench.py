@@ -30,8 +30,17 @@ Prints ONE JSON line:
                against the 8 TB/s HBM peak; `traffic` is the HBM
                bytes per launch measured with rocprofv3 counters (workload 1,
                from the committed summary; null when the kernel changed since)
+  timing_ms    per-step median/p10/p90 from HIP events around each step,
+               warm (back to back) and cold (a 512 MB buffer written before
+               every step, outside its events, to flush L2 and the MALL)
+  peak_mem_bytes  torch's peak device allocation over the timed steps
+               (inputs, outputs and workspace)
+  separate_calls  the step as gf_forward then gf_backward
+  autograd_step   the step through the torch.autograd.Function (what a
+               training loop calls: gf_forward, then gf_backward)
   plain        the unfused PyTorch composition (autograd) on the same GPU
-  cpu_baseline the FP64 CPU oracle on the host cores (bounded sample)
+  cpu_baseline the FP64 CPU oracle on the host cores (bounded sample), the
+               host CPU model, and a 1-thread rate on one image
   error_vs_fp64_oracle  errors of this run's outputs on that sample
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload N]
@@ -47,7 +56,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-KERNEL_SRC = os.path.join(ROOT, "paper_1803_05619_amd", "csrc", "gf_kernels.h")
+KERNEL_SRC_DIRS = (os.path.join(ROOT, "paper_1803_05619_amd", "csrc"), os.path.join(ROOT, "include"))
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_fp32_4x3x2048x3072.txt")
 METRIC = "high-res Mpixel/s fwd+bwd, fused vs plain at stated max-abs error; % HBM peak"
 DATA = "synthetic (seeded photo-like images: smooth field + step edges + noise)"
@@ -59,7 +68,16 @@ def log(msg):
 
 
 def kernel_hash():
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    """sha256[:16] over every source of the HIP library (csrc/ and include/,
+    in name order): a traffic figure measured on other sources is stale."""
+    h = hashlib.sha256()
+    for d in KERNEL_SRC_DIRS:
+        for name in sorted(os.listdir(d)):
+            path = os.path.join(d, name)
+            if os.path.isfile(path) and name.endswith((".h", ".hip", ".cpp")):
+                h.update(name.encode())
+                h.update(open(path, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def identity_bytes(n, c, H, W, h, w, b, with_dI=True):
@@ -74,24 +92,32 @@ def identity_bytes(n, c, H, W, h, w, b, with_dI=True):
     }
 
 
-def oracle_errors(got, ref):
-    """Errors as in the parity tests: q absolute; gradients scaled by
-    max(1, max |ref|); deps and the guide parameters' gradients (sums over
-    pixels) by max(1, sum of the magnitudes of their terms)."""
+def oracle_errors(got, ref, hidden=None):
+    """Errors as in the parity tests: q absolute; per-pixel gradients scaled
+    by max(1, max |ref|); deps relative to |ref| and to the sum of the
+    magnitudes of its terms; the guide parameters' gradients relative to the
+    largest gradient of their group (W1, W2, lam, mu, gamma, beta) and to
+    the magnitude sums of their terms."""
     import numpy as np
     err = {}
     if "q" in got:
         err["q_max_abs"] = float(np.abs(got["q"] - ref["q"]).max())
-    if "dguide" in got:
-        err["dguide_scaled"] = float((np.abs(got["dguide"] - ref["dguide"]) /
-                                      np.maximum(1.0, ref["dguide_abs"])).max())
     for k in ("dI_lo", "dp_lo", "dI_hi"):
         if k in got and k in ref:
             err[k + "_scaled"] = float(np.abs(got[k] - ref[k]).max() /
                                        max(1.0, np.abs(ref[k]).max()))
     if "deps" in got:
-        err["deps_scaled"] = float((np.abs(got["deps"] - ref["deps"]) /
-                                    np.maximum(1.0, ref["deps_abs"])).max())
+        d = np.abs(got["deps"] - ref["deps"])
+        err["deps_rel"] = float((d / np.maximum(np.abs(ref["deps"]), 1e-300)).max())
+        err["deps_sum_scaled"] = float((d / np.maximum(ref["deps_abs"], 1e-300)).max())
+    if "dguide" in got:
+        import oracle
+        d = np.abs(got["dguide"] - ref["dguide"])
+        err["dguide_sum_scaled"] = float((d / np.maximum(ref["dguide_abs"], 1e-300)).max())
+        dg = oracle.guide_grad_split(d, 3, 3, hidden)
+        rg = oracle.guide_grad_split(ref["dguide"], 3, 3, hidden)
+        err["dguide_group_rel"] = max(float(np.max(dg[g])) / max(float(np.abs(rg[g]).max()), 1e-300)
+                                      for g in ("w1", "w2", "lam", "mu", "gamma", "beta"))
     return err
 
 
@@ -186,11 +212,31 @@ def identity_workload(args, dev, prob, dt, name):
                 f"the full {n}-image batch, fwd+bwd, repeated {reps}x ({el:.1f} s); parallel "
                 f"over the {n * c} image planes", n * c, oracle_errors(got, ref))
 
+    def cpu_one():
+        import oracle
+        args1 = [prob[k][:1].double().numpy() for k in ("I_lo", "p_lo", "I_hi")]
+        t0 = time.perf_counter()
+        oracle.forward(*args1, r, prob["eps"][:1])
+        oracle.backward(*args1, r, prob["eps"][:1], prob["dq"][:1].double().numpy())
+        return H * W / 1e6, time.perf_counter() - t0, "image 0 of the batch, fwd+bwd once"
+
     def tune():
         gf.autotune(t["I_lo"], t["p_lo"], t["I_hi"], eps, t["dq"], r=r, iters=5)
 
+    # the layer as a training step would call it: the autograd function's
+    # forward (gf_forward) and backward (gf_backward, recomputing the
+    # coefficients), gradients to every input
+    leaves = [t[k].clone().requires_grad_(True) for k in ("I_lo", "p_lo", "I_hi")]
+    eps_leaf = eps.clone().requires_grad_(True)
+
+    def autograd_step():
+        for x in leaves + [eps_leaf]:
+            x.grad = None
+        gf.guided_filter(*leaves, r=r, eps=eps_leaf).backward(t["dq"])
+
     return dict(step=step, separate_step=separate_step, plain_step=plain_step,
-                cpu_sample=cpu_sample, mpx=n * H * W / 1e6, tune=tune,
+                cpu_sample=cpu_sample, cpu_one=cpu_one, autograd_step=autograd_step,
+                mpx=n * H * W / 1e6, tune=tune,
                 per_step=per_step, step_bytes=step_bytes, dtype=dt,
                 config={"workload": name, "n": n, "c": c, "H": H, "W": W, "s": prob["s"], "r": r,
                         "eps": float(prob["eps"][0])},
@@ -282,13 +328,35 @@ def workload_2(args, dev):
         return (n * H * W / 1e6 * reps, el,
                 f"the full {n}-image batch, fwd+bwd with the guide, repeated {reps}x "
                 f"({el:.1f} s); parallel over the {n * c} image planes", n * c,
-                oracle_errors(got, ref))
+                oracle_errors(got, ref, K))
 
     def tune():
         gf.autotune(t["I_lo"], t["p_lo"], t["I_hi"], eps, t["dq"], r=r, iters=5, guide=g_fwd)
 
+    def cpu_one():
+        import oracle
+        args1 = [prob[k][:1].double().numpy() for k in ("I_lo", "p_lo", "I_hi")]
+        t0 = time.perf_counter()
+        oracle.forward(*args1, r, prob["eps"], guide=gp)
+        oracle.backward(*args1, r, prob["eps"], prob["dq"][:1].double().numpy(), guide=gp)
+        return (H * W / 1e6, time.perf_counter() - t0,
+                "image 0 alone (its own batch statistics), fwd+bwd with the guide once")
+
+    # autograd step: gradients to p_l, eps and the guide parameters
+    params_leaf = params.clone().requires_grad_(True)
+    p_leaf = t["p_lo"].clone().requires_grad_(True)
+    eps_leaf = eps.clone().requires_grad_(True)
+    g_ag = gf.Guide(gf.GF_GUIDE_TRANSFORM, 3, K, params_leaf, gp["bn_eps"], gp["slope"])
+
+    def autograd_step():
+        for x in (params_leaf, p_leaf, eps_leaf):
+            x.grad = None
+        gf.guided_filter(t["I_lo"], p_leaf, t["I_hi"], r=r, eps=eps_leaf,
+                         guide=g_ag).backward(t["dq"])
+
     return dict(step=step, separate_step=separate_step, plain_step=plain_step,
-                cpu_sample=cpu_sample, mpx=n * H * W / 1e6, tune=tune,
+                cpu_sample=cpu_sample, cpu_one=cpu_one, autograd_step=autograd_step,
+                mpx=n * H * W / 1e6, tune=tune,
                 per_step=per_step, step_bytes=step_bytes, dtype="bf16",
                 config={"workload": "trainable-guide guided filtering fwd+bwd, BF16 I/O + FP32 "
                                     "accumulate, 8x3x1536x2048 <- 384x512 (s=4), r=1, eps=1e-8, "
@@ -299,13 +367,8 @@ def workload_2(args, dev):
                 traffic_ok=False)
 
 
-def _gen_item(spec):
-    from paper_1803_05619_amd import datagen
-    return datagen.batched_item(spec)
-
-
 def workload_3(args, dev):
-    import multiprocessing as mp
+    from concurrent.futures import ThreadPoolExecutor
 
     import torch
 
@@ -314,8 +377,10 @@ def workload_3(args, dev):
     log(f"generating workload 3 ({len(specs)} uneven images)")
     probs = [None] * len(specs)
     workers = max(1, min(16, len(os.sched_getaffinity(0))))
-    with mp.get_context("spawn").Pool(workers) as pool:
-        for k, p in enumerate(pool.imap(_gen_item, specs)):
+    # threads in this process (numpy and torch release the GIL in the bulk
+    # work): no child processes, which a profiler would attach to as well
+    with ThreadPoolExecutor(workers) as pool:
+        for k, p in enumerate(pool.map(datagen.batched_item, specs)):
             probs[k] = p
             if (k + 1) % 8 == 0:
                 log(f"  {k + 1}/{len(specs)} images")
@@ -387,7 +452,18 @@ def workload_3(args, dev):
     def eager_step():
         plan.run(gf.GF_RUN_FORWARD | gf.GF_RUN_BACKWARD, graph=False)
 
+    def cpu_one():
+        import oracle
+        p = probs[0]
+        args_np = [p[x].double().numpy() for x in ("I_lo", "p_lo", "I_hi")]
+        t0 = time.perf_counter()
+        oracle.forward(*args_np, p["r"], p["eps"])
+        oracle.backward(*args_np, p["r"], p["eps"], p["dq"].double().numpy())
+        return (p["H"] * p["W"] / 1e6, time.perf_counter() - t0,
+                f"image 0 ({p['H']}x{p['W']}, s={p['s']}, r={p['r']}), fwd+bwd once")
+
     return dict(step=step, eager_step=eager_step, plain_step=plain_step, cpu_sample=cpu_sample,
+                cpu_one=cpu_one,
                 mpx=mpx, per_step=per_step, step_bytes=step_bytes, dtype="f32",
                 config={"workload": f"batched uneven guided filtering fwd+bwd, FP32, "
                                     f"{len(probs)} images H,W in [512,3072], s in {{2,4,8}}, "
@@ -435,7 +511,17 @@ def workload_0(args, dev):
                 f"the 1-image forward repeated {reps}x ({el:.2f} s)", n * c,
                 oracle_errors({"q": q.double().cpu().numpy()}, ref))
 
-    return dict(step=step, plain_step=plain_step, cpu_sample=cpu_sample, mpx=n * H * W / 1e6,
+    def cpu_one():
+        import oracle
+        args_np = [prob[k].double().numpy() for k in ("I_lo", "p_lo", "I_hi")]
+        reps, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < 1.0:
+            oracle.forward(*args_np, r, prob["eps"])
+            reps += 1
+        return n * H * W / 1e6 * reps, time.perf_counter() - t0, f"the forward, {reps}x"
+
+    return dict(step=step, plain_step=plain_step, cpu_sample=cpu_sample, cpu_one=cpu_one,
+                mpx=n * H * W / 1e6,
                 per_step={"gf_coef": kb["coef"], "gf_apply": kb["apply"]},
                 step_bytes=kb["coef"] + kb["apply"], dtype="f32",
                 config={"workload": "guided filtering layer forward only, FP32, 1x3x256x256 <- "
@@ -445,6 +531,33 @@ def workload_0(args, dev):
 
 
 WORKLOADS = {0: workload_0, 1: workload_1, 2: workload_2, 3: workload_3, 4: workload_4}
+
+
+def flush_buffer(dev):
+    import torch
+    return torch.empty(512 << 20, dtype=torch.uint8, device=dev)
+
+
+def step_stats(step, iters, flush):
+    """Median, p10 and p90 (ms) of `iters` steps, each between two HIP events
+    recorded on the current stream (the stream the library launches on);
+    with `flush`, that buffer is written before each step, outside its
+    events."""
+    import torch
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(iters)]
+    for k, (a, b) in enumerate(ev):
+        if flush is not None:
+            flush.fill_(k & 255)
+        a.record()
+        step()
+        b.record()
+    torch.cuda.synchronize()
+    ts = sorted(a.elapsed_time(b) for a, b in ev)
+
+    def pct(q):
+        return round(ts[min(len(ts) - 1, int(q * (len(ts) - 1) + 0.5))], 4)
+    return {"median": pct(0.5), "p10": pct(0.1), "p90": pct(0.9), "iters": iters}
 
 
 def main():
@@ -460,6 +573,8 @@ def main():
                          "0: the planner's default shapes; default: 1 for workload 3 (the "
                          "uneven batch), 0 otherwise (the defaults are the tuned shapes of "
                          "workload 1)")
+    ap.add_argument("--timing-iters", type=int, default=50,
+                    help="steps per event-timed pass (warm, and cold after a 512 MB flush)")
     ap.add_argument("--plain-steps", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
@@ -495,6 +610,7 @@ def main():
         log("tuned shapes: " + gf.gf_tune_export().strip().replace("\n", "; "))
 
     log(f"warmup {args.warmup} steps")
+    torch.cuda.reset_peak_memory_stats(dev)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -508,7 +624,15 @@ def main():
     sec = t1 - t0
     value = wl["mpx"] * args.steps / sec
     ms_per_step = 1e3 * sec / args.steps
+    peak_mem = torch.cuda.max_memory_allocated(dev)
     log(f"fused: {ms_per_step:.4f} ms/step, {value:.1f} Mpx/s")
+    # per-step times: HIP events around each step on the launch stream, warm
+    # (steps back to back) and cold (a 512 MB buffer written before each
+    # step, outside the events, so the 256 MB MALL and the L2s hold none of
+    # the step's data)
+    timing = {"warm": step_stats(step, args.timing_iters, None),
+              "cold": step_stats(step, args.timing_iters, flush_buffer(dev))}
+    log(f"per-step ms: warm {timing['warm']}, cold (flushed) {timing['cold']}")
     # a step is its own launch sequence; per call in microseconds as well
     us_per_step = 1e3 * ms_per_step
     # the kernel breakdown: the same steps again with a HIP event pair
@@ -569,9 +693,26 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": wl["dtype"],
         "us_per_step": round(us_per_step, 2),
         "data": DATA, "config": wl["config"], "roofline": roofline,
+        "timing_ms": timing, "peak_mem_bytes": int(peak_mem),
         "step_algo_GBs": round(step_gbs, 1), "kernels": kernels,
         "profiled_pass_ms_per_step": round(prof_ms_per_step, 4),
     }
+    if "autograd_step" in wl:
+        # the layer through its torch.autograd.Function: gf_forward, then
+        # gf_backward when autograd reaches it
+        for _ in range(3):
+            wl["autograd_step"]()
+        torch.cuda.synchronize()
+        a0 = time.perf_counter()
+        for _ in range(args.steps):
+            wl["autograd_step"]()
+        torch.cuda.synchronize()
+        ag_ms = 1e3 * (time.perf_counter() - a0) / args.steps
+        out["autograd_step"] = {"ms_per_step": round(ag_ms, 4),
+                                "value": round(wl["mpx"] / (ag_ms * 1e-3), 1),
+                                "warm_ms": step_stats(wl["autograd_step"], args.timing_iters,
+                                                      None)}
+        log(f"autograd step: {ag_ms:.4f} ms/step")
     if "separate_step" in wl:
         # the same step as separate gf_forward and gf_backward calls (the
         # backward recomputing the coefficients), for comparison
@@ -617,14 +758,34 @@ def plain_leg(args, wl, value):
 def cpu_leg(args, wl):
     """The FP64 oracle on the host cores over a bounded sample, and the
     error of the timed run's final outputs on that sample."""
+    import oracle
     log("CPU oracle leg (FP64, host cores)")
     mpx, el, sample, planes, err = wl["cpu_sample"]()
     threads = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
     cores = min(threads, planes)
     cpu = {"value": round(mpx / el, 3), "unit": "Mpixel/s", "cores": cores, "kind": "oracle",
-           "sample": f"{sample}; OpenMP over planes ({threads} threads available)"}
+           "sample": f"{sample}; OpenMP over planes ({threads} threads available)",
+           "cpu_model": cpu_model(), "nproc": len(os.sched_getaffinity(0))}
+    if "cpu_one" in wl:
+        oracle.set_threads(1)
+        try:
+            mpx1, el1, sample1 = wl["cpu_one"]()
+        finally:
+            oracle.set_threads(threads)
+        cpu["one_core"] = {"value": round(mpx1 / el1, 3), "unit": "Mpixel/s",
+                           "sample": f"{sample1} ({el1:.1f} s) on 1 thread"}
     log(f"cpu oracle: {cpu['value']} Mpx/s; errors {err}")
     return cpu, {k: float(f"{v:.3e}") for k, v in err.items()}
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 if __name__ == "__main__":

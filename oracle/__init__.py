@@ -50,6 +50,7 @@ class _Guide(ctypes.Structure):
         ("beta", ctypes.POINTER(ctypes.c_double)),
         ("bn_eps", ctypes.c_double),
         ("slope", ctypes.c_double),
+        ("flip_delta", ctypes.c_double),
     ]
 
 
@@ -72,8 +73,15 @@ def _load():
         lib.gfo_guide_preact.restype = ci
         lib.gfo_guide_grad_size.argtypes = [ci, ci, ci]
         lib.gfo_guide_grad_size.restype = ctypes.c_long
+        lib.gfo_set_threads.argtypes = [ci]
+        lib.gfo_set_threads.restype = None
         _lib = lib
     return _lib
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of the oracle's following calls."""
+    _load().gfo_set_threads(int(n))
 
 
 def _f64(a) -> np.ndarray:
@@ -96,7 +104,7 @@ def _guide_struct(guide, keep):
     g = _Guide(hidden, _ptr(arrs["w1"]), _ptr(arrs["w2"]), _ptr(arrs["b2"]),
                float(guide["lam"]), float(guide["mu"]), _ptr(arrs["gamma"]),
                _ptr(arrs["beta"]), float(guide.get("bn_eps", 1e-5)),
-               float(guide.get("slope", 0.2)))
+               float(guide.get("slope", 0.2)), float(guide.get("flip_delta", 0.0)))
     return g
 
 

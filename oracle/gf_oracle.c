@@ -45,6 +45,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #include "gf_oracle.h"
 
@@ -77,6 +80,18 @@ static void bilinear_tap(int d, int D, int S, int align_corners,
 /* ------------------------------------------------------------------ */
 /* guidance transform F                                                */
 /* ------------------------------------------------------------------ */
+
+/* Branch of the leaky ReLU taken at pre-activation y: the positive branch
+ * for y > 0 (derivative 1), the negative one otherwise (derivative slope).
+ * With flip_delta > 0 every y with |y| < flip_delta takes the other branch,
+ * in the forward and the backward alike: there the branch is not fixed by
+ * any finite-precision evaluation of y, and both choices give a valid
+ * gradient (of the function that takes that branch), which tests use. */
+static int lrelu_positive(const gfo_guide_t *g, double y) {
+  int pos = y > 0.0;
+  if (g->flip_delta > 0.0 && fabs(y) < g->flip_delta) pos = !pos;
+  return pos;
+}
 
 /* Saved per-call state of the transform (needed by its backward). */
 typedef struct {
@@ -157,7 +172,7 @@ static int guide_forward(int mode, const gfo_guide_t *g, int n, int cin,
         double h = st->hpre[((long)b * K + k) * P + p];
         double hn = (h - st->mean[k]) * st->rstd[k];
         double y = g->lam * h + g->mu * (g->gamma[k] * hn + g->beta[k]);
-        z[k] = (y > 0.0) ? y : g->slope * y;
+        z[k] = lrelu_positive(g, y) ? y : g->slope * y;
       }
       for (int co = 0; co < cout; ++co) {
         double s = g->b2[co];
@@ -247,7 +262,8 @@ static int guide_backward(int mode, const gfo_guide_t *g, int n, int cin,
         double hn = (h - st->mean[k]) * st->rstd[k];
         double bn = g->gamma[k] * hn + g->beta[k];
         double y = g->lam * h + g->mu * bn;
-        double z = (y > 0.0) ? y : g->slope * y;
+        const int pos = lrelu_positive(g, y);
+        double z = pos ? y : g->slope * y;
         double dz = 0.0;
         for (int co = 0; co < cout; ++co) {
           double dg = dG[((long)b * cout + co) * P + p];
@@ -255,7 +271,7 @@ static int guide_backward(int mode, const gfo_guide_t *g, int n, int cin,
           aw2[co * K + k] += fabs(dg * z);
           dz += g->w2[co * K + k] * dg;
         }
-        double dyv = (y > 0.0) ? dz : g->slope * dz;
+        double dyv = pos ? dz : g->slope * dz;
         *dlam += dyv * h;
         *dmu += dyv * bn;
         double dbn = g->mu * dyv;
@@ -413,6 +429,14 @@ static int guide_cout_ok(int mode, int cin, int c, const gfo_guide_t *gd) {
 /* ------------------------------------------------------------------ */
 /* public entry points                                                 */
 /* ------------------------------------------------------------------ */
+
+void gfo_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
 
 long gfo_guide_grad_size(int cin, int cout, int hidden) {
   return (long)hidden * cin + (long)cout * hidden + cout + 2 + 2L * hidden;

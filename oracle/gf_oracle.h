@@ -37,7 +37,13 @@ typedef struct {
   const double *beta;  /* [hidden]                                     */
   double bn_eps;       /* batch-norm epsilon                           */
   double slope;        /* leaky ReLU negative slope                    */
+  double flip_delta;   /* > 0: pre-activations with |y| < flip_delta   */
+                       /* take the other leaky-ReLU branch (tests of   */
+                       /* branch-ambiguous pixels); 0: off             */
 } gfo_guide_t;
+
+/* OpenMP threads of the following calls (n > 0). */
+void gfo_set_threads(int n);
 
 /* Length of the flattened guide gradient:
  * dw1 | dw2 | db2 | dlam | dmu | dgamma | dbeta. */

@@ -37,14 +37,38 @@ def transform_params(x, w1, w2, b2, lam, mu, gamma, beta, bn_eps=1e-5, slope=0.2
     return F.conv2d(z, w2[:, :, None, None], b2)
 
 
-def guided_filter(G_lo, p_lo, G_hi, r, eps, mean_ab=True, align_corners=False):
-    """q from guides already transformed (G = F(I)); eps: scalar or [n]."""
+def transform_parts(x, w1, w2, b2, lam, mu, gamma, beta, bn_eps=1e-5, slope=0.2):
+    """F(I) with its intermediates exposed (each retains its gradient):
+    h = W1 x, hn = (h - m) / sqrt(v + bn_eps) (batch statistics), bn =
+    gamma hn + beta, y = lam h + mu bn, z = leaky_relu(y), G = W2 z + b2."""
+    h = F.conv2d(x, w1[:, :, None, None])
+    m = h.mean(dim=(0, 2, 3), keepdim=True)
+    v = ((h - m) ** 2).mean(dim=(0, 2, 3), keepdim=True)
+    hn = (h - m) / torch.sqrt(v + bn_eps)
+    bn = gamma.view(1, -1, 1, 1) * hn + beta.view(1, -1, 1, 1)
+    y = lam * h + mu * bn
+    z = F.leaky_relu(y, slope)
+    G = F.conv2d(z, w2[:, :, None, None], b2)
+    parts = dict(h=h, hn=hn, bn=bn, y=y, z=z, G=G)
+    for t in (h, bn, y, G):
+        if t.requires_grad:
+            t.retain_grad()
+    return parts
+
+
+def guided_filter(G_lo, p_lo, G_hi, r, eps, mean_ab=True, align_corners=False, keep=None):
+    """q from guides already transformed (G = F(I)); eps: scalar or [n].
+    `keep` (a dict), if given, receives the window variance `var` (which
+    retains its gradient)."""
     eps = torch.as_tensor(eps, dtype=G_lo.dtype)
     if eps.ndim == 1 and eps.numel() > 1:
         eps = eps.view(-1, 1, 1, 1)
     mI = box(G_lo, r)
     mP = box(p_lo, r)
     var = box(G_lo * G_lo, r) - mI * mI
+    if keep is not None and var.requires_grad:
+        var.retain_grad()
+        keep["var"] = var
     cov = box(G_lo * p_lo, r) - mI * mP
     A = cov / (var + eps)
     b = mP - A * mI

@@ -2,12 +2,8 @@
 workload (r = 8 and r = 1) and the uneven batch, each at its full size and in
 the launch configuration bench.py times (one gf_forward_backward call; the
 batch as an autotuned plan replayed as a HIP graph), against the FP64 oracle.
-Errors and bars as in test_gpu_parity.py / test_gpu_guided.py.  The uneven
-batch is compared on a sample of its images (every fourth); the others on
-every output, except, with the transform guide, the input gradients at the
-pixels whose leaky-ReLU branch is not fixed by a finite-precision
-evaluation (some pre-activation within 2e-6 of 0; see test_gpu_guided.py),
-which are checked finite."""
+Error measures and bars: tests/parity.py.  The uneven batch is compared on
+a sample of its images (every fourth); the others on every output."""
 import os
 from concurrent.futures import ThreadPoolExecutor
 
@@ -17,40 +13,16 @@ import torch
 
 import oracle
 from paper_1803_05619_amd import datagen
+from tests import parity
 
 pytestmark = pytest.mark.gpu
 
 DEV = torch.device("cuda:0")
-TOL = {"f32": 1e-4, "bf16": 2e-2, "f16": 2e-2}
 
 
 def _gf():
     from paper_1803_05619_amd import gf
     return gf
-
-
-def errors(got, ref, amb=None):
-    err = {"q": float(np.abs(got["q"] - ref["q"]).max())}
-    for k in ("dI_lo", "dp_lo", "dI_hi"):
-        if k in got:
-            diff = np.abs(got[k] - ref[k])
-            if amb is not None and k in amb:
-                assert np.isfinite(got[k]).all()
-                diff = np.where(amb[k], 0.0, diff)
-            err[k] = float(diff.max() / max(1.0, np.abs(ref[k]).max()))
-    if "deps" in got:
-        err["deps"] = float((np.abs(got["deps"] - ref["deps"]) /
-                             np.maximum(1.0, ref["deps_abs"])).max())
-    if "dparams" in got:
-        err["dparams"] = float((np.abs(got["dparams"] - ref["dguide"]) /
-                                np.maximum(1.0, ref["dguide_abs"])).max())
-    return err
-
-
-def check(err, tol):
-    print("errors:", {k: f"{v:.3e}" for k, v in err.items()}, flush=True)
-    for k, v in err.items():
-        assert v <= tol, (k, v, err)
 
 
 def test_config2_full_size():
@@ -76,10 +48,16 @@ def test_config2_full_size():
     ref = {"q": oracle.forward(*args, prob["r"], prob["eps"], guide=g)}
     ref.update(oracle.backward(*args, prob["r"], prob["eps"], prob["dq"].double().numpy(),
                                guide=g))
-    amb = {"dI_lo": (np.abs(oracle.guide_preact(args[0], g)) < 2e-6).any(axis=1, keepdims=True),
-           "dI_hi": (np.abs(oracle.guide_preact(args[2], g)) < 2e-6).any(axis=1, keepdims=True)}
+    amb = {"dI_lo": parity.branch_ambiguous(args[0], g),
+           "dI_hi": parity.branch_ambiguous(args[2], g)}
     print("branch-ambiguous pixels:", {k: int(v.sum()) for k, v in amb.items()}, flush=True)
-    check(errors(got, ref, amb), TOL["bf16"])
+    ref_flip = parity.flipped_reference(args, prob["r"], prob["eps"],
+                                        prob["dq"].double().numpy(), g)
+    n, h, w, H, W = prob["n"], prob["h"], prob["w"], prob["H"], prob["W"]
+    parity.check(parity.measure(got, ref, "bf16", n_eps_terms=n * 3 * h * w,
+                                n_guide_terms=n * (h * w + H * W),
+                                hidden=np.asarray(g["w1"]).shape[0], amb=amb, ref_flip=ref_flip),
+                 "config 2 full size")
 
 
 @pytest.mark.parametrize("r", [8, 1])
@@ -96,7 +74,9 @@ def test_config4_full_size(r):
     args = [prob[k].double().numpy() for k in ("I_lo", "p_lo", "I_hi")]
     ref = {"q": oracle.forward(*args, r, prob["eps"])}
     ref.update(oracle.backward(*args, r, prob["eps"], prob["dq"].double().numpy()))
-    check(errors(got, ref), TOL["f16"])
+    parity.check(parity.measure(got, ref, "f16",
+                                n_eps_terms=prob["n"] * 3 * prob["h"] * prob["w"]),
+                 f"config 4 full size r={r}")
 
 
 def test_config3_full_size():
@@ -140,7 +120,10 @@ def test_config3_full_size():
         ref = {"q": oracle.forward(*args, p["r"], p["eps"])}
         ref.update(oracle.backward(*args, p["r"], p["eps"], p["dq"].double().numpy()))
         got = {x: it[x].double().cpu().numpy() for x in ("q", "dI_lo", "dp_lo", "dI_hi", "deps")}
-        for name, v in errors(got, ref).items():
-            worst[name] = max(worst.get(name, 0.0), v)
+        res = parity.measure(got, ref, "f32", n_eps_terms=3 * p["h"] * p["w"])
+        print(f"image {k}: H={p['H']} W={p['W']} s={p['s']} r={p['r']}", flush=True)
+        for name, (e, bar) in res.items():
+            if name not in worst or e / bar > worst[name][0] / worst[name][1]:
+                worst[name] = (e, bar)
     plan.close()
-    check(worst, TOL["f32"])
+    parity.check(worst, "config 3 sampled images (worst)")

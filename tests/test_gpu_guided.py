@@ -1,40 +1,18 @@
 """GPU parity of the guided path (grey guide and the trainable transform
-guide of Sec. III-D) against the FP64 oracle, through the C ABI.
-
-Errors as in test_gpu_parity.py; in addition
-  dparams      per parameter group (W1, W2, b2, lam, mu, gamma, beta), per
-               entry: |gpu - ref| / max(1, sum of the magnitudes of the
-               per-pixel terms the entry adds up) -- each entry is a sum over
-               every pixel of both calls, judged like deps (b2's gradient,
-               for one, is zero up to rounding: the output does not change
-               when the same constant is added to G at both resolutions)
-  dI_lo, dI_hi  with the transform guide, pixels where some hidden
-               pre-activation y is within 2e-6 of 0 are left out (checked
-               finite only): there the leaky ReLU's branch is not fixed by a
-               finite-precision evaluation of y (the kernels' folded FP32
-               constants move y by ~1e-7), and the two branches give
-               gradients that differ by O(1) at that pixel; both are valid.
-Bars: 1e-4 for FP32 I/O, 2e-2 for BF16/FP16 I/O.
+guide of Sec. III-D) against the FP64 oracle, through the C ABI.  Error
+measures and bars (including the transform-parameter gradients and the
+branch-ambiguous pixels of the leaky ReLU): see tests/parity.py.
 """
-
-BRANCH_DELTA = 2e-6
-
-
-def branch_ambiguous(X, guide):
-    """[n, 1, H, W]: pixels whose transform pre-activations include one
-    within BRANCH_DELTA of 0 (from the oracle)."""
-    Y = oracle.guide_preact(X, guide)
-    return (np.abs(Y) < BRANCH_DELTA).any(axis=1, keepdims=True)
 import numpy as np
 import pytest
 import torch
 
 import oracle
 from paper_1803_05619_amd import datagen
+from tests import parity
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"f32": 1e-4, "bf16": 2e-2, "f16": 2e-2}
 DEV = torch.device("cuda:0")
 
 
@@ -96,44 +74,31 @@ def run_both(prob, mode, mean_ab=True, backward=True, use_stats=False):
     return out, ref
 
 
-def errors(out, ref, hidden=None, amb=None):
-    """amb: optional {"dI_lo": mask, "dI_hi": mask} of branch-ambiguous pixels."""
-    err = {"q": float(np.abs(out["q"] - ref["q"]).max())}
-    for k in ("dI_lo", "dp_lo", "dI_hi"):
-        if k in out:
-            diff = np.abs(out[k] - ref[k])
-            if amb is not None and k in amb:
-                assert np.isfinite(out[k]).all()
-                diff = np.where(amb[k], 0.0, diff)
-            err[k] = float(diff.max() / max(1.0, np.abs(ref[k]).max()))
-    if "deps" in out:
-        err["deps"] = float((np.abs(out["deps"] - ref["deps"]) /
-                             np.maximum(1.0, ref["deps_abs"])).max())
-    if "dparams" in out:
-        rel = np.abs(out["dparams"] - ref["dguide"]) / np.maximum(1.0, ref["dguide_abs"])
-        for k, v in oracle.guide_grad_split(rel, 3, 3, hidden).items():
-            err["d" + k] = float(np.max(v))
-    return err
+def measure(prob, mode, out, ref, mean_ab=True, align_corners=False):
+    """parity.measure with the problem's term counts and, for the transform
+    guide, the branch-ambiguous pixels and the oracle's flipped gradients."""
+    n, c, h, w = prob["p_lo"].shape
+    H, W = prob["I_hi"].shape[-2:]
+    kw = dict(n_eps_terms=n * c * h * w)
+    if mode == "transform":
+        g = prob["guide"]
+        args = [prob[k].double().numpy() for k in ("I_lo", "p_lo", "I_hi")]
+        amb = {"dI_lo": parity.branch_ambiguous(args[0], g),
+               "dI_hi": parity.branch_ambiguous(args[2], g)}
+        print("branch-ambiguous pixels:", {k: int(v.sum()) for k, v in amb.items()}, flush=True)
+        ref_flip = None
+        if "dI_lo" in out and (amb["dI_lo"].any() or amb["dI_hi"].any()):
+            ref_flip = parity.flipped_reference(args, prob["r"], prob["eps"],
+                                                prob["dq"].double().numpy(), g, mean_ab=mean_ab,
+                                                align_corners=align_corners)
+        kw.update(n_guide_terms=n * (h * w + H * W), hidden=np.asarray(g["w1"]).shape[0],
+                  amb=amb, ref_flip=ref_flip)
+    return parity.measure(out, ref, prob["io_dtype"], **kw)
 
 
-def ambiguous(prob, mode):
-    if mode != "transform":
-        return None
-    amb = {"dI_lo": branch_ambiguous(prob["I_lo"].double().numpy(), prob["guide"]),
-           "dI_hi": branch_ambiguous(prob["I_hi"].double().numpy(), prob["guide"])}
-    print("branch-ambiguous pixels:", {k: int(v.sum()) for k, v in amb.items()}, flush=True)
-    return amb
-
-
-def check(prob, mode, tol=None, **kw):
+def check(prob, mode, **kw):
     out, ref = run_both(prob, mode, **kw)
-    hidden = np.asarray(prob["guide"]["w1"]).shape[0] if mode == "transform" else None
-    err = errors(out, ref, hidden, ambiguous(prob, mode))
-    print("errors:", {k: f"{v:.3e}" for k, v in err.items()}, flush=True)
-    tol = TOL[prob["io_dtype"]] if tol is None else tol
-    for k, v in err.items():
-        assert v <= tol, (k, v, err)
-    return err
+    return parity.check(measure(prob, mode, out, ref, mean_ab=kw.get("mean_ab", True)))
 
 
 # ------------------------------------------------------------ grey guide
@@ -278,8 +243,4 @@ def test_guided_align_corners(mode):
                align_corners=True)
     ref = {"q": oracle.forward(*args, prob["r"], prob["eps"], **gkw)}
     ref.update(oracle.backward(*args, prob["r"], prob["eps"], prob["dq"].double().numpy(), **gkw))
-    hidden = np.asarray(prob["guide"]["w1"]).shape[0] if mode == "transform" else None
-    err = errors(got, ref, hidden, ambiguous(prob, mode))
-    print("errors:", {k: f"{v:.3e}" for k, v in err.items()}, flush=True)
-    for k, v in err.items():
-        assert v <= TOL[prob["io_dtype"]], (k, v, err)
+    parity.check(measure(prob, mode, got, ref, align_corners=True))

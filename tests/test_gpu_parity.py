@@ -1,15 +1,6 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
-same seeded inputs, element by element.
-
-Error measures (per output):
-  q            max |gpu - ref|                                  (absolute)
-  dI_lo, dp_lo, dI_hi
-               max |gpu - ref| / max(1, max |ref|)              (scaled)
-  deps         |gpu - ref| / max(1, sum |d var|)                 (scaled by the
-               sum of the magnitudes of the terms deps adds up)
-Bars: 1e-4 for FP32 I/O and 2e-2 for BF16/FP16 I/O (for half-precision I/O
-q and dI_hi are rounded once to the I/O type, so their error includes that
-rounding).
+same seeded inputs, element by element.  Error measures and bars: see
+tests/parity.py.
 """
 import numpy as np
 import pytest
@@ -17,10 +8,9 @@ import torch
 
 import oracle
 from paper_1803_05619_amd import datagen
+from tests import parity
 
 pytestmark = pytest.mark.gpu
-
-TOL = {"f32": 1e-4, "bf16": 2e-2, "f16": 2e-2}
 
 
 def _gf():
@@ -60,25 +50,14 @@ def run_both(prob, mean_ab=True, eps=None, backward=True, align_corners=False):
     return out, ref
 
 
-def errors(out, ref):
-    err = {"q": float(np.abs(out["q"] - ref["q"]).max())}
-    for k in ("dI_lo", "dp_lo", "dI_hi"):
-        if k in out:
-            err[k] = float(np.abs(out[k] - ref[k]).max() / max(1.0, np.abs(ref[k]).max()))
-    if "deps" in out:
-        err["deps"] = float((np.abs(out["deps"] - ref["deps"]) /
-                             np.maximum(1.0, ref["deps_abs"])).max())
-    return err
+def measure(prob, out, ref):
+    return parity.measure(out, ref, prob["io_dtype"],
+                          n_eps_terms=prob["n"] * prob["c"] * prob["h"] * prob["w"])
 
 
-def check(prob, tol=None, **kw):
+def check(prob, **kw):
     out, ref = run_both(prob, **kw)
-    err = errors(out, ref)
-    print("errors:", {k: f"{v:.3e}" for k, v in err.items()}, flush=True)
-    tol = TOL[prob["io_dtype"]] if tol is None else tol
-    for k, v in err.items():
-        assert v <= tol, (k, v, err)
-    return err
+    return parity.check(measure(prob, out, ref))
 
 
 # ------------------------------------------------------------ configurations

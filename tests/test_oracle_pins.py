@@ -429,3 +429,120 @@ def test_guide_preact_is_the_batch_norm_mix():
     Z = np.where(Y > 0, Y, g["slope"] * Y)
     G = np.einsum("ck,nkhw->nchw", np.asarray(g["w2"]), Z) + np.asarray(g["b2"])[None, :, None, None]
     assert np.abs(G - oracle.guide_apply(X, g)).max() <= 1e-12
+
+
+# ------------------------------------------- error scales (sums of |terms|)
+
+@pytest.mark.parametrize("eps_count", [1, 2])
+@pytest.mark.parametrize("mean_ab", [False, True])
+def test_deps_abs_is_sum_of_term_magnitudes(eps_count, mean_ab):
+    """deps = sum over channels and low-res pixels of d var (A = cov / (var +
+    eps) is the only place eps enters), so its rounding-error scale deps_abs
+    is sum |d var|: here d var is torch autograd's gradient of the library
+    composition at its var tensor (float64), independent of the oracle."""
+    rng = np.random.default_rng(60 + 2 * eps_count + mean_ab)
+    n, c, h, w, H, W, r = 2, 3, 7, 9, 21, 27, 1
+    Il, p, Ih = rnd(rng, n, c, h, w), rnd(rng, n, c, h, w), rnd(rng, n, c, H, W)
+    dq = rng.normal(size=(n, c, H, W))
+    eps = np.array([1e-3, 3e-2])[:eps_count]
+    o = oracle.backward(Il, p, Ih, r, eps, dq, mean_ab=mean_ab)
+    G_lo = torch.tensor(Il, requires_grad=True)
+    keep = {}
+    q = R.guided_filter(G_lo, torch.from_numpy(p), torch.from_numpy(Ih), r, eps,
+                        mean_ab=mean_ab, keep=keep)
+    (q * torch.from_numpy(dq)).sum().backward()
+    dvar = keep["var"].grad.numpy()
+    want = np.abs(dvar).sum(axis=(1, 2, 3))
+    want = want if eps_count == 2 else want.sum(keepdims=True)
+    np.testing.assert_allclose(o["deps_abs"], want, rtol=1e-10, atol=0)
+    # and the gradient itself is the signed sum of the same terms
+    signed = dvar.sum(axis=(1, 2, 3))
+    signed = signed if eps_count == 2 else signed.sum(keepdims=True)
+    np.testing.assert_allclose(o["deps"], signed, rtol=1e-9, atol=1e-12)
+
+
+def test_dguide_abs_is_sum_of_term_magnitudes():
+    """Each transform-parameter gradient is a sum over the pixels of both
+    calls of one term per pixel (Sec. III-D chain rule through F): dW1 of
+    dh x, dW2 of dG z, db2 of dG, dlam of dy h, dmu of dy bn, dgamma of
+    dbn hn, dbeta of dbn.  The oracle's dguide_abs must be the sum of the
+    magnitudes of those terms, with dh, dG, dy and dbn taken from torch
+    autograd of the library composition (float64) and h, hn, bn, z from its
+    forward -- no value from the oracle."""
+    rng = np.random.default_rng(61)
+    from paper_1803_05619_amd.datagen import guide_params
+    g = guide_params(rng, hidden=5)
+    n, c, h, w, H, W, r = 2, 3, 6, 7, 18, 21, 1
+    Il, p, Ih = rnd(rng, n, c, h, w), rnd(rng, n, c, h, w), rnd(rng, n, c, H, W)
+    dq = rng.normal(size=(n, c, H, W))
+    o = oracle.backward(Il, p, Ih, r, 1e-3, dq, guide=g)
+    # parameters require grad so that the intermediates keep theirs
+    P = {k: torch.tensor(np.asarray(g[k], dtype=np.float64), requires_grad=True)
+         for k in ("w1", "w2", "b2", "gamma", "beta")}
+    calls = []
+    for x in (Il, Ih):
+        xt = torch.from_numpy(x)
+        cl = R.transform_parts(xt, P["w1"], P["w2"], P["b2"], g["lam"], g["mu"], P["gamma"],
+                               P["beta"], g["bn_eps"], g["slope"])
+        cl["x"] = xt
+        calls.append(cl)
+    q = R.guided_filter(calls[0]["G"], torch.from_numpy(p), calls[1]["G"], r, 1e-3)
+    (q * torch.from_numpy(dq)).sum().backward()
+    want = {k: 0.0 for k in ("w1", "w2", "b2", "lam", "mu", "gamma", "beta")}
+    for cl in calls:
+        x, hh, hn, bn, z = (cl[k].detach() for k in ("x", "h", "hn", "bn", "z"))
+        dh, dG, dy, dbn = cl["h"].grad, cl["G"].grad, cl["y"].grad, cl["bn"].grad
+        want["w1"] = want["w1"] + torch.einsum("nkyx,niyx->ki", dh.abs(), x.abs()).numpy()
+        want["w2"] = want["w2"] + torch.einsum("ncyx,nkyx->ck", dG.abs(), z.abs()).numpy()
+        want["b2"] = want["b2"] + dG.abs().sum(dim=(0, 2, 3)).numpy()
+        want["lam"] = want["lam"] + float((dy * hh).abs().sum())
+        want["mu"] = want["mu"] + float((dy * bn).abs().sum())
+        want["gamma"] = want["gamma"] + (dbn * hn).abs().sum(dim=(0, 2, 3)).numpy()
+        want["beta"] = want["beta"] + dbn.abs().sum(dim=(0, 2, 3)).numpy()
+    got = oracle.guide_grad_split(o["dguide_abs"], c, c, 5)
+    for k, v in want.items():
+        np.testing.assert_allclose(got[k], v, rtol=1e-9, atol=0, err_msg=k)
+
+
+# ------------------------------------------------ leaky-ReLU branch flip
+
+def test_branch_flip_everywhere_is_a_reparametrised_transform():
+    """With every pre-activation flipped (flip_delta huge), the leaky ReLU
+    takes z = y for y <= 0 and slope * y for y > 0, which is
+    slope * leaky_relu(y, 1 / slope): the flipped layer equals the unflipped
+    one with W2 scaled by slope and the slope inverted -- forward, input
+    gradients, and parameter gradients (dW2 scaled by slope)."""
+    rng = np.random.default_rng(62)
+    from paper_1803_05619_amd.datagen import guide_params
+    g = guide_params(rng, hidden=6)
+    s = g["slope"]
+    n, c, h, w, H, W, r = 2, 3, 5, 6, 20, 24, 1
+    Il, p, Ih = rnd(rng, n, c, h, w), rnd(rng, n, c, h, w), rnd(rng, n, c, H, W)
+    dq = rng.normal(size=(n, c, H, W))
+    flip = dict(g, flip_delta=1e30)
+    rep = dict(g, w2=s * np.asarray(g["w2"]), slope=1.0 / s)
+    np.testing.assert_allclose(oracle.forward(Il, p, Ih, r, 1e-3, guide=flip),
+                               oracle.forward(Il, p, Ih, r, 1e-3, guide=rep), atol=1e-12)
+    a = oracle.backward(Il, p, Ih, r, 1e-3, dq, guide=flip)
+    b = oracle.backward(Il, p, Ih, r, 1e-3, dq, guide=rep)
+    for k in ("dI_lo", "dp_lo", "dI_hi", "deps"):
+        np.testing.assert_allclose(a[k], b[k], atol=1e-10 * max(1.0, np.abs(b[k]).max()))
+    ga, gb = (oracle.guide_grad_split(x["dguide"], c, c, 6) for x in (a, b))
+    for k in ("w1", "b2", "lam", "mu", "gamma", "beta"):
+        np.testing.assert_allclose(ga[k], gb[k], atol=1e-10 * max(1.0, np.abs(gb[k]).max()))
+    np.testing.assert_allclose(ga["w2"], s * gb["w2"], atol=1e-10 * max(1.0, np.abs(gb["w2"]).max()))
+
+
+def test_branch_flip_off_and_outside_band():
+    """flip_delta = 0 is the plain transform; a band below every |y| flips
+    nothing."""
+    rng = np.random.default_rng(63)
+    from paper_1803_05619_amd.datagen import guide_params
+    g = guide_params(rng)
+    Il, p, Ih = rnd(rng, 1, 3, 4, 5), rnd(rng, 1, 3, 4, 5), rnd(rng, 1, 3, 8, 10)
+    dq = rng.normal(size=(1, 3, 8, 10))
+    ymin = min(np.abs(oracle.guide_preact(x, g)).min() for x in (Il, Ih))
+    base = oracle.backward(Il, p, Ih, 1, 1e-3, dq, guide=g)
+    same = oracle.backward(Il, p, Ih, 1, 1e-3, dq, guide=dict(g, flip_delta=0.5 * ymin))
+    for k in ("dI_lo", "dp_lo", "dI_hi", "deps", "dguide"):
+        np.testing.assert_array_equal(base[k], same[k])
