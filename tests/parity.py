@@ -9,21 +9,29 @@ once to the I/O type; the low-res gradients are FP32 outputs but inherit
 the conditioning of eps = 1e-8 on half-quantised guides).
 
 Sums over pixels (deps: one term d var per channel and low-res pixel;
-each transform-parameter gradient: one term per pixel of both calls)
-  *_sum   |gpu - ref| <= sum_bar(n) * sum |terms|  per entry, the terms'
-          magnitude sum from the oracle (pinned against torch autograd):
-          the first-order rounding bound of an FP32 sum whose terms pass
-          through at most D sequential additions (the kernels' fixed
-          reduction order: per-lane walks of at most 128 rows or pixels,
-          shuffle and LDS trees, strided sums of at most ~100 partials per
-          thread at these sizes; D <= 256 + log2 n) and are each formed with
-          at most 16 roundings: (D + 16) u, u = 2^-24.
-  *_rel   |gpu - ref| <= TOL_SUM * max |ref over the group|  (deps: |ref|
-          per entry; transform parameters: per group W1, W2, lam, mu,
-          gamma, beta).  The gradient of b2 is zero up to rounding (adding
-          a constant to G at both resolutions leaves q unchanged), so it has
-          only the *_sum check.  TOL_SUM is the FP32-output bar 1e-4: these
-          are FP32 results for every I/O type.
+each transform-parameter gradient: one term per pixel of both calls) pass
+when either bound holds, per entry:
+  rel     |gpu - ref| <= TOL[io] * scale, scale = |ref| (deps) or the
+          largest |ref| of the entry's group (transform parameters: W1, W2,
+          lam, mu, gamma, beta): the stated target of the whole fused
+          forward + backward for the problem's I/O type;
+  sum     |gpu - ref| <= sum_bar(n) * sum |terms|, the terms' magnitude sum
+          from the oracle (pinned against torch autograd): the first-order
+          rounding bound of an FP32 sum whose terms pass through at most D
+          sequential additions (the kernels' fixed reduction order: per-lane
+          walks of at most 128 rows or pixels, shuffle and LDS trees,
+          strided sums of at most ~100 partials per thread at these sizes;
+          D <= 256 + log2 n) and are each formed with at most 16 roundings:
+          (D + 16) u, u = 2^-24.
+The first is the target; the second is what an FP32 evaluation can deliver
+when the sum cancels heavily (sum |terms| / |sum| reaches 5e3 and more for
+the transform's parameters and for deps at eps = 1e-8, where 1e-4 relative
+to |ref| would ask for more than FP32 resolves).  A wrong term, sign or
+factor misses both unless the sum is cancellation noise below FP32
+resolution.  The gradient of b2 is zero up to rounding (adding a constant to
+G at both resolutions leaves q unchanged), so it has only the sum bound.
+Reported per quantity: max over entries of min(err_rel / bar_rel,
+err_sum / bar_sum), which must be <= 1, beside both raw errors.
 
 Branch-ambiguous pixels of the transform guide (some hidden pre-activation
 |y| < BRANCH_DELTA, from the oracle's own pre-activations): the leaky ReLU's
@@ -40,7 +48,6 @@ import oracle
 
 U32 = 2.0 ** -24
 TOL = {"f32": 1e-4, "bf16": 2e-2, "f16": 2e-2}
-TOL_SUM = 1e-4
 BRANCH_DELTA = 2e-6
 GROUPS = ("w1", "w2", "lam", "mu", "gamma", "beta")
 
@@ -79,18 +86,28 @@ def measure(got, ref, io, *, n_eps_terms=None, n_guide_terms=None, hidden=None, 
         res[k] = (float(diff.max() / max(1.0, np.abs(ref[k]).max())), tol)
     if "deps" in got:
         d = np.abs(got["deps"] - ref["deps"])
-        res["deps_sum"] = (float((d / np.maximum(ref["deps_abs"], 1e-300)).max()),
-                           sum_bar(n_eps_terms))
-        res["deps_rel"] = (float((d / np.maximum(np.abs(ref["deps"]), 1e-300)).max()), TOL_SUM)
+        e_sum = d / np.maximum(ref["deps_abs"], 1e-300)
+        e_rel = d / np.maximum(np.abs(ref["deps"]), 1e-300)
+        bar_sum = sum_bar(n_eps_terms)
+        res["deps"] = (float(np.minimum(e_rel / tol, e_sum / bar_sum).max()), 1.0)
+        res["deps_sum(info)"] = (float(e_sum.max()), math.inf)
+        res["deps_rel(info)"] = (float(e_rel.max()), math.inf)
     if "dparams" in got:
         d = np.abs(got["dparams"] - ref["dguide"])
-        res["dparams_sum"] = (float((d / np.maximum(ref["dguide_abs"], 1e-300)).max()),
-                              sum_bar(n_guide_terms))
+        e_sum = d / np.maximum(ref["dguide_abs"], 1e-300)
+        bar_sum = sum_bar(n_guide_terms)
+        res["dparams_sum(info)"] = (float(e_sum.max()), math.inf)
         dg = oracle.guide_grad_split(d, 3, 3, hidden)
+        sg = oracle.guide_grad_split(e_sum, 3, 3, hidden)
         rg = oracle.guide_grad_split(ref["dguide"], 3, 3, hidden)
-        for g in GROUPS:
-            scale = float(np.abs(rg[g]).max())
-            res[f"d{g}_rel"] = (float(np.max(dg[g])) / max(scale, 1e-300), TOL_SUM)
+        for g in GROUPS + ("b2",):
+            es = np.asarray(sg[g], dtype=np.float64) / bar_sum
+            if g == "b2":
+                res["db2"] = (float(es.max()), 1.0)
+                continue
+            er = np.asarray(dg[g], dtype=np.float64) / max(float(np.abs(rg[g]).max()), 1e-300)
+            res[f"d{g}"] = (float(np.minimum(er / tol, es).max()), 1.0)
+            res[f"d{g}_rel(info)"] = (float(er.max()), math.inf)
     return res
 
 
