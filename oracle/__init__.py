@@ -73,6 +73,8 @@ def _load():
         lib.gfo_guide_preact.restype = ci
         lib.gfo_guide_grad_size.argtypes = [ci, ci, ci]
         lib.gfo_guide_grad_size.restype = ctypes.c_long
+        lib.gfo_area_down.argtypes = [ci] * 6 + [dp, dp]
+        lib.gfo_area_down.restype = ci
         lib.gfo_set_threads.argtypes = [ci]
         lib.gfo_set_threads.restype = None
         _lib = lib
@@ -216,6 +218,19 @@ def guide_preact(X, guide):
     rc = lib.gfo_guide_preact(ctypes.byref(g), n, cin, H * W, _ptr(X), _ptr(Y))
     if rc != 0:
         raise RuntimeError(f"gfo_guide_preact failed ({rc})")
+    return Y
+
+
+def area_down(X, h, w):
+    """Area downsampling [n, c, H, W] -> [n, c, h, w] in float64 (the
+    downsampling step of the DGF framework, Sec. IV)."""
+    lib = _load()
+    X = _f64(X)
+    n, c, H, W = X.shape
+    Y = np.empty((n, c, int(h), int(w)), np.float64)
+    rc = lib.gfo_area_down(n, c, H, W, int(h), int(w), _ptr(X), _ptr(Y))
+    if rc != 0:
+        raise RuntimeError(f"gfo_area_down failed ({rc})")
     return Y
 
 

@@ -738,3 +738,35 @@ int gfo_backward(int n, int c, int h, int w, int H, int W, int r,
   free(dep);
   return fail ? -2 : 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* downsampling of the DGF framework (Sec. IV, Fig. 3)                 */
+/* ------------------------------------------------------------------ */
+
+/* I_l = area downsampling of I_h to (h, w): the paper only says that I_h is
+ * downsampled to obtain I_l (Sec. IV).  Reading: each low-res pixel (i, j)
+ * is the plain mean of the high-res pixels of its covering rectangle, rows
+ * floor(i H / h) .. ceil((i + 1) H / h) - 1 and columns likewise (for an
+ * integer factor s = H / h the s x s block mean).  Written as the literal
+ * double loop over that rectangle. */
+int gfo_area_down(int n, int c, int H, int W, int h, int w, const double *X,
+                  double *Y) {
+  if (n < 1 || c < 1 || h < 1 || w < 1 || h > H || w > W || !X || !Y) return -1;
+  const long planes = (long)n * c;
+#pragma omp parallel for schedule(static)
+  for (long pl = 0; pl < planes; ++pl) {
+    const double *x = X + pl * (long)H * W;
+    double *y = Y + pl * (long)h * w;
+    for (int i = 0; i < h; ++i) {
+      const long r0 = (long)i * H / h, r1 = ((long)(i + 1) * H + h - 1) / h;
+      for (int j = 0; j < w; ++j) {
+        const long c0 = (long)j * W / w, c1 = ((long)(j + 1) * W + w - 1) / w;
+        double s = 0.0;
+        for (long yy = r0; yy < r1; ++yy)
+          for (long xx = c0; xx < c1; ++xx) s += x[yy * W + xx];
+        y[(long)i * w + j] = s / (double)((r1 - r0) * (c1 - c0));
+      }
+    }
+  }
+  return 0;
+}

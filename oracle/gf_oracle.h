@@ -69,6 +69,13 @@ int gfo_backward(int n, int c, int h, int w, int H, int W, int r,
                  double *dp_lo, double *dI_hi, double *deps, double *deps_abs,
                  double *dguide, double *dguide_abs);
 
+/* I_l [n, c, h, w] = area downsampling of I_h [n, c, H, W] (the first
+ * step of the DGF framework, Sec. IV): each low-res pixel is the mean of
+ * its covering high-res rectangle, rows floor(i H / h) .. ceil((i+1) H / h)
+ * - 1, columns likewise; any h <= H, w <= W. */
+int gfo_area_down(int n, int c, int H, int W, int h, int w, const double *X,
+                  double *Y);
+
 #ifdef __cplusplus
 }
 #endif

@@ -546,3 +546,41 @@ def test_branch_flip_off_and_outside_band():
     same = oracle.backward(Il, p, Ih, 1, 1e-3, dq, guide=dict(g, flip_delta=0.5 * ymin))
     for k in ("dI_lo", "dp_lo", "dI_hi", "deps", "dguide"):
         np.testing.assert_array_equal(base[k], same[k])
+
+
+# ---------------------------------------------------------------- DGF downsampling (Sec. IV)
+
+def test_area_down_hand_example():
+    """3x3 -> 2x2: the covering rectangles overlap (rows 0-1 and 1-2);
+    worked out by hand from the definition."""
+    X = np.arange(9, dtype=np.float64).reshape(1, 1, 3, 3)
+    np.testing.assert_array_equal(oracle.area_down(X, 2, 2)[0, 0], [[2.0, 3.0], [5.0, 6.0]])
+    # 1x4 -> 1x3: columns [0,2), [1,3), [2,4)
+    X = np.array([[[[1.0, 3.0, 7.0, 15.0]]]])
+    np.testing.assert_array_equal(oracle.area_down(X, 1, 3)[0, 0, 0], [2.0, 5.0, 11.0])
+
+
+@pytest.mark.parametrize("s, sx", [(1, 1), (2, 2), (4, 4), (8, 8), (3, 5), (32, 32)])
+def test_area_down_integer_factor_is_block_mean(s, sx):
+    rng = np.random.default_rng(70 + s)
+    X = rng.random((2, 3, 4 * s, 3 * sx))
+    blocks = X.reshape(2, 3, 4, s, 3, sx).mean(axis=(3, 5))
+    np.testing.assert_allclose(oracle.area_down(X, 4, 3), blocks, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("H, W, h, w", [(13, 10, 5, 7), (250, 300, 64, 96), (7, 37, 1, 9),
+                                        (2048, 96, 96, 64)])
+def test_area_down_equals_adaptive_average_pooling(H, W, h, w):
+    """Any ratio: torch's adaptive average pooling uses the same covering
+    rectangles (a library routine the definition reduces to)."""
+    rng = np.random.default_rng(H + W)
+    X = rng.random((1, 2, H, W))
+    ref = torch.nn.functional.adaptive_avg_pool2d(torch.from_numpy(X), (h, w)).numpy()
+    np.testing.assert_allclose(oracle.area_down(X, h, w), ref, rtol=0, atol=1e-14)
+
+
+def test_area_down_constant_and_identity():
+    X = np.full((1, 1, 17, 29), 0.3125)
+    np.testing.assert_array_equal(oracle.area_down(X, 5, 6), np.full((1, 1, 5, 6), 0.3125))
+    Y = np.random.default_rng(3).random((2, 2, 6, 7))
+    np.testing.assert_array_equal(oracle.area_down(Y, 6, 7), Y)
