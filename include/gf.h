@@ -232,6 +232,25 @@ int32_t gf_forward_backward(const gf_desc_t *desc, const gf_guide_t *guide,
                             float *deps, float *dparams, void *ws,
                             size_t ws_bytes, void *stream);
 
+/* gf_forward_backward without a caller workspace, for callers that cannot
+ * allocate device memory (code under stream capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Arguments, outputs and errors as for
+ * gf_forward_backward, minus ws / ws_bytes: the scratch memory is a static
+ * device array of GF_STATIC_SCRATCH_BYTES inside the library (one per GPU,
+ * held until the process ends).  A problem whose
+ * gf_workspace_size(desc, guide, 2) exceeds it returns GF_ERR_WORKSPACE
+ * before touching the device.  The call allocates nothing.  Every call on a
+ * GPU shares that GPU's array, so calls that overlap on one GPU (other
+ * streams, other host threads) race: order them on one stream. */
+#define GF_STATIC_SCRATCH_BYTES ((size_t)96 << 20)
+int32_t gf_forward_backward_static(const gf_desc_t *desc,
+                                   const gf_guide_t *guide, const void *I_lo,
+                                   const void *p_lo, const void *I_hi,
+                                   const float *eps, int32_t eps_count,
+                                   const void *dq_hi, void *q_hi, float *dI_lo,
+                                   float *dp_lo, void *dI_hi, float *deps,
+                                   float *dparams, void *stream);
+
 /* Human-readable name of a status code (static string). */
 const char *gf_status_string(int32_t status);
 

@@ -10,7 +10,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgf.so")
 OBJDIR = os.path.join(HERE, "_build")
-SOURCES = ["gf_api.cpp", "gf_batch.cpp", "gf_f32.hip", "gf_f16.hip", "gf_bf16.hip"]
+SOURCES = ["gf_api.cpp", "gf_batch.cpp", "gf_noalloc.hip", "gf_f32.hip", "gf_f16.hip",
+           "gf_bf16.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -63,6 +63,9 @@ lib.gf_backward.restype = ctypes.c_int32
 lib.gf_forward_backward.argtypes = [_dp, _gp, _vp, _vp, _vp, _fp, ctypes.c_int32, _vp, _vp, _fp,
                                     _fp, _vp, _fp, _fp, _vp, ctypes.c_size_t, _vp]
 lib.gf_forward_backward.restype = ctypes.c_int32
+lib.gf_forward_backward_static.argtypes = [_dp, _gp, _vp, _vp, _vp, _fp, ctypes.c_int32, _vp,
+                                           _vp, _fp, _fp, _vp, _fp, _fp, _vp]
+lib.gf_forward_backward_static.restype = ctypes.c_int32
 GF_RUN_FORWARD, GF_RUN_BACKWARD, GF_RUN_GRAPH = 1, 2, 4
 
 
@@ -185,6 +188,13 @@ def gf_forward_backward(desc, guide, I_lo, p_lo, I_hi, eps, eps_count, dq_hi, q_
     return int(lib.gf_forward_backward(ctypes.byref(desc), _gref(guide), I_lo, p_lo, I_hi, eps,
                                        eps_count, dq_hi, q_hi, dI_lo, dp_lo, dI_hi, deps,
                                        dparams, ws, ws_bytes, stream))
+
+
+def gf_forward_backward_static(desc, guide, I_lo, p_lo, I_hi, eps, eps_count, dq_hi, q_hi, dI_lo,
+                               dp_lo, dI_hi, deps, dparams, stream) -> int:
+    return int(lib.gf_forward_backward_static(ctypes.byref(desc), _gref(guide), I_lo, p_lo, I_hi,
+                                              eps, eps_count, dq_hi, q_hi, dI_lo, dp_lo, dI_hi,
+                                              deps, dparams, stream))
 
 
 def gf_status_string(code: int) -> str:

@@ -232,3 +232,20 @@ def test_forward_backward_checks():
                                   FAKE, None, FAKE, both - 1, None) == gf.GF_ERR_WORKSPACE
     assert gf.gf_forward_backward(desc(r=-1), None, FAKE, FAKE, FAKE, FAKE, 2, FAKE, FAKE, FAKE,
                                   FAKE, FAKE, FAKE, None, FAKE, big, None) == gf.GF_ERR_INVALID_ARG
+
+
+def test_static_scratch_entry_checks_on_the_host():
+    """gf_forward_backward_static rejects, before any HIP call, a problem
+    whose workspace exceeds the library's static scratch, and reports an
+    invalid description as gf_forward_backward does."""
+    limit = 96 << 20
+    ok = desc(n=4, h_lo=512, w_lo=768, h_hi=2048, w_hi=3072)
+    big = desc(n=8, h_lo=512, w_lo=768, h_hi=2048, w_hi=3072)
+    assert gf.gf_workspace_size(ok, None, 2) <= limit < gf.gf_workspace_size(big, None, 2)
+    st = gf.gf_forward_backward_static(big, None, FAKE, FAKE, FAKE, FAKE, 1, FAKE, FAKE, FAKE,
+                                       FAKE, FAKE, FAKE, None, None)
+    assert st == gf.GF_ERR_WORKSPACE
+    assert str(limit) in gf.gf_last_error_detail()
+    st = gf.gf_forward_backward_static(desc(r=-1), None, FAKE, FAKE, FAKE, FAKE, 1, FAKE, FAKE,
+                                       FAKE, FAKE, FAKE, FAKE, None, None)
+    assert st == gf.GF_ERR_INVALID_ARG
