@@ -20,6 +20,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gf_oracle.c")
+_SRC_CONV = os.path.join(_HERE, "gf_conv_oracle.c")
 _LIB = os.path.join(_HERE, "libgf_oracle.so")
 
 GUIDE_MODES = {"identity": 0, "grey": 1, "transform": 2}
@@ -28,11 +29,12 @@ _lib = None
 
 
 def build(force: bool = True) -> str:
-    """Compile gf_oracle.c into libgf_oracle.so (gcc, -O2, OpenMP)."""
+    """Compile gf_oracle.c and gf_conv_oracle.c into libgf_oracle.so (gcc,
+    -O2, OpenMP)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
         cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99",
-               "-Wall", "-o", tmp, _SRC, "-lm"]
+               "-Wall", "-o", tmp, _SRC, _SRC_CONV, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
     return _LIB
@@ -51,6 +53,17 @@ class _Guide(ctypes.Structure):
         ("bn_eps", ctypes.c_double),
         ("slope", ctypes.c_double),
         ("flip_delta", ctypes.c_double),
+    ]
+
+
+class _Conv(ctypes.Structure):
+    _fields_ = [
+        ("hidden", ctypes.c_int),
+        ("D", ctypes.POINTER(ctypes.c_double)),
+        ("W1", ctypes.POINTER(ctypes.c_double)),
+        ("W2", ctypes.POINTER(ctypes.c_double)),
+        ("W3", ctypes.POINTER(ctypes.c_double)),
+        ("slope", ctypes.c_double),
     ]
 
 
@@ -75,6 +88,12 @@ def _load():
         lib.gfo_guide_grad_size.restype = ctypes.c_long
         lib.gfo_area_down.argtypes = [ci] * 6 + [dp, dp]
         lib.gfo_area_down.restype = ci
+        lib.gfo_conv_param_count.argtypes = [ci, ci]
+        lib.gfo_conv_param_count.restype = ctypes.c_long
+        lib.gfo_conv_forward.argtypes = [ci] * 9 + [ctypes.POINTER(_Conv), dp, dp, dp, dp]
+        lib.gfo_conv_forward.restype = ci
+        lib.gfo_conv_backward.argtypes = ([ci] * 9 + [ctypes.POINTER(_Conv)] + [dp] * 9)
+        lib.gfo_conv_backward.restype = ci
         lib.gfo_set_threads.argtypes = [ci]
         lib.gfo_set_threads.restype = None
         _lib = lib
@@ -244,4 +263,74 @@ def guide_grad_split(flat, cin, cout, hidden):
                               ("gamma", hidden, (hidden,)), ("beta", hidden, (hidden,))):
         out[name] = np.asarray(flat[o:o + size]).reshape(shape)
         o += size
+    return out
+
+
+# ---------------------------------------------------------------- convolutional layer
+
+CONV_GROUPS = ("D", "W1", "W2", "W3")
+
+
+def conv_param_count(c, hidden):
+    return int(_load().gfo_conv_param_count(int(c), int(hidden)))
+
+
+def conv_split(flat, c, hidden):
+    """Split a flat parameter (or gradient) vector D | W1 | W2 | W3."""
+    K = int(hidden)
+    out, o = {}, 0
+    for name, shape in (("D", (c, 3, 3)), ("W1", (K, 2 * c)), ("W2", (K, K)), ("W3", (c, K))):
+        size = int(np.prod(shape))
+        out[name] = np.asarray(flat[o:o + size]).reshape(shape)
+        o += size
+    return out
+
+
+def _conv_struct(params, keep):
+    arrs = {k: _f64(params[k]).ravel() for k in CONV_GROUPS}
+    keep.extend(arrs.values())
+    return _Conv(int(np.asarray(params["W1"]).shape[0]), _ptr(arrs["D"]), _ptr(arrs["W1"]),
+                 _ptr(arrs["W2"]), _ptr(arrs["W3"]), float(params.get("slope", 0.2)))
+
+
+def conv_forward(I_lo, p_lo, I_hi, r, params, *, align_corners=False, mean_ab=True):
+    """q of the convolutional guided filtering layer (Sec. III-E) in float64;
+    params: D [c, 3, 3], W1 [K, 2c], W2 [K, K], W3 [c, K], slope."""
+    lib = _load()
+    I_lo, p_lo, I_hi = _f64(I_lo), _f64(p_lo), _f64(I_hi)
+    n, c, h, w = p_lo.shape
+    H, W = I_hi.shape[-2:]
+    if I_lo.shape != p_lo.shape or I_hi.shape[:2] != (n, c):
+        raise ValueError("inconsistent shapes")
+    keep = []
+    P = _conv_struct(params, keep)
+    q = np.empty((n, c, H, W), np.float64)
+    rc = lib.gfo_conv_forward(n, c, h, w, H, W, int(r), int(bool(align_corners)),
+                              int(bool(mean_ab)), ctypes.byref(P), _ptr(I_lo), _ptr(p_lo),
+                              _ptr(I_hi), _ptr(q))
+    if rc != 0:
+        raise RuntimeError(f"gfo_conv_forward failed ({rc})")
+    return q
+
+
+def conv_backward(I_lo, p_lo, I_hi, r, params, dq, *, align_corners=False, mean_ab=True):
+    """Gradients of <q, dq>: dI_lo, dp_lo, dI_hi, dparams (flat D | W1 | W2 |
+    W3) and dparams_abs (per entry, the sum of the magnitudes of the terms
+    it adds up)."""
+    lib = _load()
+    I_lo, p_lo, I_hi, dq = _f64(I_lo), _f64(p_lo), _f64(I_hi), _f64(dq)
+    n, c, h, w = p_lo.shape
+    H, W = I_hi.shape[-2:]
+    keep = []
+    P = _conv_struct(params, keep)
+    npar = conv_param_count(c, P.hidden)
+    out = {"dI_lo": np.empty_like(I_lo), "dp_lo": np.empty_like(p_lo),
+           "dI_hi": np.empty_like(I_hi), "dparams": np.empty(npar), "dparams_abs": np.empty(npar)}
+    rc = lib.gfo_conv_backward(n, c, h, w, H, W, int(r), int(bool(align_corners)),
+                               int(bool(mean_ab)), ctypes.byref(P), _ptr(I_lo), _ptr(p_lo),
+                               _ptr(I_hi), _ptr(dq), _ptr(out["dI_lo"]), _ptr(out["dp_lo"]),
+                               _ptr(out["dI_hi"]), _ptr(out["dparams"]),
+                               _ptr(out["dparams_abs"]))
+    if rc != 0:
+        raise RuntimeError(f"gfo_conv_backward failed ({rc})")
     return out

@@ -76,6 +76,27 @@ int gfo_backward(int n, int c, int h, int w, int H, int W, int r,
 int gfo_area_down(int n, int c, int H, int W, int h, int w, const double *X,
                   double *Y);
 
+/* ---- convolutional guided filtering layer (Sec. III-E), gf_conv_oracle.c
+ * Parameters: D [c][9] (3x3 depthwise taps per channel, row-major over
+ * (dy, dx) in {-1, 0, 1}^2, dilation r), W1 [hidden][2c], W2 [hidden]
+ * [hidden], W3 [c][hidden]; flat gradient layout D | W1 | W2 | W3. */
+typedef struct {
+  int hidden;
+  const double *D, *W1, *W2, *W3;
+  double slope;
+} gfo_conv_t;
+
+long gfo_conv_param_count(int c, int hidden);
+int gfo_conv_forward(int n, int c, int h, int w, int H, int W, int r, int align_corners,
+                     int mean_ab, const gfo_conv_t *P, const double *I_lo,
+                     const double *p_lo, const double *I_hi, double *q);
+/* dparams / dparams_abs: gfo_conv_param_count entries (may be NULL) */
+int gfo_conv_backward(int n, int c, int h, int w, int H, int W, int r, int align_corners,
+                      int mean_ab, const gfo_conv_t *P, const double *I_lo,
+                      const double *p_lo, const double *I_hi, const double *dq,
+                      double *dI_lo, double *dp_lo, double *dI_hi, double *dparams,
+                      double *dparams_abs);
+
 #ifdef __cplusplus
 }
 #endif

@@ -76,3 +76,62 @@ def guided_filter(G_lo, p_lo, G_hi, r, eps, mean_ab=True, align_corners=False, k
         A, b = box(A, r), box(b, r)
     H, W = G_hi.shape[-2:]
     return up(A, H, W, align_corners) * G_hi + up(b, H, W, align_corners)
+
+
+# ---------------------------------------------------------------- convolutional layer
+
+def conv_fd(x, D, r):
+    """Dilated 3x3 depthwise convolution (weights D [c, 3, 3], dilation r,
+    zero padding) normalised by the same convolution of the ones image."""
+    c = x.shape[1]
+    Dw = D.reshape(c, 1, 3, 3)
+    num = F.conv2d(x, Dw, padding=r, dilation=r, groups=c)
+    den = F.conv2d(torch.ones_like(x[:1]), Dw, padding=r, dilation=r, groups=c)
+    return num / den
+
+
+def conv_guided_filter(I_lo, p_lo, I_hi, r, P, mean_ab=True, align_corners=False, keep=None):
+    """The convolutional layer as a composition of library ops; P holds
+    tensors D, W1, W2, W3 and the slope.  `keep` receives the intermediates
+    (each retaining its gradient when it has one)."""
+    D, W1, W2, W3 = (P[k] for k in ("D", "W1", "W2", "W3"))
+    s = P.get("slope", 0.2)
+    mI, mP = conv_fd(I_lo, D, r), conv_fd(p_lo, D, r)
+    fIp, fII = conv_fd(I_lo * p_lo, D, r), conv_fd(I_lo * I_lo, D, r)
+    cov = fIp - mI * mP
+    var = fII - mI * mI
+    u = torch.cat([cov, var], dim=1)
+    y1 = F.conv2d(u, W1[:, :, None, None])
+    z1 = F.leaky_relu(y1, s)
+    y2 = F.conv2d(z1, W2[:, :, None, None])
+    z2 = F.leaky_relu(y2, s)
+    A = F.conv2d(z2, W3[:, :, None, None])
+    b = mP - A * mI
+    Ab, bb = (conv_fd(A, D, r), conv_fd(b, D, r)) if mean_ab else (A, b)
+    if keep is not None:
+        parts = dict(mI=mI, mP=mP, fIp=fIp, fII=fII, u=u, y1=y1, z1=z1, y2=y2, z2=z2, A=A, b=b,
+                     Ab=Ab, bb=bb)
+        for t in parts.values():
+            if t.requires_grad:
+                t.retain_grad()
+        keep.update(parts)
+    H, W = I_hi.shape[-2:]
+    return up(Ab, H, W, align_corners) * I_hi + up(bb, H, W, align_corners)
+
+
+def conv_taps(x, r):
+    """[n, c, 9, h, w]: x at the 9 dilated taps of every pixel (0 outside)."""
+    n, c, h, w = x.shape
+    cols = F.unfold(x.reshape(n * c, 1, h, w), 3, dilation=r, padding=r)
+    return cols.reshape(n, c, 9, h, w)
+
+
+def conv_fd_weight_terms(g, x, y, D, r):
+    """Per (pixel, tap) terms of the gradient of sum(g * f_d(x)) with respect
+    to D: g (x at the tap - y) / N, zero where the tap leaves the image
+    (y = f_d(x)).  Shape [n, c, 9, h, w]."""
+    c = x.shape[1]
+    ones = torch.ones_like(x[:1])
+    inside = conv_taps(ones, r)
+    N = F.conv2d(ones, D.reshape(c, 1, 3, 3), padding=r, dilation=r, groups=c)
+    return (g / N).unsqueeze(2) * (conv_taps(x, r) - y.unsqueeze(2)) * inside
