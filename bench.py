@@ -20,6 +20,9 @@ gf_backward.  Workloads (--workload):
 
   0            the plain forward only, FP32, 1 x 3 x 256 x 256 from 64 x 64
                (s = 4), r = 1, eps = 1e-2 (latency-bound: reported per call)
+  5            the convolutional guided filtering layer (Sec. III-E), FP32,
+               the images of workload 1, dilation 1: gf_conv_forward then
+               gf_conv_backward, gradients to every input and parameter
 
 Prints ONE JSON line:
   value        high-res Mpixel/s of fwd+bwd (a 3-channel pixel counts once)
@@ -42,6 +45,10 @@ Prints ONE JSON line:
   cpu_baseline the FP64 CPU oracle on the host cores (bounded sample), the
                host CPU model, and a 1-thread rate on one image
   error_vs_fp64_oracle  errors of this run's outputs on that sample
+
+  --dgf        instead: the deep guided filtering network's inference chain
+               (downsampling, C_l, the layer) over 512^2..3072^2 and Table IV's
+               I_l sizes: median ms per image, each step's share, peak memory
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload N]
 """
@@ -530,7 +537,190 @@ def workload_0(args, dev):
                 traffic_ok=False)
 
 
-WORKLOADS = {0: workload_0, 1: workload_1, 2: workload_2, 3: workload_3, 4: workload_4}
+def conv_params_np(seed, c=3, K=16):
+    """Random parameters of the convolutional layer at the scale of photo
+    statistics (positive taps; W1 large enough that the hidden units leave
+    zero on cov, var ~ 1e-3 .. 1e-2)."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    return {"D": rng.uniform(0.2, 1.0, size=(c, 3, 3)), "W1": rng.normal(0, 40.0, size=(K, 2 * c)),
+            "W2": rng.normal(0, 0.4, size=(K, K)), "W3": rng.normal(0, 0.4, size=(c, K)),
+            "slope": 0.2}
+
+
+def workload_5(args, dev):
+    """The convolutional guided filtering layer (Sec. III-E), forward then
+    backward (gradients to p_l, I_l, I_h and the 427 parameters), FP32, on the
+    4 x 3 x 2048 x 3072 images of workload 1, dilation r = 1."""
+    import torch
+
+    from paper_1803_05619_amd import datagen, gf, plain
+    log("generating workload 5 (FP32 4x3x2048x3072, convolutional layer)")
+    prob = datagen.make_config(1)
+    n, c, H, W, h, w = (prob[k] for k in ("n", "c", "H", "W", "h", "w"))
+    r, K = 1, 16
+    P = conv_params_np(225)
+    t = {k: prob[k].to(dev) for k in ("I_lo", "p_lo", "I_hi", "dq")}
+    params = gf.pack_conv_params(P["D"], P["W1"], P["W2"], P["W3"], device=dev)
+    desc = gf.make_desc(t["I_lo"], t["I_hi"], r)
+    cv = gf.gf_conv_t(K, P["slope"], params.data_ptr())
+    ws = torch.empty(gf.gf_conv_workspace_size(desc, cv, 1), dtype=torch.uint8, device=dev)
+    outs = {}
+
+    def step():
+        outs["q"] = gf.conv_forward(t["I_lo"], t["p_lo"], t["I_hi"], params, r, K, ws=ws)
+        outs["g"] = gf.conv_backward(t["I_lo"], t["p_lo"], t["I_hi"], params, t["dq"], r, K,
+                                     ws=ws)
+
+    kb = identity_bytes(n, c, H, W, h, w, 4)
+    # the statistics kernel runs in both calls (the backward recomputes them)
+    per_step = {"gf_apply": kb["apply"], "gf_bwd_hi": kb["bwd_hi"],
+                "gf_conv_stats": 2 * kb["coef"], "gf_conv_inputs_grad": kb["bwd_lo"]}
+    step_bytes = kb["apply"] + kb["bwd_hi"] + 2 * kb["coef"] + kb["bwd_lo"]
+    tp = {k: torch.tensor(P[k], dtype=torch.float32, device=dev, requires_grad=True)
+          for k in ("D", "W1", "W2", "W3")}
+    leaves = [t[k].clone().requires_grad_(True) for k in ("I_lo", "p_lo", "I_hi")]
+
+    def plain_step():
+        for x in leaves + list(tp.values()):
+            x.grad = None
+        plain.conv_guided_filter(*leaves, r, tp["D"], tp["W1"], tp["W2"], tp["W3"]).backward(
+            t["dq"])
+
+    def cpu_sample():
+        import oracle
+        args_np = [prob[k][:1].double().numpy() for k in ("I_lo", "p_lo", "I_hi")]
+        dq_np = prob["dq"][:1].double().numpy()
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            ref = {"q": oracle.conv_forward(*args_np, r, P)}
+            ref.update(oracle.conv_backward(*args_np, r, P, dq_np))
+            reps += 1
+            el = time.perf_counter() - t0
+            if el >= args.cpu_seconds or reps >= 20:
+                break
+        torch.cuda.synchronize()
+        got = {"q": outs["q"][:1].double().cpu().numpy(),
+               "dI_lo": outs["g"][0][:1].double().cpu().numpy(),
+               "dp_lo": outs["g"][1][:1].double().cpu().numpy(),
+               "dI_hi": outs["g"][2][:1].double().cpu().numpy()}
+        return (H * W / 1e6 * reps, el,
+                f"image 0 of the batch, fwd+bwd, repeated {reps}x ({el:.1f} s); parallel over "
+                f"its images (1)", 1, oracle_errors(got, ref))
+
+    return dict(step=step, plain_step=plain_step, cpu_sample=cpu_sample,
+                mpx=n * H * W / 1e6, per_step=per_step, step_bytes=step_bytes, dtype="f32",
+                config={"workload": "convolutional guided filtering layer fwd+bwd (Sec. III-E), "
+                                    "FP32, 4x3x2048x3072 <- 512x768 (s=4), dilation 1, block "
+                                    "6->16->16->3, grads to p_l, I_l, I_h and the parameters",
+                        "n": n, "c": c, "H": H, "W": W, "s": 4, "r": r, "hidden": K},
+                traffic_ok=False)
+
+
+WORKLOADS = {0: workload_0, 1: workload_1, 2: workload_2, 3: workload_3, 4: workload_4,
+             5: workload_5}
+
+
+def dgf_sweep(args, dev):
+    """The deep guided filtering network's inference chain (Sec. IV, Fig. 3):
+    area downsampling to I_l (short side 64), the low-res network C_l (the
+    context aggregation network of Table I with random weights, PyTorch
+    convolutions) and the guided filtering layer (r = 1, eps = 1e-8), over
+    square images 512^2 .. 3072^2 as in the paper's running-time figure
+    (Sec. V-D), and over I_l sizes 32 .. 512 at 2048^2 as in Table IV.  Per
+    size: median ms of the chain (eager, and replayed as a HIP graph), the
+    share of each step, and the peak device memory."""
+    import torch
+
+    from paper_1803_05619_amd import datagen, dgf, gf
+
+    net = dgf.CAN(seed=0).to(dev).eval()
+    iters = max(5, args.timing_iters)
+
+    def median_ms(fn):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(iters)]
+        for a, b in ev:
+            a.record()
+            fn()
+            b.record()
+        torch.cuda.synchronize()
+        ts = sorted(a.elapsed_time(b) for a, b in ev)
+        return ts[len(ts) // 2]
+
+    def one(S, lo):
+        rng = datagen.rng_for(5, S)
+        x = datagen.quantize(datagen.photo(rng, 3, S, S, noise=0.02)[None], "f32").to(dev)
+        h, w = dgf.low_res_size(S, S, lo)
+        ws = torch.empty(gf.gf_workspace_size(gf.make_desc(torch.empty(1, 3, h, w), x, 1), None,
+                                              0), dtype=torch.uint8, device=dev)
+        with torch.no_grad():
+            I_lo = gf.downsample(x, h, w)
+            p_lo = net(I_lo).contiguous()
+        torch.cuda.synchronize()
+        base = torch.cuda.memory_allocated(dev)
+        torch.cuda.reset_peak_memory_stats(dev)
+        chain_ms = median_ms(lambda: dgf.dgf_forward(x, net, lo=lo, ws=ws))
+        peak = torch.cuda.max_memory_allocated(dev)
+        rec = {"H": S, "W": S, "h": h, "w": w, "ms": round(chain_ms, 4),
+               "downsample_ms": round(median_ms(lambda: gf.downsample(x, h, w)), 4),
+               "can_ms": round(median_ms(lambda: net(I_lo)), 4),
+               "gf_layer_ms": round(median_ms(lambda: gf.forward(I_lo, p_lo, x, 1e-8, 1, ws=ws)),
+                                    4),
+               "peak_mem_bytes": int(peak), "input_bytes": int(x.numel() * 4),
+               "peak_mem_beyond_resident_bytes": int(peak - base)}
+        rec["gf_layer_share"] = round(rec["gf_layer_ms"] / chain_ms, 3)
+        try:
+            g = torch.cuda.CUDAGraph()
+            s = torch.cuda.Stream()
+            s.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(s):
+                for _ in range(2):
+                    out = dgf.dgf_forward(x, net, lo=lo, ws=ws)
+            torch.cuda.current_stream().wait_stream(s)
+            torch.cuda.synchronize()
+            with torch.cuda.graph(g):
+                out = dgf.dgf_forward(x, net, lo=lo, ws=ws)
+            torch.cuda.synchronize()
+            rec["graph_ms"] = round(median_ms(g.replay), 4)
+            ref = dgf.dgf_forward(x, net, lo=lo, ws=ws)
+            g.replay()
+            torch.cuda.synchronize()
+            rec["graph_matches_eager"] = bool(torch.equal(out, ref))
+            del g
+        except Exception as e:  # capture of the library's convolutions may be refused
+            rec["graph_ms"] = None
+            rec["graph_error"] = f"{type(e).__name__}: {e}"[:200]
+        log(f"DGF {S}^2 <- {h}x{w}: {rec}")
+        del x, ws, I_lo, p_lo
+        torch.cuda.empty_cache()
+        return rec
+
+    sweep = [one(S, 64) for S in (512, 1024, 1536, 2048, 2560, 3072)]
+    table4 = [one(2048, lo) for lo in (32, 64, 96, 128, 256, 512)]
+    at2048 = next(r for r in sweep if r["H"] == 2048)
+    best = lambda r: min(v for v in (r["ms"], r.get("graph_ms")) if v is not None)
+    out = {
+        "metric": "deep guided filtering network inference (area downsampling + C_l + guided "
+                  "filtering layer), ms per 2048x2048 image",
+        "value": round(best(at2048), 4), "unit": "ms", "n_gpus": 1, "steps": iters,
+        "warmup": 3, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": DATA + "; C_l with random weights",
+        "config": {"workload": "DGF_b inference, 1x3xSxS FP32, I_l short side 64, C_l = CAN "
+                               "(Table I, 24 channels, dilations 1,1,2,4,8,16,1), r=1, "
+                               "eps=1e-8"},
+        "sweep_512_to_3072": sweep, "table4_low_res_sweep_at_2048": table4,
+        "paper_context": {"hardware": "Nvidia Titan X (Pascal), Intel E5-2650 2.20GHz",
+                          "DGF_b_ms_at_2048": 6, "DGF_b_under_ms_512_to_3072": 10,
+                          "CAN_full_res_ms_at_2048": 160, "DGF_b_peak_mem_GB_at_3072": "< 1",
+                          "table4_ms": {"32": 6, "64": 6, "96": 6, "128": 7, "256": 7, "512": 19},
+                          "table4_mem_GB": {"32": 0.67, "64": 0.68, "96": 0.70, "128": 0.73,
+                                            "256": 0.87, "512": 1.41}},
+    }
+    print(json.dumps(out), flush=True)
 
 
 def flush_buffer(dev):
@@ -579,6 +769,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain PyTorch leg")
+    ap.add_argument("--dgf", action="store_true",
+                    help="time the deep guided filtering network's inference chain over "
+                         "512^2..3072^2 and the I_l sizes of Table IV instead of a workload")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run one 1 GiB device copy (torch copy_) as a known-size "
                          "reference for hardware byte counters")
@@ -593,6 +786,9 @@ def main():
     from paper_1803_05619_amd import gf
 
     dev = torch.device("cuda:0")
+    if args.dgf:
+        dgf_sweep(args, dev)
+        return
     if args.copy_probe:
         src = torch.ones(256 << 20, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)

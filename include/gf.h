@@ -35,8 +35,11 @@
  *        dq_hi, dI_hi    [n, c, h_hi, w_hi]   io_dtype
  *        dI_lo, dp_lo    [n, c, h_lo, w_lo]   float32 (any io_dtype)
  *        eps, deps       [eps_count]          float32, eps_count = 1 or n
- *  - h_hi = s * h_lo and w_hi = s * w_lo with one integer factor
- *    s in {1, 2, 4, 8}; other ratios return GF_ERR_UNSUPPORTED.
+ *  - Any sizes h_lo <= h_hi, w_lo <= w_hi (the ratio may differ per axis
+ *    and need not be an integer; Sec. III-A).  One integer factor
+ *    s in {1, 2, 4, 8} on both axes takes kernels with compile-time tap
+ *    weights; other ratios take general kernels with exact per-row and
+ *    per-column taps (the batched plans take the integer factors only).
  *  - The caller owns all memory.  Scratch memory is passed in as `ws`
  *    (device pointer, ws_bytes long, at least gf_workspace_size(...)).
  *    The library allocates nothing.
@@ -76,8 +79,8 @@ typedef struct {
   int32_t c;        /* channels; guide channel k filters input channel k  */
   int32_t h_lo;     /* low-res height                                     */
   int32_t w_lo;     /* low-res width                                      */
-  int32_t h_hi;     /* high-res height = s * h_lo                         */
-  int32_t w_hi;     /* high-res width  = s * w_lo                         */
+  int32_t h_hi;     /* high-res height >= h_lo                            */
+  int32_t w_hi;     /* high-res width  >= w_lo                            */
   int32_t r;        /* box radius, >= 0 (window side 2r + 1)              */
   int32_t mean_ab;  /* 1: window-mean A and b before upsampling; 0: not   */
   int32_t io_dtype; /* gf_dtype_t of I_lo, p_lo, I_hi, q_hi, dq_hi, dI_hi */
@@ -153,6 +156,61 @@ int32_t gf_backward(const gf_desc_t *desc, const gf_guide_t *guide,
                     const float *eps, int32_t eps_count, const void *dq_hi,
                     float *dI_lo, float *dp_lo, void *dI_hi, float *deps,
                     float *dparams, void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------- convolutional layer
+ * The convolutional guided filtering layer (Sec. III-E, the layer of the
+ * DGF_b^c variant): the mean filter becomes a learned 3x3 depthwise
+ * convolution per channel with dilation desc->r (>= 1), normalised by the
+ * same convolution of the all-ones image,
+ *   f_d(X)(m) = sum_t D[t] X(m + r t) / sum_t D[t] [m + r t in the image],
+ * and the local linear model a bias-free pointwise block on the per-pixel
+ * (cov_0..cov_{c-1}, var_0..var_{c-1}) of all channels:
+ *   A = W3 lrelu(W2 lrelu(W1 u))     (2c -> hidden -> hidden -> c)
+ * with mean_I = f_d(I), mean_p = f_d(p), cov = f_d(I p) - mean_I mean_p,
+ * var = f_d(I I) - mean_I^2; eps is dropped.  b = mean_p - A mean_I, the
+ * window means Abar = f_d(A), bbar = f_d(b) (desc->mean_ab), bilinear
+ * upsampling and q = A_h I_h + b_h as in gf_forward.  The paper fixes
+ * neither the normalisation nor the block's depth and widths; this is the
+ * library's reading (uniform D at r = 1 is the clipped box mean).
+ * desc->c in 1..4 (guide channel k filters output channel k), hidden in
+ * 1..16; the sum of each channel's in-image tap weights must be nonzero.
+ * Shapes and dtypes as for gf_forward / gf_backward (identity guide, any
+ * size ratio); params is a DEVICE float array of gf_conv_param_count
+ * entries: D [c][9] (taps row-major over (dy, dx) in {-1, 0, 1}^2) |
+ * W1 [hidden][2c] | W2 [hidden][hidden] | W3 [c][hidden]; dparams (nullable)
+ * receives the gradient in the same layout. */
+typedef struct {
+  int32_t hidden;        /* width of the pointwise block's hidden layers   */
+  float slope;           /* leaky-ReLU negative slope (derivative at 0)    */
+  const float *params;   /* DEVICE, gf_conv_param_count(c, hidden) floats  */
+} gf_conv_t;
+
+size_t gf_conv_param_count(int32_t c, int32_t hidden);
+size_t gf_conv_workspace_size(const gf_desc_t *desc, const gf_conv_t *conv,
+                              int32_t backward);
+int32_t gf_conv_forward(const gf_desc_t *desc, const gf_conv_t *conv,
+                        const void *I_lo, const void *p_lo, const void *I_hi,
+                        void *q_hi, void *ws, size_t ws_bytes, void *stream);
+/* Gradients of sum(q * dq_hi); each output may be NULL.  Recomputes the
+ * low-res statistics from the inputs. */
+int32_t gf_conv_backward(const gf_desc_t *desc, const gf_conv_t *conv,
+                         const void *I_lo, const void *p_lo, const void *I_hi,
+                         const void *dq_hi, float *dI_lo, float *dp_lo,
+                         void *dI_hi, float *dparams, void *ws, size_t ws_bytes,
+                         void *stream);
+
+/* Area downsampling, the first step of the deep guided filtering network
+ * (Sec. IV, Fig. 3: I_h is downsampled to obtain I_l).  I_lo
+ * [n, c, h_lo, w_lo] receives, per pixel (i, j), the mean of its covering
+ * rectangle of I_hi [n, c, h_hi, w_hi]: rows floor(i h_hi / h_lo) ..
+ * ceil((i + 1) h_hi / h_lo) - 1, columns likewise (the s x s block mean for
+ * an integer factor s).  Both tensors have io_dtype; sums run in float32
+ * and the result is rounded once.  Any h_lo <= h_hi, w_lo <= w_hi with
+ * n * c and h_lo at most 65535 and at most 8191 high-res columns per
+ * low-res pixel (GF_ERR_UNSUPPORTED otherwise).  No workspace. */
+int32_t gf_downsample(int32_t n, int32_t c, int32_t h_hi, int32_t w_hi,
+                      int32_t h_lo, int32_t w_lo, int32_t io_dtype,
+                      const void *I_hi, void *I_lo, void *stream);
 
 /* ------------------------------------------------------------- batched
  * Many independent problems of different sizes, factors, radii and eps

@@ -68,11 +68,14 @@ int make_plan(const gf_desc_t* d, const gf_guide_t* g, Plan* p, const char** why
   if (d->align_corners != 0 && d->align_corners != 1)
     return bad(GF_ERR_INVALID_ARG, "align_corners must be 0 or 1");
   if (dtype_size(d->io_dtype) == 0) return bad(GF_ERR_INVALID_ARG, "unknown io_dtype");
-  if (d->h_hi % d->h_lo || d->w_hi % d->w_lo || d->h_hi / d->h_lo != d->w_hi / d->w_lo)
-    return bad(GF_ERR_UNSUPPORTED, "high/low size ratio must be one integer factor for both axes");
-  const int S = d->h_hi / d->h_lo;
-  if (S != 1 && S != 2 && S != 4 && S != 8)
-    return bad(GF_ERR_UNSUPPORTED, "upsampling factor must be 1, 2, 4 or 8");
+  // one integer factor in {1, 2, 4, 8} for both axes takes the kernels with
+  // compile-time tap weights; any other ratio (per axis) the general ones
+  int S = 0;
+  if (d->h_hi % d->h_lo == 0 && d->w_hi % d->w_lo == 0 &&
+      d->h_hi / d->h_lo == d->w_hi / d->w_lo) {
+    S = d->h_hi / d->h_lo;
+    if (S != 1 && S != 2 && S != 4 && S != 8) S = 0;
+  }
   const double hi_elems = (double)d->n * d->c * d->h_hi * d->w_hi;
   if (hi_elems > 9.0e15 || (double)d->h_hi * d->w_hi > 2.0e9)
     return bad(GF_ERR_UNSUPPORTED, "problem too large");
@@ -112,6 +115,7 @@ int make_plan(const gf_desc_t* d, const gf_guide_t* g, Plan* p, const char** why
   q.ac = d->align_corners;
   q.dtype = d->io_dtype;
   q.S = S;
+  q.gen = S == 0;
   q.xcd = std::max(0, env_int("GF_XCD", 0));  // workgroup order run; see xcd_order
   q.planes = d->n * d->c;
   // elements per lane-load on the high-res side: 4 (16 bytes of float, 8 of
@@ -160,7 +164,7 @@ int make_plan(const gf_desc_t* d, const gf_guide_t* g, Plan* p, const char** why
     auto apply_wgs = [&](int rb) {
       return planes * ((d->h_hi + rb - 1) / rb) * (d->w_hi / vec) / 256;
     };
-    while (tv.RB > S && apply_wgs(tv.RB) < 256) tv.RB /= 2;
+    while (tv.RB > std::max(S, 1) && apply_wgs(tv.RB) < 256) tv.RB /= 2;
   }
   if (env_int("GF_LO_ROWS", 0) > 0) tv.coTR = tv.loTR = env_int("GF_LO_ROWS", 0);
   if (env_int("GF_BWD_LO_ROWS", 0) > 0) tv.loTR = env_int("GF_BWD_LO_ROWS", 0);
@@ -177,18 +181,28 @@ int make_plan(const gf_desc_t* d, const gf_guide_t* g, Plan* p, const char** why
   q.lo_ny = (q.h + q.loTR - 1) / q.loTR;
   q.loLDS = bwd_lo_lds_bytes(r);  // row buffers (+ input and X rings for large r)
 
-  q.RB = ((tv.RB + S - 1) / S) * S;  // whole low-res row blocks
+  q.RB = S ? ((tv.RB + S - 1) / S) * S : tv.RB;  // whole low-res row blocks
   q.nrb = (q.H + q.RB - 1) / q.RB;
   q.nxv = q.W / q.VEC;
 
-  q.tw = 64 * q.VEC / S;
-  q.hw = hi_merge(d->io_dtype == GF_F32, S) ? kHiWaves : 1;  // waves per high-res workgroup
-  q.bh = tv.bh;  // rows per wave; fewer when the workgroup's merge buffers would exceed 64 KB
-  while (q.bh > 2 && bwd_hi_lds_bytes(q.hw * q.bh, q.tw) > kHiLdsMax) --q.bh;
-  q.ubh = q.hw * q.bh;
-  q.hiLDS = bwd_hi_lds_bytes(q.ubh, q.tw);
-  q.nby = (q.h + q.ubh - 1) / q.ubh;
-  q.nbx = (q.W + 64 * q.VEC - 1) / (64 * q.VEC);
+  if (S) {
+    q.tw = 64 * q.VEC / S;
+    q.hw = hi_merge(d->io_dtype == GF_F32, S) ? kHiWaves : 1;  // waves per high-res workgroup
+    q.bh = tv.bh;  // rows per wave; fewer when the workgroup's merge buffers would exceed 64 KB
+    while (q.bh > 2 && bwd_hi_lds_bytes(q.hw * q.bh, q.tw) > kHiLdsMax) --q.bh;
+    q.ubh = q.hw * q.bh;
+    q.hiLDS = bwd_hi_lds_bytes(q.ubh, q.tw);
+    q.nby = (q.h + q.ubh - 1) / q.ubh;
+    q.nbx = (q.W + 64 * q.VEC - 1) / (64 * q.VEC);
+  } else {
+    // any ratio: the partial planes are one block per plane, the whole
+    // low-res plane with a border of one row and column
+    q.tw = q.w;
+    q.hw = 1;
+    q.bh = q.ubh = q.h;
+    q.hiLDS = 0;
+    q.nby = q.nbx = 1;
+  }
   q.ublk_floats = (size_t)2 * (q.ubh + 2) * (q.tw + 2);
   // the low-res walkers address a plane, and its partial planes, with
   // 32-bit byte offsets
@@ -204,7 +218,9 @@ int make_plan(const gf_desc_t* d, const gf_guide_t* g, Plan* p, const char** why
   // backward pass reads bbar while it writes them)
   q.off_u = q.off_bbar + align_up(lo_plane, 256);
   const size_t ubytes = (size_t)q.planes * q.nby * q.nbx * q.ublk_floats * sizeof(float);
-  q.off_eps = q.off_u + align_up(ubytes, 256);
+  q.off_v = q.off_u + align_up(ubytes, 256);
+  const size_t vbytes = q.gen ? (size_t)q.planes * 2 * q.h * q.W * sizeof(float) : 0;
+  q.off_eps = q.off_v + align_up(vbytes, 256);
   q.ws_bwd = q.off_eps + align_up((size_t)q.planes * q.lo_nx * q.lo_ny * sizeof(float), 256);
   if (gmode != GF_GUIDE_IDENTITY) {
     // guided path: the guide planes and the transform's reductions follow the
@@ -451,6 +467,226 @@ int32_t gf_forward_backward(const gf_desc_t* desc, const gf_guide_t* guide, cons
                             size_t ws_bytes, void* stream) {
   return run_backward(desc, guide, I_lo, p_lo, I_hi, eps, eps_count, dq_hi, q_hi, dI_lo, dp_lo,
                       dI_hi, deps, dparams, ws, ws_bytes, stream, true);
+}
+
+size_t gf_conv_param_count(int32_t c, int32_t hidden) {
+  if (c < 1 || c > gf::kConvMaxC || hidden < 1 || hidden > gf::kConvMaxK) return 0;
+  return (size_t)gf::conv_param_count(c, hidden);
+}
+
+}  // extern "C"
+
+namespace gf {
+namespace {
+// Plan of the convolutional layer: the high-res kernels' plan (the radius of
+// the box filter plays no part, the dilation lives in cp->r) and the
+// low-res workspace appended to that plan's layout.
+int make_conv_plan(const gf_desc_t* d, const gf_conv_t* cv, ConvPlan* cp, const char** why) {
+  static thread_local std::string msg;
+  auto bad = [&](int code, const std::string& m) {
+    msg = m;
+    *why = msg.c_str();
+    return code;
+  };
+  if (!d) return bad(GF_ERR_INVALID_ARG, "desc is NULL");
+  if (!cv) return bad(GF_ERR_INVALID_ARG, "conv is NULL");
+  if (d->r < 1) return bad(GF_ERR_INVALID_ARG, "dilation r must be >= 1");
+  if (d->r > 1 << 20) return bad(GF_ERR_UNSUPPORTED, "dilation too large");
+  if (d->c < 1 || d->c > kConvMaxC) return bad(GF_ERR_UNSUPPORTED, "channels must be 1..4");
+  if (cv->hidden < 1 || cv->hidden > kConvMaxK)
+    return bad(GF_ERR_UNSUPPORTED, "hidden width must be 1..16");
+  if (!cv->params) return bad(GF_ERR_INVALID_ARG, "conv params is NULL");
+  if (!(cv->slope >= 0.f) || !(cv->slope <= 1.f))
+    return bad(GF_ERR_INVALID_ARG, "leaky ReLU slope must be in [0, 1]");
+  gf_desc_t d1 = *d;
+  d1.r = 1;
+  int st = make_plan(&d1, nullptr, &cp->p, why);
+  if (st != GF_OK) return st;
+  if ((double)d->n * d->h_lo * d->w_lo > 2.0e9) return bad(GF_ERR_UNSUPPORTED, "problem too large");
+  cp->r = d->r;
+  cp->K = cv->hidden;
+  cp->slope = cv->slope;
+  cp->params = cv->params;
+  cp->nparam = conv_param_count(d->c, cv->hidden);
+  const long long npix = (long long)d->n * d->h_lo * d->w_lo;
+  const long long tiles = (npix + kConvTile - 1) / kConvTile;
+  cp->blk_grid = (int)std::min<long long>(tiles, kConvBlocks);
+  cp->ab_grid = (int)std::min<long long>(((long long)d->h_lo * d->w_lo + 255) / 256, 64);
+  const size_t lo = align_up((size_t)cp->p.planes * d->h_lo * d->w_lo * sizeof(float), 256);
+  size_t o = align_up(std::max(cp->p.ws_fwd, cp->p.ws_bwd), 256);
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o += align_up(bytes, 256);
+    return at;
+  };
+  cp->off_A = take(lo);
+  cp->off_B = take(lo);
+  cp->ws_fwd = o;
+  cp->off_mI = take(lo);
+  cp->off_mP = take(lo);
+  cp->off_cov = take(lo);
+  cp->off_var = take(lo);
+  cp->off_dAb = take(lo);
+  cp->off_dBb = take(lo);
+  cp->off_dA = take(lo);
+  cp->off_dB = take(lo);
+  cp->off_gmI = take(lo);
+  cp->off_gmP = take(lo);
+  cp->off_gcov = take(lo);
+  cp->off_gvar = take(lo);
+  cp->off_part = take((size_t)cp->blk_grid * cp->nparam * sizeof(float));
+  cp->off_partab = take((size_t)cp->p.planes * cp->ab_grid * 9 * sizeof(float));
+  cp->ws_bwd = o;
+  return GF_OK;
+}
+
+ConvArgs conv_args(const ConvPlan& cp, const gf_desc_t* d, const void* I_lo, const void* p_lo,
+                   char* ws, bool backward) {
+  auto f = [&](size_t off) { return reinterpret_cast<float*>(ws + off); };
+  ConvArgs a{};
+  a.I_lo = I_lo;
+  a.p_lo = p_lo;
+  a.params = cp.params;
+  a.n = d->n;
+  a.c = d->c;
+  a.h = d->h_lo;
+  a.w = d->w_lo;
+  a.r = cp.r;
+  a.K = cp.K;
+  a.nparam = cp.nparam;
+  a.mean_ab = d->mean_ab;
+  a.slope = cp.slope;
+  a.abar = f(cp.p.off_abar);
+  a.bbar = f(cp.p.off_bbar);
+  // without the window means, A and b are the upsampled planes themselves
+  a.A = d->mean_ab ? f(cp.off_A) : a.abar;
+  a.B = d->mean_ab ? f(cp.off_B) : a.bbar;
+  if (backward) {
+    a.mI = f(cp.off_mI);
+    a.mP = f(cp.off_mP);
+    a.cov = f(cp.off_cov);
+    a.var = f(cp.off_var);
+    a.dAb = f(cp.off_dAb);
+    a.dBb = f(cp.off_dBb);
+    a.dA = d->mean_ab ? f(cp.off_dA) : a.dAb;
+    a.dB = d->mean_ab ? f(cp.off_dB) : a.dBb;
+    a.gmI = f(cp.off_gmI);
+    a.gmP = f(cp.off_gmP);
+    a.gcov = f(cp.off_gcov);
+    a.gvar = f(cp.off_gvar);
+    a.part = f(cp.off_part);
+    a.partab = f(cp.off_partab);
+  }
+  a.blk_grid = cp.blk_grid;
+  a.ab_grid = cp.ab_grid;
+  return a;
+}
+}  // namespace
+}  // namespace gf
+
+extern "C" {
+
+size_t gf_conv_workspace_size(const gf_desc_t* desc, const gf_conv_t* conv, int32_t backward) {
+  gf::ConvPlan cp;
+  const char* why = nullptr;
+  if (gf::make_conv_plan(desc, conv, &cp, &why) != GF_OK) return 0;
+  return backward ? cp.ws_bwd : cp.ws_fwd;
+}
+
+int32_t gf_conv_forward(const gf_desc_t* desc, const gf_conv_t* conv, const void* I_lo,
+                        const void* p_lo, const void* I_hi, void* q_hi, void* ws,
+                        size_t ws_bytes, void* stream) {
+  gf::g_detail.clear();
+  gf::ConvPlan cp;
+  const char* why = nullptr;
+  int st = gf::make_conv_plan(desc, conv, &cp, &why);
+  if (st != GF_OK) return fail(st, why);
+  if (!I_lo || !p_lo || !I_hi || !q_hi) return fail(GF_ERR_INVALID_ARG, "a required pointer is NULL");
+  if (misaligned(I_lo) || misaligned(p_lo) || misaligned(I_hi) || misaligned(q_hi) ||
+      misaligned(ws) || misaligned(conv->params))
+    return fail(GF_ERR_INVALID_ARG, "tensor pointers must be 16-byte aligned");
+  if (!ws || ws_bytes < cp.ws_fwd)
+    return fail(GF_ERR_WORKSPACE, "workspace smaller than gf_conv_workspace_size(desc, conv, 0) = " +
+                                      std::to_string(cp.ws_fwd));
+  char* w = static_cast<char*>(ws);
+  const gf::ConvArgs a = gf::conv_args(cp, desc, I_lo, p_lo, w, false);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipErrorInvalidValue;
+  switch (desc->io_dtype) {
+    case GF_F32: e = gf::launch_conv_forward_f32(cp, a, I_hi, q_hi, w, s); break;
+    case GF_F16: e = gf::launch_conv_forward_f16(cp, a, I_hi, q_hi, w, s); break;
+    case GF_BF16: e = gf::launch_conv_forward_bf16(cp, a, I_hi, q_hi, w, s); break;
+  }
+  if (e != hipSuccess) return fail(GF_ERR_HIP, hipGetErrorString(e));
+  return GF_OK;
+}
+
+int32_t gf_conv_backward(const gf_desc_t* desc, const gf_conv_t* conv, const void* I_lo,
+                         const void* p_lo, const void* I_hi, const void* dq_hi, float* dI_lo,
+                         float* dp_lo, void* dI_hi, float* dparams, void* ws, size_t ws_bytes,
+                         void* stream) {
+  gf::g_detail.clear();
+  gf::ConvPlan cp;
+  const char* why = nullptr;
+  int st = gf::make_conv_plan(desc, conv, &cp, &why);
+  if (st != GF_OK) return fail(st, why);
+  if (!I_lo || !p_lo || !I_hi || !dq_hi)
+    return fail(GF_ERR_INVALID_ARG, "a required pointer is NULL");
+  if (misaligned(I_lo) || misaligned(p_lo) || misaligned(I_hi) || misaligned(dq_hi) ||
+      misaligned(dI_lo) || misaligned(dp_lo) || misaligned(dI_hi) || misaligned(dparams) ||
+      misaligned(ws) || misaligned(conv->params))
+    return fail(GF_ERR_INVALID_ARG, "tensor pointers must be 16-byte aligned");
+  if (!ws || ws_bytes < cp.ws_bwd)
+    return fail(GF_ERR_WORKSPACE, "workspace smaller than gf_conv_workspace_size(desc, conv, 1) = " +
+                                      std::to_string(cp.ws_bwd));
+  char* w = static_cast<char*>(ws);
+  gf::ConvArgs a = gf::conv_args(cp, desc, I_lo, p_lo, w, true);
+  a.dI_lo = dI_lo;
+  a.dp_lo = dp_lo;
+  a.dparams = dparams;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipErrorInvalidValue;
+  switch (desc->io_dtype) {
+    case GF_F32: e = gf::launch_conv_backward_f32(cp, a, I_hi, dq_hi, dI_hi, w, s); break;
+    case GF_F16: e = gf::launch_conv_backward_f16(cp, a, I_hi, dq_hi, dI_hi, w, s); break;
+    case GF_BF16: e = gf::launch_conv_backward_bf16(cp, a, I_hi, dq_hi, dI_hi, w, s); break;
+  }
+  if (e != hipSuccess) return fail(GF_ERR_HIP, hipGetErrorString(e));
+  return GF_OK;
+}
+
+int32_t gf_downsample(int32_t n, int32_t c, int32_t h_hi, int32_t w_hi, int32_t h_lo,
+                      int32_t w_lo, int32_t io_dtype, const void* I_hi, void* I_lo,
+                      void* stream) {
+  gf::g_detail.clear();
+  if (n < 1 || c < 1 || h_hi < 1 || w_hi < 1 || h_lo < 1 || w_lo < 1)
+    return fail(GF_ERR_INVALID_ARG, "sizes must be >= 1");
+  if (h_lo > h_hi || w_lo > w_hi)
+    return fail(GF_ERR_INVALID_ARG, "low-res size must not exceed high-res size");
+  if (gf::dtype_size(io_dtype) == 0) return fail(GF_ERR_INVALID_ARG, "unknown io_dtype");
+  if (!I_hi || !I_lo) return fail(GF_ERR_INVALID_ARG, "a required pointer is NULL");
+  if (misaligned(I_hi) || misaligned(I_lo))
+    return fail(GF_ERR_INVALID_ARG, "tensor pointers must be 16-byte aligned");
+  const long long planes = (long long)n * c;
+  if (planes > 65535 || h_lo > 65535 || (double)planes * h_hi * w_hi > 9.0e15)
+    return fail(GF_ERR_UNSUPPORTED, "problem too large");
+  // low-res columns per workgroup: at most 256, fewer while the high-res
+  // columns they cover exceed the LDS row buffer
+  int jc = std::min(256, (int)w_lo);
+  auto span = [&](int j) { return (int)(((long long)j * w_hi + w_lo - 1) / w_lo) + 1; };
+  while (jc > 1 && span(jc) > gf::kDownMaxSpan) jc /= 2;
+  if (span(jc) > gf::kDownMaxSpan)
+    return fail(GF_ERR_UNSUPPORTED, "a low-res pixel covers more than 8191 high-res columns");
+  gf::DownArgs a{I_hi, I_lo, (int)planes, h_hi, w_hi, h_lo, w_lo, jc, span(jc)};
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipErrorInvalidValue;
+  switch (io_dtype) {
+    case GF_F32: e = gf::launch_downsample_f32(a, s); break;
+    case GF_F16: e = gf::launch_downsample_f16(a, s); break;
+    case GF_BF16: e = gf::launch_downsample_bf16(a, s); break;
+  }
+  if (e != hipSuccess) return fail(GF_ERR_HIP, hipGetErrorString(e));
+  return GF_OK;
 }
 
 const char* gf_status_string(int32_t status) {

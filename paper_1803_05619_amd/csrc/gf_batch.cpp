@@ -136,6 +136,10 @@ int create(const gf_item_t* items, int count, gf_plan** out) {
     const char* why = nullptr;
     const int st = make_plan(&it.d, nullptr, &geo[k].p, &why);
     if (st != GF_OK) return set_error(st, tag + why);
+    if (geo[k].p.gen)
+      return set_error(GF_ERR_UNSUPPORTED,
+                       tag + "batched plans take one integer factor 1, 2, 4 or 8 for both "
+                             "axes (other ratios: gf_forward / gf_backward)");
     if (it.d.io_dtype != items[0].d.io_dtype)
       return set_error(GF_ERR_INVALID_ARG, tag + "io_dtype differs from item 0");
     if (!(it.eps >= 0.f) || !isfinite(it.eps))

@@ -1,5 +1,7 @@
 // Launchers of the guided filtering kernels for bf16 image I/O.
 #include "gf_guide.h"
+#include "gf_resample.h"
+#include "gf_conv.h"
 
 namespace gf {
 
@@ -21,6 +23,20 @@ hipError_t launch_backward_guided_bf16(const Plan& p, const BwdArgs& a, hipStrea
 
 hipError_t launch_batched_bf16(const BatchLaunch& b, int mode, char* ws, hipStream_t s) {
   return batched_t<bf16>(b, mode, ws, s);
+}
+
+hipError_t launch_downsample_bf16(const DownArgs& a, hipStream_t s) {
+  return downsample_t<bf16>(a, s);
+}
+
+hipError_t launch_conv_forward_bf16(const ConvPlan& cp, const ConvArgs& a, const void* I_hi,
+                                   void* q, char* ws, hipStream_t s) {
+  return conv_forward_t<bf16>(cp, a, I_hi, q, ws, s);
+}
+
+hipError_t launch_conv_backward_bf16(const ConvPlan& cp, const ConvArgs& a, const void* I_hi,
+                                    const void* dq, void* dI_hi, char* ws, hipStream_t s) {
+  return conv_backward_t<bf16>(cp, a, I_hi, dq, dI_hi, ws, s);
 }
 
 }  // namespace gf

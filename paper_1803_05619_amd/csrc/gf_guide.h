@@ -764,7 +764,8 @@ hipError_t backward_guided_t(const Plan& p, const BwdArgs& b, hipStream_t s) {
   // dG_h = dq * A_h (the guide gradient at high resolution) and the
   // transposed-bilinear partial planes (and q, in the same pass, with the
   // forward)
-  e = launch_bwd_hi<float, T, float, T>(p, Gh, b.dq, dGh, abar, U, s, bbar, b.q);
+  float* V = reinterpret_cast<float*>(b.ws + p.off_v);
+  e = launch_bwd_hi<float, T, float, T>(p, Gh, b.dq, dGh, abar, U, V, s, bbar, b.q);
   if (e != hipSuccess) return e;
   float* epart = reinterpret_cast<float*>(b.ws + p.off_eps);
   e = launch_bwd_lo<float, T>(p, Gl, b.p_lo, b.eps, b.eps_count, U, dGl, b.dp_lo, epart, s);

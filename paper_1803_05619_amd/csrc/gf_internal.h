@@ -19,7 +19,8 @@ namespace gf {
 struct Plan {
   int n, c, h, w, H, W, r, mean_ab, dtype;
   int ac;       // corner-aligned bilinear (align_corners)
-  int S;        // integer upsampling factor (H = S h, W = S w)
+  int S;        // integer upsampling factor (H = S h, W = S w); 0 for any other ratio
+  int gen;      // 1: any size ratio (the general high-res kernels), S = 0
   int xcd;      // XCD-aware workgroup order for the high-res kernels (0: off; see xcd_order)
   int VEC;      // high-res elements per thread-load (16 bytes, or 1)
   int planes;   // n * c
@@ -50,6 +51,9 @@ struct Plan {
   int g_chunks_lo, g_chunks_hi;
   // workspace layout (bytes)
   size_t off_abar, off_bbar, off_u, off_eps, ws_fwd, ws_bwd;
+  // any size ratio: the vertical adjoint's low-res rows x high-res columns
+  // (dA_bar and db_bar parts)
+  size_t off_v;
   // guided path: G_l, G_h (float planes), dG_l, dG_h, moments partials,
   // folded transform parameters (2 calls), accumulator partials/totals
   size_t off_gl, off_gh, off_dgl, off_dgh, off_mom, off_fold, off_accp, off_acct;
@@ -177,6 +181,30 @@ struct BwdHiArgs {
   void* q;
 };
 
+// The high-res kernels of problems of any size ratio (one problem each).
+struct GenArgs {
+  const void* G_hi;
+  const void* dq;
+  void* dI_hi;        // may be null
+  void* q;            // forward output (apply; the fused backward pass)
+  const float* abar;
+  const float* bbar;
+  float* V;           // [planes][2][h][W] vertical adjoint
+  float* U;           // [planes][2][h + 2][w + 2] partial planes, one block
+  int planes, h, w, H, W, RB, nrb, nxv;
+  long long total;    // threads of the launch
+};
+
+// Area downsampling (the DGF framework's I_h -> I_l): one workgroup per
+// (low-res column chunk of jc pixels, low-res row, plane); span = the most
+// high-res columns a chunk covers (its LDS floats).
+struct DownArgs {
+  const void* x;
+  void* y;
+  int planes, H, W, h, w, jc, span;
+};
+constexpr int kDownMaxSpan = 8192;
+
 struct BwdLoArgs {
   const void* I_lo;
   const void* p_lo;
@@ -190,6 +218,61 @@ struct BwdLoArgs {
   float* eps_part;  // [planes][pny][pnx]: one partial per strip segment
   int pnx, pny;     // strips and row segments per plane
 };
+
+// ------------------------------------------------------------ convolutional layer
+// The convolutional guided filtering layer (Sec. III-E): 3x3 depthwise
+// dilated convolutions (normalised by their response to ones) in place of
+// the box filter, a bias-free pointwise block 2c -> K -> K -> c on (cov,
+// var) in place of A = cov / (var + eps).  Parameters (device, float):
+// D [c][9] | W1 [K][2c] | W2 [K][K] | W3 [c][K].
+constexpr int kConvMaxC = 4, kConvMaxK = 16;
+constexpr int kConvTile = 128;   // pixels per tile of the parameter-gradient sums
+constexpr int kConvBlocks = 1024;  // most workgroups of those sums
+constexpr int conv_param_count(int c, int K) { return 9 * c + 2 * c * K + K * K + c * K; }
+
+struct ConvPlan {
+  Plan p;        // the high-res kernels' plan (and the identity workspace layout)
+  int r, K;      // dilation, hidden width
+  float slope;
+  const float* params;
+  int nparam;
+  int blk_grid;  // workgroups of the parameter-gradient sums over pixels
+  int ab_grid;   // workgroups per plane of the window-mean adjoint
+  // workspace (bytes): per-pixel statistics, coefficients and adjoints, all
+  // low-res float planes [n][c][h][w]; partial parameter gradients
+  size_t off_mI, off_mP, off_cov, off_var, off_A, off_B, off_dAb, off_dBb;
+  size_t off_gmI, off_gmP, off_gcov, off_gvar, off_dA, off_dB, off_part, off_partab;
+  size_t ws_fwd, ws_bwd;
+};
+
+struct ConvArgs {
+  const void* I_lo;
+  const void* p_lo;
+  const float* params;
+  int n, c, h, w, r, K, nparam, mean_ab;
+  float slope;
+  float *mI, *mP, *cov, *var, *A, *B, *abar, *bbar;
+  float *dAb, *dBb, *dA, *dB, *gmI, *gmP, *gcov, *gvar;
+  float *dI_lo, *dp_lo, *dparams;
+  float *part, *partab;
+  int blk_grid, ab_grid;
+  // the high-res backward's partial planes
+  const float* U;
+  int bh, tw, nby, nbx;
+};
+
+hipError_t launch_conv_forward_f32(const ConvPlan& cp, const ConvArgs& a, const void* I_hi,
+                                   void* q, char* ws, hipStream_t s);
+hipError_t launch_conv_forward_f16(const ConvPlan& cp, const ConvArgs& a, const void* I_hi,
+                                   void* q, char* ws, hipStream_t s);
+hipError_t launch_conv_forward_bf16(const ConvPlan& cp, const ConvArgs& a, const void* I_hi,
+                                    void* q, char* ws, hipStream_t s);
+hipError_t launch_conv_backward_f32(const ConvPlan& cp, const ConvArgs& a, const void* I_hi,
+                                    const void* dq, void* dI_hi, char* ws, hipStream_t s);
+hipError_t launch_conv_backward_f16(const ConvPlan& cp, const ConvArgs& a, const void* I_hi,
+                                    const void* dq, void* dI_hi, char* ws, hipStream_t s);
+hipError_t launch_conv_backward_bf16(const ConvPlan& cp, const ConvArgs& a, const void* I_hi,
+                                     const void* dq, void* dI_hi, char* ws, hipStream_t s);
 
 // ------------------------------------------------------------ batched launches
 // One launch per phase and launch class covers the tiles of many problems:
@@ -276,6 +359,10 @@ hipError_t launch_forward_f16(const Plan& p, const FwdArgs& a, hipStream_t s);
 hipError_t launch_backward_f16(const Plan& p, const BwdArgs& a, hipStream_t s);
 hipError_t launch_forward_bf16(const Plan& p, const FwdArgs& a, hipStream_t s);
 hipError_t launch_backward_bf16(const Plan& p, const BwdArgs& a, hipStream_t s);
+
+hipError_t launch_downsample_f32(const DownArgs& a, hipStream_t s);
+hipError_t launch_downsample_f16(const DownArgs& a, hipStream_t s);
+hipError_t launch_downsample_bf16(const DownArgs& a, hipStream_t s);
 
 // Profiling hooks (gf_api.cpp): wrap one kernel launch.
 void prof_begin(const char* name, hipStream_t s);

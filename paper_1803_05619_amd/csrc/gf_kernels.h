@@ -1541,6 +1541,249 @@ __global__ __launch_bounds__(256) void eps_reduce_kernel(const float* part, int 
   if (threadIdx.x == 0) deps[k] = ((red[0] + red[1]) + red[2]) + red[3];
 }
 
+// ------------------------------------------------------------ any size ratio
+//
+// Problems whose high-res size is not one integer factor {1, 2, 4, 8} of the
+// low-res size on both axes (the problem statement of Sec. III-A allows any
+// h_lo <= h_hi, w_lo <= w_hi).  The bilinear taps of every high-res row and
+// column come from exact integer quotients of the source coordinate, so the
+// kernels below take any ratio, per axis, and both alignments.
+//
+//   apply_gen_kernel     q = A_h G_h + b_h; a thread walks RB rows of VEC
+//                        columns and keeps the two interpolated low-res rows
+//                        its current row taps (recomputed when the tap row
+//                        moves).
+//   bwd_gen_rows_kernel  vertical adjoint: one thread per (low-res row i,
+//                        VEC high-res columns) sums the high-res rows whose
+//                        taps touch row i, weighted, into V (low-res rows x
+//                        high-res columns, dA_bar and db_bar parts); the rows
+//                        whose first tap is i also get dI_h = dq A_h (and q in
+//                        the fused pass), so each high-res pixel is written
+//                        once.  High-res rows are read by the (at most two)
+//                        low-res rows they touch.
+//   bwd_gen_cols_kernel  horizontal adjoint: one thread per low-res pixel sums
+//                        its V row over the columns whose taps touch it,
+//                        into the partial-plane layout of the low-res
+//                        backward as one block per plane.
+// No atomics: each output is one thread's fixed-order sum.
+
+// Taps of high-res index y on a low-res axis of n samples (high-res N >= n):
+// half-pixel source ((2y + 1) n - N) / (2N), clamped at 0, or corner-aligned
+// y (n - 1) / (N - 1); floor from the exact integer quotient, the weight
+// from the exact remainder (one rounding).
+template <bool AC>
+__device__ __forceinline__ Tap tap_gen(int y, int n, int N) {
+  Tap t;
+  if constexpr (AC) {
+    if (N <= 1 || n <= 1) {
+      t.i0 = t.i1 = 0;
+      t.w = 0.f;
+      return t;
+    }
+    const long long num = (long long)y * (n - 1);
+    const long long den = N - 1;
+    t.i0 = (int)(num / den);
+    t.w = (float)(num - (long long)t.i0 * den) / (float)den;
+  } else {
+    const long long num = (long long)(2 * y + 1) * n - N;
+    if (num <= 0) {
+      t.i0 = 0;
+      t.i1 = min(1, n - 1);
+      t.w = 0.f;
+      return t;
+    }
+    const long long den = 2LL * N;
+    t.i0 = (int)(num / den);
+    t.w = (float)(num - (long long)t.i0 * den) / (float)den;
+  }
+  t.i1 = min(t.i0 + 1, n - 1);
+  return t;
+}
+
+// Smallest high-res index whose first tap is >= k (N when there is none):
+// the high-res rows (columns) that touch low-res row i are
+// [first_tap_ge(i - 1), first_tap_ge(i + 1)).
+template <bool AC>
+__device__ __forceinline__ int first_tap_ge(int k, int n, int N) {
+  if (k <= 0) return 0;
+  long long y;
+  if constexpr (AC) {
+    if (n <= 1) return N;
+    const long long a = (long long)k * (N - 1), b = n - 1;
+    y = (a + b - 1) / b;
+  } else {
+    const long long a = 2LL * N * k + N - n, b = 2LL * n;
+    y = (a + b - 1) / b;
+  }
+  return (int)min((long long)N, y);
+}
+
+// Weight of high-res index y's taps on low-res index i.
+__device__ __forceinline__ float tap_weight(const Tap& t, int i) {
+  return (t.i0 == i ? 1.f - t.w : 0.f) + (t.i1 == i ? t.w : 0.f);
+}
+
+template <typename TG, typename TQ, int VEC, bool AC>
+__global__ __launch_bounds__(256) void apply_gen_kernel(GenArgs a) {
+  const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (t >= a.total) return;
+  const int xv = (int)(t % a.nxv);
+  const long long rest = t / a.nxv;
+  const int rb = (int)(rest % a.nrb);
+  const int plane = (int)(rest / a.nrb);
+  const int h = a.h, w = a.w, H = a.H, W = a.W;
+  const int x0 = xv * VEC;
+  int j0[VEC], j1[VEC];
+  float wx[VEC];
+#pragma unroll
+  for (int e = 0; e < VEC; ++e) {
+    const Tap tx = tap_gen<AC>(x0 + e, w, W);
+    j0[e] = tx.i0;
+    j1[e] = tx.i1;
+    wx[e] = tx.w;
+  }
+  const float* Ab = a.abar + (size_t)plane * h * w;
+  const float* Bb = a.bbar + (size_t)plane * h * w;
+  const size_t hofs = (size_t)plane * H * W + x0;
+  const TG* Gp = reinterpret_cast<const TG*>(a.G_hi) + hofs;
+  TQ* Qp = reinterpret_cast<TQ*>(a.q) + hofs;
+  float a0[VEC], a1[VEC], b0[VEC], b1[VEC];
+  int r0 = -1, r1 = -1;  // low-res rows held in a0/b0 and a1/b1
+  const int y_end = min(H, (rb + 1) * a.RB);
+  for (int y = rb * a.RB; y < y_end; ++y) {
+    const Tap ty = tap_gen<AC>(y, h, H);
+    if (ty.i0 != r0) {
+      if (ty.i0 == r1) {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+          a0[e] = a1[e];
+          b0[e] = b1[e];
+        }
+      } else {
+        hrow<VEC>(Ab, ty.i0, h, w, j0, j1, wx, a0);
+        hrow<VEC>(Bb, ty.i0, h, w, j0, j1, wx, b0);
+      }
+      r0 = ty.i0;
+      hrow<VEC>(Ab, ty.i1, h, w, j0, j1, wx, a1);
+      hrow<VEC>(Bb, ty.i1, h, w, j0, j1, wx, b1);
+      r1 = ty.i1;
+    }
+    float g[VEC], q[VEC];
+    load_vec_nt<TG, VEC>(Gp + (size_t)y * W, g);
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      const float A = a0[e] + ty.w * (a1[e] - a0[e]);
+      const float B = b0[e] + ty.w * (b1[e] - b0[e]);
+      q[e] = A * g[e] + B;
+    }
+    store_vec_nt<TQ, VEC>(Qp + (size_t)y * W, q);
+  }
+}
+
+template <typename TG, typename TD, typename TO, typename TQ, int VEC, bool AC, bool FWD>
+__global__ __launch_bounds__(256) void bwd_gen_rows_kernel(GenArgs a) {
+  const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (t >= a.total) return;
+  const int xv = (int)(t % a.nxv);
+  const long long rest = t / a.nxv;
+  const int i = (int)(rest % a.h);
+  const int plane = (int)(rest / a.h);
+  const int h = a.h, w = a.w, H = a.H, W = a.W;
+  const int x0 = xv * VEC;
+  int j0[VEC], j1[VEC];
+  float wx[VEC];
+#pragma unroll
+  for (int e = 0; e < VEC; ++e) {
+    const Tap tx = tap_gen<AC>(x0 + e, w, W);
+    j0[e] = tx.i0;
+    j1[e] = tx.i1;
+    wx[e] = tx.w;
+  }
+  // the coefficient rows of the high-res rows whose first tap is i: rows i
+  // and i + 1 (clamped)
+  const float* Ab = a.abar + (size_t)plane * h * w;
+  float a0[VEC], a1[VEC], b0[VEC], b1[VEC];
+  const bool need_a = a.dI_hi != nullptr || FWD;
+  if (need_a) {
+    hrow<VEC>(Ab, i, h, w, j0, j1, wx, a0);
+    hrow<VEC>(Ab, min(i + 1, h - 1), h, w, j0, j1, wx, a1);
+  }
+  if constexpr (FWD) {
+    const float* Bb = a.bbar + (size_t)plane * h * w;
+    hrow<VEC>(Bb, i, h, w, j0, j1, wx, b0);
+    hrow<VEC>(Bb, min(i + 1, h - 1), h, w, j0, j1, wx, b1);
+  }
+  const size_t hofs = (size_t)plane * H * W + x0;
+  const TG* Gp = reinterpret_cast<const TG*>(a.G_hi) + hofs;
+  const TD* Dp = reinterpret_cast<const TD*>(a.dq) + hofs;
+  TO* Op = reinterpret_cast<TO*>(a.dI_hi) + hofs;
+  TQ* Qp = reinterpret_cast<TQ*>(a.q) + hofs;
+  float vA[VEC], vB[VEC];
+#pragma unroll
+  for (int e = 0; e < VEC; ++e) vA[e] = vB[e] = 0.f;
+  const int y_beg = first_tap_ge<AC>(i - 1, h, H), y_end = first_tap_ge<AC>(i + 1, h, H);
+  for (int y = y_beg; y < y_end; ++y) {
+    const Tap ty = tap_gen<AC>(y, h, H);
+    const float wy = tap_weight(ty, i);
+    float g[VEC], d[VEC];
+    load_vec_nt<TG, VEC>(Gp + (size_t)y * W, g);
+    load_vec_nt<TD, VEC>(Dp + (size_t)y * W, d);
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      vA[e] += wy * (d[e] * g[e]);
+      vB[e] += wy * d[e];
+    }
+    if (ty.i0 == i) {
+      if (a.dI_hi) {
+        float o[VEC];
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) o[e] = d[e] * (a0[e] + ty.w * (a1[e] - a0[e]));
+        store_vec_nt<TO, VEC>(Op + (size_t)y * W, o);
+      }
+      if constexpr (FWD) {
+        float q[VEC];
+#pragma unroll
+        for (int e = 0; e < VEC; ++e)
+          q[e] = (a0[e] + ty.w * (a1[e] - a0[e])) * g[e] + (b0[e] + ty.w * (b1[e] - b0[e]));
+        store_vec_nt<TQ, VEC>(Qp + (size_t)y * W, q);
+      }
+    }
+  }
+  float* V = a.V + (size_t)plane * 2 * h * W + (size_t)i * W + x0;
+#pragma unroll
+  for (int e = 0; e < VEC; ++e) {
+    V[e] = vA[e];
+    V[(size_t)h * W + e] = vB[e];
+  }
+}
+
+// One thread per low-res pixel (i, j) of a plane; writes dA_bar and db_bar
+// at row i + 1, column j + 1 of the plane's single partial block
+// (2 x (h + 2) x (w + 2) floats, the layout the low-res backward gathers).
+template <bool AC>
+__global__ __launch_bounds__(256) void bwd_gen_cols_kernel(GenArgs a) {
+  const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+  const int h = a.h, w = a.w, W = a.W;
+  if (t >= (long long)a.planes * h * w) return;
+  const int j = (int)(t % w);
+  const long long rest = t / w;
+  const int i = (int)(rest % h);
+  const int plane = (int)(rest / h);
+  const float* VA = a.V + (size_t)plane * 2 * h * W + (size_t)i * W;
+  const float* VB = VA + (size_t)h * W;
+  float sA = 0.f, sB = 0.f;
+  const int x_beg = first_tap_ge<AC>(j - 1, w, W), x_end = first_tap_ge<AC>(j + 1, w, W);
+  for (int x = x_beg; x < x_end; ++x) {
+    const float wt = tap_weight(tap_gen<AC>(x, w, W), j);
+    sA += wt * VA[x];
+    sB += wt * VB[x];
+  }
+  const size_t UP = (size_t)(h + 2) * (w + 2);
+  float* U = a.U + (size_t)plane * 2 * UP + (size_t)(i + 1) * (w + 2) + (j + 1);
+  U[0] = sA;
+  U[UP] = sB;
+}
+
 // ------------------------------------------------------------ batched (multi-problem) kernels
 
 template <typename T>
@@ -1728,9 +1971,76 @@ hipError_t with_hires_shape(int S, int VEC, int ac, F&& f) {
   return hipErrorInvalidValue;
 }
 
+// Any size ratio: the general high-res kernels (VEC 4 or 1, both alignments).
+template <typename F>
+hipError_t with_gen_shape(int VEC, int ac, F&& f) {
+  auto by_ac = [&](auto vc) -> hipError_t {
+    if (ac) return f(vc, std::integral_constant<bool, true>{});
+    return f(vc, std::integral_constant<bool, false>{});
+  };
+  if (VEC == 1) return by_ac(std::integral_constant<int, 1>{});
+  return by_ac(std::integral_constant<int, kVec>{});
+}
+
+inline GenArgs gen_args(const Plan& p, const void* G_hi, const void* dq, void* out, void* q,
+                        const float* abar, const float* bbar, float* V, float* U) {
+  return GenArgs{G_hi, dq, out, q, abar, bbar, V, U, p.planes, p.h, p.w, p.H, p.W, p.RB,
+                 p.nrb, p.nxv, 0};
+}
+
+template <typename TG, typename TQ>
+hipError_t launch_apply_gen(const Plan& p, const void* G_hi, void* q, const float* abar,
+                            const float* bbar, hipStream_t s) {
+  GenArgs a = gen_args(p, G_hi, nullptr, nullptr, q, abar, bbar, nullptr, nullptr);
+  a.total = (long long)p.planes * p.nrb * p.nxv;
+  const unsigned blocks = (unsigned)((a.total + 255) / 256);
+  prof_begin("gf_apply_gen", s);
+  hipError_t e = with_gen_shape(p.VEC, p.ac, [&](auto vc, auto acc) {
+    hipLaunchKernelGGL((apply_gen_kernel<TG, TQ, decltype(vc)::value, decltype(acc)::value>),
+                       dim3(blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+  });
+  prof_end(s);
+  return e;
+}
+
+// Vertical then horizontal adjoint into one partial block per plane (and
+// dI_h, and q with the forward).
+template <typename TG, typename TD, typename TO, typename TQ>
+hipError_t launch_bwd_gen(const Plan& p, const void* G_hi, const void* dq, void* out,
+                          const float* abar, float* U, float* V, const float* bbar, void* q,
+                          hipStream_t s) {
+  GenArgs a = gen_args(p, G_hi, dq, out, q, abar, bbar, V, U);
+  a.total = (long long)p.planes * p.h * p.nxv;
+  prof_begin(q ? "gf_fwd_bwd_gen_rows" : "gf_bwd_gen_rows", s);
+  hipError_t e = with_gen_shape(p.VEC, p.ac, [&](auto vc, auto acc) {
+    constexpr int VV = decltype(vc)::value;
+    constexpr bool AA = decltype(acc)::value;
+    const unsigned blocks = (unsigned)((a.total + 255) / 256);
+    if (q)
+      hipLaunchKernelGGL((bwd_gen_rows_kernel<TG, TD, TO, TQ, VV, AA, true>), dim3(blocks),
+                         dim3(256), 0, s, a);
+    else
+      hipLaunchKernelGGL((bwd_gen_rows_kernel<TG, TD, TO, TQ, VV, AA, false>), dim3(blocks),
+                         dim3(256), 0, s, a);
+    return hipGetLastError();
+  });
+  prof_end(s);
+  if (e != hipSuccess) return e;
+  const unsigned blocks = (unsigned)(((long long)p.planes * p.h * p.w + 255) / 256);
+  prof_begin("gf_bwd_gen_cols", s);
+  if (p.ac)
+    hipLaunchKernelGGL((bwd_gen_cols_kernel<true>), dim3(blocks), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((bwd_gen_cols_kernel<false>), dim3(blocks), dim3(256), 0, s, a);
+  prof_end(s);
+  return hipGetLastError();
+}
+
 template <typename TG, typename TQ>
 hipError_t launch_apply(const Plan& p, const void* G_hi, void* q, const float* abar,
                         const float* bbar, hipStream_t s) {
+  if (p.gen) return launch_apply_gen<TG, TQ>(p, G_hi, q, abar, bbar, s);
   return with_hires_shape(p.S, p.VEC, p.ac, [&](auto sc, auto vc, auto acc) {
     return launch_apply_t<TG, TQ, decltype(sc)::value, decltype(vc)::value, decltype(acc)::value>(
         p, G_hi, q, abar, bbar, s);
@@ -1739,10 +2049,13 @@ hipError_t launch_apply(const Plan& p, const void* G_hi, void* q, const float* a
 
 // With q set, the fused pass: forward output and backward in one read of
 // G_h and dq (bbar needed then).
+// V: the general kernels' vertical adjoint (workspace at off_v; unused for
+// the integer factors).
 template <typename TG, typename TD, typename TO, typename TQ = TD>
 hipError_t launch_bwd_hi(const Plan& p, const void* G_hi, const void* dq, void* out,
-                         const float* abar, float* U, hipStream_t s,
+                         const float* abar, float* U, float* V, hipStream_t s,
                          const float* bbar = nullptr, void* q = nullptr) {
+  if (p.gen) return launch_bwd_gen<TG, TD, TO, TQ>(p, G_hi, dq, out, abar, U, V, bbar, q, s);
   return with_hires_shape(p.S, p.VEC, p.ac, [&](auto sc, auto vc, auto acc) {
     constexpr int SS = decltype(sc)::value, VV = decltype(vc)::value;
     constexpr bool AA = decltype(acc)::value;
@@ -1802,7 +2115,8 @@ hipError_t backward_t(const Plan& p, const BwdArgs& b, hipStream_t s) {
   hipError_t err = launch_coef<T, T>(p, b.I_lo, b.p_lo, b.eps, b.eps_count, abar, bbar, s);
   if (err != hipSuccess) return err;
   // with the forward: one high-res pass writes q, dI_h and the partial planes
-  err = launch_bwd_hi<T, T, T, T>(p, b.I_hi, b.dq, b.dI_hi, abar, U, s, bbar, b.q);
+  float* V = reinterpret_cast<float*>(b.ws + p.off_v);
+  err = launch_bwd_hi<T, T, T, T>(p, b.I_hi, b.dq, b.dI_hi, abar, U, V, s, bbar, b.q);
   if (err != hipSuccess) return err;
   if (!b.dI_lo && !b.dp_lo && !b.deps) return hipSuccess;
   float* part = reinterpret_cast<float*>(b.ws + p.off_eps);

@@ -87,6 +87,44 @@ def area_down(x: np.ndarray, sy: int, sx: int) -> np.ndarray:
     return x.reshape(*lead, H // sy, sy, W // sx, sx).mean(axis=(-3, -1))
 
 
+def area_resize(x: np.ndarray, h: int, w: int) -> np.ndarray:
+    """Area mean to (h, w) for any size ratio over the last two axes: output
+    pixel i covers input rows [floor(i H / h), ceil((i + 1) H / h)), likewise
+    columns (the s x s mean when H = s h).  Input generation only."""
+    *lead, H, W = x.shape
+    rows = [(i * H // h, -(-(i + 1) * H // h)) for i in range(h)]
+    cols = [(j * W // w, -(-(j + 1) * W // w)) for j in range(w)]
+    tmp = np.stack([x[..., a:b, :].mean(axis=-2) for a, b in rows], axis=-2)
+    return np.stack([tmp[..., a:b].mean(axis=-1) for a, b in cols], axis=-1)
+
+
+def make_problem_sizes(n: int, c: int, H: int, W: int, h: int, w: int, r: int, eps,
+                       io_dtype: str, config: int, noise: float = 0.0,
+                       with_dq: bool = True) -> dict:
+    """Like make_problem, for any low-res size h <= H, w <= W (the size
+    ratio need not be an integer, nor the same on both axes): I_l is the
+    area mean of the quantised I_h."""
+    I_hi = torch.empty((n, c, H, W), dtype=TORCH_DTYPES[io_dtype])
+    I_lo = torch.empty((n, c, h, w), dtype=TORCH_DTYPES[io_dtype])
+    p_lo = torch.empty((n, c, h, w), dtype=TORCH_DTYPES[io_dtype])
+    dq = torch.empty((n, c, H, W), dtype=TORCH_DTYPES[io_dtype]) if with_dq else None
+    for b in range(n):
+        rng = rng_for(config, b, salt=3)
+        ih = quantize(photo(rng, c, H, W, noise=noise), io_dtype)
+        il = quantize(area_resize(ih.double().numpy(), h, w), io_dtype)
+        pl = np.clip(0.8 * il.double().numpy() + 0.1 * rng.normal(0.0, 0.05, size=(c, h, w)),
+                     0.0, 1.0)
+        I_hi[b] = ih
+        I_lo[b] = il
+        p_lo[b] = quantize(pl, io_dtype)
+        if with_dq:
+            dq[b] = quantize(rng.standard_normal((c, H, W)), io_dtype)
+    eps_arr = np.atleast_1d(np.asarray(eps, dtype=np.float64))
+    return {"I_lo": I_lo, "p_lo": p_lo, "I_hi": I_hi, "dq": dq, "r": int(r),
+            "eps": eps_arr.astype(np.float32).astype(np.float64), "s": None, "sx": None,
+            "io_dtype": io_dtype, "n": n, "c": c, "H": H, "W": W, "h": h, "w": w}
+
+
 def guide_params(rng: np.random.Generator, cin: int = 3, cout: int = 3, hidden: int = 15) -> dict:
     """Random parameters of the 3 -> hidden -> 3 guidance transform."""
     return {

@@ -66,6 +66,24 @@ lib.gf_forward_backward.restype = ctypes.c_int32
 lib.gf_forward_backward_static.argtypes = [_dp, _gp, _vp, _vp, _vp, _fp, ctypes.c_int32, _vp,
                                            _vp, _fp, _fp, _vp, _fp, _fp, _vp]
 lib.gf_forward_backward_static.restype = ctypes.c_int32
+lib.gf_downsample.argtypes = [ctypes.c_int32] * 7 + [_vp, _vp, _vp]
+lib.gf_downsample.restype = ctypes.c_int32
+
+
+class gf_conv_t(ctypes.Structure):
+    _fields_ = [("hidden", ctypes.c_int32), ("slope", ctypes.c_float), ("params", ctypes.c_void_p)]
+
+
+_cp = ctypes.POINTER(gf_conv_t)
+lib.gf_conv_param_count.argtypes = [ctypes.c_int32, ctypes.c_int32]
+lib.gf_conv_param_count.restype = ctypes.c_size_t
+lib.gf_conv_workspace_size.argtypes = [_dp, _cp, ctypes.c_int32]
+lib.gf_conv_workspace_size.restype = ctypes.c_size_t
+lib.gf_conv_forward.argtypes = [_dp, _cp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+lib.gf_conv_forward.restype = ctypes.c_int32
+lib.gf_conv_backward.argtypes = [_dp, _cp, _vp, _vp, _vp, _vp, _fp, _fp, _vp, _fp, _vp,
+                                 ctypes.c_size_t, _vp]
+lib.gf_conv_backward.restype = ctypes.c_int32
 GF_RUN_FORWARD, GF_RUN_BACKWARD, GF_RUN_GRAPH = 1, 2, 4
 
 
@@ -195,6 +213,29 @@ def gf_forward_backward_static(desc, guide, I_lo, p_lo, I_hi, eps, eps_count, dq
     return int(lib.gf_forward_backward_static(ctypes.byref(desc), _gref(guide), I_lo, p_lo, I_hi,
                                               eps, eps_count, dq_hi, q_hi, dI_lo, dp_lo, dI_hi,
                                               deps, dparams, stream))
+
+
+def gf_downsample(n, c, h_hi, w_hi, h_lo, w_lo, io_dtype, I_hi, I_lo, stream) -> int:
+    return int(lib.gf_downsample(n, c, h_hi, w_hi, h_lo, w_lo, io_dtype, I_hi, I_lo, stream))
+
+
+def gf_conv_param_count(c: int, hidden: int) -> int:
+    return int(lib.gf_conv_param_count(int(c), int(hidden)))
+
+
+def gf_conv_workspace_size(desc, conv, backward: int) -> int:
+    return int(lib.gf_conv_workspace_size(ctypes.byref(desc), ctypes.byref(conv), int(backward)))
+
+
+def gf_conv_forward(desc, conv, I_lo, p_lo, I_hi, q_hi, ws, ws_bytes, stream) -> int:
+    return int(lib.gf_conv_forward(ctypes.byref(desc), ctypes.byref(conv), I_lo, p_lo, I_hi,
+                                   q_hi, ws, ws_bytes, stream))
+
+
+def gf_conv_backward(desc, conv, I_lo, p_lo, I_hi, dq_hi, dI_lo, dp_lo, dI_hi, dparams, ws,
+                     ws_bytes, stream) -> int:
+    return int(lib.gf_conv_backward(ctypes.byref(desc), ctypes.byref(conv), I_lo, p_lo, I_hi,
+                                    dq_hi, dI_lo, dp_lo, dI_hi, dparams, ws, ws_bytes, stream))
 
 
 def gf_status_string(code: int) -> str:
@@ -418,6 +459,109 @@ def forward_backward(I_lo, p_lo, I_hi, eps, dq, r=1, mean_ab=True, ws=None, outs
     if st != GF_OK:
         raise GFError(st)
     return q, dI_lo, dp_lo, dI_hi, deps, dparams
+
+
+def downsample(I_hi: torch.Tensor, h: int, w: int, out: torch.Tensor = None) -> torch.Tensor:
+    """I_l = area downsampling of I_hi [n, c, H, W] to (h, w): one
+    gf_downsample call on the current stream (the first step of the deep
+    guided filtering network, Sec. IV)."""
+    dev = I_hi.device
+    _check(dict(I_hi=I_hi, out=out), I_hi.dtype, dev)
+    n, c, H, W = I_hi.shape
+    if out is None:
+        out = torch.empty((n, c, int(h), int(w)), dtype=I_hi.dtype, device=dev)
+    st = gf_downsample(n, c, H, W, int(h), int(w), DTYPE_CODES[I_hi.dtype], _ptr(I_hi),
+                       _ptr(out), _stream(dev))
+    if st != GF_OK:
+        raise GFError(st)
+    return out
+
+
+# ------------------------------------------------------------------ convolutional layer
+
+CONV_HIDDEN = 16
+
+
+def pack_conv_params(D, W1, W2, W3, device=None) -> torch.Tensor:
+    """Flat float32 parameters of the convolutional layer: D [c][3][3] |
+    W1 [K][2c] | W2 [K][K] | W3 [c][K]."""
+    parts = [torch.as_tensor(x, dtype=torch.float32).reshape(-1) for x in (D, W1, W2, W3)]
+    return torch.cat(parts).to(device).contiguous()
+
+
+def _conv_struct(params, hidden, slope):
+    return gf_conv_t(int(hidden), float(slope), _ptr(params))
+
+
+def conv_forward(I_lo, p_lo, I_hi, params, r=1, hidden=CONV_HIDDEN, slope=0.2, mean_ab=True,
+                 out=None, ws=None, align_corners=False):
+    """q of the convolutional guided filtering layer (Sec. III-E): one
+    gf_conv_forward call on the current stream; r is the dilation."""
+    dev = I_hi.device
+    _check(dict(I_lo=I_lo, p_lo=p_lo, I_hi=I_hi, out=out), I_hi.dtype, dev)
+    _check(dict(params=params), torch.float32, dev)
+    desc = make_desc(I_lo, I_hi, r, mean_ab, align_corners=align_corners)
+    cv = _conv_struct(params, hidden, slope)
+    q = out if out is not None else torch.empty_like(I_hi)
+    ws = _ws(gf_conv_workspace_size(desc, cv, 0), dev, ws)
+    st = gf_conv_forward(desc, cv, _ptr(I_lo), _ptr(p_lo), _ptr(I_hi), _ptr(q), _ptr(ws),
+                         ws.numel(), _stream(dev))
+    if st != GF_OK:
+        raise GFError(st)
+    return q
+
+
+def conv_backward(I_lo, p_lo, I_hi, params, dq, r=1, hidden=CONV_HIDDEN, slope=0.2,
+                  mean_ab=True, need_dI_lo=True, need_dp_lo=True, need_dI_hi=True,
+                  need_dparams=True, ws=None, align_corners=False):
+    """(dI_lo, dp_lo, dI_hi, dparams) of the convolutional layer; the low-res
+    gradients and dparams are float32."""
+    dev = I_hi.device
+    _check(dict(I_lo=I_lo, p_lo=p_lo, I_hi=I_hi, dq=dq), I_hi.dtype, dev)
+    _check(dict(params=params), torch.float32, dev)
+    desc = make_desc(I_lo, I_hi, r, mean_ab, align_corners=align_corners)
+    cv = _conv_struct(params, hidden, slope)
+    f32 = dict(dtype=torch.float32, device=dev)
+    dI_lo = torch.empty(I_lo.shape, **f32) if need_dI_lo else None
+    dp_lo = torch.empty(p_lo.shape, **f32) if need_dp_lo else None
+    dI_hi = torch.empty_like(I_hi) if need_dI_hi else None
+    dparams = torch.empty(params.numel(), **f32) if need_dparams else None
+    ws = _ws(gf_conv_workspace_size(desc, cv, 1), dev, ws)
+    st = gf_conv_backward(desc, cv, _ptr(I_lo), _ptr(p_lo), _ptr(I_hi), _ptr(dq), _ptr(dI_lo),
+                          _ptr(dp_lo), _ptr(dI_hi), _ptr(dparams), _ptr(ws), ws.numel(),
+                          _stream(dev))
+    if st != GF_OK:
+        raise GFError(st)
+    return dI_lo, dp_lo, dI_hi, dparams
+
+
+class ConvGuidedFilterFn(torch.autograd.Function):
+    """Differentiable convolutional guided filtering layer; the backward
+    recomputes the low-res statistics from the saved inputs."""
+
+    @staticmethod
+    def forward(ctx, I_lo, p_lo, I_hi, params, r, hidden, slope, mean_ab):
+        ctx.cfg = (r, hidden, slope, mean_ab)
+        ctx.save_for_backward(I_lo, p_lo, I_hi, params)
+        return conv_forward(I_lo, p_lo, I_hi, params, r, hidden, slope, mean_ab)
+
+    @staticmethod
+    def backward(ctx, dq):
+        I_lo, p_lo, I_hi, params = ctx.saved_tensors
+        r, hidden, slope, mean_ab = ctx.cfg
+        need = ctx.needs_input_grad
+        dI_lo, dp_lo, dI_hi, dparams = conv_backward(
+            I_lo, p_lo, I_hi, params, dq.contiguous(), r, hidden, slope, mean_ab,
+            need_dI_lo=need[0], need_dp_lo=need[1], need_dI_hi=need[2], need_dparams=need[3])
+        cast = lambda g, ref: None if g is None else g.to(ref.dtype)
+        return cast(dI_lo, I_lo), cast(dp_lo, p_lo), dI_hi, dparams, None, None, None, None
+
+
+def conv_guided_filter(I_lo, p_lo, I_hi, params, r=1, hidden=CONV_HIDDEN, slope=0.2,
+                       mean_ab=True):
+    """The convolutional guided filtering layer with autograd (gradients to
+    I_lo, p_lo, I_hi and params)."""
+    return ConvGuidedFilterFn.apply(I_lo, p_lo, I_hi, params, r, hidden, slope, mean_ab)
 
 
 class GuidedFilterFn(torch.autograd.Function):

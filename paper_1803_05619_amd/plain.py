@@ -43,3 +43,32 @@ def guide_transform(x, w1, w2, b2, lam, mu, gamma, beta, bn_eps=1e-5, slope=0.2)
     bn = gamma.view(1, -1, 1, 1) * (h - m) / torch.sqrt(v + bn_eps) + beta.view(1, -1, 1, 1)
     y = lam * h + mu * bn
     return F.conv2d(F.leaky_relu(y, slope), w2[:, :, None, None], b2)
+
+
+def _conv_fd(x, D, r):
+    c = x.shape[1]
+    Dw = D.reshape(c, 1, 3, 3)
+    num = F.conv2d(x, Dw, padding=r, dilation=r, groups=c)
+    den = F.conv2d(torch.ones_like(x[:1]), Dw, padding=r, dilation=r, groups=c)
+    return num / den
+
+
+def conv_guided_filter(I_lo, p_lo, I_hi, r, D, W1, W2, W3, slope=0.2, mean_ab=True):
+    """The convolutional guided filtering layer (Sec. III-E) as framework
+    operators in float32: normalised dilated depthwise convolutions for the
+    window means, a pointwise block of 1x1 convolutions on (cov, var),
+    bilinear upsampling."""
+    I_lo, p_lo, I_hi = I_lo.float(), p_lo.float(), I_hi.float()
+    mI, mP = _conv_fd(I_lo, D, r), _conv_fd(p_lo, D, r)
+    cov = _conv_fd(I_lo * p_lo, D, r) - mI * mP
+    var = _conv_fd(I_lo * I_lo, D, r) - mI * mI
+    z = F.leaky_relu(F.conv2d(torch.cat([cov, var], 1), W1[:, :, None, None]), slope)
+    z = F.leaky_relu(F.conv2d(z, W2[:, :, None, None]), slope)
+    A = F.conv2d(z, W3[:, :, None, None])
+    b = mP - A * mI
+    if mean_ab:
+        A, b = _conv_fd(A, D, r), _conv_fd(b, D, r)
+    size = I_hi.shape[-2:]
+    A_h = F.interpolate(A, size=size, mode="bilinear", align_corners=False)
+    b_h = F.interpolate(b, size=size, mode="bilinear", align_corners=False)
+    return A_h * I_hi + b_h

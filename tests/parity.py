@@ -117,3 +117,42 @@ def check(res, label=""):
     bad = {k: v for k, v in res.items() if not v[0] <= v[1]}
     assert not bad, bad
     return res
+
+
+# ---------------------------------------------------------------- convolutional layer
+
+CONV_TILE, CONV_BLOCKS = 128, 1024
+
+
+def conv_sum_bar(n_pix: int, h: int, w: int, planes: int) -> float:
+    """Rounding bound of the convolutional layer's parameter-gradient sums:
+    per tile a sequential sum of CONV_TILE pixels, per workgroup a sequential
+    sum over its tiles, then the fixed-order total over the workgroups (and,
+    for D, over the window-mean adjoint's per-plane partials); each term
+    formed with at most 32 roundings."""
+    tiles = -(-n_pix // CONV_TILE)
+    grid = min(tiles, CONV_BLOCKS)
+    ab = min(-(-(h * w) // 256), 64)
+    depth = CONV_TILE + -(-tiles // grid) + grid + planes * ab + 256
+    return (depth + 32) * U32
+
+
+def measure_conv(got, ref, io, n, c, h, w, hidden):
+    """Errors and bars of the convolutional layer's outputs: per-pixel ones as
+    in measure(); each parameter group (D, W1, W2, W3) entry by entry passes
+    when within TOL[io] of the group's largest |ref| or within the rounding
+    bound of its sum (reported as the smaller ratio to its bar)."""
+    tol = TOL[io]
+    res = measure({k: v for k, v in got.items() if k != "dparams"}, ref, io)
+    if "dparams" in got:
+        d = np.abs(got["dparams"] - ref["dparams"])
+        bar = conv_sum_bar(n * h * w, h, w, n * c)
+        e_sum = d / np.maximum(ref["dparams_abs"], 1e-300) / bar
+        dg = oracle.conv_split(d, c, hidden)
+        sg = oracle.conv_split(e_sum, c, hidden)
+        rg = oracle.conv_split(ref["dparams"], c, hidden)
+        for g in oracle.CONV_GROUPS:
+            er = np.asarray(dg[g]) / max(float(np.abs(rg[g]).max()), 1e-300)
+            res[f"d{g}"] = (float(np.minimum(er / tol, np.asarray(sg[g])).max()), 1.0)
+            res[f"d{g}_rel(info)"] = (float(er.max()), math.inf)
+    return res

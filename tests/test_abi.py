@@ -53,9 +53,6 @@ FAKE = 0x10000  # aligned, never dereferenced: every case below fails validation
     (dict(mean_ab=2), gf.GF_ERR_INVALID_ARG),
     (dict(io_dtype=7), gf.GF_ERR_INVALID_ARG),
     (dict(align_corners=2), gf.GF_ERR_INVALID_ARG),
-    (dict(h_hi=250), gf.GF_ERR_UNSUPPORTED),
-    (dict(h_hi=192, w_hi=288), gf.GF_ERR_UNSUPPORTED),    # factor 3
-    (dict(h_hi=128), gf.GF_ERR_UNSUPPORTED),              # different factors per axis
     (dict(r=40), gf.GF_ERR_UNSUPPORTED),
     # a low-res plane above 2^31 bytes (the walkers' 32-bit buffer offsets)
     (dict(h_lo=24000, w_lo=24000, h_hi=24000, w_hi=24000), gf.GF_ERR_UNSUPPORTED),
@@ -249,3 +246,36 @@ def test_static_scratch_entry_checks_on_the_host():
     st = gf.gf_forward_backward_static(desc(r=-1), None, FAKE, FAKE, FAKE, FAKE, 1, FAKE, FAKE,
                                        FAKE, FAKE, FAKE, FAKE, None, None)
     assert st == gf.GF_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("kw", [dict(h_hi=250), dict(h_hi=192, w_hi=288), dict(h_hi=128),
+                                dict(h_lo=1, w_lo=1), dict(h_hi=64 * 48, w_hi=96 * 48)])
+def test_any_size_ratio_is_accepted(kw):
+    """Any h_lo <= h_hi, w_lo <= w_hi (non-integer ratios, different ratios
+    per axis, integer factors outside {1, 2, 4, 8}) plans a workspace."""
+    d = desc(**kw)
+    for k in (0, 1, 2):
+        assert gf.gf_workspace_size(d, None, k) > 0, gf.gf_last_error_detail()
+
+
+def test_batched_plan_rejects_other_ratios():
+    item = gf.gf_item_t()
+    item.d = desc(n=1, h_hi=250)
+    item.eps = 1e-3
+    item.I_lo = item.p_lo = item.I_hi = item.q_hi = FAKE
+    items = (gf.gf_item_t * 1)(item)
+    st, plan = gf.gf_plan_create(items, 1)
+    assert st == gf.GF_ERR_UNSUPPORTED and plan is None
+    assert "integer factor" in gf.gf_last_error_detail()
+
+
+@pytest.mark.parametrize("args, code", [
+    ((1, 3, 64, 64, 65, 64, 0), gf.GF_ERR_INVALID_ARG),     # low-res larger than high-res
+    ((0, 3, 64, 64, 16, 16, 0), gf.GF_ERR_INVALID_ARG),
+    ((1, 3, 64, 64, 16, 16, 9), gf.GF_ERR_INVALID_ARG),     # unknown dtype
+    ((1, 3, 2, 20000, 1, 1, 0), gf.GF_ERR_UNSUPPORTED),     # one pixel covers 20000 columns
+])
+def test_downsample_checks_on_the_host(args, code):
+    assert gf.gf_downsample(*args, FAKE, FAKE, None) == code
+    assert gf.gf_downsample(1, 3, 64, 64, 16, 16, 0, None, FAKE, None) == gf.GF_ERR_INVALID_ARG
+    assert gf.gf_downsample(1, 3, 64, 64, 16, 16, 0, FAKE + 4, FAKE, None) == gf.GF_ERR_INVALID_ARG

@@ -244,3 +244,17 @@ def test_guided_align_corners(mode):
     ref = {"q": oracle.forward(*args, prob["r"], prob["eps"], **gkw)}
     ref.update(oracle.backward(*args, prob["r"], prob["eps"], prob["dq"].double().numpy(), **gkw))
     parity.check(measure(prob, mode, got, ref, align_corners=True))
+
+
+@pytest.mark.parametrize("mode", ["grey", "transform"])
+def test_guided_any_ratio(mode):
+    """Guided paths at a size ratio that is no integer factor (the general
+    high-res kernels under the guide maps)."""
+    prob = datagen.make_problem_sizes(2, 3, 250, 300, 64, 96, 1, 1e-3, "f32", config=195,
+                                      noise=0.02)
+    if mode == "grey":
+        prob["p_lo"] = prob["p_lo"][:, :2].contiguous()
+        prob["dq"] = prob["dq"][:, :2].contiguous()
+    else:
+        prob["guide"] = datagen.guide_params(datagen.rng_for(195, 0, salt=1))
+    check(prob, mode)

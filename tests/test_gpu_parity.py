@@ -282,3 +282,59 @@ def test_degenerate_shapes(h, w, s):
     """One-pixel, one-row and one-column low-res images."""
     prob = datagen.make_problem(2, 3, s * h, s * w, s, 1, 1e-2, "f32", config=182, noise=0.02)
     check(prob)
+
+
+# ------------------------------------------------------------ any size ratio
+
+# (h, w, H, W): non-integer ratios, ratios that differ per axis, integer
+# factors outside {1, 2, 4, 8}, one-pixel low-res axes
+ANY_RATIO = [
+    (5, 7, 13, 10),
+    (64, 96, 250, 300),
+    (32, 48, 64, 192),      # factor 2 vertically, 4 horizontally
+    (48, 64, 144, 192),     # factor 3
+    (30, 40, 480, 640),     # factor 16
+    (20, 30, 960, 1440),    # factor 48 (a 64-pixel I_l under a large I_h)
+    (1, 9, 7, 37),
+    (9, 1, 40, 3),
+]
+
+
+@pytest.mark.parametrize("h, w, H, W", ANY_RATIO)
+@pytest.mark.parametrize("ac", [False, True])
+def test_any_ratio(h, w, H, W, ac):
+    """Sizes the problem statement allows (any h <= H, w <= W): the general
+    high-res kernels, forward and backward, against the oracle."""
+    prob = datagen.make_problem_sizes(2, 3, H, W, h, w, 1 + (h * w) % 2, [1e-3, 1e-2], "f32",
+                                      config=190, noise=0.02)
+    check(prob, align_corners=ac)
+
+
+@pytest.mark.parametrize("dt", ["bf16", "f16"])
+def test_any_ratio_half_io(dt):
+    prob = datagen.make_problem_sizes(2, 3, 250, 300, 64, 96, 2, 1e-4, dt, config=191,
+                                      noise=0.02)
+    check(prob)
+
+
+def test_any_ratio_without_ab_mean_and_scalar_width():
+    """Algorithm 1's form (no window mean of A, b) and a width that is not a
+    multiple of 4."""
+    prob = datagen.make_problem_sizes(1, 3, 101, 203, 40, 70, 1, 1e-3, "f32", config=192,
+                                      noise=0.02)
+    check(prob, mean_ab=False)
+
+
+def test_any_ratio_forward_backward_equals_separate_calls():
+    gf = _gf()
+    prob = datagen.make_problem_sizes(2, 3, 250, 300, 64, 96, 1, [1e-4, 1e-2], "f32",
+                                      config=193, noise=0.02)
+    d = to_dev(prob)
+    print("case any-ratio fused call 64x96 -> 250x300", flush=True)
+    q = gf.forward(d["I_lo"], d["p_lo"], d["I_hi"], prob["eps"], prob["r"])
+    g = gf.backward(d["I_lo"], d["p_lo"], d["I_hi"], prob["eps"], d["dq"], prob["r"])
+    fb = gf.forward_backward(d["I_lo"], d["p_lo"], d["I_hi"], prob["eps"], d["dq"], prob["r"])
+    torch.cuda.synchronize()
+    assert torch.equal(fb[0], q)
+    for a, b in zip(fb[1:5], g[:4]):
+        assert torch.equal(a, b)
