@@ -671,10 +671,14 @@ int32_t gf_downsample(int32_t n, int32_t c, int32_t h_hi, int32_t w_hi, int32_t 
   if (planes > 65535 || h_lo > 65535 || (double)planes * h_hi * w_hi > 9.0e15)
     return fail(GF_ERR_UNSUPPORTED, "problem too large");
   // low-res columns per workgroup: at most 256, fewer while the high-res
-  // columns they cover exceed the LDS row buffer
+  // columns they cover exceed the LDS row buffer, and fewer (down to 4)
+  // while the grid would not give the chip a few workgroups per CU (a 64 x 64
+  // I_l under a 3072^2 I_h is 192 rows x planes otherwise)
   int jc = std::min(256, (int)w_lo);
   auto span = [&](int j) { return (int)(((long long)j * w_hi + w_lo - 1) / w_lo) + 1; };
   while (jc > 1 && span(jc) > gf::kDownMaxSpan) jc /= 2;
+  auto wgs = [&](int j) { return planes * h_lo * (long long)((w_lo + j - 1) / j); };
+  while (jc > 4 && wgs(jc) < 2048) jc /= 2;
   if (span(jc) > gf::kDownMaxSpan)
     return fail(GF_ERR_UNSUPPORTED, "a low-res pixel covers more than 8191 high-res columns");
   gf::DownArgs a{I_hi, I_lo, (int)planes, h_hi, w_hi, h_lo, w_lo, jc, span(jc)};

@@ -21,8 +21,8 @@
 //                           as a 9-tap gather) and those uses' weight terms
 //   conv_bwd_block_kernel   b's adjoint, the block's backward, the adjoint
 //                           inputs of the statistics, and the pixel sums of
-//                           the parameter gradients (per-tile vectors in LDS,
-//                           one thread per parameter entry)
+//                           the parameter gradients (the weight products on
+//                           the matrix cores, 4 pixels per instruction)
 //   conv_inputs_grad_kernel dI_l, dp_l: transposed statistics as a gather
 //   conv_param_reduce_kernel  fixed-order totals of the partial sums
 // No atomics; every sum runs in a fixed order (bitwise reproducible).
@@ -36,9 +36,6 @@ namespace gf {
 namespace {
 
 constexpr int kConvParamMax = conv_param_count(kConvMaxC, kConvMaxK);
-// per-pixel floats a tile keeps in LDS for the parameter sums:
-// u [2c], z1 [K], z2 [K], dy1 [K], dy2 [K], dA [c], the weight terms [9c]
-constexpr int kConvVec = 2 * kConvMaxC + 4 * kConvMaxK + kConvMaxC + 9 * kConvMaxC;
 
 __device__ __forceinline__ float lrelu_f(float y, float s) { return y > 0.f ? y : s * y; }
 __device__ __forceinline__ float lrelu_df(float y, float s) { return y > 0.f ? 1.f : s; }
@@ -113,11 +110,12 @@ __global__ __launch_bounds__(256) void conv_stats_kernel(ConvArgs a) {
   __shared__ float prm[kConvParamMax];
   load_params(a, prm);
   const int h = a.h, w = a.w, c = a.c, r = a.r;
-  const long long P = (long long)h * w;
-  const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (t >= (long long)a.n * P) return;
+  // pixel indices in 32 bits (the planner keeps n h w below 2^31)
+  const unsigned P = (unsigned)h * (unsigned)w;
+  const unsigned t = blockIdx.x * 256u + threadIdx.x;
+  if (t >= (unsigned)a.n * P) return;
   const int b = (int)(t / P);
-  const int m = (int)(t - (long long)b * P);
+  const int m = (int)(t - (unsigned)b * P);
   const int i = m / w, j = m - (m / w) * w;
   const float* W1 = prm + 9 * c;
   const float* W2 = W1 + 2 * c * a.K;
@@ -180,13 +178,15 @@ __global__ __launch_bounds__(256) void conv_stats_kernel(ConvArgs a) {
 // Abar = f_d(A), bbar = f_d(b): one thread per plane pixel.
 __global__ __launch_bounds__(256) void conv_fd_ab_kernel(ConvArgs a) {
   const int h = a.h, w = a.w, c = a.c, r = a.r;
-  const long long P = (long long)h * w;
-  const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (t >= (long long)a.n * c * P) return;
+  const unsigned P = (unsigned)h * (unsigned)w;
+  const unsigned t = blockIdx.x * 256u + threadIdx.x;
+  if (t >= (unsigned)(a.n * c) * P) return;
   const int plane = (int)(t / P);
-  const int m = (int)(t - (long long)plane * P);
+  const int m = (int)(t - (unsigned)plane * P);
   const int i = m / w, j = m - (m / w) * w;
-  const float* Dk = a.params + 9 * (plane % c);
+  float Dk[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) Dk[q] = a.params[9 * (plane % c) + q];
   const float* A = a.A + (size_t)plane * P;
   const float* B = a.B + (size_t)plane * P;
   float N = 0.f, sa = 0.f, sb = 0.f;
@@ -208,11 +208,11 @@ __global__ __launch_bounds__(256) void conv_fd_ab_kernel(ConvArgs a) {
 // quantity whose border rows and columns overlap the neighbouring blocks'.
 __global__ __launch_bounds__(256) void conv_collapse_kernel(ConvArgs a) {
   const int h = a.h, w = a.w;
-  const long long P = (long long)h * w;
-  const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (t >= (long long)a.n * a.c * P) return;
+  const unsigned P = (unsigned)h * (unsigned)w;
+  const unsigned t = blockIdx.x * 256u + threadIdx.x;
+  if (t >= (unsigned)(a.n * a.c) * P) return;
   const int plane = (int)(t / P);
-  const int m = (int)(t - (long long)plane * P);
+  const int m = (int)(t - (unsigned)plane * P);
   const int i = m / w, j = m - (m / w) * w;
   const int bh = a.bh, tw = a.tw, UW = tw + 2;
   const size_t UP = (size_t)(bh + 2) * UW;
@@ -264,7 +264,12 @@ __global__ __launch_bounds__(256) void conv_fdT_ab_kernel(ConvArgs a) {
   const int h = a.h, w = a.w, r = a.r;
   const int plane = blockIdx.y;
   const int P = h * w;
-  const float* Dk = a.params + 9 * (plane % a.c);
+  float Dk[9], Dsum = 0.f;
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    Dk[q] = a.params[9 * (plane % a.c) + q];
+    Dsum += Dk[q];
+  }
   const size_t pofs = (size_t)plane * P;
   const float *A = a.A + pofs, *B = a.B + pofs, *Ab = a.abar + pofs, *Bb = a.bbar + pofs;
   const float *gA = a.dAb + pofs, *gB = a.dBb + pofs;
@@ -273,6 +278,9 @@ __global__ __launch_bounds__(256) void conv_fdT_ab_kernel(ConvArgs a) {
   for (int q = 0; q < 9; ++q) acc[q] = 0.f;
   for (int m = blockIdx.x * 256 + threadIdx.x; m < P; m += 256 * gridDim.x) {
     const int i = m / w, j = m - (m / w) * w;
+    // pixels at least 2r from every border: all windows that touch them are
+    // whole, so every normaliser is the sum of the weights
+    const bool inner = i >= 2 * r && i < h - 2 * r && j >= 2 * r && j < w - 2 * r;
     float dA = 0.f, dB = 0.f;
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
@@ -280,14 +288,14 @@ __global__ __launch_bounds__(256) void conv_fdT_ab_kernel(ConvArgs a) {
       const int oi = i - (q / 3 - 1) * r, oj = j - (q % 3 - 1) * r;
       if ((unsigned)oi < (unsigned)h && (unsigned)oj < (unsigned)w) {
         const int o = oi * w + oj;
-        const float wq = Dk[q] / conv_norm(Dk, oi, oj, r, h, w);
+        const float wq = Dk[q] / (inner ? Dsum : conv_norm(Dk, oi, oj, r, h, w));
         dA += wq * gA[o];
         dB += wq * gB[o];
       }
     }
     a.dA[pofs + m] = dA;
     a.dB[pofs + m] = dB;
-    const float rN = 1.f / conv_norm(Dk, i, j, r, h, w);
+    const float rN = 1.f / (inner ? Dsum : conv_norm(Dk, i, j, r, h, w));
     const float ga = gA[m] * rN, gb = gB[m] * rN;
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
@@ -306,42 +314,81 @@ __global__ __launch_bounds__(256) void conv_fdT_ab_kernel(ConvArgs a) {
 // Per pixel: b = mean_p - A mean_I and the block backward (dA through W3,
 // W2, W1 to (dcov, dvar)); the statistics' adjoint inputs (gmI, gmP, gcov,
 // gvar: the direct gradients of mean_I, mean_p and of cov, var as whole
-// functions of the taps) are stored for conv_inputs_grad_kernel.  The pixel
-// sums of the parameter gradients: each tile of kConvTile pixels writes its
-// per-pixel vectors to LDS and thread e adds entry e's products over the
-// tile; workgroups stride over tiles and write one partial per entry.
+// functions of the taps) are stored for conv_inputs_grad_kernel.
+//
+// The pixel sums of the block's weight gradients are matrix products with
+// the pixels as the contraction: dW2 = sum_p dy2_p z1_p^T, dW1 = sum_p dy1_p
+// u_p^T, dW3 = sum_p dA_p z2_p^T (16 x 16 at most).  Each wave (one pixel
+// per lane) stages a pair of per-pixel vectors in its LDS block (pixel-major,
+// 16 floats per pixel) and accumulates them on the matrix cores,
+// v_mfma_f32_16x16x4f32 taking 4 pixels per instruction: lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16], the two operands read from the
+// same 64 consecutive floats (no bank conflicts).  The accumulators stay in
+// registers across the wave's tiles (lane l, register g holds row
+// 4 (l / 16) + g, column l % 16); the 27 weight terms of D are summed per
+// lane in registers.  At the end each wave's sums go to an LDS row and the
+// workgroup writes the waves' rows summed in wave order.  The hardware's
+// accumulation order is fixed, so results are reproducible.
+constexpr int kConvWaves = 4;
+typedef float conv_f4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// Adds sum over the wave's 64 pixels of a_p b_p^T (16-vectors staged in
+// S[0] and S[1], pixel-major) to C.
+__device__ __forceinline__ conv_f4 mfma_pixels(const float* S0, const float* S1, int lane,
+                                               conv_f4 C) {
+#pragma unroll
+  for (int g = 0; g < 16; ++g)
+    C = __builtin_amdgcn_mfma_f32_16x16x4f32(S0[64 * g + lane], S1[64 * g + lane], C, 0, 0, 0);
+  return C;
+}
+
 template <typename T>
-__global__ __launch_bounds__(kConvTile) void conv_bwd_block_kernel(ConvArgs a) {
+__global__ __launch_bounds__(64 * kConvWaves) void conv_bwd_block_kernel(ConvArgs a) {
   __shared__ float prm[kConvParamMax];
-  __shared__ float vec[kConvVec][kConvTile];
+  __shared__ float stage[kConvWaves][2][64 * 16];
+  __shared__ float wacc[kConvWaves][kConvParamMax];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   load_params(a, prm);
   const int h = a.h, w = a.w, c = a.c, r = a.r, K = a.K;
   const long long P = (long long)h * w, total = (long long)a.n * P;
   const float* W1 = prm + 9 * c;
   const float* W2 = W1 + 2 * c * K;
   const float* W3 = W2 + K * K;
-  // LDS rows of the per-pixel vectors
-  const int ru = 0, rz1 = 2 * c, rz2 = rz1 + K, ry1 = rz2 + K, ry2 = ry1 + K, rdA = ry2 + K,
-            rD = rdA + c;
-  // this thread's parameter entries: e = threadIdx.x + kConvTile * s
-  constexpr int kSlots = (kConvParamMax + kConvTile - 1) / kConvTile;
-  float acc[kSlots];
+  float* S0 = stage[wave][0];
+  float* S1 = stage[wave][1];
+  conv_f4 C1 = {0.f, 0.f, 0.f, 0.f}, C2 = C1, C3 = C1;
+  float dacc[kConvMaxC][9];
 #pragma unroll
-  for (int s = 0; s < kSlots; ++s) acc[s] = 0.f;
-  const long long tiles = (total + kConvTile - 1) / kConvTile;
+  for (int k = 0; k < kConvMaxC; ++k)
+#pragma unroll
+    for (int q = 0; q < 9; ++q) dacc[k][q] = 0.f;
+  constexpr int kTile = 64 * kConvWaves;
+  const long long tiles = (total + kTile - 1) / kTile;
   for (long long tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
-    const long long t = tile * kConvTile + threadIdx.x;
-    const int tid = threadIdx.x;
-    if (t < total) {
-      const int b = (int)(t / P);
-      const int m = (int)(t - (long long)b * P);
-      const int i = m / w, j = m - (m / w) * w;
-      float u[2 * kConvMaxC], mi[kConvMaxC], mp[kConvMaxC], Ak[kConvMaxC], dAt[kConvMaxC];
+    const long long t = tile * kTile + threadIdx.x;
+    float u[2 * kConvMaxC], dAt[kConvMaxC];
+    float y1[kConvMaxK], z1[kConvMaxK], y2[kConvMaxK], z2[kConvMaxK];
+    float dy2[kConvMaxK], dy1[kConvMaxK];
 #pragma unroll
-      for (int e = 0; e < 2 * kConvMaxC; ++e) u[e] = 0.f;
+    for (int e = 0; e < 2 * kConvMaxC; ++e) u[e] = 0.f;
+#pragma unroll
+    for (int k = 0; k < kConvMaxC; ++k) dAt[k] = 0.f;
+#pragma unroll
+    for (int e = 0; e < kConvMaxK; ++e) y1[e] = z1[e] = y2[e] = z2[e] = dy1[e] = dy2[e] = 0.f;
+    if (t < total) {
+      const int b = (int)((unsigned)t / (unsigned)P);
+      const int m = (int)((unsigned)t - (unsigned)b * (unsigned)P);
+      const int i = m / w, j = m - (m / w) * w;
+      float mi[kConvMaxC], mp[kConvMaxC], Ak[kConvMaxC], dBk[kConvMaxC];
 #pragma unroll
       for (int k = 0; k < kConvMaxC; ++k) {
-        mi[k] = mp[k] = Ak[k] = dAt[k] = 0.f;
+        mi[k] = mp[k] = Ak[k] = dBk[k] = 0.f;
         if (k >= c) continue;
         const size_t o = (size_t)(b * c + k) * P + m;
         mi[k] = a.mI[o];
@@ -349,38 +396,37 @@ __global__ __launch_bounds__(kConvTile) void conv_bwd_block_kernel(ConvArgs a) {
         u[k] = a.cov[o];
         u[c + k] = a.var[o];
         Ak[k] = a.A[o];
-        const float dB = a.dB[o];
-        dAt[k] = a.dA[o] - dB * mi[k];
-        a.gmP[o] = dB;
-        a.gmI[o] = -dB * Ak[k];
+        dBk[k] = a.dB[o];
+        dAt[k] = a.dA[o] - dBk[k] * mi[k];
+        a.gmP[o] = dBk[k];
+        a.gmI[o] = -dBk[k] * Ak[k];
       }
-      float y1[kConvMaxK], z1[kConvMaxK], y2[kConvMaxK], z2[kConvMaxK], Ar[kConvMaxC];
+      float Ar[kConvMaxC];
       conv_block(W1, W2, W3, c, K, a.slope, u, y1, z1, y2, z2, Ar);
-      float dy2[kConvMaxK], dy1[kConvMaxK];
 #pragma unroll
       for (int e = 0; e < kConvMaxK; ++e) {
-        float s = 0.f;
+        float sacc = 0.f;
 #pragma unroll
         for (int k = 0; k < kConvMaxC; ++k)
-          if (k < c && e < K) s += W3[k * K + e] * dAt[k];
-        dy2[e] = s * lrelu_df(y2[e], a.slope);
+          if (k < c && e < K) sacc += W3[k * K + e] * dAt[k];
+        dy2[e] = sacc * lrelu_df(y2[e], a.slope);
       }
 #pragma unroll
       for (int e = 0; e < kConvMaxK; ++e) {
-        float s = 0.f;
+        float sacc = 0.f;
 #pragma unroll
         for (int q = 0; q < kConvMaxK; ++q)
-          if (q < K && e < K) s += W2[q * K + e] * dy2[q];
-        dy1[e] = s * lrelu_df(y1[e], a.slope);
+          if (q < K && e < K) sacc += W2[q * K + e] * dy2[q];
+        dy1[e] = sacc * lrelu_df(y1[e], a.slope);
       }
       float du[2 * kConvMaxC];
 #pragma unroll
       for (int e = 0; e < 2 * kConvMaxC; ++e) {
-        float s = 0.f;
+        float sacc = 0.f;
 #pragma unroll
         for (int q = 0; q < kConvMaxK; ++q)
-          if (q < K && e < 2 * c) s += W1[q * 2 * c + e] * dy1[q];
-        du[e] = s;
+          if (q < K && e < 2 * c) sacc += W1[q * 2 * c + e] * dy1[q];
+        du[e] = sacc;
       }
       // the statistics' weight terms at this pixel, per channel and tap
 #pragma unroll
@@ -394,73 +440,68 @@ __global__ __launch_bounds__(kConvTile) void conv_bwd_block_kernel(ConvArgs a) {
         const T* pk = reinterpret_cast<const T*>(a.p_lo) + pofs;
         const float* Dk = prm + 9 * k;
         const float rN = 1.f / conv_norm(Dk, i, j, r, h, w);
-        const float gmI = -a.dB[pofs + m] * Ak[k], gmP = a.dB[pofs + m];
+        const float gmI = -dBk[k] * Ak[k], gmP = dBk[k];
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
           int o;
-          float term = 0.f;
           if (conv_tap(i, j, q, r, h, w, o)) {
             const float di = to_f(Ik[o]) - mi[k], dp = to_f(pk[o]) - mp[k];
-            term = (gmI * di + gmP * dp + dcov * (di * dp - u[k]) + dvar * (di * di - u[c + k])) *
-                   rN;
+            dacc[k][q] += (gmI * di + gmP * dp + dcov * (di * dp - u[k]) +
+                           dvar * (di * di - u[c + k])) * rN;
           }
-          vec[rD + 9 * k + q][tid] = term;
         }
       }
-#pragma unroll
-      for (int e = 0; e < 2 * kConvMaxC; ++e)
-        if (e < 2 * c) vec[ru + e][tid] = u[e];
-#pragma unroll
-      for (int e = 0; e < kConvMaxK; ++e)
-        if (e < K) {
-          vec[rz1 + e][tid] = z1[e];
-          vec[rz2 + e][tid] = z2[e];
-          vec[ry1 + e][tid] = dy1[e];
-          vec[ry2 + e][tid] = dy2[e];
-        }
-#pragma unroll
-      for (int k = 0; k < kConvMaxC; ++k)
-        if (k < c) vec[rdA + k][tid] = dAt[k];
-    } else {
-      for (int e = 0; e < rD + 9 * c; ++e) vec[e][tid] = 0.f;
     }
-    __syncthreads();
-    // entry e: D (k, q) | W1 (q, e') | W2 (q, e') | W3 (k, e')
+    // the three weight products of the wave's 64 pixels on the matrix
+    // cores (pixels past the end contribute zero vectors)
 #pragma unroll
-    for (int s = 0; s < kSlots; ++s) {
-      const int e = threadIdx.x + kConvTile * s;
-      if (e >= a.nparam) continue;
-      int ra, rb;  // the two LDS rows whose product the entry sums (rb < 0: one row)
-      if (e < 9 * c) {
-        ra = rD + e;
-        rb = -1;
-      } else if (e < 9 * c + 2 * c * K) {
-        const int f = e - 9 * c;
-        ra = ry1 + f / (2 * c);
-        rb = ru + f % (2 * c);
-      } else if (e < 9 * c + 2 * c * K + K * K) {
-        const int f = e - 9 * c - 2 * c * K;
-        ra = ry2 + f / K;
-        rb = rz1 + f % K;
-      } else {
-        const int f = e - 9 * c - 2 * c * K - K * K;
-        ra = rdA + f / K;
-        rb = rz2 + f % K;
-      }
-      float s2 = 0.f;
-      if (rb < 0) {
-        for (int x = 0; x < kConvTile; ++x) s2 += vec[ra][x];
-      } else {
-        for (int x = 0; x < kConvTile; ++x) s2 += vec[ra][x] * vec[rb][x];
-      }
-      acc[s] += s2;
+    for (int e = 0; e < 16; ++e) {
+      S0[lane * 16 + e] = dy2[e];
+      S1[lane * 16 + e] = z1[e];
     }
-    __syncthreads();
+    wave_sync();
+    C2 = mfma_pixels(S0, S1, lane, C2);
+    wave_sync();
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      S0[lane * 16 + e] = dy1[e];
+      S1[lane * 16 + e] = e < 2 * kConvMaxC ? u[e < 2 * kConvMaxC ? e : 0] : 0.f;
+    }
+    wave_sync();
+    C1 = mfma_pixels(S0, S1, lane, C1);
+    wave_sync();
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      S0[lane * 16 + e] = e < kConvMaxC ? dAt[e < kConvMaxC ? e : 0] : 0.f;
+      S1[lane * 16 + e] = z2[e];
+    }
+    wave_sync();
+    C3 = mfma_pixels(S0, S1, lane, C3);
+    wave_sync();
+  }
+  // this wave's sums into its LDS row: C[4 (lane / 16) + g][lane % 16]
+  float* acc = wacc[wave];
+  const int oW1 = 9 * c, oW2 = oW1 + 2 * c * K, oW3 = oW2 + K * K;
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    const int row = 4 * (lane >> 4) + g, col = lane & 15;
+    if (row < K && col < K) acc[oW2 + row * K + col] = C2[g];
+    if (row < K && col < 2 * c) acc[oW1 + row * 2 * c + col] = C1[g];
+    if (row < c && col < K) acc[oW3 + row * K + col] = C3[g];
   }
 #pragma unroll
-  for (int s = 0; s < kSlots; ++s) {
-    const int e = threadIdx.x + kConvTile * s;
-    if (e < a.nparam) a.part[(size_t)blockIdx.x * a.nparam + e] = acc[s];
+  for (int k = 0; k < kConvMaxC; ++k)
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      const float v = wave_sum(dacc[k][q]);
+      if (k < c && lane == 0) acc[9 * k + q] = v;
+    }
+  __syncthreads();
+  for (int e = threadIdx.x; e < a.nparam; e += 64 * kConvWaves) {
+    float v = wacc[0][e];
+#pragma unroll
+    for (int q = 1; q < kConvWaves; ++q) v += wacc[q][e];
+    a.part[(size_t)blockIdx.x * a.nparam + e] = v;
   }
 }
 
@@ -470,14 +511,20 @@ __global__ __launch_bounds__(kConvTile) void conv_bwd_block_kernel(ConvArgs a) {
 template <typename T>
 __global__ __launch_bounds__(256) void conv_inputs_grad_kernel(ConvArgs a) {
   const int h = a.h, w = a.w, c = a.c, r = a.r;
-  const long long P = (long long)h * w;
-  const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (t >= (long long)a.n * c * P) return;
+  const unsigned P = (unsigned)h * (unsigned)w;
+  const unsigned t = blockIdx.x * 256u + threadIdx.x;
+  if (t >= (unsigned)(a.n * c) * P) return;
   const int plane = (int)(t / P);
-  const int m = (int)(t - (long long)plane * P);
+  const int m = (int)(t - (unsigned)plane * P);
   const int i = m / w, j = m - (m / w) * w;
   const size_t pofs = (size_t)plane * P;
-  const float* Dk = a.params + 9 * (plane % c);
+  float Dk[9], Dsum = 0.f;
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    Dk[q] = a.params[9 * (plane % c) + q];
+    Dsum += Dk[q];
+  }
+  const bool inner = i >= 2 * r && i < h - 2 * r && j >= 2 * r && j < w - 2 * r;
   const float Im = to_f(reinterpret_cast<const T*>(a.I_lo)[pofs + m]);
   const float pm = to_f(reinterpret_cast<const T*>(a.p_lo)[pofs + m]);
   float dI = 0.f, dp = 0.f;
@@ -486,7 +533,7 @@ __global__ __launch_bounds__(256) void conv_inputs_grad_kernel(ConvArgs a) {
     const int oi = i - (q / 3 - 1) * r, oj = j - (q % 3 - 1) * r;
     if ((unsigned)oi < (unsigned)h && (unsigned)oj < (unsigned)w) {
       const size_t o = pofs + (size_t)oi * w + oj;
-      const float aq = Dk[q] / conv_norm(Dk, oi, oj, r, h, w);
+      const float aq = Dk[q] / (inner ? Dsum : conv_norm(Dk, oi, oj, r, h, w));
       const float di = Im - a.mI[o], dpp = pm - a.mP[o];
       dI += aq * (a.gmI[o] + a.gcov[o] * dpp + 2.f * a.gvar[o] * di);
       dp += aq * (a.gmP[o] + a.gcov[o] * di);
@@ -499,18 +546,24 @@ __global__ __launch_bounds__(256) void conv_inputs_grad_kernel(ConvArgs a) {
 // Totals of the parameter gradients: entry e sums the workgroups' partials
 // in order, then (D entries, with the window means) the window-mean
 // adjoint's partials image by image.
-__global__ __launch_bounds__(512) void conv_param_reduce_kernel(ConvArgs a) {
-  const int e = threadIdx.x;
-  if (e >= a.nparam) return;
+__global__ __launch_bounds__(256) void conv_param_reduce_kernel(ConvArgs a) {
+  __shared__ float red[4];
+  const int e = blockIdx.x, tid = threadIdx.x;
   float s = 0.f;
-  for (int g = 0; g < a.blk_grid; ++g) s += a.part[(size_t)g * a.nparam + e];
+  for (int g = tid; g < a.blk_grid; g += 256) s += a.part[(size_t)g * a.nparam + e];
   if (a.mean_ab && e < 9 * a.c) {
     const int k = e / 9, q = e - (e / 9) * 9;
-    for (int b = 0; b < a.n; ++b)
-      for (int g = 0; g < a.ab_grid; ++g)
-        s += a.partab[(((size_t)b * a.c + k) * a.ab_grid + g) * 9 + q];
+    const int nab = a.n * a.ab_grid;
+    for (int g = tid; g < nab; g += 256) {
+      const int b = g / a.ab_grid, gg = g - b * a.ab_grid;
+      s += a.partab[(((size_t)b * a.c + k) * a.ab_grid + gg) * 9 + q];
+    }
   }
-  a.dparams[e] = s;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if ((tid & 63) == 0) red[tid >> 6] = s;
+  __syncthreads();
+  if (tid == 0) a.dparams[e] = ((red[0] + red[1]) + red[2]) + red[3];
 }
 
 }  // namespace
@@ -577,7 +630,8 @@ hipError_t conv_backward_t(const ConvPlan& cp, const ConvArgs& a0, const void* I
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   prof_begin("gf_conv_bwd_block", s);
-  hipLaunchKernelGGL((conv_bwd_block_kernel<T>), dim3(a.blk_grid), dim3(kConvTile), 0, s, a);
+  hipLaunchKernelGGL((conv_bwd_block_kernel<T>), dim3(a.blk_grid), dim3(64 * kConvWaves), 0, s,
+                     a);
   prof_end(s);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (a.dI_lo || a.dp_lo) {
@@ -588,7 +642,7 @@ hipError_t conv_backward_t(const ConvPlan& cp, const ConvArgs& a0, const void* I
   }
   if (a.dparams) {
     prof_begin("gf_conv_param_reduce", s);
-    hipLaunchKernelGGL(conv_param_reduce_kernel, dim3(1), dim3(512), 0, s, a);
+    hipLaunchKernelGGL(conv_param_reduce_kernel, dim3(a.nparam), dim3(256), 0, s, a);
     prof_end(s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }

@@ -226,7 +226,7 @@ struct BwdLoArgs {
 // var) in place of A = cov / (var + eps).  Parameters (device, float):
 // D [c][9] | W1 [K][2c] | W2 [K][K] | W3 [c][K].
 constexpr int kConvMaxC = 4, kConvMaxK = 16;
-constexpr int kConvTile = 128;   // pixels per tile of the parameter-gradient sums
+constexpr int kConvTile = 256;   // pixels per workgroup tile of the parameter-gradient sums
 constexpr int kConvBlocks = 1024;  // most workgroups of those sums
 constexpr int conv_param_count(int c, int K) { return 9 * c + 2 * c * K + K * K + c * K; }
 

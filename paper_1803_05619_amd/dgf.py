@@ -74,10 +74,11 @@ def low_res_size(H: int, W: int, lo: int) -> tuple:
 
 
 def dgf_forward(I_hi: torch.Tensor, net: torch.nn.Module, lo: int = 64, r: int = 1,
-                eps: float = 1e-8, ws: torch.Tensor | None = None, return_all: bool = False):
+                eps=1e-8, ws: torch.Tensor | None = None, return_all: bool = False):
     """O_h of the DGF framework for the high-res input I_hi [n, 3, H, W]:
     downsampling and the guided filtering layer run in this library's
-    kernels, C_l in PyTorch."""
+    kernels, C_l in PyTorch.  eps: a float, or a float32 device tensor (no
+    host-to-device copy inside the call: what stream capture needs)."""
     H, W = I_hi.shape[-2:]
     h, w = low_res_size(H, W, lo)
     with torch.no_grad():  # inference: no autograd graph through C_l

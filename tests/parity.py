@@ -121,15 +121,14 @@ def check(res, label=""):
 
 # ---------------------------------------------------------------- convolutional layer
 
-CONV_TILE, CONV_BLOCKS = 128, 1024
+CONV_TILE, CONV_BLOCKS = 256, 1024
 
 
 def conv_sum_bar(n_pix: int, h: int, w: int, planes: int) -> float:
-    """Rounding bound of the convolutional layer's parameter-gradient sums:
-    per tile a sequential sum of CONV_TILE pixels, per workgroup a sequential
-    sum over its tiles, then the fixed-order total over the workgroups (and,
-    for D, over the window-mean adjoint's per-plane partials); each term
-    formed with at most 32 roundings."""
+    """Rounding bound of the convolutional layer's parameter-gradient sums
+    (an upper bound of the kernels' sequential depth: a tile's pixels, a
+    workgroup's tiles, the workgroups, and for D the window-mean adjoint's
+    per-plane partials), each term formed with at most 32 roundings."""
     tiles = -(-n_pix // CONV_TILE)
     grid = min(tiles, CONV_BLOCKS)
     ab = min(-(-(h * w) // 256), 64)
