@@ -63,7 +63,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-KERNEL_SRC_DIRS = (os.path.join(ROOT, "paper_1803_05619_amd", "csrc"), os.path.join(ROOT, "include"))
+# MI355X FP32 vector peak (256 CUs x 4 SIMDs x 16 lanes x 2 (packed) x 2 (FMA)
+# x 2.4 GHz); the library is built without packed FP32, so 78.6 is its cap
+FP32_VEC_PEAK_TFLOPS = 157.3
+# the sources that define, configure and launch the identity-guide kernels
+# whose HBM traffic is profiled (the FP32 instantiation): a traffic figure
+# measured on other versions of them is stale
+KERNEL_SRCS = tuple(os.path.join(ROOT, p) for p in (
+    "include/gf.h", "paper_1803_05619_amd/csrc/gf_internal.h",
+    "paper_1803_05619_amd/csrc/gf_kernels.h", "paper_1803_05619_amd/csrc/gf_api.cpp",
+    "paper_1803_05619_amd/csrc/gf_f32.hip"))
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_fp32_4x3x2048x3072.txt")
 METRIC = "high-res Mpixel/s fwd+bwd, fused vs plain at stated max-abs error; % HBM peak"
 DATA = "synthetic (seeded photo-like images: smooth field + step edges + noise)"
@@ -75,15 +84,11 @@ def log(msg):
 
 
 def kernel_hash():
-    """sha256[:16] over every source of the HIP library (csrc/ and include/,
-    in name order): a traffic figure measured on other sources is stale."""
+    """sha256[:16] over KERNEL_SRCS, in that order."""
     h = hashlib.sha256()
-    for d in KERNEL_SRC_DIRS:
-        for name in sorted(os.listdir(d)):
-            path = os.path.join(d, name)
-            if os.path.isfile(path) and name.endswith((".h", ".hip", ".cpp")):
-                h.update(name.encode())
-                h.update(open(path, "rb").read())
+    for path in KERNEL_SRCS:
+        h.update(os.path.basename(path).encode())
+        h.update(open(path, "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -577,6 +582,12 @@ def workload_5(args, dev):
     per_step = {"gf_apply": kb["apply"], "gf_bwd_hi": kb["bwd_hi"],
                 "gf_conv_stats": 2 * kb["coef"], "gf_conv_inputs_grad": kb["bwd_lo"]}
     step_bytes = kb["apply"] + kb["bwd_hi"] + 2 * kb["coef"] + kb["bwd_lo"]
+    # the block kernel is arithmetic-bound: per low-res pixel the pointwise
+    # block's forward (recomputed) and backward products (2 x (2cK + K^2 + cK)
+    # FMA), the weight gradients' outer products (2cK + K^2 + cK FMA) and the
+    # 9c dilated-conv weight terms (8 flops each)
+    blk = 2 * c * K + K * K + c * K
+    flops = {"gf_conv_bwd_block": n * h * w * (3 * 2 * blk + 8 * 9 * c)}
     tp = {k: torch.tensor(P[k], dtype=torch.float32, device=dev, requires_grad=True)
           for k in ("D", "W1", "W2", "W3")}
     leaves = [t[k].clone().requires_grad_(True) for k in ("I_lo", "p_lo", "I_hi")]
@@ -614,7 +625,7 @@ def workload_5(args, dev):
                                     "FP32, 4x3x2048x3072 <- 512x768 (s=4), dilation 1, block "
                                     "6->16->16->3, grads to p_l, I_l, I_h and the parameters",
                         "n": n, "c": c, "H": H, "W": W, "s": 4, "r": r, "hidden": K},
-                traffic_ok=False)
+                traffic_ok=False, flops=flops)
 
 
 WORKLOADS = {0: workload_0, 1: workload_1, 2: workload_2, 3: workload_3, 4: workload_4,
@@ -870,6 +881,9 @@ def main():
         kernels[name] = {"avg_us": round(1e3 * ms / max(cnt, 1), 3), "launches": cnt,
                          "us_per_step": round(1e6 * step_s, 3), "algo_bytes_per_step": b,
                          "algo_GBs": round(b / step_s / 1e9, 1) if step_s > 0 else None}
+        fl = wl.get("flops", {}).get(name, 0)
+        if fl and step_s > 0:
+            kernels[name]["algo_TFLOPs"] = round(fl / step_s / 1e12, 3)
     # graph replays record no per-kernel events: fall back to the whole step
     if prof:
         dom = max(prof.items(), key=lambda kv: kv[1][0])[0]
@@ -877,6 +891,7 @@ def main():
         dom_bytes = wl["per_step"].get(dom, 0)
     else:
         dom, dom_s, dom_bytes = "step (graph replay)", ms_per_step * 1e-3, wl["step_bytes"]
+    dom_flops = wl.get("flops", {}).get(dom, 0)
     achieved = dom_bytes / dom_s / 1e9
     traffic = None
     if wl.get("traffic_ok") and os.path.exists(TRAFFIC_FILE):
@@ -884,10 +899,18 @@ def main():
         if rec.get("kernel_src_sha256_16") == kernel_hash() and dom in rec.get("kernels", {}):
             traffic = rec["kernels"][dom]["hbm_bytes_per_launch"]
     launches = prof[dom][1] / prof_steps if prof else 1
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic,
-                "algo_bytes_per_launch": int(dom_bytes / max(launches, 1))}
+    if dom_flops and not dom_bytes:
+        # an arithmetic-bound kernel: algorithmic FP32 flops over its time
+        tf = dom_flops / dom_s / 1e12
+        roofline = {"bound": "alu", "kernel": dom, "achieved": round(tf, 3),
+                    "peak": FP32_VEC_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(tf / FP32_VEC_PEAK_TFLOPS, 4), "traffic": None,
+                    "algo_flops_per_launch": int(dom_flops / max(launches, 1))}
+    else:
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                    "algo_bytes_per_launch": int(dom_bytes / max(launches, 1))}
     step_gbs = wl["step_bytes"] / (ms_per_step * 1e-3) / 1e9
 
     out = {
