@@ -511,7 +511,7 @@ int make_conv_plan(const gf_desc_t* d, const gf_conv_t* cv, ConvPlan* cp, const 
   const long long npix = (long long)d->n * d->h_lo * d->w_lo;
   const long long tiles = (npix + kConvTile - 1) / kConvTile;
   cp->blk_grid = (int)std::min<long long>(tiles, kConvBlocks);
-  cp->ab_grid = (int)std::min<long long>(((long long)d->h_lo * d->w_lo + 255) / 256, 64);
+  cp->ab_grid = (int)std::min<long long>(((long long)d->h_lo * d->w_lo + 255) / 256, kConvAbGrid);
   const size_t lo = align_up((size_t)cp->p.planes * d->h_lo * d->w_lo * sizeof(float), 256);
   size_t o = align_up(std::max(cp->p.ws_fwd, cp->p.ws_bwd), 256);
   auto take = [&](size_t bytes) {

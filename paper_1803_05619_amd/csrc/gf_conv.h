@@ -48,6 +48,15 @@ __device__ __forceinline__ bool conv_tap(int i, int j, int t, int r, int h, int 
   return (unsigned)u < (unsigned)h && (unsigned)v < (unsigned)w;
 }
 
+// The same with the tap's row and column clamped into the image, so that
+// `o` is always a valid index (loads need no branch; the caller masks).
+__device__ __forceinline__ bool conv_tap_clamped(int i, int j, int t, int r, int h, int w,
+                                                 int& o) {
+  const int u = i + (t / 3 - 1) * r, v = j + (t % 3 - 1) * r;
+  o = min(max(u, 0), h - 1) * w + min(max(v, 0), w - 1);
+  return (unsigned)u < (unsigned)h && (unsigned)v < (unsigned)w;
+}
+
 // f_d's normaliser at (i, j): the in-image taps' weights summed.
 __device__ __forceinline__ float conv_norm(const float* Dk, int i, int j, int r, int h, int w) {
   float N = 0.f;
@@ -59,57 +68,87 @@ __device__ __forceinline__ float conv_norm(const float* Dk, int i, int j, int r,
   return N;
 }
 
-__device__ __forceinline__ void load_params(const ConvArgs& a, float* prm) {
-  for (int e = threadIdx.x; e < a.nparam; e += blockDim.x) prm[e] = a.params[e];
+// The block's weights and the taps' weights in LDS, zero-padded to fixed
+// shapes so that every loop over them has compile-time bounds and offsets
+// (a padded weight multiplies a zero input or yields an unused zero):
+// W1 [16][8] (inputs cov_0..c-1, var_0..c-1, then zeros), W2 [16][16],
+// W3 [4][16], D [4][9].
+struct ConvW {
+  float w1[kConvMaxK][2 * kConvMaxC];
+  float w2[kConvMaxK][kConvMaxK];
+  float w3[kConvMaxC][kConvMaxK];
+  float d[kConvMaxC][9];
+};
+constexpr int kConvWFloats = (int)(sizeof(ConvW) / sizeof(float));
+
+__device__ __forceinline__ void load_conv_w(const ConvArgs& a, ConvW& W) {
+  const int c = a.c, K = a.K;
+  const float* W1 = a.params + 9 * c;
+  const float* W2 = W1 + 2 * c * K;
+  const float* W3 = W2 + K * K;
+  float* f = reinterpret_cast<float*>(&W);
+  constexpr int n1 = kConvMaxK * 2 * kConvMaxC, n2 = n1 + kConvMaxK * kConvMaxK,
+                n3 = n2 + kConvMaxC * kConvMaxK;
+  for (int e = threadIdx.x; e < kConvWFloats; e += blockDim.x) {
+    float v = 0.f;
+    if (e < n1) {
+      const int q = e / (2 * kConvMaxC), x = e % (2 * kConvMaxC);
+      if (q < K && x < 2 * c) v = W1[q * 2 * c + x];
+    } else if (e < n2) {
+      const int q = (e - n1) / kConvMaxK, x = (e - n1) % kConvMaxK;
+      if (q < K && x < K) v = W2[q * K + x];
+    } else if (e < n3) {
+      const int k = (e - n2) / kConvMaxK, x = (e - n2) % kConvMaxK;
+      if (k < c && x < K) v = W3[k * K + x];
+    } else {
+      const int k = (e - n3) / 9, t = (e - n3) % 9;
+      if (k < c) v = a.params[9 * k + t];
+    }
+    f[e] = v;
+  }
   __syncthreads();
 }
 
-// The pointwise block at one pixel.
-__device__ __forceinline__ void conv_block(const float* W1, const float* W2, const float* W3,
-                                           int c, int K, float slope, const float* u,
-                                           float* y1, float* z1, float* y2, float* z2,
-                                           float* A) {
+// The pointwise block at one pixel of C channels from u = (cov_0..C-1,
+// var_0..C-1): the hidden activations z1, z2, the leaky-ReLU branches (bit q
+// of m1, m2 set where the pre-activation is positive) and A.
+template <int C>
+__device__ __forceinline__ void conv_block(const ConvW& W, float slope, const float (&u)[2 * C],
+                                           float (&z1)[kConvMaxK], float (&z2)[kConvMaxK],
+                                           unsigned& m1, unsigned& m2, float (&A)[C]) {
+  m1 = m2 = 0u;
 #pragma unroll
   for (int q = 0; q < kConvMaxK; ++q) {
     float s = 0.f;
-    if (q < K) {
 #pragma unroll
-      for (int e = 0; e < 2 * kConvMaxC; ++e)
-        if (e < 2 * c) s += W1[q * 2 * c + e] * u[e];
-    }
-    y1[q] = s;
+    for (int e = 0; e < 2 * C; ++e) s += W.w1[q][e] * u[e];
     z1[q] = lrelu_f(s, slope);
+    m1 |= (s > 0.f ? 1u : 0u) << q;
   }
 #pragma unroll
   for (int q = 0; q < kConvMaxK; ++q) {
     float s = 0.f;
-    if (q < K) {
 #pragma unroll
-      for (int e = 0; e < kConvMaxK; ++e)
-        if (e < K) s += W2[q * K + e] * z1[e];
-    }
-    y2[q] = s;
+    for (int e = 0; e < kConvMaxK; ++e) s += W.w2[q][e] * z1[e];
     z2[q] = lrelu_f(s, slope);
+    m2 |= (s > 0.f ? 1u : 0u) << q;
   }
 #pragma unroll
-  for (int k = 0; k < kConvMaxC; ++k) {
+  for (int k = 0; k < C; ++k) {
     float s = 0.f;
-    if (k < c) {
 #pragma unroll
-      for (int e = 0; e < kConvMaxK; ++e)
-        if (e < K) s += W3[k * K + e] * z2[e];
-    }
+    for (int e = 0; e < kConvMaxK; ++e) s += W.w3[k][e] * z2[e];
     A[k] = s;
   }
 }
 
 // Statistics, block, A and b of every low-res pixel (all channels).  With
 // a.mI set (backward) the statistics are kept for the adjoint.
-template <typename T>
+template <typename T, int C>
 __global__ __launch_bounds__(256) void conv_stats_kernel(ConvArgs a) {
-  __shared__ float prm[kConvParamMax];
-  load_params(a, prm);
-  const int h = a.h, w = a.w, c = a.c, r = a.r;
+  __shared__ ConvW W;
+  load_conv_w(a, W);
+  const int h = a.h, w = a.w, r = a.r;
   // pixel indices in 32 bits (the planner keeps n h w below 2^31)
   const unsigned P = (unsigned)h * (unsigned)w;
   const unsigned t = blockIdx.x * 256u + threadIdx.x;
@@ -117,28 +156,19 @@ __global__ __launch_bounds__(256) void conv_stats_kernel(ConvArgs a) {
   const int b = (int)(t / P);
   const int m = (int)(t - (unsigned)b * P);
   const int i = m / w, j = m - (m / w) * w;
-  const float* W1 = prm + 9 * c;
-  const float* W2 = W1 + 2 * c * a.K;
-  const float* W3 = W2 + a.K * a.K;
-  // u = (cov_0 .. cov_{c-1}, var_0 .. var_{c-1}): cleared before the
-  // channel loop writes it
-  float u[2 * kConvMaxC], mi[kConvMaxC], mp[kConvMaxC];
+  // u = (cov_0 .. cov_C-1, var_0 .. var_C-1)
+  float u[2 * C], mi[C], mp[C];
 #pragma unroll
-  for (int e = 0; e < 2 * kConvMaxC; ++e) u[e] = 0.f;
-#pragma unroll
-  for (int k = 0; k < kConvMaxC; ++k) {
-    mi[k] = mp[k] = 0.f;
-    if (k >= c) continue;
-    const size_t pofs = (size_t)(b * c + k) * P;
+  for (int k = 0; k < C; ++k) {
+    const unsigned pofs = (unsigned)(b * C + k) * P;
     const T* Ik = reinterpret_cast<const T*>(a.I_lo) + pofs;
     const T* pk = reinterpret_cast<const T*>(a.p_lo) + pofs;
-    const float* Dk = prm + 9 * k;
     float xi[9], xp[9], wt[9], N = 0.f, si = 0.f, sp = 0.f;
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
       int o;
-      const bool in = conv_tap(i, j, q, r, h, w, o);
-      wt[q] = in ? Dk[q] : 0.f;
+      const bool in = conv_tap_clamped(i, j, q, r, h, w, o);
+      wt[q] = in ? W.d[k][q] : 0.f;
       xi[q] = in ? to_f(Ik[o]) : 0.f;
       xp[q] = in ? to_f(pk[o]) : 0.f;
       N += wt[q];
@@ -156,20 +186,20 @@ __global__ __launch_bounds__(256) void conv_stats_kernel(ConvArgs a) {
     mi[k] = mI;
     mp[k] = mP;
     u[k] = sc / N;
-    u[c + k] = sv / N;
+    u[C + k] = sv / N;
     if (a.mI) {
       a.mI[pofs + m] = mI;
       a.mP[pofs + m] = mP;
-      a.cov[pofs + m] = sc / N;
-      a.var[pofs + m] = sv / N;
+      a.cov[pofs + m] = u[k];
+      a.var[pofs + m] = u[C + k];
     }
   }
-  float y1[kConvMaxK], z1[kConvMaxK], y2[kConvMaxK], z2[kConvMaxK], Av[kConvMaxC];
-  conv_block(W1, W2, W3, c, a.K, a.slope, u, y1, z1, y2, z2, Av);
+  float z1[kConvMaxK], z2[kConvMaxK], Av[C];
+  unsigned m1, m2;
+  conv_block<C>(W, a.slope, u, z1, z2, m1, m2, Av);
 #pragma unroll
-  for (int k = 0; k < kConvMaxC; ++k) {
-    if (k >= c) continue;
-    const size_t o = (size_t)(b * c + k) * P + m;
+  for (int k = 0; k < C; ++k) {
+    const unsigned o = (unsigned)(b * C + k) * P + m;
     a.A[o] = Av[k];
     a.B[o] = mp[k] - Av[k] * mi[k];
   }
@@ -264,12 +294,16 @@ __global__ __launch_bounds__(256) void conv_fdT_ab_kernel(ConvArgs a) {
   const int h = a.h, w = a.w, r = a.r;
   const int plane = blockIdx.y;
   const int P = h * w;
-  float Dk[9], Dsum = 0.f;
+  float Dk[9], Dsum = 0.f, wi[9];
 #pragma unroll
   for (int q = 0; q < 9; ++q) {
     Dk[q] = a.params[9 * (plane % a.c) + q];
     Dsum += Dk[q];
   }
+  // interior pixels' tap weights D[q] / N (N the sum of the weights)
+  const float rDsum = 1.f / Dsum;
+#pragma unroll
+  for (int q = 0; q < 9; ++q) wi[q] = Dk[q] / Dsum;
   const size_t pofs = (size_t)plane * P;
   const float *A = a.A + pofs, *B = a.B + pofs, *Ab = a.abar + pofs, *Bb = a.bbar + pofs;
   const float *gA = a.dAb + pofs, *gB = a.dBb + pofs;
@@ -282,20 +316,29 @@ __global__ __launch_bounds__(256) void conv_fdT_ab_kernel(ConvArgs a) {
     // whole, so every normaliser is the sum of the weights
     const bool inner = i >= 2 * r && i < h - 2 * r && j >= 2 * r && j < w - 2 * r;
     float dA = 0.f, dB = 0.f;
+    if (inner) {
 #pragma unroll
-    for (int q = 0; q < 9; ++q) {
-      // the pixel o whose tap q is m
-      const int oi = i - (q / 3 - 1) * r, oj = j - (q % 3 - 1) * r;
-      if ((unsigned)oi < (unsigned)h && (unsigned)oj < (unsigned)w) {
-        const int o = oi * w + oj;
-        const float wq = Dk[q] / (inner ? Dsum : conv_norm(Dk, oi, oj, r, h, w));
-        dA += wq * gA[o];
-        dB += wq * gB[o];
+      for (int q = 0; q < 9; ++q) {
+        // the pixel o whose tap q is m
+        const int o = m - (q / 3 - 1) * r * w - (q % 3 - 1) * r;
+        dA += wi[q] * gA[o];
+        dB += wi[q] * gB[o];
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        const int oi = i - (q / 3 - 1) * r, oj = j - (q % 3 - 1) * r;
+        if ((unsigned)oi < (unsigned)h && (unsigned)oj < (unsigned)w) {
+          const int o = oi * w + oj;
+          const float wq = Dk[q] / conv_norm(Dk, oi, oj, r, h, w);
+          dA += wq * gA[o];
+          dB += wq * gB[o];
+        }
       }
     }
     a.dA[pofs + m] = dA;
     a.dB[pofs + m] = dB;
-    const float rN = 1.f / (inner ? Dsum : conv_norm(Dk, i, j, r, h, w));
+    const float rN = inner ? rDsum : 1.f / conv_norm(Dk, i, j, r, h, w);
     const float ga = gA[m] * rN, gb = gB[m] * rN;
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
@@ -348,159 +391,162 @@ __device__ __forceinline__ conv_f4 mfma_pixels(const float* S0, const float* S1,
   return C;
 }
 
-template <typename T>
-__global__ __launch_bounds__(64 * kConvWaves) void conv_bwd_block_kernel(ConvArgs a) {
-  __shared__ float prm[kConvParamMax];
-  __shared__ float stage[kConvWaves][2][64 * 16];
-  __shared__ float wacc[kConvWaves][kConvParamMax];
+// Stages this lane's pixel vectors x, y (16 each) pixel-major in the wave's
+// LDS block and adds the wave's sum of x y^T to C.
+__device__ __forceinline__ conv_f4 stage_mfma(float* S0, float* S1, int lane,
+                                              const float (&x)[16], const float (&y)[16],
+                                              conv_f4 C) {
+#pragma unroll
+  for (int e = 0; e < 16; e += 4) {
+    *reinterpret_cast<float4*>(S0 + lane * 16 + e) = make_float4(x[e], x[e + 1], x[e + 2], x[e + 3]);
+    *reinterpret_cast<float4*>(S1 + lane * 16 + e) = make_float4(y[e], y[e + 1], y[e + 2], y[e + 3]);
+  }
+  wave_sync();
+  C = mfma_pixels(S0, S1, lane, C);
+  wave_sync();
+  return C;
+}
+
+template <typename T, int C>
+__global__ __launch_bounds__(64 * kConvWaves, 2) void conv_bwd_block_kernel(ConvArgs a) {
+  __shared__ ConvW W;
+  __shared__ __align__(16) float stage[kConvWaves][2][64 * 16];
+  static_assert(kConvParamMax <= 2 * 64 * 16, "a wave's sums fit its staging block");
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  load_params(a, prm);
-  const int h = a.h, w = a.w, c = a.c, r = a.r, K = a.K;
-  const long long P = (long long)h * w, total = (long long)a.n * P;
-  const float* W1 = prm + 9 * c;
-  const float* W2 = W1 + 2 * c * K;
-  const float* W3 = W2 + K * K;
+  load_conv_w(a, W);
+  const int h = a.h, w = a.w, r = a.r, K = a.K;
+  const unsigned P = (unsigned)h * (unsigned)w, total = (unsigned)a.n * P;
   float* S0 = stage[wave][0];
   float* S1 = stage[wave][1];
+  const float slope = a.slope;
   conv_f4 C1 = {0.f, 0.f, 0.f, 0.f}, C2 = C1, C3 = C1;
-  float dacc[kConvMaxC][9];
+  float dacc[C][9];
 #pragma unroll
-  for (int k = 0; k < kConvMaxC; ++k)
+  for (int k = 0; k < C; ++k)
 #pragma unroll
     for (int q = 0; q < 9; ++q) dacc[k][q] = 0.f;
-  constexpr int kTile = 64 * kConvWaves;
-  const long long tiles = (total + kTile - 1) / kTile;
-  for (long long tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
-    const long long t = tile * kTile + threadIdx.x;
-    float u[2 * kConvMaxC], dAt[kConvMaxC];
-    float y1[kConvMaxK], z1[kConvMaxK], y2[kConvMaxK], z2[kConvMaxK];
-    float dy2[kConvMaxK], dy1[kConvMaxK];
+  constexpr unsigned kTile = 64 * kConvWaves;
+  const unsigned tiles = (total + kTile - 1) / kTile;
+  for (unsigned tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    const unsigned t = tile * kTile + threadIdx.x;
+    const bool live = t < total;
+    // pixels past the end run on zero vectors and contribute nothing
+    const unsigned tt = live ? t : 0u;
+    const int b = (int)(tt / P);
+    const int m = (int)(tt - (unsigned)b * P);
+    const int i = m / w, j = m - (m / w) * w;
+    float u[2 * C], dAt[C], mi[C], mp[C], Ak[C], dBk[C];
 #pragma unroll
-    for (int e = 0; e < 2 * kConvMaxC; ++e) u[e] = 0.f;
-#pragma unroll
-    for (int k = 0; k < kConvMaxC; ++k) dAt[k] = 0.f;
-#pragma unroll
-    for (int e = 0; e < kConvMaxK; ++e) y1[e] = z1[e] = y2[e] = z2[e] = dy1[e] = dy2[e] = 0.f;
-    if (t < total) {
-      const int b = (int)((unsigned)t / (unsigned)P);
-      const int m = (int)((unsigned)t - (unsigned)b * (unsigned)P);
-      const int i = m / w, j = m - (m / w) * w;
-      float mi[kConvMaxC], mp[kConvMaxC], Ak[kConvMaxC], dBk[kConvMaxC];
-#pragma unroll
-      for (int k = 0; k < kConvMaxC; ++k) {
-        mi[k] = mp[k] = Ak[k] = dBk[k] = 0.f;
-        if (k >= c) continue;
-        const size_t o = (size_t)(b * c + k) * P + m;
-        mi[k] = a.mI[o];
-        mp[k] = a.mP[o];
-        u[k] = a.cov[o];
-        u[c + k] = a.var[o];
-        Ak[k] = a.A[o];
-        dBk[k] = a.dB[o];
-        dAt[k] = a.dA[o] - dBk[k] * mi[k];
+    for (int k = 0; k < C; ++k) {
+      const unsigned o = (unsigned)(b * C + k) * P + m;
+      mi[k] = live ? a.mI[o] : 0.f;
+      mp[k] = live ? a.mP[o] : 0.f;
+      u[k] = live ? a.cov[o] : 0.f;
+      u[C + k] = live ? a.var[o] : 0.f;
+      Ak[k] = live ? a.A[o] : 0.f;
+      dBk[k] = live ? a.dB[o] : 0.f;
+      dAt[k] = live ? a.dA[o] - dBk[k] * mi[k] : 0.f;
+      if (live) {
         a.gmP[o] = dBk[k];
         a.gmI[o] = -dBk[k] * Ak[k];
       }
-      float Ar[kConvMaxC];
-      conv_block(W1, W2, W3, c, K, a.slope, u, y1, z1, y2, z2, Ar);
+    }
+    float z1[kConvMaxK], z2[kConvMaxK], Ar[C];
+    unsigned m1, m2;
+    conv_block<C>(W, slope, u, z1, z2, m1, m2, Ar);
+    (void)Ar;  // A as stored by the statistics pass is the one used
+    float dy[kConvMaxK];
 #pragma unroll
-      for (int e = 0; e < kConvMaxK; ++e) {
-        float sacc = 0.f;
+    for (int e = 0; e < kConvMaxK; ++e) {
+      float sacc = 0.f;
 #pragma unroll
-        for (int k = 0; k < kConvMaxC; ++k)
-          if (k < c && e < K) sacc += W3[k * K + e] * dAt[k];
-        dy2[e] = sacc * lrelu_df(y2[e], a.slope);
+      for (int k = 0; k < C; ++k) sacc += W.w3[k][e] * dAt[k];
+      dy[e] = ((m2 >> e) & 1u) ? sacc : slope * sacc;
+    }
+    C2 = stage_mfma(S0, S1, lane, dy, z1, C2);  // dW2 += dy2 z1^T
+    float dy1[kConvMaxK];
+#pragma unroll
+    for (int e = 0; e < kConvMaxK; ++e) {
+      float sacc = 0.f;
+#pragma unroll
+      for (int q = 0; q < kConvMaxK; ++q) sacc += W.w2[q][e] * dy[q];
+      dy1[e] = ((m1 >> e) & 1u) ? sacc : slope * sacc;
+    }
+    {
+      float u16[16];
+#pragma unroll
+      for (int e = 0; e < 16; ++e) u16[e] = e < 2 * C ? u[e < 2 * C ? e : 0] : 0.f;
+      C1 = stage_mfma(S0, S1, lane, dy1, u16, C1);  // dW1 += dy1 u^T
+    }
+    {
+      float a16[16];
+#pragma unroll
+      for (int e = 0; e < 16; ++e) a16[e] = e < C ? dAt[e < C ? e : 0] : 0.f;
+      C3 = stage_mfma(S0, S1, lane, a16, z2, C3);  // dW3 += dA z2^T
+    }
+    float du[2 * C];
+#pragma unroll
+    for (int e = 0; e < 2 * C; ++e) {
+      float sacc = 0.f;
+#pragma unroll
+      for (int q = 0; q < kConvMaxK; ++q) sacc += W.w1[q][e] * dy1[q];
+      du[e] = sacc;
+    }
+    if (!live) continue;
+    // the statistics' weight terms at this pixel, per channel and tap
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+      const unsigned pofs = (unsigned)(b * C + k) * P;
+      const float dcov = du[k], dvar = du[C + k];
+      a.gcov[pofs + m] = dcov;
+      a.gvar[pofs + m] = dvar;
+      const T* Ik = reinterpret_cast<const T*>(a.I_lo) + pofs;
+      const T* pk = reinterpret_cast<const T*>(a.p_lo) + pofs;
+      // all 18 tap loads first (clamped, unconditional), then the terms
+      float xi[9], xp[9], in[9], N = 0.f;
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        int o;
+        in[q] = conv_tap_clamped(i, j, q, r, h, w, o) ? 1.f : 0.f;
+        xi[q] = to_f(Ik[o]);
+        xp[q] = to_f(pk[o]);
+        N += in[q] * W.d[k][q];
       }
+      const float rN = 1.f / N;
+      const float gmI = -dBk[k] * Ak[k], gmP = dBk[k];
+      const float cu = u[k], vu = u[C + k];
 #pragma unroll
-      for (int e = 0; e < kConvMaxK; ++e) {
-        float sacc = 0.f;
-#pragma unroll
-        for (int q = 0; q < kConvMaxK; ++q)
-          if (q < K && e < K) sacc += W2[q * K + e] * dy2[q];
-        dy1[e] = sacc * lrelu_df(y1[e], a.slope);
-      }
-      float du[2 * kConvMaxC];
-#pragma unroll
-      for (int e = 0; e < 2 * kConvMaxC; ++e) {
-        float sacc = 0.f;
-#pragma unroll
-        for (int q = 0; q < kConvMaxK; ++q)
-          if (q < K && e < 2 * c) sacc += W1[q * 2 * c + e] * dy1[q];
-        du[e] = sacc;
-      }
-      // the statistics' weight terms at this pixel, per channel and tap
-#pragma unroll
-      for (int k = 0; k < kConvMaxC; ++k) {
-        if (k >= c) continue;
-        const size_t pofs = (size_t)(b * c + k) * P;
-        const float dcov = du[k], dvar = du[c + k];
-        a.gcov[pofs + m] = dcov;
-        a.gvar[pofs + m] = dvar;
-        const T* Ik = reinterpret_cast<const T*>(a.I_lo) + pofs;
-        const T* pk = reinterpret_cast<const T*>(a.p_lo) + pofs;
-        const float* Dk = prm + 9 * k;
-        const float rN = 1.f / conv_norm(Dk, i, j, r, h, w);
-        const float gmI = -dBk[k] * Ak[k], gmP = dBk[k];
-#pragma unroll
-        for (int q = 0; q < 9; ++q) {
-          int o;
-          if (conv_tap(i, j, q, r, h, w, o)) {
-            const float di = to_f(Ik[o]) - mi[k], dp = to_f(pk[o]) - mp[k];
-            dacc[k][q] += (gmI * di + gmP * dp + dcov * (di * dp - u[k]) +
-                           dvar * (di * di - u[c + k])) * rN;
-          }
-        }
+      for (int q = 0; q < 9; ++q) {
+        const float di = xi[q] - mi[k], dp = xp[q] - mp[k];
+        dacc[k][q] += in[q] * ((gmI * di + gmP * dp + dcov * (di * dp - cu) +
+                                dvar * (di * di - vu)) * rN);
       }
     }
-    // the three weight products of the wave's 64 pixels on the matrix
-    // cores (pixels past the end contribute zero vectors)
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      S0[lane * 16 + e] = dy2[e];
-      S1[lane * 16 + e] = z1[e];
-    }
-    wave_sync();
-    C2 = mfma_pixels(S0, S1, lane, C2);
-    wave_sync();
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      S0[lane * 16 + e] = dy1[e];
-      S1[lane * 16 + e] = e < 2 * kConvMaxC ? u[e < 2 * kConvMaxC ? e : 0] : 0.f;
-    }
-    wave_sync();
-    C1 = mfma_pixels(S0, S1, lane, C1);
-    wave_sync();
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      S0[lane * 16 + e] = e < kConvMaxC ? dAt[e < kConvMaxC ? e : 0] : 0.f;
-      S1[lane * 16 + e] = z2[e];
-    }
-    wave_sync();
-    C3 = mfma_pixels(S0, S1, lane, C3);
-    wave_sync();
   }
-  // this wave's sums into its LDS row: C[4 (lane / 16) + g][lane % 16]
-  float* acc = wacc[wave];
-  const int oW1 = 9 * c, oW2 = oW1 + 2 * c * K, oW3 = oW2 + K * K;
+  // this wave's sums into its own staging block (the other waves may still
+  // be reading theirs): C[4 (lane / 16) + g][lane % 16]
+  float* acc = S0;
+  constexpr int oW1 = 9 * C;
+  const int oW2 = oW1 + 2 * C * K, oW3 = oW2 + K * K;
 #pragma unroll
   for (int g = 0; g < 4; ++g) {
     const int row = 4 * (lane >> 4) + g, col = lane & 15;
     if (row < K && col < K) acc[oW2 + row * K + col] = C2[g];
-    if (row < K && col < 2 * c) acc[oW1 + row * 2 * c + col] = C1[g];
-    if (row < c && col < K) acc[oW3 + row * K + col] = C3[g];
+    if (row < K && col < 2 * C) acc[oW1 + row * 2 * C + col] = C1[g];
+    if (row < C && col < K) acc[oW3 + row * K + col] = C3[g];
   }
 #pragma unroll
-  for (int k = 0; k < kConvMaxC; ++k)
+  for (int k = 0; k < C; ++k)
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
       const float v = wave_sum(dacc[k][q]);
-      if (k < c && lane == 0) acc[9 * k + q] = v;
+      if (lane == 0) acc[9 * k + q] = v;
     }
   __syncthreads();
   for (int e = threadIdx.x; e < a.nparam; e += 64 * kConvWaves) {
-    float v = wacc[0][e];
+    float v = stage[0][0][e];
 #pragma unroll
-    for (int q = 1; q < kConvWaves; ++q) v += wacc[q][e];
+    for (int q = 1; q < kConvWaves; ++q) v += stage[q][0][e];
     a.part[(size_t)blockIdx.x * a.nparam + e] = v;
   }
 }
@@ -517,7 +563,7 @@ __global__ __launch_bounds__(256) void conv_inputs_grad_kernel(ConvArgs a) {
   const int plane = (int)(t / P);
   const int m = (int)(t - (unsigned)plane * P);
   const int i = m / w, j = m - (m / w) * w;
-  const size_t pofs = (size_t)plane * P;
+  const unsigned pofs = (unsigned)plane * P;
   float Dk[9], Dsum = 0.f;
 #pragma unroll
   for (int q = 0; q < 9; ++q) {
@@ -528,15 +574,21 @@ __global__ __launch_bounds__(256) void conv_inputs_grad_kernel(ConvArgs a) {
   const float Im = to_f(reinterpret_cast<const T*>(a.I_lo)[pofs + m]);
   const float pm = to_f(reinterpret_cast<const T*>(a.p_lo)[pofs + m]);
   float dI = 0.f, dp = 0.f;
+  auto gather = [&](unsigned o, float aq) __attribute__((always_inline)) {
+    const float di = Im - a.mI[o], dpp = pm - a.mP[o];
+    dI += aq * (a.gmI[o] + a.gcov[o] * dpp + 2.f * a.gvar[o] * di);
+    dp += aq * (a.gmP[o] + a.gcov[o] * di);
+  };
+  if (inner) {  // every window touching m is whole: N = the weights' sum
 #pragma unroll
-  for (int q = 0; q < 9; ++q) {
-    const int oi = i - (q / 3 - 1) * r, oj = j - (q % 3 - 1) * r;
-    if ((unsigned)oi < (unsigned)h && (unsigned)oj < (unsigned)w) {
-      const size_t o = pofs + (size_t)oi * w + oj;
-      const float aq = Dk[q] / (inner ? Dsum : conv_norm(Dk, oi, oj, r, h, w));
-      const float di = Im - a.mI[o], dpp = pm - a.mP[o];
-      dI += aq * (a.gmI[o] + a.gcov[o] * dpp + 2.f * a.gvar[o] * di);
-      dp += aq * (a.gmP[o] + a.gcov[o] * di);
+    for (int q = 0; q < 9; ++q)
+      gather(pofs + m - (q / 3 - 1) * r * w - (q % 3 - 1) * r, Dk[q] / Dsum);
+  } else {
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      const int oi = i - (q / 3 - 1) * r, oj = j - (q % 3 - 1) * r;
+      if ((unsigned)oi < (unsigned)h && (unsigned)oj < (unsigned)w)
+        gather(pofs + (unsigned)(oi * w + oj), Dk[q] / conv_norm(Dk, oi, oj, r, h, w));
     }
   }
   if (a.dI_lo) a.dI_lo[pofs + m] = dI;
@@ -566,6 +618,15 @@ __global__ __launch_bounds__(256) void conv_param_reduce_kernel(ConvArgs a) {
   if (tid == 0) a.dparams[e] = ((red[0] + red[1]) + red[2]) + red[3];
 }
 
+// One of four instantiations (channel counts 1..4, checked by the planner).
+template <typename T>
+void launch_conv_c(int c, void (*k1)(ConvArgs), void (*k2)(ConvArgs), void (*k3)(ConvArgs),
+                   void (*k4)(ConvArgs), dim3 grid, dim3 block, hipStream_t s,
+                   const ConvArgs& a) {
+  void (*k)(ConvArgs) = c == 1 ? k1 : c == 2 ? k2 : c == 3 ? k3 : k4;
+  hipLaunchKernelGGL(k, grid, block, 0, s, a);
+}
+
 }  // namespace
 
 template <typename T>
@@ -574,8 +635,8 @@ hipError_t conv_forward_t(const ConvPlan& cp, const ConvArgs& a0, const void* I_
   ConvArgs a = a0;
   const long long npix = (long long)a.n * a.h * a.w, nplane = npix * a.c;
   prof_begin("gf_conv_stats", s);
-  hipLaunchKernelGGL((conv_stats_kernel<T>), dim3((unsigned)((npix + 255) / 256)), dim3(256), 0,
-                     s, a);
+  launch_conv_c<T>(a.c, conv_stats_kernel<T, 1>, conv_stats_kernel<T, 2>, conv_stats_kernel<T, 3>,
+                   conv_stats_kernel<T, 4>, dim3((unsigned)((npix + 255) / 256)), dim3(256), s, a);
   prof_end(s);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -599,8 +660,8 @@ hipError_t conv_backward_t(const ConvPlan& cp, const ConvArgs& a0, const void* I
   const long long npix = (long long)a.n * a.h * a.w, nplane = npix * a.c;
   const unsigned gplane = (unsigned)((nplane + 255) / 256);
   prof_begin("gf_conv_stats", s);
-  hipLaunchKernelGGL((conv_stats_kernel<T>), dim3((unsigned)((npix + 255) / 256)), dim3(256), 0,
-                     s, a);
+  launch_conv_c<T>(a.c, conv_stats_kernel<T, 1>, conv_stats_kernel<T, 2>, conv_stats_kernel<T, 3>,
+                   conv_stats_kernel<T, 4>, dim3((unsigned)((npix + 255) / 256)), dim3(256), s, a);
   prof_end(s);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -630,8 +691,9 @@ hipError_t conv_backward_t(const ConvPlan& cp, const ConvArgs& a0, const void* I
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   prof_begin("gf_conv_bwd_block", s);
-  hipLaunchKernelGGL((conv_bwd_block_kernel<T>), dim3(a.blk_grid), dim3(64 * kConvWaves), 0, s,
-                     a);
+  launch_conv_c<T>(a.c, conv_bwd_block_kernel<T, 1>, conv_bwd_block_kernel<T, 2>,
+                   conv_bwd_block_kernel<T, 3>, conv_bwd_block_kernel<T, 4>, dim3(a.blk_grid),
+                   dim3(64 * kConvWaves), s, a);
   prof_end(s);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (a.dI_lo || a.dp_lo) {

@@ -228,6 +228,10 @@ struct BwdLoArgs {
 constexpr int kConvMaxC = 4, kConvMaxK = 16;
 constexpr int kConvTile = 256;   // pixels per workgroup tile of the parameter-gradient sums
 constexpr int kConvBlocks = 1024;  // most workgroups of those sums
+// most workgroups per plane of the window-mean adjoint (each thread walks
+// its plane's pixels with a stride of 256 x this; enough workgroups that the
+// gathers' latency is hidden)
+constexpr int kConvAbGrid = 512;
 constexpr int conv_param_count(int c, int K) { return 9 * c + 2 * c * K + K * K + c * K; }
 
 struct ConvPlan {

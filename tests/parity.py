@@ -121,7 +121,7 @@ def check(res, label=""):
 
 # ---------------------------------------------------------------- convolutional layer
 
-CONV_TILE, CONV_BLOCKS = 256, 1024
+CONV_TILE, CONV_BLOCKS, CONV_AB_GRID = 256, 1024, 512
 
 
 def conv_sum_bar(n_pix: int, h: int, w: int, planes: int) -> float:
@@ -131,7 +131,7 @@ def conv_sum_bar(n_pix: int, h: int, w: int, planes: int) -> float:
     per-plane partials), each term formed with at most 32 roundings."""
     tiles = -(-n_pix // CONV_TILE)
     grid = min(tiles, CONV_BLOCKS)
-    ab = min(-(-(h * w) // 256), 64)
+    ab = min(-(-(h * w) // 256), CONV_AB_GRID)
     depth = CONV_TILE + -(-tiles // grid) + grid + planes * ab + 256
     return (depth + 32) * U32
 
