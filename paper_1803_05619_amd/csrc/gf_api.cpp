@@ -48,6 +48,11 @@ int env_int(const char* name, int dflt) {
 
 }  // namespace
 
+int wide_bwd_min_r() {
+  static const int v = std::max(kWideMinR, env_int("GF_WIDE_BWD_R", kWideBwdR));
+  return v;
+}
+
 int set_error(int code, const std::string& why) { return fail(code, why); }
 
 int make_plan(const gf_desc_t* d, const gf_guide_t* g, Plan* p, const char** why) {
@@ -139,11 +144,13 @@ int make_plan(const gf_desc_t* d, const gf_guide_t* g, Plan* p, const char** why
   //  - low-res rows per backward high-res wave: 2 for FP32 (short walks
   //    stream best; at S >= 4 four waves stack into one partial block), 8
   //    for the half types (one wave per workgroup: fewer partial rows)
-  //  - the backward walker at r > 4: 128 rows (its 4r-row warm-up)
+  //  - the wide backward (r >= wide_bwd_min_r()): 32 rows (its 2r-row
+  //    warm-up against parallelism: on the FP16 2 x 3 x 2160 x 3840 workload
+  //    at r = 8 its two passes took 175 / 117 / 137 us at 64 / 32 / 16 rows)
   const int walk = r <= 2 ? 16 : r <= 4 ? 32 : 64;
   // the backward walker at small radii: 24 rows (4 waves per SIMD; 16-row
   // segments leave a second, mostly empty round of waves)
-  TuneVal tv{walk, r <= 2 ? 24 : r <= 4 ? walk : 128, S >= 8 ? S : 8,
+  TuneVal tv{walk, r <= 2 ? 24 : wide_bwd(r) ? 32 : r <= 4 ? walk : 128, S >= 8 ? S : 8,
              d->io_dtype == GF_F32 ? 2 : 8};
   TuneVal tuned;
   if (tune_lookup(TuneKey{d->io_dtype, S, r, gmode, d->mean_ab}, &tuned)) {
@@ -177,9 +184,14 @@ int make_plan(const gf_desc_t* d, const gf_guide_t* g, Plan* p, const char** why
   q.co_ny = (q.h + q.coTR - 1) / q.coTR;
   q.coLDS = coef_lds_bytes(r);  // row buffers (+ (g,p), (A,b) rings for large r)
   q.loTR = tv.loTR;
-  q.lo_nx = (q.w + (64 - 4 * r) - 1) / (64 - 4 * r);
+  if (wide_bwd(r)) {  // wide backward: strips of 256 input columns, halo r
+    q.lo_nx = (q.w + (kWideBThreads - 2 * r) - 1) / (kWideBThreads - 2 * r);
+    q.loLDS = bwd_wide_lds_bytes();
+  } else {
+    q.lo_nx = (q.w + (64 - 4 * r) - 1) / (64 - 4 * r);
+    q.loLDS = bwd_lo_lds_bytes(r);  // row buffers (+ input and X rings for large r)
+  }
   q.lo_ny = (q.h + q.loTR - 1) / q.loTR;
-  q.loLDS = bwd_lo_lds_bytes(r);  // row buffers (+ input and X rings for large r)
 
   q.RB = S ? ((tv.RB + S - 1) / S) * S : tv.RB;  // whole low-res row blocks
   q.nrb = (q.H + q.RB - 1) / q.RB;
@@ -221,7 +233,9 @@ int make_plan(const gf_desc_t* d, const gf_guide_t* g, Plan* p, const char** why
   q.off_v = q.off_u + align_up(ubytes, 256);
   const size_t vbytes = q.gen ? (size_t)q.planes * 2 * q.h * q.W * sizeof(float) : 0;
   q.off_eps = q.off_v + align_up(vbytes, 256);
-  q.ws_bwd = q.off_eps + align_up((size_t)q.planes * q.lo_nx * q.lo_ny * sizeof(float), 256);
+  q.off_x = q.off_eps + align_up((size_t)q.planes * q.lo_nx * q.lo_ny * sizeof(float), 256);
+  const size_t xbytes = wide_bwd(r) ? (size_t)q.planes * q.h * q.w * 4 * sizeof(float) : 0;
+  q.ws_bwd = q.off_x + align_up(xbytes, 256);
   if (gmode != GF_GUIDE_IDENTITY) {
     // guided path: the guide planes and the transform's reductions follow the
     // identity layout (a superset is allocated for both directions)

@@ -52,7 +52,7 @@ bool misaligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) !
 
 struct Geo {
   Plan p;
-  size_t off_abar, off_bbar, off_u, off_eps;
+  size_t off_abar, off_bbar, off_u, off_eps, off_x;
   long long t_coef, t_apply, t_bwd_hi, t_bwd_lo;
 };
 
@@ -163,6 +163,8 @@ int create(const gf_item_t* items, int count, gf_plan** out) {
     ws += align_up((size_t)p.planes * p.nby * p.nbx * p.ublk_floats * sizeof(float), 256);
     g.off_eps = ws;
     ws += align_up((size_t)p.planes * p.lo_nx * p.lo_ny * sizeof(float), 256);
+    g.off_x = ws;  // the wide backward's X planes
+    if (wide_bwd(p.r)) ws += align_up((size_t)p.planes * p.h * p.w * 4 * sizeof(float), 256);
     g.t_coef = (long long)p.co_nx * p.co_ny * p.planes;
     g.t_bwd_lo = (long long)p.lo_nx * p.lo_ny * p.planes;
     g.t_apply = ((long long)p.planes * p.nrb * p.nxv + 255) / 256;
@@ -253,7 +255,7 @@ int create(const gf_item_t* items, int count, gf_plan** out) {
         return BwdLoArgs{items[k].I_lo, items[k].p_lo, eps_dev + k, 1, p.c,
                          ws_rel<float>(geo[k].off_u), p.ubh, p.tw, p.nby, p.nbx, p.h, p.w, p.loTR,
                          items[k].dI_lo, items[k].dp_lo, ws_rel<float>(geo[k].off_eps), p.lo_nx,
-                         p.lo_ny};
+                         p.lo_ny, wide_bwd(p.r) ? ws_rel<float>(geo[k].off_x) : nullptr};
       },
       [](const Geo& g, int& nx, int& ny) {
         nx = g.p.lo_nx;

@@ -768,7 +768,8 @@ hipError_t backward_guided_t(const Plan& p, const BwdArgs& b, hipStream_t s) {
   e = launch_bwd_hi<float, T, float, T>(p, Gh, b.dq, dGh, abar, U, V, s, bbar, b.q);
   if (e != hipSuccess) return e;
   float* epart = reinterpret_cast<float*>(b.ws + p.off_eps);
-  e = launch_bwd_lo<float, T>(p, Gl, b.p_lo, b.eps, b.eps_count, U, dGl, b.dp_lo, epart, s);
+  e = launch_bwd_lo<float, T>(p, Gl, b.p_lo, b.eps, b.eps_count, U, dGl, b.dp_lo, epart,
+                              reinterpret_cast<float*>(b.ws + p.off_x), s);
   if (e != hipSuccess) return e;
   if (b.deps) {
     e = launch_eps_reduce(p, epart, b.eps_count, b.deps, s);

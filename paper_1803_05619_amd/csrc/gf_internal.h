@@ -54,6 +54,8 @@ struct Plan {
   // any size ratio: the vertical adjoint's low-res rows x high-res columns
   // (dA_bar and db_bar parts)
   size_t off_v;
+  // wide low-res backward (wide_bwd(r)): its X planes, 16 bytes per pixel
+  size_t off_x;
   // guided path: G_l, G_h (float planes), dG_l, dG_h, moments partials,
   // folded transform parameters (2 calls), accumulator partials/totals
   size_t off_gl, off_gh, off_dgl, off_dgh, off_mom, off_fold, off_accp, off_acct;
@@ -96,6 +98,19 @@ constexpr size_t bwd_hi_lds_bytes(int ubh, int tw) {
 }
 constexpr size_t kHiLdsMax = 65536;
 constexpr int kCoefRingPow2Max = 32;  // coef: 64 * (16 KR + 24 * 4) bytes
+// Wide low-res backward (gf_wide.h), from radius wide_bwd_min_r(): 256
+// threads (input columns) per strip, blocks of kWideB rows, LDS rows of
+// 256 + 256 / 4 padded columns holding the block's FP64 column sums (6
+// quantities in the first pass, 48 bytes per padded column and row; 4 in the
+// second).  The environment variable GF_WIDE_BWD_R overrides the default
+// radius (at least kWideMinR), for measurements.
+constexpr int kWideMinR = 3, kWideBwdR = 5;
+constexpr int kWideB = 4;
+constexpr int kWideBThreads = 256;
+constexpr size_t wide_row(int nt) { return (size_t)nt + nt / 4; }
+constexpr size_t bwd_wide_lds_bytes() { return (size_t)kWideB * wide_row(kWideBThreads) * 48; }
+int wide_bwd_min_r();
+inline bool wide_bwd(int r) { return r >= wide_bwd_min_r(); }
 constexpr int kBwdLoRingPow2Max = 16;  // bwd_lo: 64 * (32 KR + 40 * 4) bytes
 
 // Radii up to 8 keep each lane's vertical windows (2R + block rows) in
@@ -217,6 +232,7 @@ struct BwdLoArgs {
   float* dp_lo;     // may be null
   float* eps_part;  // [planes][pny][pnx]: one partial per strip segment
   int pnx, pny;     // strips and row segments per plane
+  float* X;         // wide walkers: [planes][h][w][4] adjoint quantities
 };
 
 // ------------------------------------------------------------ convolutional layer

@@ -1884,6 +1884,35 @@ __global__ __launch_bounds__(256) void eps_multi_kernel(const EpsItem* items, ch
   if (threadIdx.x == 0) *it.deps = ((red[0] + red[1]) + red[2]) + red[3];
 }
 
+#include "gf_wide.h"
+
+template <typename TG, typename TP, bool MAB>
+__global__ __launch_bounds__(kWideBT) void bwd_wide_x_multi_kernel(MultiLaunch m, int R) {
+  for (long long t = blockIdx.x; t < m.total; t += gridDim.x) {
+    long long l;
+    const MultiItem<BwdLoArgs>& it = item_of<BwdLoArgs>(m, t, l);
+    BwdLoArgs a = it.a;
+    a.U = rebase(m.ws, a.U);
+    a.eps_part = rebase(m.ws, a.eps_part);
+    a.X = rebase(m.ws, a.X);
+    const long long xy = (long long)it.nx * it.ny;
+    bwd_wide_x_body<TG, TP, MAB>(a, (int)(l % it.nx), (int)((l / it.nx) % it.ny), (int)(l / xy),
+                                 R);
+  }
+}
+
+template <typename TG, typename TP>
+__global__ __launch_bounds__(kWideBT) void bwd_wide_out_multi_kernel(MultiLaunch m, int R) {
+  for (long long t = blockIdx.x; t < m.total; t += gridDim.x) {
+    long long l;
+    const MultiItem<BwdLoArgs>& it = item_of<BwdLoArgs>(m, t, l);
+    BwdLoArgs a = it.a;
+    a.X = rebase(m.ws, a.X);
+    const long long xy = (long long)it.nx * it.ny;
+    bwd_wide_out_body<TG, TP>(a, (int)(l % it.nx), (int)((l / it.nx) % it.ny), (int)(l / xy), R);
+  }
+}
+
 // ------------------------------------------------------------ dispatch
 
 // Calls f(std::integral_constant<int, R>) for the runtime radius r.
@@ -2070,10 +2099,25 @@ hipError_t launch_bwd_hi(const Plan& p, const void* G_hi, const void* dq, void* 
 template <typename TG, typename TP>
 hipError_t launch_bwd_lo(const Plan& p, const void* G_lo, const void* p_lo, const float* eps,
                          int eps_count, const float* U, float* dG_lo, float* dp_lo,
-                         float* part, hipStream_t s) {
+                         float* part, float* X, hipStream_t s) {
   BwdLoArgs a{G_lo, p_lo, eps, eps_count, p.c, U, p.ubh, p.tw, p.nby, p.nbx,
-              p.h, p.w, p.loTR, dG_lo, dp_lo, part, p.lo_nx, p.lo_ny};
+              p.h, p.w, p.loTR, dG_lo, dp_lo, part, p.lo_nx, p.lo_ny, X};
   const dim3 grid(p.lo_nx, p.lo_ny, p.planes);
+  if (wide_bwd(p.r)) {
+    prof_begin("gf_bwd_lo", s);
+    if (p.mean_ab)
+      hipLaunchKernelGGL((bwd_wide_x_kernel<TG, TP, true>), grid, dim3(kWideBT), p.loLDS, s, a, p.r);
+    else
+      hipLaunchKernelGGL((bwd_wide_x_kernel<TG, TP, false>), grid, dim3(kWideBT), p.loLDS, s, a,
+                         p.r);
+    prof_end(s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    prof_begin("gf_bwd_lo_out", s);
+    hipLaunchKernelGGL((bwd_wide_out_kernel<TG, TP>), grid, dim3(kWideBT), p.loLDS, s, a, p.r);
+    prof_end(s);
+    return hipGetLastError();
+  }
   prof_begin("gf_bwd_lo", s);
   hipError_t err = with_radius(p.r, [&](auto rc) {
     constexpr int R = decltype(rc)::value;
@@ -2120,7 +2164,8 @@ hipError_t backward_t(const Plan& p, const BwdArgs& b, hipStream_t s) {
   if (err != hipSuccess) return err;
   if (!b.dI_lo && !b.dp_lo && !b.deps) return hipSuccess;
   float* part = reinterpret_cast<float*>(b.ws + p.off_eps);
-  err = launch_bwd_lo<T, T>(p, b.I_lo, b.p_lo, b.eps, b.eps_count, U, b.dI_lo, b.dp_lo, part, s);
+  err = launch_bwd_lo<T, T>(p, b.I_lo, b.p_lo, b.eps, b.eps_count, U, b.dI_lo, b.dp_lo, part,
+                            reinterpret_cast<float*>(b.ws + p.off_x), s);
   if (err != hipSuccess || !b.deps) return err;
   return launch_eps_reduce(p, part, b.eps_count, b.deps, s);
 }
@@ -2170,6 +2215,21 @@ hipError_t launch_bwd_lo_multi(const BatchClass& c, char* ws, hipStream_t s) {
   MultiLaunch m = c.m;
   m.ws = ws;
   prof_begin(class_name_r(kClassBwdLo, c.R), s);
+  if (wide_bwd(c.R)) {
+    const dim3 g(m.grid);
+    if (c.MAB)
+      hipLaunchKernelGGL((bwd_wide_x_multi_kernel<TG, TP, true>), g, dim3(kWideBT), c.lds, s, m, c.R);
+    else
+      hipLaunchKernelGGL((bwd_wide_x_multi_kernel<TG, TP, false>), g, dim3(kWideBT), c.lds, s, m,
+                         c.R);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL((bwd_wide_out_multi_kernel<TG, TP>), g, dim3(kWideBT), c.lds, s, m, c.R);
+      e = hipGetLastError();
+    }
+    prof_end(s);
+    return e;
+  }
   hipError_t err = with_radius(c.R, [&](auto rc) {
     constexpr int R = decltype(rc)::value;
     if (c.MAB)

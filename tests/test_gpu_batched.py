@@ -26,7 +26,9 @@ def _gf():
 def uneven_items(count, div, io_dtype="f32", extra=True):
     """The uneven-batch recipe at reduced size, plus edge items: a width that
     forces the scalar high-res path, Algorithm 1's form (no window mean of
-    A and b), s = 1 and two images in one item."""
+    A and b), s = 1, two images in one item, and radii that take the wide
+    low-res backward (a low-res width over one 256-column strip; a low-res
+    image smaller than its windows)."""
     probs = datagen.batched_items(count, div=div, io_dtype=io_dtype)
     for p in probs:
         p["mean_ab"] = True
@@ -38,7 +40,10 @@ def uneven_items(count, div, io_dtype="f32", extra=True):
         e5 = datagen.make_problem(1, 3, 4 * 24, 4 * 36, 4, 1, 1e-3, io_dtype, config=144)
         e1["mean_ab"], e2["mean_ab"], e3["mean_ab"], e4["mean_ab"] = True, False, True, True
         e5["mean_ab"], e5["align_corners"] = True, True
-        probs += [e1, e2, e3, e4, e5]
+        e6 = datagen.make_problem(1, 3, 4 * 70, 4 * 300, 4, 6, 1e-3, io_dtype, config=145)
+        e7 = datagen.make_problem(1, 3, 2 * 9, 2 * 11, 2, 5, 1e-2, io_dtype, config=146)
+        e6["mean_ab"], e7["mean_ab"] = True, False
+        probs += [e1, e2, e3, e4, e5, e6, e7]
     return probs
 
 

@@ -98,6 +98,16 @@ def test_factors_and_radii(s, r):
     check(prob)
 
 
+@pytest.mark.parametrize("r, mean_ab, dt", [(5, True, "f32"), (6, False, "f32"), (10, True, "f32"),
+                                          (8, True, "f16"), (7, False, "bf16")])
+def test_wide_backward_radii(r, mean_ab, dt):
+    """The wide low-res backward (large radii): low-res 77 x 530 spans three
+    256-column strips with a ragged last one and three 32-row tiles with a
+    ragged last one; two images."""
+    prob = datagen.make_problem(2, 3, 4 * 77, 4 * 530, 4, r, [1e-4, 1e-2], dt, config=91)
+    check(prob, mean_ab=mean_ab)
+
+
 def test_scalar_path_odd_width():
     """W not a multiple of 4: the element-wise (VEC = 1) kernels."""
     prob = datagen.make_problem(1, 2, 2 * 37, 2 * 49, 2, 2, 1e-3, "f32", config=91)
