@@ -22,6 +22,7 @@ struct Plan {
   int S;        // integer upsampling factor (H = S h, W = S w); 0 for any other ratio
   int gen;      // 1: any size ratio (the general high-res kernels), S = 0
   int xcd;      // XCD-aware workgroup order for the high-res kernels (0: off; see xcd_order)
+  int lo_xcd;   // the same for the single-problem low-res walkers
   int VEC;      // high-res elements per thread-load (16 bytes, or 1)
   int planes;   // n * c
   // low-res coefficient kernel: one wave per strip of 64 lanes (columns)
@@ -170,6 +171,7 @@ struct CoefArgs {
   int eps_count, c, h, w, TR;
   float* abar;  // [planes, h, w]
   float* bbar;  // [planes, h, w] or null
+  int xcd;      // XCD-aware strip order (see xcd_order)
 };
 
 struct ApplyArgs {
@@ -233,6 +235,7 @@ struct BwdLoArgs {
   float* eps_part;  // [planes][pny][pnx]: one partial per strip segment
   int pnx, pny;     // strips and row segments per plane
   float* X;         // wide walkers: [planes][h][w][4] adjoint quantities
+  int xcd;          // XCD-aware strip order (see xcd_order)
 };
 
 // ------------------------------------------------------------ convolutional layer

@@ -655,9 +655,24 @@ __device__ __forceinline__ void coef_body(const CoefArgs& a, const int bx, const
   }
 }
 
+// The (strip, row tile, plane) of this workgroup; with `xcd` the launch order
+// is remapped so that each XCD (workgroups are dispatched to the 8 XCDs in
+// turn) takes a contiguous run of tiles, whose shared halo rows and columns
+// then meet in that XCD's L2.
+__device__ __forceinline__ void lo_tile(int xcd, int& bx, int& by, int& bz) {
+  const long long nx = gridDim.x, nxy = nx * gridDim.y;
+  const long long lin = xcd_order(blockIdx.x + nx * blockIdx.y + nxy * blockIdx.z,
+                                  nxy * gridDim.z, xcd);
+  bx = (int)(lin % nx);
+  by = (int)((lin / nx) % gridDim.y);
+  bz = (int)(lin / nxy);
+}
+
 template <typename TG, typename TP, int R, bool MAB>
 __global__ __launch_bounds__(64) void coef_kernel(CoefArgs a) {
-  coef_body<TG, TP, R, MAB>(a, blockIdx.x, blockIdx.y, blockIdx.z);
+  int bx, by, bz;
+  lo_tile(a.xcd, bx, by, bz);
+  coef_body<TG, TP, R, MAB>(a, bx, by, bz);
 }
 
 // ------------------------------------------------------------ forward: high-res
@@ -1520,7 +1535,9 @@ __device__ __forceinline__ void bwd_lo_body(const BwdLoArgs& a, const int bx, co
 
 template <typename TG, typename TP, int R, bool MAB>
 __global__ __launch_bounds__(64) void bwd_lo_kernel(BwdLoArgs a) {
-  bwd_lo_body<TG, TP, R, MAB>(a, blockIdx.x, blockIdx.y, blockIdx.z);
+  int bx, by, bz;
+  lo_tile(a.xcd, bx, by, bz);
+  bwd_lo_body<TG, TP, R, MAB>(a, bx, by, bz);
 }
 
 __global__ __launch_bounds__(256) void eps_reduce_kernel(const float* part, int per_plane,
@@ -1930,7 +1947,7 @@ hipError_t with_radius(int r, F&& f) {
 template <typename TG, typename TP>
 hipError_t launch_coef(const Plan& p, const void* I_lo, const void* p_lo, const float* eps,
                        int eps_count, float* abar, float* bbar, hipStream_t s) {
-  CoefArgs a{I_lo, p_lo, eps, eps_count, p.c, p.h, p.w, p.coTR, abar, bbar};
+  CoefArgs a{I_lo, p_lo, eps, eps_count, p.c, p.h, p.w, p.coTR, abar, bbar, p.lo_xcd};
   const dim3 grid(p.co_nx, p.co_ny, p.planes);
   prof_begin("gf_coef", s);
   hipError_t err = with_radius(p.r, [&](auto rc) {
@@ -2101,7 +2118,7 @@ hipError_t launch_bwd_lo(const Plan& p, const void* G_lo, const void* p_lo, cons
                          int eps_count, const float* U, float* dG_lo, float* dp_lo,
                          float* part, float* X, hipStream_t s) {
   BwdLoArgs a{G_lo, p_lo, eps, eps_count, p.c, U, p.ubh, p.tw, p.nby, p.nbx,
-              p.h, p.w, p.loTR, dG_lo, dp_lo, part, p.lo_nx, p.lo_ny, X};
+              p.h, p.w, p.loTR, dG_lo, dp_lo, part, p.lo_nx, p.lo_ny, X, p.lo_xcd};
   const dim3 grid(p.lo_nx, p.lo_ny, p.planes);
   if (wide_bwd(p.r)) {
     prof_begin("gf_bwd_lo", s);
