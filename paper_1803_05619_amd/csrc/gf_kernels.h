@@ -1218,13 +1218,25 @@ __device__ __forceinline__ URow u_row(const BwdLoArgs& a, unsigned bmul, int i) 
 }
 
 // The four partial-plane reads per plane (ub: UP * 4, the byte offset of the
-// second plane of a block's partials).
+// second plane of a block's partials).  The neighbouring block row's reads
+// are skipped on rows inside a block (weight wb = 0, the same for the whole
+// wave): their terms are zero either way.
 __device__ __forceinline__ URaw gather_u_raw(__amdgpu_buffer_rsrc_t r, unsigned ub, const URow& ro,
                                              const UCol& co) {
-  return URaw{buf_ld<float>(r, co.o0, ro.o0),      buf_ld<float>(r, co.o1, ro.o0),
-              buf_ld<float>(r, co.o0, ro.o1),      buf_ld<float>(r, co.o1, ro.o1),
-              buf_ld<float>(r, co.o0, ro.o0 + ub), buf_ld<float>(r, co.o1, ro.o0 + ub),
-              buf_ld<float>(r, co.o0, ro.o1 + ub), buf_ld<float>(r, co.o1, ro.o1 + ub)};
+  URaw z;
+  z.a00 = buf_ld<float>(r, co.o0, ro.o0);
+  z.a01 = buf_ld<float>(r, co.o1, ro.o0);
+  z.v00 = buf_ld<float>(r, co.o0, ro.o0 + ub);
+  z.v01 = buf_ld<float>(r, co.o1, ro.o0 + ub);
+  if (ro.wb != 0.f) {
+    z.a10 = buf_ld<float>(r, co.o0, ro.o1);
+    z.a11 = buf_ld<float>(r, co.o1, ro.o1);
+    z.v10 = buf_ld<float>(r, co.o0, ro.o1 + ub);
+    z.v11 = buf_ld<float>(r, co.o1, ro.o1 + ub);
+  } else {
+    z.a10 = z.a11 = z.v10 = z.v11 = 0.f;
+  }
+  return z;
 }
 
 // Adjoint of the low-res part (Algorithm 1, plus the adjoint of the A/b
