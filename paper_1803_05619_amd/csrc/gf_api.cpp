@@ -48,6 +48,10 @@ int env_int(const char* name, int dflt) {
 
 }  // namespace
 
+int wide_coef_min_r() {
+  static const int v = std::max(kWideMinR, env_int("GF_WIDE_COEF_R", kWideCoefR));
+  return v;
+}
 int wide_bwd_min_r() {
   static const int v = std::max(kWideMinR, env_int("GF_WIDE_BWD_R", kWideBwdR));
   return v;
@@ -151,8 +155,9 @@ int make_plan(const gf_desc_t* d, const gf_guide_t* g, Plan* p, const char** why
   //    for the half types (one wave per workgroup: fewer partial rows)
   //  - the wide backward (r >= wide_bwd_min_r()): 32 rows (its 2r-row
   //    warm-up against parallelism: on the FP16 2 x 3 x 2160 x 3840 workload
-  //    at r = 8 its two passes took 175 / 117 / 137 us at 64 / 32 / 16 rows)
-  const int walk = r <= 2 ? 16 : r <= 4 ? 32 : 64;
+  //    at r = 8 its two passes took 175 / 117 / 137 us at 64 / 32 / 16 rows);
+  //    the wide coefficient passes: 16 rows (86 / 70 us at 64 / 16 rows)
+  const int walk = r <= 2 ? 16 : r <= 4 ? 32 : wide_coef(r) ? 16 : 64;
   // the backward walker at small radii: 24 rows (4 waves per SIMD; 16-row
   // segments leave a second, mostly empty round of waves)
   TuneVal tv{walk, r <= 2 ? 24 : wide_bwd(r) ? 32 : r <= 4 ? walk : 128, S >= 8 ? S : 8,
@@ -185,9 +190,14 @@ int make_plan(const gf_desc_t* d, const gf_guide_t* g, Plan* p, const char** why
   if (tv.coTR < 1 || tv.loTR < 1 || tv.RB < 1 || tv.bh < 2)
     return bad(GF_ERR_INVALID_ARG, "invalid launch shape");
   q.coTR = tv.coTR;
-  q.co_nx = (q.w + (64 - 2 * hal) - 1) / (64 - 2 * hal);
+  if (wide_coef(r)) {  // wide coefficient passes: strips of 256 input columns, halo r
+    q.co_nx = (q.w + (kWideBThreads - 2 * r) - 1) / (kWideBThreads - 2 * r);
+    q.coLDS = bwd_wide_lds_bytes();
+  } else {
+    q.co_nx = (q.w + (64 - 2 * hal) - 1) / (64 - 2 * hal);
+    q.coLDS = coef_lds_bytes(r);  // row buffers (+ (g,p), (A,b) rings for large r)
+  }
   q.co_ny = (q.h + q.coTR - 1) / q.coTR;
-  q.coLDS = coef_lds_bytes(r);  // row buffers (+ (g,p), (A,b) rings for large r)
   q.loTR = tv.loTR;
   if (wide_bwd(r)) {  // wide backward: strips of 256 input columns, halo r
     q.lo_nx = (q.w + (kWideBThreads - 2 * r) - 1) / (kWideBThreads - 2 * r);
@@ -239,8 +249,12 @@ int make_plan(const gf_desc_t* d, const gf_guide_t* g, Plan* p, const char** why
   const size_t vbytes = q.gen ? (size_t)q.planes * 2 * q.h * q.W * sizeof(float) : 0;
   q.off_eps = q.off_v + align_up(vbytes, 256);
   q.off_x = q.off_eps + align_up((size_t)q.planes * q.lo_nx * q.lo_ny * sizeof(float), 256);
-  const size_t xbytes = wide_bwd(r) ? (size_t)q.planes * q.h * q.w * 4 * sizeof(float) : 0;
+  // the wide passes' plane: X of the backward (16 bytes per pixel), or the
+  // coefficients' (A, b) (8), which the forward-only calls need as well
+  const bool wide_x = wide_bwd(r) || (wide_coef(r) && q.mean_ab);
+  const size_t xbytes = wide_x ? (size_t)q.planes * q.h * q.w * 4 * sizeof(float) : 0;
   q.ws_bwd = q.off_x + align_up(xbytes, 256);
+  if (wide_coef(r) && q.mean_ab) q.ws_fwd = std::max(q.ws_fwd, q.ws_bwd);
   if (gmode != GF_GUIDE_IDENTITY) {
     // guided path: the guide planes and the transform's reductions follow the
     // identity layout (a superset is allocated for both directions)

@@ -164,7 +164,7 @@ int create(const gf_item_t* items, int count, gf_plan** out) {
     g.off_eps = ws;
     ws += align_up((size_t)p.planes * p.lo_nx * p.lo_ny * sizeof(float), 256);
     g.off_x = ws;  // the wide backward's X planes
-    if (wide_bwd(p.r)) ws += align_up((size_t)p.planes * p.h * p.w * 4 * sizeof(float), 256);
+    if (wide_bwd(p.r) || (wide_coef(p.r) && p.mean_ab)) ws += align_up((size_t)p.planes * p.h * p.w * 4 * sizeof(float), 256);
     g.t_coef = (long long)p.co_nx * p.co_ny * p.planes;
     g.t_bwd_lo = (long long)p.lo_nx * p.lo_ny * p.planes;
     g.t_apply = ((long long)p.planes * p.nrb * p.nxv + 255) / 256;
@@ -214,7 +214,8 @@ int create(const gf_item_t* items, int count, gf_plan** out) {
       [&](int k) {
         const Plan& p = geo[k].p;
         return CoefArgs{items[k].I_lo, items[k].p_lo, eps_dev + k, 1, p.c, p.h, p.w, p.coTR,
-                        ws_rel<float>(geo[k].off_abar), ws_rel<float>(geo[k].off_bbar)};
+                        ws_rel<float>(geo[k].off_abar), ws_rel<float>(geo[k].off_bbar), 0,
+                        wide_coef(p.r) && p.mean_ab ? ws_rel<float>(geo[k].off_x) : nullptr};
       },
       [](const Geo& g, int& nx, int& ny) {
         nx = g.p.co_nx;

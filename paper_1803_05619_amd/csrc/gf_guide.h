@@ -707,7 +707,8 @@ hipError_t forward_guided_t(const Plan& p, const FwdArgs& f, hipStream_t s) {
   if (e != hipSuccess) return e;
   float* abar = reinterpret_cast<float*>(f.ws + p.off_abar);
   float* bbar = reinterpret_cast<float*>(f.ws + p.off_bbar);
-  e = launch_coef<float, T>(p, Gl, f.p_lo, f.eps, f.eps_count, abar, bbar, s);
+  e = launch_coef<float, T>(p, Gl, f.p_lo, f.eps, f.eps_count, abar, bbar,
+                            reinterpret_cast<float*>(f.ws + p.off_x), s);
   if (e != hipSuccess) return e;
   return launch_apply<float, T>(p, Gh, f.q, abar, bbar, s);
 }
@@ -759,7 +760,8 @@ hipError_t backward_guided_t(const Plan& p, const BwdArgs& b, hipStream_t s) {
   float* abar = reinterpret_cast<float*>(b.ws + p.off_abar);
   float* U = reinterpret_cast<float*>(b.ws + p.off_u);
   float* bbar = b.q ? reinterpret_cast<float*>(b.ws + p.off_bbar) : nullptr;
-  e = launch_coef<float, T>(p, Gl, b.p_lo, b.eps, b.eps_count, abar, bbar, s);
+  e = launch_coef<float, T>(p, Gl, b.p_lo, b.eps, b.eps_count, abar, bbar,
+                            reinterpret_cast<float*>(b.ws + p.off_x), s);
   if (e != hipSuccess) return e;
   // dG_h = dq * A_h (the guide gradient at high resolution) and the
   // transposed-bilinear partial planes (and q, in the same pass, with the

@@ -99,19 +99,23 @@ constexpr size_t bwd_hi_lds_bytes(int ubh, int tw) {
 }
 constexpr size_t kHiLdsMax = 65536;
 constexpr int kCoefRingPow2Max = 32;  // coef: 64 * (16 KR + 24 * 4) bytes
-// Wide low-res backward (gf_wide.h), from radius wide_bwd_min_r(): 256
+// Wide low-res walkers (gf_wide.h), from radius wide_bwd_min_r(): 256
 // threads (input columns) per strip, blocks of kWideB rows, LDS rows of
 // 256 + 256 / 4 padded columns holding the block's FP64 column sums (6
 // quantities in the first pass, 48 bytes per padded column and row; 4 in the
 // second).  The environment variable GF_WIDE_BWD_R overrides the default
 // radius (at least kWideMinR), for measurements.
-constexpr int kWideMinR = 3, kWideBwdR = 5;
+constexpr int kWideMinR = 3, kWideBwdR = 5, kWideCoefR = 5;
 constexpr int kWideB = 4;
 constexpr int kWideBThreads = 256;
 constexpr size_t wide_row(int nt) { return (size_t)nt + nt / 4; }
 constexpr size_t bwd_wide_lds_bytes() { return (size_t)kWideB * wide_row(kWideBThreads) * 48; }
 int wide_bwd_min_r();
 inline bool wide_bwd(int r) { return r >= wide_bwd_min_r(); }
+// The coefficients the same way (two passes: (A, b) per pixel, then their
+// window mean); GF_WIDE_COEF_R overrides the radius.
+int wide_coef_min_r();
+inline bool wide_coef(int r) { return r >= wide_coef_min_r(); }
 constexpr int kBwdLoRingPow2Max = 16;  // bwd_lo: 64 * (32 KR + 40 * 4) bytes
 
 // Radii up to 8 keep each lane's vertical windows (2R + block rows) in
@@ -172,6 +176,7 @@ struct CoefArgs {
   float* abar;  // [planes, h, w]
   float* bbar;  // [planes, h, w] or null
   int xcd;      // XCD-aware strip order (see xcd_order)
+  float* X;     // wide coefficient passes with the window mean: the (A, b) plane
 };
 
 struct ApplyArgs {

@@ -105,6 +105,22 @@ __device__ __forceinline__ void load_vec_nt(const T* p, float (&out)[VEC]) {
   for (int e = 0; e < VEC; ++e) out[e] = to_f(t[e]);
 }
 
+// The same in two steps: the raw vector (held in flight, packed for the half
+// types), then its elements as float.
+template <typename T, int VEC>
+using RawVec = typename Carrier<sizeof(T) * VEC>::type;
+template <typename T, int VEC>
+__device__ __forceinline__ RawVec<T, VEC> load_raw_nt(const T* p) {
+  return __builtin_nontemporal_load(reinterpret_cast<const RawVec<T, VEC>*>(p));
+}
+template <typename T, int VEC>
+__device__ __forceinline__ void unpack_vec(const RawVec<T, VEC>& c, float (&out)[VEC]) {
+  T t[VEC];
+  __builtin_memcpy(t, &c, sizeof(c));
+#pragma unroll
+  for (int e = 0; e < VEC; ++e) out[e] = to_f(t[e]);
+}
+
 template <typename T, int VEC>
 __device__ __forceinline__ void store_vec_nt(T* p, const float (&v)[VEC]) {
   typedef typename Carrier<sizeof(T) * VEC>::type C;
@@ -1011,20 +1027,24 @@ __device__ __forceinline__ void bwd_hi_body(const BwdHiArgs& a, const int bx, co
   // are zeroed), so that no load sits in a divergent branch
   // Rows are loaded in units of SR rows (a low-res row block at S <= 4,
   // half of one at S = 8: the two register buffers then hold 2 x 4 rows of
-  // G and dq, not 2 x 8) while the previous unit is computed.
+  // G and dq, not 2 x 8) while the previous unit is computed.  The buffers
+  // hold the raw vectors (two half elements per register for the half
+  // types), converted row by row where they are used: the FP16 fused pass
+  // 170 -> 148 VGPRs, a third wave per SIMD.
   constexpr int SR = S >= 8 ? S / 2 : S;
   constexpr int NH = S / SR;
-  auto load_unit = [&](int i, int u, float (&d)[SR][VEC], float (&g)[SR][VEC])
-                       __attribute__((always_inline)) {
+  typedef RawVec<TD, VEC> RD;
+  typedef RawVec<TG, VEC> RG;
+  auto load_unit = [&](int i, int u, RD (&d)[SR], RG (&g)[SR]) __attribute__((always_inline)) {
 #pragma unroll
     for (int t = 0; t < SR; ++t) {
-      load_vec_nt<TD, VEC>(Dp + (size_t)(S * i + SR * u + t) * W, d[t]);
-      load_vec_nt<TG, VEC>(Gp + (size_t)(S * i + SR * u + t) * W, g[t]);
+      d[t] = load_raw_nt<TD, VEC>(Dp + (size_t)(S * i + SR * u + t) * W);
+      g[t] = load_raw_nt<TG, VEC>(Gp + (size_t)(S * i + SR * u + t) * W);
     }
   };
   // unit U of low-res row block i
-  auto part = [&](auto uc, int i, float (&d)[SR][VEC], float (&g)[SR][VEC],
-                  float (&dn)[SR][VEC], float (&gn)[SR][VEC]) __attribute__((always_inline)) {
+  auto part = [&](auto uc, int i, RD (&dr)[SR], RG (&gr)[SR], RD (&dn)[SR], RG (&gn)[SR])
+                  __attribute__((always_inline)) {
     constexpr int U = decltype(uc)::value;
     if constexpr (U == 0) {
       hrow<VEC>(Ab, i + 1, h, w, j0, j1, wx, ap);
@@ -1040,6 +1060,9 @@ __device__ __forceinline__ void bwd_hi_body(const BwdHiArgs& a, const int bx, co
       const int t2 = SR * U + t;  // row within the block
       const int num = 2 * t2 + 1 - S;
       float o[VEC], qo[FWD ? VEC : 1];
+      float d[1][VEC], g[1][VEC];  // this row as float (index 0)
+      unpack_vec<TD, VEC>(dr[t], d[0]);
+      unpack_vec<TG, VEC>(gr[t], g[0]);
       // weights of this row on the low-res rows i-1, i, i+1; at the image's
       // first/last row block the source row is clamped and all weight goes
       // to row i (selected as weights, not as branches over accumulators)
@@ -1047,12 +1070,12 @@ __device__ __forceinline__ void bwd_hi_body(const BwdHiArgs& a, const int bx, co
         const RowW rw = row_weights_ac(S * i + t2, i, h, a.H);
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
-          const float dv = valid ? d[t][e] : 0.f;
+          const float dv = valid ? d[0][e] : 0.f;
           const float Av = rw.m * am[e] + rw.c * ac[e] + rw.p * ap[e];
           if constexpr (FWD)
-            qo[e] = Av * g[t][e] + (rw.m * bm[e] + rw.c * bc[e] + rw.p * bp[e]);
+            qo[e] = Av * g[0][e] + (rw.m * bm[e] + rw.c * bc[e] + rw.p * bp[e]);
           o[e] = dv * Av;
-          const float vA = dv * g[t][e], vB = dv;
+          const float vA = dv * g[0][e], vB = dv;
           pA[e] += rw.m * vA;
           cA[e] += rw.c * vA;
           nA[e] += rw.p * vA;
@@ -1065,11 +1088,11 @@ __device__ __forceinline__ void bwd_hi_body(const BwdHiArgs& a, const int bx, co
         const float wp = top ? 0.f : 1.f - wy, wc = top ? 1.f : wy;
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
-          const float dv = valid ? d[t][e] : 0.f;
+          const float dv = valid ? d[0][e] : 0.f;
           const float Av = am[e] + wy * (ac[e] - am[e]);
-          if constexpr (FWD) qo[e] = Av * g[t][e] + (bm[e] + wy * (bc[e] - bm[e]));
+          if constexpr (FWD) qo[e] = Av * g[0][e] + (bm[e] + wy * (bc[e] - bm[e]));
           o[e] = dv * Av;
-          const float vA = dv * g[t][e], vB = dv;
+          const float vA = dv * g[0][e], vB = dv;
           pA[e] += wp * vA;
           cA[e] += wc * vA;
           pB[e] += wp * vB;
@@ -1080,11 +1103,11 @@ __device__ __forceinline__ void bwd_hi_body(const BwdHiArgs& a, const int bx, co
         const float wc = bot ? 1.f : 1.f - wy, wn = bot ? 0.f : wy;
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
-          const float dv = valid ? d[t][e] : 0.f;
+          const float dv = valid ? d[0][e] : 0.f;
           const float Av = ac[e] + wy * (ap[e] - ac[e]);
-          if constexpr (FWD) qo[e] = Av * g[t][e] + (bc[e] + wy * (bp[e] - bc[e]));
+          if constexpr (FWD) qo[e] = Av * g[0][e] + (bc[e] + wy * (bp[e] - bc[e]));
           o[e] = dv * Av;
-          const float vA = dv * g[t][e], vB = dv;
+          const float vA = dv * g[0][e], vB = dv;
           cA[e] += wc * vA;
           nA[e] += wn * vA;
           cB[e] += wc * vB;
@@ -1122,7 +1145,8 @@ __device__ __forceinline__ void bwd_hi_body(const BwdHiArgs& a, const int bx, co
       hrow<VEC>(Bb, i_a - 1, h, w, j0, j1, wx, bm);
       hrow<VEC>(Bb, i_a, h, w, j0, j1, wx, bc);
     }
-    float da[SR][VEC], ga[SR][VEC], db[SR][VEC], gb[SR][VEC];
+    RD da[SR], db[SR];
+    RG ga[SR], gb[SR];
     load_unit(i_a, 0, da, ga);
     if constexpr (NH == 1) {
       for (int i = i_a; i < i_b; i += 2) {
@@ -1915,30 +1939,59 @@ __global__ __launch_bounds__(256) void eps_multi_kernel(const EpsItem* items, ch
 
 #include "gf_wide.h"
 
-template <typename TG, typename TP, bool MAB>
-__global__ __launch_bounds__(kWideBT) void bwd_wide_x_multi_kernel(MultiLaunch m, int R) {
+template <typename TG, typename TP, int MODE>
+__global__ __launch_bounds__(kWideBT) void wide_stats_multi_kernel(MultiLaunch m, int R) {
   for (long long t = blockIdx.x; t < m.total; t += gridDim.x) {
     long long l;
-    const MultiItem<BwdLoArgs>& it = item_of<BwdLoArgs>(m, t, l);
-    BwdLoArgs a = it.a;
-    a.U = rebase(m.ws, a.U);
-    a.eps_part = rebase(m.ws, a.eps_part);
-    a.X = rebase(m.ws, a.X);
-    const long long xy = (long long)it.nx * it.ny;
-    bwd_wide_x_body<TG, TP, MAB>(a, (int)(l % it.nx), (int)((l / it.nx) % it.ny), (int)(l / xy),
-                                 R);
+    BwdLoArgs a;
+    int nx, ny;
+    if constexpr (MODE == kWideCoef) {
+      const MultiItem<CoefArgs>& it = item_of<CoefArgs>(m, t, l);
+      CoefArgs c = it.a;
+      c.abar = rebase(m.ws, c.abar);
+      c.bbar = rebase(m.ws, c.bbar);
+      c.X = rebase(m.ws, c.X);
+      a = wide_coef_args(c);
+      nx = it.nx;
+      ny = it.ny;
+    } else {
+      const MultiItem<BwdLoArgs>& it = item_of<BwdLoArgs>(m, t, l);
+      a = it.a;
+      a.U = rebase(m.ws, a.U);
+      a.eps_part = rebase(m.ws, a.eps_part);
+      a.X = rebase(m.ws, a.X);
+      nx = it.nx;
+      ny = it.ny;
+    }
+    const long long xy = (long long)nx * ny;
+    wide_stats_body<TG, TP, MODE>(a, (int)(l % nx), (int)((l / nx) % ny), (int)(l / xy), R);
   }
 }
 
-template <typename TG, typename TP>
-__global__ __launch_bounds__(kWideBT) void bwd_wide_out_multi_kernel(MultiLaunch m, int R) {
+template <typename TG, typename TP, int MODE>
+__global__ __launch_bounds__(kWideBT) void wide_box_multi_kernel(MultiLaunch m, int R) {
   for (long long t = blockIdx.x; t < m.total; t += gridDim.x) {
     long long l;
-    const MultiItem<BwdLoArgs>& it = item_of<BwdLoArgs>(m, t, l);
-    BwdLoArgs a = it.a;
-    a.X = rebase(m.ws, a.X);
-    const long long xy = (long long)it.nx * it.ny;
-    bwd_wide_out_body<TG, TP>(a, (int)(l % it.nx), (int)((l / it.nx) % it.ny), (int)(l / xy), R);
+    BwdLoArgs a;
+    int nx, ny;
+    if constexpr (MODE == kWideCoef) {
+      const MultiItem<CoefArgs>& it = item_of<CoefArgs>(m, t, l);
+      CoefArgs c = it.a;
+      c.abar = rebase(m.ws, c.abar);
+      c.bbar = rebase(m.ws, c.bbar);
+      c.X = rebase(m.ws, c.X);
+      a = wide_coef_args(c);
+      nx = it.nx;
+      ny = it.ny;
+    } else {
+      const MultiItem<BwdLoArgs>& it = item_of<BwdLoArgs>(m, t, l);
+      a = it.a;
+      a.X = rebase(m.ws, a.X);
+      nx = it.nx;
+      ny = it.ny;
+    }
+    const long long xy = (long long)nx * ny;
+    wide_box_body<TG, TP, MODE>(a, (int)(l % nx), (int)((l / nx) % ny), (int)(l / xy), R);
   }
 }
 
@@ -1958,9 +2011,24 @@ hipError_t with_radius(int r, F&& f) {
 
 template <typename TG, typename TP>
 hipError_t launch_coef(const Plan& p, const void* I_lo, const void* p_lo, const float* eps,
-                       int eps_count, float* abar, float* bbar, hipStream_t s) {
-  CoefArgs a{I_lo, p_lo, eps, eps_count, p.c, p.h, p.w, p.coTR, abar, bbar, p.lo_xcd};
+                       int eps_count, float* abar, float* bbar, float* X, hipStream_t s) {
+  CoefArgs a{I_lo, p_lo, eps, eps_count, p.c, p.h, p.w, p.coTR, abar, bbar, p.lo_xcd,
+             p.mean_ab ? X : nullptr};
   const dim3 grid(p.co_nx, p.co_ny, p.planes);
+  if (wide_coef(p.r)) {
+    const BwdLoArgs wa = wide_coef_args(a);
+    prof_begin("gf_coef", s);
+    hipLaunchKernelGGL((wide_stats_kernel<TG, TP, kWideCoef>), grid, dim3(kWideBT), p.coLDS, s, wa,
+                       p.r);
+    prof_end(s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !p.mean_ab) return e;
+    prof_begin("gf_coef_mean", s);
+    hipLaunchKernelGGL((wide_box_kernel<TG, TP, kWideCoef>), grid, dim3(kWideBT), p.coLDS, s, wa,
+                       p.r);
+    prof_end(s);
+    return hipGetLastError();
+  }
   prof_begin("gf_coef", s);
   hipError_t err = with_radius(p.r, [&](auto rc) {
     constexpr int R = decltype(rc)::value;
@@ -2135,15 +2203,17 @@ hipError_t launch_bwd_lo(const Plan& p, const void* G_lo, const void* p_lo, cons
   if (wide_bwd(p.r)) {
     prof_begin("gf_bwd_lo", s);
     if (p.mean_ab)
-      hipLaunchKernelGGL((bwd_wide_x_kernel<TG, TP, true>), grid, dim3(kWideBT), p.loLDS, s, a, p.r);
+      hipLaunchKernelGGL((wide_stats_kernel<TG, TP, kWideBwdMab>), grid, dim3(kWideBT), p.loLDS, s,
+                         a, p.r);
     else
-      hipLaunchKernelGGL((bwd_wide_x_kernel<TG, TP, false>), grid, dim3(kWideBT), p.loLDS, s, a,
-                         p.r);
+      hipLaunchKernelGGL((wide_stats_kernel<TG, TP, kWideBwdPlain>), grid, dim3(kWideBT), p.loLDS,
+                         s, a, p.r);
     prof_end(s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     prof_begin("gf_bwd_lo_out", s);
-    hipLaunchKernelGGL((bwd_wide_out_kernel<TG, TP>), grid, dim3(kWideBT), p.loLDS, s, a, p.r);
+    hipLaunchKernelGGL((wide_box_kernel<TG, TP, kWideBwdMab>), grid, dim3(kWideBT), p.loLDS, s, a,
+                       p.r);
     prof_end(s);
     return hipGetLastError();
   }
@@ -2173,7 +2243,8 @@ template <typename T>
 hipError_t forward_t(const Plan& p, const FwdArgs& f, hipStream_t s) {
   float* abar = reinterpret_cast<float*>(f.ws + p.off_abar);
   float* bbar = reinterpret_cast<float*>(f.ws + p.off_bbar);
-  hipError_t err = launch_coef<T, T>(p, f.I_lo, f.p_lo, f.eps, f.eps_count, abar, bbar, s);
+  hipError_t err = launch_coef<T, T>(p, f.I_lo, f.p_lo, f.eps, f.eps_count, abar, bbar,
+                                     reinterpret_cast<float*>(f.ws + p.off_x), s);
   if (err != hipSuccess) return err;
   return launch_apply<T, T>(p, f.I_hi, f.q, abar, bbar, s);
 }
@@ -2185,7 +2256,8 @@ hipError_t backward_t(const Plan& p, const BwdArgs& b, hipStream_t s) {
   float* abar = reinterpret_cast<float*>(b.ws + p.off_abar);
   float* bbar = b.q ? reinterpret_cast<float*>(b.ws + p.off_bbar) : nullptr;
   float* U = reinterpret_cast<float*>(b.ws + p.off_u);
-  hipError_t err = launch_coef<T, T>(p, b.I_lo, b.p_lo, b.eps, b.eps_count, abar, bbar, s);
+  hipError_t err = launch_coef<T, T>(p, b.I_lo, b.p_lo, b.eps, b.eps_count, abar, bbar,
+                                     reinterpret_cast<float*>(b.ws + p.off_x), s);
   if (err != hipSuccess) return err;
   // with the forward: one high-res pass writes q, dI_h and the partial planes
   float* V = reinterpret_cast<float*>(b.ws + p.off_v);
@@ -2226,6 +2298,19 @@ hipError_t launch_coef_multi(const BatchClass& c, char* ws, hipStream_t s) {
   MultiLaunch m = c.m;
   m.ws = ws;
   prof_begin(class_name_r(kClassCoef, c.R), s);
+  if (wide_coef(c.R)) {
+    const dim3 g(m.grid);
+    hipLaunchKernelGGL((wide_stats_multi_kernel<TG, TP, kWideCoef>), g, dim3(kWideBT), c.lds, s, m,
+                       c.R);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && c.MAB) {
+      hipLaunchKernelGGL((wide_box_multi_kernel<TG, TP, kWideCoef>), g, dim3(kWideBT), c.lds, s, m,
+                         c.R);
+      e = hipGetLastError();
+    }
+    prof_end(s);
+    return e;
+  }
   hipError_t err = with_radius(c.R, [&](auto rc) {
     constexpr int R = decltype(rc)::value;
     if (c.MAB)
@@ -2247,13 +2332,15 @@ hipError_t launch_bwd_lo_multi(const BatchClass& c, char* ws, hipStream_t s) {
   if (wide_bwd(c.R)) {
     const dim3 g(m.grid);
     if (c.MAB)
-      hipLaunchKernelGGL((bwd_wide_x_multi_kernel<TG, TP, true>), g, dim3(kWideBT), c.lds, s, m, c.R);
+      hipLaunchKernelGGL((wide_stats_multi_kernel<TG, TP, kWideBwdMab>), g, dim3(kWideBT), c.lds, s,
+                         m, c.R);
     else
-      hipLaunchKernelGGL((bwd_wide_x_multi_kernel<TG, TP, false>), g, dim3(kWideBT), c.lds, s, m,
-                         c.R);
+      hipLaunchKernelGGL((wide_stats_multi_kernel<TG, TP, kWideBwdPlain>), g, dim3(kWideBT), c.lds,
+                         s, m, c.R);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) {
-      hipLaunchKernelGGL((bwd_wide_out_multi_kernel<TG, TP>), g, dim3(kWideBT), c.lds, s, m, c.R);
+      hipLaunchKernelGGL((wide_box_multi_kernel<TG, TP, kWideBwdMab>), g, dim3(kWideBT), c.lds, s, m,
+                         c.R);
       e = hipGetLastError();
     }
     prof_end(s);

@@ -1,13 +1,14 @@
-// Wide low-res backward for radii r >= wide_bwd_min_r() (included by
-// gf_kernels.h inside its namespace; the helpers it uses are defined there).
+// Wide low-res walkers for large radii: the backward from radius
+// wide_bwd_min_r(), the coefficients from wide_coef_min_r() (included by
+// gf_kernels.h inside its namespace; the helpers they use are defined there).
 //
-// The column walker of gf_kernels.h forms every window with direct
-// (2r + 1)-tap sums, down the column and across the lanes, and keeps 64 - 4r
-// of a wave's 64 columns: its work per output grows with r, and at r = 8
-// half the lanes are halo.  Here a workgroup of 256 threads owns a strip of
-// 256 input columns (256 - 2r outputs) and walks down its rows in blocks of
-// kWideB rows; every box sum is a running sum, so the work per output does
-// not depend on r:
+// The column walkers of gf_kernels.h form every window with direct
+// (2r + 1)-tap sums, down the column and across the lanes, and keep 64 - 4r
+// (64 - 2r without the A/b window mean) of a wave's 64 columns: their work
+// per output grows with r, and at r = 8 half the lanes are halo.  Here a
+// workgroup of 256 threads owns a strip of 256 input columns (256 - 2r
+// outputs) and walks down its rows in blocks of kWideB rows; every box sum
+// is a running sum, so the work per output does not depend on r:
 //   - down the walk, each thread keeps its column's running sums over the
 //     last 2r + 1 rows (add the row that enters, subtract the row that
 //     leaves; both rows' loads are issued one block ahead, the leaving one
@@ -19,6 +20,9 @@
 // value, and with sums of squares exact to ~1e-16 relative the variance
 // E[g^2] - E[g]^2 loses nothing to cancellation; the running sums do not
 // drift along the walk (FP64 adds run at the unpacked FP32 rate on MI355X).
+// A nested box (the window mean of A and b, and the backward's transposed
+// box of X) is a second pass over a plane that the first writes, rather
+// than a ring of rows in LDS.
 
 constexpr int kWideSeg = 4;  // columns per thread in the horizontal passes
 static_assert(wide_row(64) == 64 + 64 / kWideSeg, "the planner's LDS rows pad one per kWideSeg");
@@ -68,18 +72,19 @@ __device__ __forceinline__ double4 d4sub(double4 a, double4 b) {
   return make_double4(a.x - b.x, a.y - b.y, a.z - b.z, a.w - b.w);
 }
 
-// ------------------------------------------------------------ backward (two passes)
+// ------------------------------------------------------------ the two passes
 //
-// The low-res adjoint (Algorithm 1, plus the adjoint of the A/b window mean)
-// as two wide walkers over strips of kWideBT columns and TR rows:
-//   bwd_wide_x   per pixel: the window statistics, dA and db (the box sums
-//                of dAbar/N and dbbar/N with the window mean, else the
-//                gathered values themselves), and the adjoint quantities
-//                X = (dmean_I, dmean_p, dcov, dvar) / N, written to a plane
-//                (16 bytes per pixel) by the strip that owns the pixel; the
-//                strip's sum of dvar over its pixels goes to the deps partials;
-//   bwd_wide_out box sums of X give dI_l = B0 + 2 B3 g' + B2 p' and
-//                dp_l = B1 + B2 g'.
+// wide_stats  per pixel: the window statistics and
+//             - backward: dA and db (the box sums of dAbar/N and dbbar/N with
+//               the window mean, else the gathered values themselves) and the
+//               adjoint quantities X = (dmean_I, dmean_p, dcov, dvar) / N,
+//               written to a plane (16 bytes per pixel) by the strip that
+//               owns the pixel; the strip's sum of dvar goes to the deps
+//               partials;
+//             - coefficients: A and b, written to a plane (8 bytes per
+//               pixel) with the window mean, else as the outputs;
+// wide_box    box sums of that plane: dI_l = B0 + 2 B3 g' + B2 p' and
+//             dp_l = B1 + B2 g' (backward), or Abar and bbar (coefficients).
 // Both recentre the guide and input by the plane's value at its centre
 // pixel, so that the second pass's g', p' match the first pass's means.
 constexpr int kWideBT = 256;  // threads (input columns) of the backward walkers
@@ -92,9 +97,16 @@ __device__ __forceinline__ void plane_centre(const BwdLoArgs& a, const TG* G, co
   cp = to_f(P[o]);
 }
 
-template <typename TG, typename TP, bool MAB>
-__device__ __forceinline__ void bwd_wide_x_body(const BwdLoArgs& a, const int bx, const int by,
+// Pass modes: the backward with and without the A/b window mean, and the
+// coefficients (pass 1 writes (A, b) per pixel, as a float2 plane in X with
+// the window mean, else straight to the Abar and bbar planes, which the
+// coefficient passes receive as dI_lo and dp_lo).
+enum { kWideBwdMab = 0, kWideBwdPlain = 1, kWideCoef = 2 };
+
+template <typename TG, typename TP, int MODE>
+__device__ __forceinline__ void wide_stats_body(const BwdLoArgs& a, const int bx, const int by,
                                                 const int plane, const int R) {
+  constexpr bool MAB = MODE == kWideBwdMab, COEF = MODE == kWideCoef;
   constexpr int kTPR = kWideBT / kWideB;
   extern __shared__ double4 wlds[];
   // padded rows of (g', p', g'^2, g'p') and (dAbar/N, dbbar/N) column sums
@@ -119,12 +131,12 @@ __device__ __forceinline__ void bwd_wide_x_body(const BwdLoArgs& a, const int bx
   const int jcl = min(max(j, 0), w - 1);
   const unsigned jg = (unsigned)jcl * sizeof(TG), jp = (unsigned)jcl * sizeof(TP);
   // the upstream partial planes (dAbar, dbbar of the high-res backward)
-  const size_t UP = (size_t)(a.bh + 2) * (a.tw + 2);
-  const size_t uplane = (size_t)a.nby * a.nbx * 2 * UP;
-  const __amdgpu_buffer_rsrc_t uR = buf_rsrc(a.U + (size_t)plane * uplane, uplane * 4);
+  const size_t UP = COEF ? 0 : (size_t)(a.bh + 2) * (a.tw + 2);
+  const size_t uplane = COEF ? 0 : (size_t)a.nby * a.nbx * 2 * UP;
+  const __amdgpu_buffer_rsrc_t uR = buf_rsrc(COEF ? nullptr : a.U + (size_t)plane * uplane, uplane * 4);
   const unsigned ub = (unsigned)UP * 4u;
-  const UCol ucol = u_col(a, jcl);
-  const unsigned bmul = 0xffffffffu / (unsigned)a.bh + 1u;
+  const UCol ucol = COEF ? UCol{0u, 0u, 0.f} : u_col(a, jcl);
+  const unsigned bmul = COEF ? 0u : 0xffffffffu / (unsigned)a.bh + 1u;
   const int ncol_j = clip_count(jcl, R, w);
   // (dAbar, dbbar) at (x, j), divided by the window count with the window
   // mean (f_mu^T(y) is the box sum of y / N); zero outside the image
@@ -149,6 +161,7 @@ __device__ __forceinline__ void bwd_wide_x_body(const BwdLoArgs& a, const int bx
       q[d].p0 = buf_ld<TP>(pR, jp, o * (unsigned)sizeof(TP));
       q[d].g1 = buf_ld<TG>(gR, jg, ol * (unsigned)sizeof(TG));
       q[d].p1 = buf_ld<TP>(pR, jp, ol * (unsigned)sizeof(TP));
+      if constexpr (COEF) continue;
       const URow r0 = u_row(a, bmul, min(max(MAB ? x : x - R, 0), h - 1));
       q[d].z0 = gather_u_raw(uR, ub, r0, ucol);
       q[d].wb0 = r0.wb;
@@ -192,7 +205,8 @@ __device__ __forceinline__ void bwd_wide_x_body(const BwdLoArgs& a, const int bx
         sp += p - p2;
         sgg += g * g - g2 * g2;
         sgp += g * p - g2 * p2;
-        if (MAB) {
+        if constexpr (COEF) {
+        } else if (MAB) {
           const float2 in = upstream(x, q[d].z0, q[d].wb0);
           const float2 out = xl >= x0 ? upstream(xl, q[d].z1, q[d].wb1) : make_float2(0.f, 0.f);
           su += (double)in.x - (double)out.x;
@@ -204,7 +218,7 @@ __device__ __forceinline__ void bwd_wide_x_body(const BwdLoArgs& a, const int bx
         }
       }
       CS.put4(d, t, make_double4(sg, sp, sgg, sgp));  // row rc = x - R
-      CS.put2(4, d, t, make_double2(su, sv));
+      if constexpr (!COEF) CS.put2(4, d, t, make_double2(su, sv));
     }
     fetch(xb + kWideB);
     __syncthreads();
@@ -215,7 +229,7 @@ __device__ __forceinline__ void bwd_wide_x_body(const BwdLoArgs& a, const int bx
       if (xb + d < xend && rc >= i0 && rc < i1 && c0 < kWideBT - R) {
         const int nrow = clip_count(rc, R, h);
         double4 W = CS.get4(d, c0 - R), W2 = make_double4(0.0, 0.0, 0.0, 0.0);
-        double2 U = CS.get2(4, d, c0 - R), U2 = make_double2(0.0, 0.0);
+        double2 U = MAB ? CS.get2(4, d, c0 - R) : make_double2(0.0, 0.0), U2 = make_double2(0.0, 0.0);
         for (int k = c0 - R + 1; k < c0 + R; k += 2) {
           W = d4add(W, CS.get4(d, k));
           W2 = d4add(W2, CS.get4(d, k + 1));
@@ -231,6 +245,7 @@ __device__ __forceinline__ void bwd_wide_x_body(const BwdLoArgs& a, const int bx
         U.x += U2.x;
         U.y += U2.y;
         float4* Xrow = reinterpret_cast<float4*>(a.X + 4 * (pofs + (size_t)rc * w));
+        float2* ABrow = reinterpret_cast<float2*>(a.X + 2 * (pofs + (size_t)rc * w));
 #pragma unroll
         for (int uu = 0; uu < kWideSeg; ++uu) {
           const int c = c0 + uu;
@@ -251,6 +266,18 @@ __device__ __forceinline__ void bwd_wide_x_body(const BwdLoArgs& a, const int bx
             const float var = (float)(W.z * Nd - W.x * W.x) * (invN * invN);
             const float cov = (float)(W.w * Nd - W.x * W.y) * (invN * invN);
             const float mg = (float)W.x * invN, mp = (float)W.y * invN;
+            if constexpr (COEF) {
+              const float den = var + e;
+              const float A = den > 0.f ? cov * rcp(den) : 0.f;
+              const float B = (mp + cp) - A * (mg + cg);
+              if (a.X) {
+                ABrow[jj] = make_float2(A, B);
+              } else {
+                a.dI_lo[pofs + (size_t)rc * w + jj] = A;
+                if (a.dp_lo) a.dp_lo[pofs + (size_t)rc * w + jj] = B;
+              }
+              continue;
+            }
             // dA, db: the box sums of dAbar/N, dbbar/N (or the values)
             const double2 uc = MAB ? U : CS.get2(4, d, c);
             const float dA = (float)uc.x, db = (float)uc.y;
@@ -270,6 +297,7 @@ __device__ __forceinline__ void bwd_wide_x_body(const BwdLoArgs& a, const int bx
     }
     __syncthreads();
   }
+  if constexpr (COEF) return;
   // fixed-order workgroup sum of the strip's deps contribution
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) deps_acc += __shfl_xor(deps_acc, off);
@@ -283,13 +311,18 @@ __device__ __forceinline__ void bwd_wide_x_body(const BwdLoArgs& a, const int bx
   }
 }
 
-template <typename TG, typename TP>
-__device__ __forceinline__ void bwd_wide_out_body(const BwdLoArgs& a, const int bx, const int by,
-                                                  const int plane, const int R) {
+// Pass 2: box sums of the first pass's plane.  Backward: the four X
+// quantities give dI_l = B0 + 2 B3 g' + B2 p' and dp_l = B1 + B2 g'.
+// Coefficients: the two (A, b) quantities, divided by the window's count,
+// give Abar and bbar (written to dI_lo and dp_lo).
+template <typename TG, typename TP, int MODE>
+__device__ __forceinline__ void wide_box_body(const BwdLoArgs& a, const int bx, const int by,
+                                              const int plane, const int R) {
+  constexpr bool COEF = MODE == kWideCoef;
   constexpr int kTPR = kWideBT / kWideB;
   extern __shared__ double4 wlds[];
   constexpr int ROW = kWideBT + kWideBT / kWideSeg;
-  const WRows CS{reinterpret_cast<double*>(wlds), ROW};  // padded rows of X column sums
+  const WRows CS{reinterpret_cast<double*>(wlds), ROW};  // padded rows of column sums
   const int K = 2 * R + 1, TWo = kWideBT - 2 * R;
   const int t = threadIdx.x;
   const int h = a.h, w = a.w;
@@ -302,15 +335,25 @@ __device__ __forceinline__ void bwd_wide_out_body(const BwdLoArgs& a, const int 
   const TP* P = reinterpret_cast<const TP*>(a.p_lo) + pofs;
   float cg, cp;
   plane_centre(a, G, P, cg, cp);
-  const float4* X = reinterpret_cast<const float4*>(a.X) + pofs;
+  const float4* X4 = reinterpret_cast<const float4*>(a.X) + pofs;
+  const float2* X2 = reinterpret_cast<const float2*>(a.X) + pofs;
   const int jcl = min(max(j, 0), w - 1);
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  float4 qi[kWideB], qo[kWideB];  // X of the entering and leaving rows, one block ahead
+  // the plane's entering and leaving rows, one block ahead
+  float4 qi[kWideB], qo[kWideB];
   auto fetch = [&](int xb) __attribute__((always_inline)) {
 #pragma unroll
     for (int d = 0; d < kWideB; ++d) {
-      qi[d] = X[(size_t)min(max(xb + d, 0), h - 1) * w + jcl];
-      qo[d] = X[(size_t)min(max(xb + d - K, 0), h - 1) * w + jcl];
+      const size_t oi = (size_t)min(max(xb + d, 0), h - 1) * w + jcl;
+      const size_t oo = (size_t)min(max(xb + d - K, 0), h - 1) * w + jcl;
+      if constexpr (COEF) {
+        const float2 vi = X2[oi], vo = X2[oo];
+        qi[d] = make_float4(vi.x, vi.y, 0.f, 0.f);
+        qo[d] = make_float4(vo.x, vo.y, 0.f, 0.f);
+      } else {
+        qi[d] = X4[oi];
+        qo[d] = X4[oo];
+      }
     }
   };
   fetch(x0);
@@ -325,17 +368,24 @@ __device__ __forceinline__ void bwd_wide_out_body(const BwdLoArgs& a, const int 
         if (ok) {
           s0 += (double)in.x;
           s1 += (double)in.y;
-          s2 += (double)in.z;
-          s3 += (double)in.w;
+          if (!COEF) {
+            s2 += (double)in.z;
+            s3 += (double)in.w;
+          }
         }
         if (okl) {
           s0 -= (double)out.x;
           s1 -= (double)out.y;
-          s2 -= (double)out.z;
-          s3 -= (double)out.w;
+          if (!COEF) {
+            s2 -= (double)out.z;
+            s3 -= (double)out.w;
+          }
         }
       }
-      CS.put4(d, t, make_double4(s0, s1, s2, s3));  // row rx = x - R
+      if constexpr (COEF)
+        CS.put2(0, d, t, make_double2(s0, s1));  // row rx = x - R
+      else
+        CS.put4(d, t, make_double4(s0, s1, s2, s3));
     }
     fetch(xb + kWideB);
     __syncthreads();
@@ -344,24 +394,39 @@ __device__ __forceinline__ void bwd_wide_out_body(const BwdLoArgs& a, const int 
       const int rx = xb + d - R;
       const int c0 = R + s * kWideSeg;
       if (xb + d < xend && rx >= i0 && rx < i1 && c0 < kWideBT - R) {
-        double4 W = CS.get4(d, c0 - R), W2 = make_double4(0.0, 0.0, 0.0, 0.0);
+        auto get = [&](int c) __attribute__((always_inline)) {
+          if constexpr (COEF) {
+            const double2 v = CS.get2(0, d, c);
+            return make_double4(v.x, v.y, 0.0, 0.0);
+          } else {
+            return CS.get4(d, c);
+          }
+        };
+        double4 W = get(c0 - R), W2 = make_double4(0.0, 0.0, 0.0, 0.0);
         for (int k = c0 - R + 1; k < c0 + R; k += 2) {
-          W = d4add(W, CS.get4(d, k));
-          W2 = d4add(W2, CS.get4(d, k + 1));
+          W = d4add(W, get(k));
+          W2 = d4add(W2, get(k + 1));
         }
         W = d4add(W, W2);
+        const int nrow = clip_count(rx, R, h);
 #pragma unroll
         for (int u = 0; u < kWideSeg; ++u) {
           const int c = c0 + u;
           if (c >= kWideBT - R) break;
-          if (u > 0) W = d4sub(d4add(W, CS.get4(d, c + R)), CS.get4(d, c - R - 1));
+          if (u > 0) W = d4sub(d4add(W, get(c + R)), get(c - R - 1));
           const int jj = jl + c;
           if ((unsigned)jj < (unsigned)w) {
             const size_t o = (size_t)rx * w + jj;
-            const float g = to_f(G[o]) - cg, p = to_f(P[o]) - cp;
-            const float B0 = (float)W.x, B1 = (float)W.y, B2 = (float)W.z, B3 = (float)W.w;
-            if (a.dI_lo) a.dI_lo[pofs + o] = B0 + 2.f * B3 * g + B2 * p;
-            if (a.dp_lo) a.dp_lo[pofs + o] = B1 + B2 * g;
+            if constexpr (COEF) {
+              const float invN = 1.f / (float)(nrow * clip_count(jj, R, w));
+              a.dI_lo[pofs + o] = (float)W.x * invN;
+              if (a.dp_lo) a.dp_lo[pofs + o] = (float)W.y * invN;
+            } else {
+              const float g = to_f(G[o]) - cg, p = to_f(P[o]) - cp;
+              const float B0 = (float)W.x, B1 = (float)W.y, B2 = (float)W.z, B3 = (float)W.w;
+              if (a.dI_lo) a.dI_lo[pofs + o] = B0 + 2.f * B3 * g + B2 * p;
+              if (a.dp_lo) a.dp_lo[pofs + o] = B1 + B2 * g;
+            }
           }
         }
       }
@@ -370,11 +435,29 @@ __device__ __forceinline__ void bwd_wide_out_body(const BwdLoArgs& a, const int 
   }
 }
 
-template <typename TG, typename TP, bool MAB>
-__global__ __launch_bounds__(kWideBT) void bwd_wide_x_kernel(BwdLoArgs a, int R) {
-  bwd_wide_x_body<TG, TP, MAB>(a, blockIdx.x, blockIdx.y, blockIdx.z, R);
+template <typename TG, typename TP, int MODE>
+__global__ __launch_bounds__(kWideBT) void wide_stats_kernel(BwdLoArgs a, int R) {
+  wide_stats_body<TG, TP, MODE>(a, blockIdx.x, blockIdx.y, blockIdx.z, R);
 }
-template <typename TG, typename TP>
-__global__ __launch_bounds__(kWideBT) void bwd_wide_out_kernel(BwdLoArgs a, int R) {
-  bwd_wide_out_body<TG, TP>(a, blockIdx.x, blockIdx.y, blockIdx.z, R);
+template <typename TG, typename TP, int MODE>
+__global__ __launch_bounds__(kWideBT) void wide_box_kernel(BwdLoArgs a, int R) {
+  wide_box_body<TG, TP, MODE>(a, blockIdx.x, blockIdx.y, blockIdx.z, R);
+}
+
+// The coefficient passes' arguments from the coefficient walker's: the
+// outputs Abar, bbar travel as dI_lo, dp_lo, the (A, b) plane as X.
+__device__ __host__ __forceinline__ BwdLoArgs wide_coef_args(const CoefArgs& c) {
+  BwdLoArgs a{};
+  a.I_lo = c.I_lo;
+  a.p_lo = c.p_lo;
+  a.eps = c.eps;
+  a.eps_count = c.eps_count;
+  a.c = c.c;
+  a.h = c.h;
+  a.w = c.w;
+  a.TR = c.TR;
+  a.dI_lo = c.abar;
+  a.dp_lo = c.bbar;
+  a.X = c.X;
+  return a;
 }
