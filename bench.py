@@ -366,9 +366,14 @@ def workload_2(args, dev):
         gf.guided_filter(t["I_lo"], p_leaf, t["I_hi"], r=r, eps=eps_leaf,
                          guide=g_ag).backward(t["dq"])
 
+    # the guide backward is arithmetic-bound: per pixel and hidden unit the
+    # pre-activation (6 flops), its branch (1), the W2 gradient sums (6),
+    # dz = W2^T dG (5), dy (1), the sums of dy and of dy (x - mean) (1 + 6);
+    # per pixel the sums of dG and the centred input (6); both calls
+    flops = {"gf_guide_bwd": (n * H * W + n * h * w) * (26 * K + 6)}
     return dict(step=step, separate_step=separate_step, plain_step=plain_step,
                 cpu_sample=cpu_sample, cpu_one=cpu_one, autograd_step=autograd_step,
-                mpx=n * H * W / 1e6, tune=tune,
+                mpx=n * H * W / 1e6, tune=tune, flops=flops,
                 per_step=per_step, step_bytes=step_bytes, dtype="bf16",
                 config={"workload": "trainable-guide guided filtering fwd+bwd, BF16 I/O + FP32 "
                                     "accumulate, 8x3x1536x2048 <- 384x512 (s=4), r=1, eps=1e-8, "
@@ -899,13 +904,15 @@ def main():
         if rec.get("kernel_src_sha256_16") == kernel_hash() and dom in rec.get("kernels", {}):
             traffic = rec["kernels"][dom]["hbm_bytes_per_launch"]
     launches = prof[dom][1] / prof_steps if prof else 1
-    if dom_flops and not dom_bytes:
-        # an arithmetic-bound kernel: algorithmic FP32 flops over its time
-        tf = dom_flops / dom_s / 1e12
+    tf = dom_flops / dom_s / 1e12 if dom_flops else 0.0
+    if dom_flops and tf / FP32_VEC_PEAK_TFLOPS > achieved / HBM_PEAK_GBS:
+        # the arithmetic roofline binds: algorithmic FP32 flops over the
+        # kernel's time, against the FP32 vector peak
         roofline = {"bound": "alu", "kernel": dom, "achieved": round(tf, 3),
                     "peak": FP32_VEC_PEAK_TFLOPS, "unit": "TFLOP/s",
                     "frac": round(tf / FP32_VEC_PEAK_TFLOPS, 4), "traffic": None,
-                    "algo_flops_per_launch": int(dom_flops / max(launches, 1))}
+                    "algo_flops_per_launch": int(dom_flops / max(launches, 1)),
+                    "hbm_frac": round(achieved / HBM_PEAK_GBS, 4)}
     else:
         roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                     "peak": HBM_PEAK_GBS, "unit": "GB/s",

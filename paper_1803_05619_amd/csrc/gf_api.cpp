@@ -153,17 +153,15 @@ int make_plan(const gf_desc_t* d, const gf_guide_t* g, Plan* p, const char** why
   //  - low-res rows per backward high-res wave: 2 for FP32 (short walks
   //    stream best; at S >= 4 four waves stack into one partial block), 8
   //    for the half types (one wave per workgroup: fewer partial rows)
-  //  - the wide backward (r >= wide_bwd_min_r()): 32 rows (its 2r-row
-  //    warm-up against parallelism: on the FP16 2 x 3 x 2160 x 3840 workload
-  //    at r = 8 its two passes took 175 / 117 / 137 us at 64 / 32 / 16 rows);
-  //    the wide coefficient passes: 16 rows (86 / 70 us at 64 / 16 rows)
-  const int walk = r <= 2 ? 16 : r <= 4 ? 32 : wide_coef(r) ? 16 : 64;
+  //  - the wide passes (large r): see one_round below
+  const int walk = r <= 2 ? 16 : r <= 4 ? 32 : 64;
   // the backward walker at small radii: 24 rows (4 waves per SIMD; 16-row
   // segments leave a second, mostly empty round of waves)
-  TuneVal tv{walk, r <= 2 ? 24 : wide_bwd(r) ? 32 : r <= 4 ? walk : 128, S >= 8 ? S : 8,
+  TuneVal tv{walk, r <= 2 ? 24 : r <= 4 ? walk : 128, S >= 8 ? S : 8,
              d->io_dtype == GF_F32 ? 2 : 8};
   TuneVal tuned;
-  if (tune_lookup(TuneKey{d->io_dtype, S, r, gmode, d->mean_ab}, &tuned)) {
+  const bool tuned_hit = tune_lookup(TuneKey{d->io_dtype, S, r, gmode, d->mean_ab}, &tuned);
+  if (tuned_hit) {
     tv = tuned;
   } else if (r <= 2) {
     // small problems (latency-bound launches): shorter walks spread the
@@ -182,6 +180,25 @@ int make_plan(const gf_desc_t* d, const gf_guide_t* g, Plan* p, const char** why
       return planes * ((d->h_hi + rb - 1) / rb) * (d->w_hi / vec) / 256;
     };
     while (tv.RB > std::max(S, 1) && apply_wgs(tv.RB) < 256) tv.RB /= 2;
+  }
+  // the wide passes (when nothing was tuned): the row tile that fills one
+  // round of resident workgroups (LDS-limited: 3 per CU for the coefficient
+  // passes, 2 for the backward's), multiples of 8 from 16 rows; a problem too
+  // large for one round at 128 rows takes 64 (its halo rows then matter
+  // more than the tail of the last round).  Measured at r = 8 on the FP16
+  // 2 x 3 x 2160 x 3840 workload, the backward's two passes: 125 / 145 /
+  // 106 / 135 us at 16 / 24 / 32 / 48 rows (408 workgroups at 32 rows fit
+  // the 512 resident, 552 at 24 do not).
+  auto one_round = [&](int cap_per_cu, int nx) {
+    const long long planes = (long long)d->n * d->c;
+    for (int tr = 16; tr <= 128; tr += 8)
+      if (nx * planes * ((d->h_lo + tr - 1) / tr) <= 256LL * cap_per_cu) return tr;
+    return 64;
+  };
+  if (!tuned_hit) {
+    const int nxw = (d->w_lo + (kWideBThreads - 2 * r) - 1) / (kWideBThreads - 2 * r);
+    if (wide_coef(r)) tv.coTR = one_round((int)(kLdsPerCU / wide_lds_bytes(4)), nxw);
+    if (wide_bwd(r)) tv.loTR = one_round((int)(kLdsPerCU / wide_lds_bytes(6)), nxw);
   }
   if (env_int("GF_LO_ROWS", 0) > 0) tv.coTR = tv.loTR = env_int("GF_LO_ROWS", 0);
   if (env_int("GF_BWD_LO_ROWS", 0) > 0) tv.loTR = env_int("GF_BWD_LO_ROWS", 0);

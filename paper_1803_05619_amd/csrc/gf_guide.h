@@ -453,11 +453,15 @@ __global__ __launch_bounds__(256) void guide_bwd_kernel(GBwdArgs a) {
     int coff = 0;
     asm volatile("" : "+v"(coff));
     const float4* cc = cst + coff;
+    float xc[2][3];  // the inputs less their batch means, once per pixel
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       acc[AC_DG] += d[j][0];
       acc[AC_DG + 1] += d[j][1];
       acc[AC_DG + 2] += d[j][2];
+      xc[j][0] = x[j][0] - mx0;
+      xc[j][1] = x[j][1] - mx1;
+      xc[j][2] = x[j][2] - mx2;
     }
 #pragma unroll
     for (int k = 0; k < kKP; ++k) {
@@ -473,9 +477,9 @@ __global__ __launch_bounds__(256) void guide_bwd_kernel(GBwdArgs a) {
         const float dz = v.x * d[j][0] + v.y * d[j][1] + v.z * d[j][2];
         const float dy = pos ? dz : slope * dz;
         acc[AC_DY + k] += dy;
-        acc[AC_DYX + 3 * k] += dy * (x[j][0] - mx0);
-        acc[AC_DYX + 3 * k + 1] += dy * (x[j][1] - mx1);
-        acc[AC_DYX + 3 * k + 2] += dy * (x[j][2] - mx2);
+        acc[AC_DYX + 3 * k] += dy * xc[j][0];
+        acc[AC_DYX + 3 * k + 1] += dy * xc[j][1];
+        acc[AC_DYX + 3 * k + 2] += dy * xc[j][2];
       }
     }
   }

@@ -110,6 +110,10 @@ constexpr int kWideB = 4;
 constexpr int kWideBThreads = 256;
 constexpr size_t wide_row(int nt) { return (size_t)nt + nt / 4; }
 constexpr size_t bwd_wide_lds_bytes() { return (size_t)kWideB * wide_row(kWideBThreads) * 48; }
+// LDS of one wide pass holding nq FP64 quantities per padded column and row
+// (coefficients: 4 in the statistics pass, 2 in the mean; backward: 6, 4).
+constexpr size_t wide_lds_bytes(int nq) { return (size_t)kWideB * wide_row(kWideBThreads) * 8 * nq; }
+constexpr size_t kLdsPerCU = 160 * 1024;  // MI355X
 int wide_bwd_min_r();
 inline bool wide_bwd(int r) { return r >= wide_bwd_min_r(); }
 // The coefficients the same way (two passes: (A, b) per pixel, then their

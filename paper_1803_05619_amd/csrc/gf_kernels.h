@@ -2018,14 +2018,14 @@ hipError_t launch_coef(const Plan& p, const void* I_lo, const void* p_lo, const 
   if (wide_coef(p.r)) {
     const BwdLoArgs wa = wide_coef_args(a);
     prof_begin("gf_coef", s);
-    hipLaunchKernelGGL((wide_stats_kernel<TG, TP, kWideCoef>), grid, dim3(kWideBT), p.coLDS, s, wa,
-                       p.r);
+    hipLaunchKernelGGL((wide_stats_kernel<TG, TP, kWideCoef>), grid, dim3(kWideBT),
+                       wide_lds_bytes(4), s, wa, p.r);
     prof_end(s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !p.mean_ab) return e;
     prof_begin("gf_coef_mean", s);
-    hipLaunchKernelGGL((wide_box_kernel<TG, TP, kWideCoef>), grid, dim3(kWideBT), p.coLDS, s, wa,
-                       p.r);
+    hipLaunchKernelGGL((wide_box_kernel<TG, TP, kWideCoef>), grid, dim3(kWideBT), wide_lds_bytes(2),
+                       s, wa, p.r);
     prof_end(s);
     return hipGetLastError();
   }
@@ -2212,8 +2212,8 @@ hipError_t launch_bwd_lo(const Plan& p, const void* G_lo, const void* p_lo, cons
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     prof_begin("gf_bwd_lo_out", s);
-    hipLaunchKernelGGL((wide_box_kernel<TG, TP, kWideBwdMab>), grid, dim3(kWideBT), p.loLDS, s, a,
-                       p.r);
+    hipLaunchKernelGGL((wide_box_kernel<TG, TP, kWideBwdMab>), grid, dim3(kWideBT),
+                       wide_lds_bytes(4), s, a, p.r);
     prof_end(s);
     return hipGetLastError();
   }
@@ -2300,12 +2300,12 @@ hipError_t launch_coef_multi(const BatchClass& c, char* ws, hipStream_t s) {
   prof_begin(class_name_r(kClassCoef, c.R), s);
   if (wide_coef(c.R)) {
     const dim3 g(m.grid);
-    hipLaunchKernelGGL((wide_stats_multi_kernel<TG, TP, kWideCoef>), g, dim3(kWideBT), c.lds, s, m,
-                       c.R);
+    hipLaunchKernelGGL((wide_stats_multi_kernel<TG, TP, kWideCoef>), g, dim3(kWideBT),
+                       wide_lds_bytes(4), s, m, c.R);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess && c.MAB) {
-      hipLaunchKernelGGL((wide_box_multi_kernel<TG, TP, kWideCoef>), g, dim3(kWideBT), c.lds, s, m,
-                         c.R);
+      hipLaunchKernelGGL((wide_box_multi_kernel<TG, TP, kWideCoef>), g, dim3(kWideBT),
+                         wide_lds_bytes(2), s, m, c.R);
       e = hipGetLastError();
     }
     prof_end(s);
@@ -2339,8 +2339,8 @@ hipError_t launch_bwd_lo_multi(const BatchClass& c, char* ws, hipStream_t s) {
                          s, m, c.R);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) {
-      hipLaunchKernelGGL((wide_box_multi_kernel<TG, TP, kWideBwdMab>), g, dim3(kWideBT), c.lds, s, m,
-                         c.R);
+      hipLaunchKernelGGL((wide_box_multi_kernel<TG, TP, kWideBwdMab>), g, dim3(kWideBT),
+                         wide_lds_bytes(4), s, m, c.R);
       e = hipGetLastError();
     }
     prof_end(s);
