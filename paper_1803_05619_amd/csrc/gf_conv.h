@@ -595,6 +595,171 @@ __global__ __launch_bounds__(256) void conv_inputs_grad_kernel(ConvArgs a) {
   if (a.dp_lo) a.dp_lo[pofs + m] = dp;
 }
 
+// ------------------------------------------------------------ LDS-tiled gathers
+//
+// The window means and the inputs' gradients over output tiles of kCTH x kCTW
+// pixels of one plane: the workgroup first stages the tile of each input
+// plane with a halo of r rows and columns (zero outside the image) in LDS with
+// coalesced row loads, then every thread takes its kCTH / 4 pixels of one
+// column, reading the 9 taps from LDS.  Used up to dilation kConvTileMaxR (the
+// LDS of six staged planes stays within 64 KB); the per-pixel kernels above
+// take larger dilations.  The arithmetic and its order are those of the
+// per-pixel kernels.  (The statistics and the window-mean adjoint stay per
+// pixel: their longer per-pixel arithmetic gains less from shared loads than
+// the LDS costs them in occupancy.)
+// Tiles of 16 x 64 low-res pixels, up to dilation kConvTileMaxR (six staged
+// planes with their halo stay within 64 KB).
+constexpr int kConvTileH = 16, kConvTileW = 64, kConvTileMaxR = 8;
+constexpr size_t conv_tile_lds(int r, int planes) {
+  return (size_t)planes * (kConvTileH + 2 * r) * (kConvTileW + 2 * r) * sizeof(float);
+}
+constexpr int kCTH = kConvTileH, kCTW = kConvTileW;
+
+// Stages the tiles of NP planes: every thread first issues all its loads (at
+// most kStageIt rows x 2 columns per plane, addresses clamped into the image
+// so that no load sits behind a branch), then writes them to LDS; zero
+// outside the image.  Src(k, offset) reads plane k.
+constexpr int kStageIt = (kCTH + 2 * kConvTileMaxR + 3) / 4;
+
+template <int NP, typename Src>
+__device__ __forceinline__ void conv_stage_n(Src src, int h, int w, int i0, int j0, int r,
+                                             float* L, int LN) {
+  const int LW = kCTW + 2 * r, LH = kCTH + 2 * r;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  // rows of this wave (ty is the wave's index: a wave-uniform bound) and
+  // whether this lane also holds a column of the second pass (the halo)
+  const int nit = (LH - ty + 3) / 4;
+  const bool col2 = tx + 64 < LW;
+  float v[NP][kStageIt][2];
+#pragma unroll
+  for (int it = 0; it < kStageIt; ++it) {
+    if (it >= nit) break;
+    const int li = ty + 4 * it, i = i0 - r + li;
+    const int ic = min(max(i, 0), h - 1);
+#pragma unroll
+    for (int c2 = 0; c2 < 2; ++c2) {
+      if (c2 == 1 && !col2) continue;
+      const int lj = tx + 64 * c2, j = j0 - r + lj;
+      const int jc = min(max(j, 0), w - 1);
+      const bool ok = (unsigned)i < (unsigned)h && (unsigned)j < (unsigned)w;
+#pragma unroll
+      for (int k = 0; k < NP; ++k) {
+        const float x = src(k, (size_t)ic * w + jc);
+        v[k][it][c2] = ok ? x : 0.f;
+      }
+    }
+  }
+#pragma unroll
+  for (int it = 0; it < kStageIt; ++it) {
+    if (it >= nit) break;
+    const int li = ty + 4 * it;
+#pragma unroll
+    for (int c2 = 0; c2 < 2; ++c2) {
+      if (c2 == 1 && !col2) continue;
+      const int lj = tx + 64 * c2;
+#pragma unroll
+      for (int k = 0; k < NP; ++k) L[k * LN + li * LW + lj] = v[k][it][c2];
+    }
+  }
+}
+
+// Abar = f_d(A), bbar = f_d(b).  Grid: (tiles across, tiles down, planes).
+__global__ __launch_bounds__(256) void conv_fd_ab_tiled_kernel(ConvArgs a) {
+  extern __shared__ float ctl[];
+  const int h = a.h, w = a.w, r = a.r, plane = blockIdx.z;
+  const int i0 = blockIdx.y * kCTH, j0 = blockIdx.x * kCTW;
+  const int LW = kCTW + 2 * r, LN = LW * (kCTH + 2 * r);
+  float* LA = ctl;
+  float* LB = ctl + LN;
+  const size_t pofs = (size_t)plane * h * w;
+  const float *SA = a.A + pofs, *SB = a.B + pofs;
+  conv_stage_n<2>([&](int k, size_t o) { return k == 0 ? SA[o] : SB[o]; }, h, w, i0, j0, r, ctl, LN);
+  float Dk[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) Dk[q] = a.params[9 * (plane % a.c) + q];
+  __syncthreads();
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int j = j0 + tx;
+#pragma unroll
+  for (int k = 0; k < kCTH / 4; ++k) {
+    const int ti = ty * (kCTH / 4) + k, i = i0 + ti;
+    if (i >= h || j >= w) continue;
+    float N = 0.f, sa = 0.f, sb = 0.f;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      int o;
+      if (conv_tap(i, j, q, r, h, w, o)) {
+        const int l = (ti + r + (q / 3 - 1) * r) * LW + (tx + r + (q % 3 - 1) * r);
+        N += Dk[q];
+        sa += Dk[q] * LA[l];
+        sb += Dk[q] * LB[l];
+      }
+    }
+    a.abar[pofs + (size_t)i * w + j] = sa / N;
+    a.bbar[pofs + (size_t)i * w + j] = sb / N;
+  }
+}
+
+// dI_l, dp_l (as conv_inputs_grad_kernel).  Grid: (tiles across, tiles
+// down, planes).
+template <typename T>
+__global__ __launch_bounds__(256) void conv_inputs_grad_tiled_kernel(ConvArgs a) {
+  extern __shared__ float ctl[];
+  const int h = a.h, w = a.w, r = a.r, plane = blockIdx.z;
+  const int i0 = blockIdx.y * kCTH, j0 = blockIdx.x * kCTW;
+  const int LW = kCTW + 2 * r, LN = LW * (kCTH + 2 * r);
+  float* LmI = ctl;
+  float* LmP = ctl + LN;
+  float* LgmI = ctl + 2 * LN;
+  float* LgmP = ctl + 3 * LN;
+  float* Lgc = ctl + 4 * LN;
+  float* Lgv = ctl + 5 * LN;
+  const size_t pofs = (size_t)plane * h * w;
+  const float* src6[6] = {a.mI + pofs,  a.mP + pofs,   a.gmI + pofs,
+                          a.gmP + pofs, a.gcov + pofs, a.gvar + pofs};
+  conv_stage_n<6>([&](int k, size_t o) { return src6[k][o]; }, h, w, i0, j0, r, ctl, LN);
+  float Dk[9], Dsum = 0.f;
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    Dk[q] = a.params[9 * (plane % a.c) + q];
+    Dsum += Dk[q];
+  }
+  __syncthreads();
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int j = j0 + tx;
+#pragma unroll 1
+  for (int k = 0; k < kCTH / 4; ++k) {
+    const int ti = ty * (kCTH / 4) + k, i = i0 + ti;
+    if (i >= h || j >= w) continue;
+    const size_t m = (size_t)i * w + j;
+    const int lc = (ti + r) * LW + tx + r;
+    const bool inner = i >= 2 * r && i < h - 2 * r && j >= 2 * r && j < w - 2 * r;
+    const float Im = to_f(reinterpret_cast<const T*>(a.I_lo)[pofs + m]);
+    const float pm = to_f(reinterpret_cast<const T*>(a.p_lo)[pofs + m]);
+    float dI = 0.f, dp = 0.f;
+    auto gather = [&](int l, float aq) __attribute__((always_inline)) {
+      const float di = Im - LmI[l], dpp = pm - LmP[l];
+      dI += aq * (LgmI[l] + Lgc[l] * dpp + 2.f * Lgv[l] * di);
+      dp += aq * (LgmP[l] + Lgc[l] * di);
+    };
+    if (inner) {
+#pragma unroll
+      for (int q = 0; q < 9; ++q)
+        gather(lc - (q / 3 - 1) * r * LW - (q % 3 - 1) * r, Dk[q] / Dsum);
+    } else {
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        const int oi = i - (q / 3 - 1) * r, oj = j - (q % 3 - 1) * r;
+        if ((unsigned)oi < (unsigned)h && (unsigned)oj < (unsigned)w)
+          gather(lc - (q / 3 - 1) * r * LW - (q % 3 - 1) * r,
+                 Dk[q] / conv_norm(Dk, oi, oj, r, h, w));
+      }
+    }
+    if (a.dI_lo) a.dI_lo[pofs + m] = dI;
+    if (a.dp_lo) a.dp_lo[pofs + m] = dp;
+  }
+}
+
 // Totals of the parameter gradients: entry e sums the workgroups' partials
 // in order, then (D entries, with the window means) the window-mean
 // adjoint's partials image by image.
@@ -627,13 +792,32 @@ void launch_conv_c(int c, void (*k1)(ConvArgs), void (*k2)(ConvArgs), void (*k3)
   hipLaunchKernelGGL(k, grid, block, 0, s, a);
 }
 
+// Tiles of the LDS-tiled stencil kernels: (across, down, planes).
+inline dim3 conv_tile_grid(const ConvArgs& a) {
+  return dim3((unsigned)((a.w + kCTW - 1) / kCTW), (unsigned)((a.h + kCTH - 1) / kCTH),
+              (unsigned)(a.n * a.c));
+}
+
+// Abar, bbar: the tiled kernel up to kConvTileMaxR, else one thread per pixel.
+inline void launch_fd_ab(const ConvArgs& a, hipStream_t s) {
+  if (a.r <= kConvTileMaxR) {
+    hipLaunchKernelGGL(conv_fd_ab_tiled_kernel, conv_tile_grid(a), dim3(256),
+                       conv_tile_lds(a.r, 2), s, a);
+  } else {
+    const long long nplane = (long long)a.n * a.c * a.h * a.w;
+    hipLaunchKernelGGL(conv_fd_ab_kernel, dim3((unsigned)((nplane + 255) / 256)), dim3(256), 0,
+                       s, a);
+  }
+}
+
+
 }  // namespace
 
 template <typename T>
 hipError_t conv_forward_t(const ConvPlan& cp, const ConvArgs& a0, const void* I_hi, void* q,
                           char* ws, hipStream_t s) {
   ConvArgs a = a0;
-  const long long npix = (long long)a.n * a.h * a.w, nplane = npix * a.c;
+  const long long npix = (long long)a.n * a.h * a.w;
   prof_begin("gf_conv_stats", s);
   launch_conv_c<T>(a.c, conv_stats_kernel<T, 1>, conv_stats_kernel<T, 2>, conv_stats_kernel<T, 3>,
                    conv_stats_kernel<T, 4>, dim3((unsigned)((npix + 255) / 256)), dim3(256), s, a);
@@ -642,8 +826,7 @@ hipError_t conv_forward_t(const ConvPlan& cp, const ConvArgs& a0, const void* I_
   if (e != hipSuccess) return e;
   if (a.mean_ab) {
     prof_begin("gf_conv_fd_ab", s);
-    hipLaunchKernelGGL(conv_fd_ab_kernel, dim3((unsigned)((nplane + 255) / 256)), dim3(256), 0,
-                       s, a);
+    launch_fd_ab(a, s);
     prof_end(s);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -667,7 +850,7 @@ hipError_t conv_backward_t(const ConvPlan& cp, const ConvArgs& a0, const void* I
   if (e != hipSuccess) return e;
   if (a.mean_ab) {
     prof_begin("gf_conv_fd_ab", s);
-    hipLaunchKernelGGL(conv_fd_ab_kernel, dim3(gplane), dim3(256), 0, s, a);
+    launch_fd_ab(a, s);
     prof_end(s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
@@ -698,7 +881,11 @@ hipError_t conv_backward_t(const ConvPlan& cp, const ConvArgs& a0, const void* I
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (a.dI_lo || a.dp_lo) {
     prof_begin("gf_conv_inputs_grad", s);
-    hipLaunchKernelGGL((conv_inputs_grad_kernel<T>), dim3(gplane), dim3(256), 0, s, a);
+    if (a.r <= kConvTileMaxR)
+      hipLaunchKernelGGL((conv_inputs_grad_tiled_kernel<T>), conv_tile_grid(a), dim3(256),
+                         conv_tile_lds(a.r, 6), s, a);
+    else
+      hipLaunchKernelGGL((conv_inputs_grad_kernel<T>), dim3(gplane), dim3(256), 0, s, a);
     prof_end(s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }

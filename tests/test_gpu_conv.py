@@ -69,6 +69,15 @@ def test_conv_dilations(r, mean_ab):
     check(prob, conv_params(211 + r), r, mean_ab=mean_ab)
 
 
+@pytest.mark.parametrize("r", [8, 9])
+def test_conv_tiled_gathers_edge(r):
+    """Low-res 70 x 150: the LDS-tiled gathers' 16 x 64 tiles, three across
+    and five down with ragged last ones, at their largest dilation (8) and
+    the per-pixel kernels' first (9)."""
+    prob = datagen.make_problem(1, 3, 2 * 70, 2 * 150, 2, r, 0.0, "f32", config=220, noise=0.02)
+    check(prob, conv_params(221), r)
+
+
 def test_conv_align_corners_and_any_ratio():
     prob = datagen.make_problem(2, 3, 2 * 48, 2 * 56, 2, 1, 0.0, "f32", config=212, noise=0.02)
     check(prob, conv_params(213), 1, ac=True)
