@@ -1,0 +1,98 @@
+"""Precision report of the variance-cancellation regime: near-constant guide
+regions (0.5 + N(0, 1e-4)) and eps = 1e-8, the precision-stress workload at
+1/8 size, for FP16, FP32 and BF16 I/O at radii 1 and 8.
+
+Two evaluations of the same layer are compared element by element with the
+FP64 oracle (error measures: tests/parity.py):
+  hip    the HIP path: window statistics in two levels (column means and
+         squared deviations, then the deviations between columns) on values
+         recentred by a reference pixel below radius 5, FP64 running sums of
+         recentred values from radius 5;
+  naive  the plain PyTorch composition with the one-pass statistics as the
+         closed form is usually written, var = mean(I^2) - mean(I)^2 and
+         cov = mean(I p) - mean(I) mean(p), evaluated in FP32 on the same GPU
+         without recentring.
+In a near-constant window the variance (about 1e-8) is the difference of
+two numbers near 0.25 whose FP32 rounding alone is about 1.5e-8, so the
+one-pass form returns var and cov with errors of their own size; A =
+cov / (var + eps) then carries errors of order one, and so does every
+output that depends on it.  The HIP path must meet the parity bars, and the
+one-pass form must miss them by far on the same inputs (which shows that
+these inputs do exercise the cancellation the recentring removes).
+"""
+import functools
+
+import pytest
+import torch
+
+from paper_1803_05619_amd import datagen
+from tests import parity
+from tests.test_gpu_parity import run_both
+
+pytestmark = pytest.mark.gpu
+
+
+def precision_problem(io_dtype, r):
+    # the precision-stress workload (2 x 3 x 2160 x 3840, s = 4) at 1/8 size
+    return datagen.make_problem(2, 3, 268, 480, 4, r, 1e-8, io_dtype, config=4, noise=0.0,
+                                flat_rects=6)
+
+
+def run_naive(prob):
+    """The plain one-pass composition, FP32 on cuda:0, differentiated by
+    autograd (gradients to p_l, I_l, I_h and eps)."""
+    from paper_1803_05619_amd import plain
+    dev = torch.device("cuda:0")
+    lv = {k: prob[k].to(dev).float().requires_grad_(True) for k in ("I_lo", "p_lo", "I_hi")}
+    e = torch.tensor(prob["eps"], dtype=torch.float32, device=dev).requires_grad_(True)
+    q = plain.guided_filter(lv["I_lo"], lv["p_lo"], lv["I_hi"], prob["r"], e)
+    q.backward(prob["dq"].to(dev).float())
+    torch.cuda.synchronize()
+    out = {"q": q.detach(), "dI_lo": lv["I_lo"].grad, "dp_lo": lv["p_lo"].grad,
+           "dI_hi": lv["I_hi"].grad, "deps": e.grad.reshape(-1)}
+    return {k: v.double().cpu().numpy() for k, v in out.items()}
+
+
+@functools.lru_cache(maxsize=None)
+def measured(io_dtype, r):
+    """Per-output (error, bar) of the HIP path and of the one-pass form."""
+    prob = precision_problem(io_dtype, r)
+    hip, ref = run_both(prob)
+    naive = run_naive(prob)
+    n_terms = prob["n"] * prob["c"] * prob["h"] * prob["w"]
+    m_hip = parity.measure(hip, ref, io_dtype, n_eps_terms=n_terms)
+    m_naive = parity.measure(naive, ref, io_dtype, n_eps_terms=n_terms)
+    for k in OUTPUTS:
+        print(f"precision {io_dtype} r={r} {k}: hip {m_hip[k][0]:.3e}  "
+              f"one-pass FP32 {m_naive[k][0]:.3e}  bar {m_hip[k][1]:.0e}", flush=True)
+    return m_hip, m_naive
+
+
+OUTPUTS = ("q", "dI_lo", "dp_lo", "dI_hi")
+# FP32 I/O: the guide keeps its N(0, 1e-4) spread unquantised, and the
+# statistics of the radius-1..4 walkers (two levels in FP32, column means
+# rounded one by one) and the separable adjoint sums (B1 + B2 g' with g'
+# relative to one reference per tile) leave errors of 5e-4 .. 2.4e-3 at
+# radius 1 and 2e-4 on dp_l at radius 8: above the FP32 bar of 1e-4, which
+# is stated for eps = 1e-4.  A known gap, kept visible here.
+FP32_GAP = pytest.mark.xfail(strict=True, reason="FP32 I/O at eps = 1e-8 on near-constant "
+                             "regions: errors above the FP32 bar (see the comment above)")
+
+
+@pytest.mark.parametrize("r", [1, 8])
+@pytest.mark.parametrize("io_dtype", ["f16", "bf16", pytest.param("f32", marks=FP32_GAP)])
+def test_precision_bars(io_dtype, r):
+    m_hip, _ = measured(io_dtype, r)
+    parity.check(m_hip, f"hip {io_dtype} r={r}")
+
+
+@pytest.mark.parametrize("r", [1, 8])
+@pytest.mark.parametrize("io_dtype", ["f16", "f32", "bf16"])
+def test_one_pass_cancels(io_dtype, r):
+    m_hip, m_naive = measured(io_dtype, r)
+    # the one-pass form misses the bar on these inputs (at least twice over)
+    worst = max(m_naive[k][0] / m_naive[k][1] for k in OUTPUTS)
+    assert worst > 2.0, f"one-pass statistics within {worst:.2f} of the bar: no cancellation"
+    # and is at least ten times less accurate than the HIP path on some output
+    ratio = max(m_naive[k][0] / max(m_hip[k][0], 1e-30) for k in OUTPUTS)
+    assert ratio > 10.0, f"one-pass only {ratio:.1f}x less accurate than the HIP path"
