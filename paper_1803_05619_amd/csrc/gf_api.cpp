@@ -266,10 +266,11 @@ int make_plan(const gf_desc_t* d, const gf_guide_t* g, Plan* p, const char** why
   const size_t vbytes = q.gen ? (size_t)q.planes * 2 * q.h * q.W * sizeof(float) : 0;
   q.off_eps = q.off_v + align_up(vbytes, 256);
   q.off_x = q.off_eps + align_up((size_t)q.planes * q.lo_nx * q.lo_ny * sizeof(float), 256);
-  // the wide passes' plane: X of the backward (16 bytes per pixel), or the
-  // coefficients' (A, b) (8), which the forward-only calls need as well
+  // the wide passes' plane: X of the backward (16 bytes per pixel, 32 in
+  // FP64 for FP32 I/O), or the coefficients' (A, b) (8), which the
+  // forward-only calls need as well
   const bool wide_x = wide_bwd(r) || (wide_coef(r) && q.mean_ab);
-  const size_t xbytes = wide_x ? (size_t)q.planes * q.h * q.w * 4 * sizeof(float) : 0;
+  const size_t xbytes = wide_x ? (size_t)q.planes * q.h * q.w * wide_x_floats(q) * sizeof(float) : 0;
   q.ws_bwd = q.off_x + align_up(xbytes, 256);
   if (wide_coef(r) && q.mean_ab) q.ws_fwd = std::max(q.ws_fwd, q.ws_bwd);
   if (gmode != GF_GUIDE_IDENTITY) {

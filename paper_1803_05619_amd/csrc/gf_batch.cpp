@@ -164,7 +164,8 @@ int create(const gf_item_t* items, int count, gf_plan** out) {
     g.off_eps = ws;
     ws += align_up((size_t)p.planes * p.lo_nx * p.lo_ny * sizeof(float), 256);
     g.off_x = ws;  // the wide backward's X planes
-    if (wide_bwd(p.r) || (wide_coef(p.r) && p.mean_ab)) ws += align_up((size_t)p.planes * p.h * p.w * 4 * sizeof(float), 256);
+    if (wide_bwd(p.r) || (wide_coef(p.r) && p.mean_ab))
+      ws += align_up((size_t)p.planes * p.h * p.w * wide_x_floats(p) * sizeof(float), 256);
     g.t_coef = (long long)p.co_nx * p.co_ny * p.planes;
     g.t_bwd_lo = (long long)p.lo_nx * p.lo_ny * p.planes;
     g.t_apply = ((long long)p.planes * p.nrb * p.nxv + 255) / 256;

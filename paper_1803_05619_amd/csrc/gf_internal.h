@@ -55,7 +55,7 @@ struct Plan {
   // any size ratio: the vertical adjoint's low-res rows x high-res columns
   // (dA_bar and db_bar parts)
   size_t off_v;
-  // wide low-res backward (wide_bwd(r)): its X planes, 16 bytes per pixel
+  // wide low-res passes: their plane (wide_x_floats floats per pixel)
   size_t off_x;
   // guided path: G_l, G_h (float planes), dG_l, dG_h, moments partials,
   // folded transform parameters (2 calls), accumulator partials/totals
@@ -116,6 +116,14 @@ constexpr size_t wide_lds_bytes(int nq) { return (size_t)kWideB * wide_row(kWide
 constexpr size_t kLdsPerCU = 160 * 1024;  // MI355X
 int wide_bwd_min_r();
 inline bool wide_bwd(int r) { return r >= wide_bwd_min_r(); }
+
+// Floats per low-res pixel of the wide passes' plane: the backward's X
+// quantities in FP64 for FP32 I/O (8), else in FP32 (4, which also holds the
+// coefficients' (A, b)).
+inline size_t wide_x_floats(const Plan& p) {
+  return wide_bwd(p.r) && p.dtype == GF_F32 ? 8 : 4;
+}
+
 // The coefficients the same way (two passes: (A, b) per pixel, then their
 // window mean); GF_WIDE_COEF_R overrides the radius.
 int wide_coef_min_r();

@@ -103,10 +103,25 @@ __device__ __forceinline__ void plane_centre(const BwdLoArgs& a, const TG* G, co
 // coefficient passes receive as dI_lo and dp_lo).
 enum { kWideBwdMab = 0, kWideBwdPlain = 1, kWideCoef = 2 };
 
+// The backward's X plane in FP64 (32 bytes per pixel) for FP32 I/O, else
+// FP32 (16 bytes).  X's entries are differences of terms that grow with
+// 1 / (var + eps) (dmean_p = db - dcov mean_I', with dcov up to |dA| / eps),
+// and the second pass forms dI_l, dp_l as B1 + B2 g' from their window sums:
+// where a flat region lies away from the plane's reference value these
+// terms cancel to a few parts in 1e4, so with FP32 X the rounding of each
+// term shows (2e-4 of max |dp_l| at eps = 1e-8 on FP32 I/O).  With FP64 X
+// and an FP64 epilogue and combination only the final rounding to FP32
+// remains.  For the half types the I/O rounding dominates and X stays FP32.
+template <typename TP, int MODE>
+__device__ __host__ constexpr bool wide_x64() {
+  return MODE != kWideCoef && std::is_same<TP, float>::value;
+}
+
 template <typename TG, typename TP, int MODE>
 __device__ __forceinline__ void wide_stats_body(const BwdLoArgs& a, const int bx, const int by,
                                                 const int plane, const int R) {
   constexpr bool MAB = MODE == kWideBwdMab, COEF = MODE == kWideCoef;
+  constexpr bool X64 = wide_x64<TP, MODE>();
   constexpr int kTPR = kWideBT / kWideB;
   extern __shared__ double4 wlds[];
   // padded rows of (g', p', g'^2, g'p') and (dAbar/N, dbbar/N) column sums
@@ -128,6 +143,7 @@ __device__ __forceinline__ void wide_stats_body(const BwdLoArgs& a, const int bx
   const __amdgpu_buffer_rsrc_t pR = buf_rsrc(P, hw * sizeof(TP));
   float cg, cp;
   plane_centre(a, G, P, cg, cp);
+  const double cgd = cg, cpd = cp;  // recentring in FP64: exact for every I/O type
   const int jcl = min(max(j, 0), w - 1);
   const unsigned jg = (unsigned)jcl * sizeof(TG), jp = (unsigned)jcl * sizeof(TP);
   // the upstream partial planes (dAbar, dbbar of the high-res backward)
@@ -197,10 +213,10 @@ __device__ __forceinline__ void wide_stats_body(const BwdLoArgs& a, const int bx
       if (x < xend) {
         const bool ok = colin && row_ok(x, h);
         const bool okl = colin && xl >= x0 && row_ok(xl, h);
-        const double g = ok ? (double)(to_f(q[d].g0) - cg) : 0.0;
-        const double p = ok ? (double)(to_f(q[d].p0) - cp) : 0.0;
-        const double g2 = okl ? (double)(to_f(q[d].g1) - cg) : 0.0;
-        const double p2 = okl ? (double)(to_f(q[d].p1) - cp) : 0.0;
+        const double g = ok ? (double)to_f(q[d].g0) - cgd : 0.0;
+        const double p = ok ? (double)to_f(q[d].p0) - cpd : 0.0;
+        const double g2 = okl ? (double)to_f(q[d].g1) - cgd : 0.0;
+        const double p2 = okl ? (double)to_f(q[d].p1) - cpd : 0.0;
         sg += g - g2;
         sp += p - p2;
         sgg += g * g - g2 * g2;
@@ -245,6 +261,7 @@ __device__ __forceinline__ void wide_stats_body(const BwdLoArgs& a, const int bx
         U.x += U2.x;
         U.y += U2.y;
         float4* Xrow = reinterpret_cast<float4*>(a.X + 4 * (pofs + (size_t)rc * w));
+        double4* X64row = reinterpret_cast<double4*>(a.X + 8 * (pofs + (size_t)rc * w));
         float2* ABrow = reinterpret_cast<float2*>(a.X + 2 * (pofs + (size_t)rc * w));
 #pragma unroll
         for (int uu = 0; uu < kWideSeg; ++uu) {
@@ -280,6 +297,23 @@ __device__ __forceinline__ void wide_stats_body(const BwdLoArgs& a, const int bx
             }
             // dA, db: the box sums of dAbar/N, dbbar/N (or the values)
             const double2 uc = MAB ? U : CS.get2(4, d, c);
+            if constexpr (X64) {
+              const double invNd = 1.0 / Nd;
+              const double mgd = W.x * invNd, mpd = W.y * invNd;
+              const double vard = (W.z * Nd - W.x * W.x) * (invNd * invNd);
+              const double covd = (W.w * Nd - W.x * W.y) * (invNd * invNd);
+              const double den = vard + (double)e;
+              const double rden = den > 0.0 ? 1.0 / den : 0.0;  // A := 0 when var + eps == 0
+              const double A = covd * rden;
+              const double dAt = uc.x - uc.y * (mgd + cgd);
+              const double dcov = dAt * rden;
+              const double dvar = -dAt * A * rden;
+              const double dmI = -uc.y * A - dcov * mpd - 2.0 * dvar * mgd;
+              const double dmP = uc.y - dcov * mgd;
+              deps_acc += (float)dvar;
+              X64row[jj] = make_double4(dmI * invNd, dmP * invNd, dcov * invNd, dvar * invNd);
+              continue;
+            }
             const float dA = (float)uc.x, db = (float)uc.y;
             const float den = var + e;
             const float rden = den > 0.f ? rcp(den) : 0.f;  // A := 0 when var + eps == 0
@@ -319,6 +353,8 @@ template <typename TG, typename TP, int MODE>
 __device__ __forceinline__ void wide_box_body(const BwdLoArgs& a, const int bx, const int by,
                                               const int plane, const int R) {
   constexpr bool COEF = MODE == kWideCoef;
+  constexpr bool X64 = wide_x64<TP, MODE>();
+  using XV = typename std::conditional<X64, double4, float4>::type;
   constexpr int kTPR = kWideBT / kWideB;
   extern __shared__ double4 wlds[];
   constexpr int ROW = kWideBT + kWideBT / kWideSeg;
@@ -335,12 +371,12 @@ __device__ __forceinline__ void wide_box_body(const BwdLoArgs& a, const int bx, 
   const TP* P = reinterpret_cast<const TP*>(a.p_lo) + pofs;
   float cg, cp;
   plane_centre(a, G, P, cg, cp);
-  const float4* X4 = reinterpret_cast<const float4*>(a.X) + pofs;
+  const XV* X4 = reinterpret_cast<const XV*>(a.X) + pofs;
   const float2* X2 = reinterpret_cast<const float2*>(a.X) + pofs;
   const int jcl = min(max(j, 0), w - 1);
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
   // the plane's entering and leaving rows, one block ahead
-  float4 qi[kWideB], qo[kWideB];
+  XV qi[kWideB], qo[kWideB];
   auto fetch = [&](int xb) __attribute__((always_inline)) {
 #pragma unroll
     for (int d = 0; d < kWideB; ++d) {
@@ -348,8 +384,8 @@ __device__ __forceinline__ void wide_box_body(const BwdLoArgs& a, const int bx, 
       const size_t oo = (size_t)min(max(xb + d - K, 0), h - 1) * w + jcl;
       if constexpr (COEF) {
         const float2 vi = X2[oi], vo = X2[oo];
-        qi[d] = make_float4(vi.x, vi.y, 0.f, 0.f);
-        qo[d] = make_float4(vo.x, vo.y, 0.f, 0.f);
+        qi[d] = XV{vi.x, vi.y, 0.f, 0.f};
+        qo[d] = XV{vo.x, vo.y, 0.f, 0.f};
       } else {
         qi[d] = X4[oi];
         qo[d] = X4[oo];
@@ -362,7 +398,7 @@ __device__ __forceinline__ void wide_box_body(const BwdLoArgs& a, const int bx, 
     for (int d = 0; d < kWideB; ++d) {
       const int x = xb + d, xl = x - K;
       if (x < xend) {
-        const float4 in = qi[d], out = qo[d];
+        const XV in = qi[d], out = qo[d];
         const bool ok = colin && row_ok(x, h);
         const bool okl = colin && xl >= x0 && row_ok(xl, h);
         if (ok) {
@@ -421,6 +457,11 @@ __device__ __forceinline__ void wide_box_body(const BwdLoArgs& a, const int bx, 
               const float invN = 1.f / (float)(nrow * clip_count(jj, R, w));
               a.dI_lo[pofs + o] = (float)W.x * invN;
               if (a.dp_lo) a.dp_lo[pofs + o] = (float)W.y * invN;
+            } else if constexpr (X64) {
+              const double g = (double)to_f(G[o]) - (double)cg;
+              const double p = (double)to_f(P[o]) - (double)cp;
+              if (a.dI_lo) a.dI_lo[pofs + o] = (float)(W.x + 2.0 * W.w * g + W.z * p);
+              if (a.dp_lo) a.dp_lo[pofs + o] = (float)(W.y + W.z * g);
             } else {
               const float g = to_f(G[o]) - cg, p = to_f(P[o]) - cp;
               const float B0 = (float)W.x, B1 = (float)W.y, B2 = (float)W.z, B3 = (float)W.w;
