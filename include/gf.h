@@ -86,6 +86,13 @@ typedef struct {
   int32_t io_dtype; /* gf_dtype_t of I_lo, p_lo, I_hi, q_hi, dq_hi, dI_hi */
   int32_t align_corners; /* 0: half-pixel centres (default); 1: corner   */
                          /* alignment, source y (h_lo-1)/(h_hi-1)        */
+  int32_t precise;  /* 0: window statistics of radii 0..4 in two levels in
+                       FP32 (faster); 1: FP64 running window sums at every
+                       radius, and for FP32 I/O the backward's adjoint
+                       quantities in FP64 too: FP32-level accuracy also at
+                       tiny eps on nearly flat guides (about 1.7x the time
+                       of the low-res passes' share at radius 1).  Radii
+                       >= 5 take the FP64 walkers either way.            */
 } gf_desc_t;
 
 /* Guidance map G = F(I) (Sec. III-D).  Pass NULL for the identity.

@@ -76,6 +76,7 @@ int make_plan(const gf_desc_t* d, const gf_guide_t* g, Plan* p, const char** why
   if (d->mean_ab != 0 && d->mean_ab != 1) return bad(GF_ERR_INVALID_ARG, "mean_ab must be 0 or 1");
   if (d->align_corners != 0 && d->align_corners != 1)
     return bad(GF_ERR_INVALID_ARG, "align_corners must be 0 or 1");
+  if (d->precise != 0 && d->precise != 1) return bad(GF_ERR_INVALID_ARG, "precise must be 0 or 1");
   if (dtype_size(d->io_dtype) == 0) return bad(GF_ERR_INVALID_ARG, "unknown io_dtype");
   // one integer factor in {1, 2, 4, 8} for both axes takes the kernels with
   // compile-time tap weights; any other ratio (per axis) the general ones
@@ -122,6 +123,8 @@ int make_plan(const gf_desc_t* d, const gf_guide_t* g, Plan* p, const char** why
   q.r = d->r;
   q.mean_ab = d->mean_ab;
   q.ac = d->align_corners;
+  q.wide_co = wide_coef(d->r) || d->precise;
+  q.wide_lo = wide_bwd(d->r) || d->precise;
   q.dtype = d->io_dtype;
   q.S = S;
   q.gen = S == 0;
@@ -197,8 +200,8 @@ int make_plan(const gf_desc_t* d, const gf_guide_t* g, Plan* p, const char** why
   };
   if (!tuned_hit) {
     const int nxw = (d->w_lo + (kWideBThreads - 2 * r) - 1) / (kWideBThreads - 2 * r);
-    if (wide_coef(r)) tv.coTR = one_round((int)(kLdsPerCU / wide_lds_bytes(4)), nxw);
-    if (wide_bwd(r)) tv.loTR = one_round((int)(kLdsPerCU / wide_lds_bytes(6)), nxw);
+    if (q.wide_co) tv.coTR = one_round((int)(kLdsPerCU / wide_lds_bytes(4)), nxw);
+    if (q.wide_lo) tv.loTR = one_round((int)(kLdsPerCU / wide_lds_bytes(6)), nxw);
   }
   if (env_int("GF_LO_ROWS", 0) > 0) tv.coTR = tv.loTR = env_int("GF_LO_ROWS", 0);
   if (env_int("GF_BWD_LO_ROWS", 0) > 0) tv.loTR = env_int("GF_BWD_LO_ROWS", 0);
@@ -207,7 +210,7 @@ int make_plan(const gf_desc_t* d, const gf_guide_t* g, Plan* p, const char** why
   if (tv.coTR < 1 || tv.loTR < 1 || tv.RB < 1 || tv.bh < 2)
     return bad(GF_ERR_INVALID_ARG, "invalid launch shape");
   q.coTR = tv.coTR;
-  if (wide_coef(r)) {  // wide coefficient passes: strips of 256 input columns, halo r
+  if (q.wide_co) {  // wide coefficient passes: strips of 256 input columns, halo r
     q.co_nx = (q.w + (kWideBThreads - 2 * r) - 1) / (kWideBThreads - 2 * r);
     q.coLDS = bwd_wide_lds_bytes();
   } else {
@@ -216,7 +219,7 @@ int make_plan(const gf_desc_t* d, const gf_guide_t* g, Plan* p, const char** why
   }
   q.co_ny = (q.h + q.coTR - 1) / q.coTR;
   q.loTR = tv.loTR;
-  if (wide_bwd(r)) {  // wide backward: strips of 256 input columns, halo r
+  if (q.wide_lo) {  // wide backward: strips of 256 input columns, halo r
     q.lo_nx = (q.w + (kWideBThreads - 2 * r) - 1) / (kWideBThreads - 2 * r);
     q.loLDS = bwd_wide_lds_bytes();
   } else {
@@ -269,10 +272,10 @@ int make_plan(const gf_desc_t* d, const gf_guide_t* g, Plan* p, const char** why
   // the wide passes' plane: X of the backward (16 bytes per pixel, 32 in
   // FP64 for FP32 I/O), or the coefficients' (A, b) (8), which the
   // forward-only calls need as well
-  const bool wide_x = wide_bwd(r) || (wide_coef(r) && q.mean_ab);
+  const bool wide_x = q.wide_lo || (q.wide_co && q.mean_ab);
   const size_t xbytes = wide_x ? (size_t)q.planes * q.h * q.w * wide_x_floats(q) * sizeof(float) : 0;
   q.ws_bwd = q.off_x + align_up(xbytes, 256);
-  if (wide_coef(r) && q.mean_ab) q.ws_fwd = std::max(q.ws_fwd, q.ws_bwd);
+  if (q.wide_co && q.mean_ab) q.ws_fwd = std::max(q.ws_fwd, q.ws_bwd);
   if (gmode != GF_GUIDE_IDENTITY) {
     // guided path: the guide planes and the transform's reductions follow the
     // identity layout (a superset is allocated for both directions)

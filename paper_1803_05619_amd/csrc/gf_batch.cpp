@@ -99,7 +99,8 @@ void build_classes(const ClassMap& cm, int kind, std::vector<char>& host, size_t
     c.kind = kind;
     if (kind == kClassCoef || kind == kClassBwdLo) {
       c.R = kv.first.first;
-      c.MAB = kv.first.second;
+      c.MAB = kv.first.second % 2;
+      c.wide = kv.first.second / 2;
     } else {  // high-res key: (S, 2 VEC + corner alignment)
       c.S = kv.first.first;
       c.VEC = kv.first.second / 2;
@@ -164,7 +165,7 @@ int create(const gf_item_t* items, int count, gf_plan** out) {
     g.off_eps = ws;
     ws += align_up((size_t)p.planes * p.lo_nx * p.lo_ny * sizeof(float), 256);
     g.off_x = ws;  // the wide backward's X planes
-    if (wide_bwd(p.r) || (wide_coef(p.r) && p.mean_ab))
+    if (p.wide_lo || (p.wide_co && p.mean_ab))
       ws += align_up((size_t)p.planes * p.h * p.w * wide_x_floats(p) * sizeof(float), 256);
     g.t_coef = (long long)p.co_nx * p.co_ny * p.planes;
     g.t_bwd_lo = (long long)p.lo_nx * p.lo_ny * p.planes;
@@ -175,8 +176,9 @@ int create(const gf_item_t* items, int count, gf_plan** out) {
   int n_eps = 0;
   for (int k = 0; k < count; ++k) {
     const Plan& p = geo[k].p;
-    cm_coef[{p.r, p.mean_ab}].push_back({k, geo[k].t_coef});
-    cm_lo[{p.r, p.mean_ab}].push_back({k, geo[k].t_bwd_lo});
+    // low-res classes: (radius, mean_ab + 2 x walker kind)
+    cm_coef[{p.r, p.mean_ab + 2 * p.wide_co}].push_back({k, geo[k].t_coef});
+    cm_lo[{p.r, p.mean_ab + 2 * p.wide_lo}].push_back({k, geo[k].t_bwd_lo});
     cm_hi[{p.S, 2 * p.VEC + p.ac}].push_back({k, geo[k].t_bwd_hi});
     if (items[k].deps) ++n_eps;
   }
@@ -216,7 +218,7 @@ int create(const gf_item_t* items, int count, gf_plan** out) {
         const Plan& p = geo[k].p;
         return CoefArgs{items[k].I_lo, items[k].p_lo, eps_dev + k, 1, p.c, p.h, p.w, p.coTR,
                         ws_rel<float>(geo[k].off_abar), ws_rel<float>(geo[k].off_bbar), 0,
-                        wide_coef(p.r) && p.mean_ab ? ws_rel<float>(geo[k].off_x) : nullptr};
+                        p.wide_co && p.mean_ab ? ws_rel<float>(geo[k].off_x) : nullptr};
       },
       [](const Geo& g, int& nx, int& ny) {
         nx = g.p.co_nx;
@@ -257,7 +259,7 @@ int create(const gf_item_t* items, int count, gf_plan** out) {
         return BwdLoArgs{items[k].I_lo, items[k].p_lo, eps_dev + k, 1, p.c,
                          ws_rel<float>(geo[k].off_u), p.ubh, p.tw, p.nby, p.nbx, p.h, p.w, p.loTR,
                          items[k].dI_lo, items[k].dp_lo, ws_rel<float>(geo[k].off_eps), p.lo_nx,
-                         p.lo_ny, wide_bwd(p.r) ? ws_rel<float>(geo[k].off_x) : nullptr};
+                         p.lo_ny, p.wide_lo ? ws_rel<float>(geo[k].off_x) : nullptr};
       },
       [](const Geo& g, int& nx, int& ny) {
         nx = g.p.lo_nx;

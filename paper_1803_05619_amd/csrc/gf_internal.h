@@ -23,6 +23,7 @@ struct Plan {
   int gen;      // 1: any size ratio (the general high-res kernels), S = 0
   int xcd;      // XCD-aware workgroup order for the high-res kernels (0: off; see xcd_order)
   int lo_xcd;   // the same for the single-problem low-res walkers
+  int wide_co, wide_lo;  // coefficients / low-res backward through the wide (FP64) walkers
   int VEC;      // high-res elements per thread-load (16 bytes, or 1)
   int planes;   // n * c
   // low-res coefficient kernel: one wave per strip of 64 lanes (columns)
@@ -104,8 +105,9 @@ constexpr int kCoefRingPow2Max = 32;  // coef: 64 * (16 KR + 24 * 4) bytes
 // 256 + 256 / 4 padded columns holding the block's FP64 column sums (6
 // quantities in the first pass, 48 bytes per padded column and row; 4 in the
 // second).  The environment variable GF_WIDE_BWD_R overrides the default
-// radius (at least kWideMinR), for measurements.
-constexpr int kWideMinR = 3, kWideBwdR = 5, kWideCoefR = 5;
+// radius (at least kWideMinR), for measurements; a precise descriptor takes
+// them at every radius.
+constexpr int kWideMinR = 1, kWideBwdR = 5, kWideCoefR = 5;
 constexpr int kWideB = 4;
 constexpr int kWideBThreads = 256;
 constexpr size_t wide_row(int nt) { return (size_t)nt + nt / 4; }
@@ -121,7 +123,7 @@ inline bool wide_bwd(int r) { return r >= wide_bwd_min_r(); }
 // quantities in FP64 for FP32 I/O (8), else in FP32 (4, which also holds the
 // coefficients' (A, b)).
 inline size_t wide_x_floats(const Plan& p) {
-  return wide_bwd(p.r) && p.dtype == GF_F32 ? 8 : 4;
+  return p.wide_lo && p.dtype == GF_F32 ? 8 : 4;
 }
 
 // The coefficients the same way (two passes: (A, b) per pixel, then their
@@ -351,6 +353,7 @@ struct BatchClass {
   int kind;
   int S, VEC, AC; // high-res classes (AC: corner alignment)
   int R, MAB;     // low-res classes
+  int wide;       // low-res classes: the wide (FP64) walkers
   size_t lds;     // dynamic LDS bytes
   int hw;         // high-res backward: waves per workgroup
   MultiLaunch m;

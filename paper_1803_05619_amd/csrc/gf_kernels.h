@@ -1367,8 +1367,11 @@ __device__ __forceinline__ void bwd_lo_body(const BwdLoArgs& a, const int bx, co
     const float A = st.cov * rden;
     // b = mean_p - A mean_I (actual means), A = cov / (var + eps)
     const float dAt = dA - db * (st.mI + cg);
-    const float dcov = dAt * rden;
-    const float dvar = -dAt * A * rden;
+    // one-pixel windows (R = 0): var and cov do not depend on the pixel, and
+    // their terms would only cancel up to rounding against terms of size
+    // dA / eps
+    const float dcov = R == 0 ? 0.f : dAt * rden;
+    const float dvar = R == 0 ? 0.f : -dAt * A * rden;
     // var = E[g'^2] - mI'^2, cov = E[g'p'] - mI' mP' (recentred g', p')
     const float dmI = -db * A - dcov * st.mP - 2.f * dvar * st.mI;
     const float dmP = db - dcov * st.mI;
@@ -2015,7 +2018,7 @@ hipError_t launch_coef(const Plan& p, const void* I_lo, const void* p_lo, const 
   CoefArgs a{I_lo, p_lo, eps, eps_count, p.c, p.h, p.w, p.coTR, abar, bbar, p.lo_xcd,
              p.mean_ab ? X : nullptr};
   const dim3 grid(p.co_nx, p.co_ny, p.planes);
-  if (wide_coef(p.r)) {
+  if (p.wide_co) {
     const BwdLoArgs wa = wide_coef_args(a);
     prof_begin("gf_coef", s);
     hipLaunchKernelGGL((wide_stats_kernel<TG, TP, kWideCoef>), grid, dim3(kWideBT),
@@ -2200,7 +2203,7 @@ hipError_t launch_bwd_lo(const Plan& p, const void* G_lo, const void* p_lo, cons
   BwdLoArgs a{G_lo, p_lo, eps, eps_count, p.c, U, p.ubh, p.tw, p.nby, p.nbx,
               p.h, p.w, p.loTR, dG_lo, dp_lo, part, p.lo_nx, p.lo_ny, X, p.lo_xcd};
   const dim3 grid(p.lo_nx, p.lo_ny, p.planes);
-  if (wide_bwd(p.r)) {
+  if (p.wide_lo) {
     prof_begin("gf_bwd_lo", s);
     if (p.mean_ab)
       hipLaunchKernelGGL((wide_stats_kernel<TG, TP, kWideBwdMab>), grid, dim3(kWideBT), p.loLDS, s,
@@ -2298,7 +2301,7 @@ hipError_t launch_coef_multi(const BatchClass& c, char* ws, hipStream_t s) {
   MultiLaunch m = c.m;
   m.ws = ws;
   prof_begin(class_name_r(kClassCoef, c.R), s);
-  if (wide_coef(c.R)) {
+  if (c.wide) {
     const dim3 g(m.grid);
     hipLaunchKernelGGL((wide_stats_multi_kernel<TG, TP, kWideCoef>), g, dim3(kWideBT),
                        wide_lds_bytes(4), s, m, c.R);
@@ -2329,7 +2332,7 @@ hipError_t launch_bwd_lo_multi(const BatchClass& c, char* ws, hipStream_t s) {
   MultiLaunch m = c.m;
   m.ws = ws;
   prof_begin(class_name_r(kClassBwdLo, c.R), s);
-  if (wide_bwd(c.R)) {
+  if (c.wide) {
     const dim3 g(m.grid);
     if (c.MAB)
       hipLaunchKernelGGL((wide_stats_multi_kernel<TG, TP, kWideBwdMab>), g, dim3(kWideBT), c.lds, s,

@@ -280,8 +280,11 @@ __device__ __forceinline__ void wide_stats_body(const BwdLoArgs& a, const int bx
             const int N = nrow * clip_count(jj, R, w);
             const double Nd = (double)N;
             const float invN = 1.f / (float)N;
-            const float var = (float)(W.z * Nd - W.x * W.x) * (invN * invN);
-            const float cov = (float)(W.w * Nd - W.x * W.y) * (invN * invN);
+            // a one-pixel window (radius 0) has var = cov = 0 exactly, which
+            // the running sums only approach (their rounding along the walk)
+            const bool pix = R == 0;
+            const float var = pix ? 0.f : (float)(W.z * Nd - W.x * W.x) * (invN * invN);
+            const float cov = pix ? 0.f : (float)(W.w * Nd - W.x * W.y) * (invN * invN);
             const float mg = (float)W.x * invN, mp = (float)W.y * invN;
             if constexpr (COEF) {
               const float den = var + e;
@@ -300,14 +303,15 @@ __device__ __forceinline__ void wide_stats_body(const BwdLoArgs& a, const int bx
             if constexpr (X64) {
               const double invNd = 1.0 / Nd;
               const double mgd = W.x * invNd, mpd = W.y * invNd;
-              const double vard = (W.z * Nd - W.x * W.x) * (invNd * invNd);
-              const double covd = (W.w * Nd - W.x * W.y) * (invNd * invNd);
+              const double vard = pix ? 0.0 : (W.z * Nd - W.x * W.x) * (invNd * invNd);
+              const double covd = pix ? 0.0 : (W.w * Nd - W.x * W.y) * (invNd * invNd);
               const double den = vard + (double)e;
               const double rden = den > 0.0 ? 1.0 / den : 0.0;  // A := 0 when var + eps == 0
               const double A = covd * rden;
               const double dAt = uc.x - uc.y * (mgd + cgd);
-              const double dcov = dAt * rden;
-              const double dvar = -dAt * A * rden;
+              // one-pixel windows: var and cov do not depend on the pixel
+              const double dcov = pix ? 0.0 : dAt * rden;
+              const double dvar = pix ? 0.0 : -dAt * A * rden;
               const double dmI = -uc.y * A - dcov * mpd - 2.0 * dvar * mgd;
               const double dmP = uc.y - dcov * mgd;
               deps_acc += (float)dvar;
@@ -319,8 +323,9 @@ __device__ __forceinline__ void wide_stats_body(const BwdLoArgs& a, const int bx
             const float rden = den > 0.f ? rcp(den) : 0.f;  // A := 0 when var + eps == 0
             const float A = cov * rden;
             const float dAt = dA - db * (mg + cg);
-            const float dcov = dAt * rden;
-            const float dvar = -dAt * A * rden;
+            // one-pixel windows: var and cov do not depend on the pixel
+            const float dcov = pix ? 0.f : dAt * rden;
+            const float dvar = pix ? 0.f : -dAt * A * rden;
             const float dmI = -db * A - dcov * mp - 2.f * dvar * mg;
             const float dmP = db - dcov * mg;
             deps_acc += dvar;

@@ -31,7 +31,7 @@ DTYPE_CODES = {torch.float32: GF_F32, torch.float16: GF_F16, torch.bfloat16: GF_
 class gf_desc_t(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int32) for name in
                 ("n", "c", "h_lo", "w_lo", "h_hi", "w_hi", "r", "mean_ab", "io_dtype",
-                 "align_corners")]
+                 "align_corners", "precise")]
 
 
 GF_GUIDE_IDENTITY, GF_GUIDE_GREY, GF_GUIDE_TRANSFORM = 0, 1, 2
@@ -271,13 +271,14 @@ def _ptr(t):
 
 
 def make_desc(I_lo: torch.Tensor, I_hi: torch.Tensor, r: int, mean_ab: bool = True,
-              c: int = None, align_corners: bool = False) -> gf_desc_t:
+              c: int = None, align_corners: bool = False, precise: bool = False) -> gf_desc_t:
     """Problem description; `c` (output channels) defaults to I_lo's channels
-    (a guide may map c_in input channels to c)."""
+    (a guide may map c_in input channels to c).  `precise`: FP64 window sums
+    at every radius (see gf_desc_t.precise)."""
     n, c_in, h, w = I_lo.shape
     H, W = I_hi.shape[-2:]
     return gf_desc_t(n, c_in if c is None else int(c), h, w, H, W, int(r), int(bool(mean_ab)),
-                     DTYPE_CODES[I_lo.dtype], int(bool(align_corners)))
+                     DTYPE_CODES[I_lo.dtype], int(bool(align_corners)), int(bool(precise)))
 
 
 class Guide:
@@ -364,12 +365,13 @@ def _out_channels(I_lo, guide, c):
 
 
 def forward(I_lo, p_lo, I_hi, eps, r=1, mean_ab=True, out=None, ws=None, guide=None,
-            align_corners=False):
+            align_corners=False, precise=False):
     """q = GF(I_lo, p_lo, I_hi): one gf_forward call on the current stream.
     With a Guide, I_lo and I_hi have guide.c_in channels and q has p_lo's."""
     dev = I_hi.device
     _check(dict(I_lo=I_lo, p_lo=p_lo, I_hi=I_hi, out=out), I_hi.dtype, dev)
-    desc = make_desc(I_lo, I_hi, r, mean_ab, c=p_lo.shape[1], align_corners=align_corners)
+    desc = make_desc(I_lo, I_hi, r, mean_ab, c=p_lo.shape[1], align_corners=align_corners,
+                     precise=precise)
     g = None if guide is None else guide.struct()
     e = _eps_tensor(eps, desc.n, dev)
     q = out if out is not None else torch.empty(
@@ -388,13 +390,14 @@ def forward(I_lo, p_lo, I_hi, eps, r=1, mean_ab=True, out=None, ws=None, guide=N
 
 def backward(I_lo, p_lo, I_hi, eps, dq, r=1, mean_ab=True, need_dI_lo=True, need_dp_lo=True,
              need_dI_hi=True, need_deps=True, ws=None, outs=None, guide=None,
-             need_dparams=None, align_corners=False):
+             need_dparams=None, align_corners=False, precise=False):
     """Gradients (dI_lo, dp_lo, dI_hi, deps, dparams) of sum(q * dq); None
     where not requested.  dparams only with a transform Guide (requested by
     default there)."""
     dev = I_hi.device
     _check(dict(I_lo=I_lo, p_lo=p_lo, I_hi=I_hi, dq=dq), I_hi.dtype, dev)
-    desc = make_desc(I_lo, I_hi, r, mean_ab, c=p_lo.shape[1], align_corners=align_corners)
+    desc = make_desc(I_lo, I_hi, r, mean_ab, c=p_lo.shape[1], align_corners=align_corners,
+                     precise=precise)
     g = None if guide is None else guide.struct()
     transform = guide is not None and guide.mode == GF_GUIDE_TRANSFORM
     if need_dparams is None:
@@ -426,12 +429,13 @@ def backward(I_lo, p_lo, I_hi, eps, dq, r=1, mean_ab=True, need_dI_lo=True, need
 
 def forward_backward(I_lo, p_lo, I_hi, eps, dq, r=1, mean_ab=True, ws=None, outs=None,
                      guide=None, need_dI_lo=True, need_dp_lo=True, need_dI_hi=True,
-                     need_deps=True, need_dparams=None, align_corners=False):
+                     need_deps=True, need_dparams=None, align_corners=False, precise=False):
     """q and the gradients (dI_lo, dp_lo, dI_hi, deps, dparams) in one call
     (gf_forward_backward: coefficients and guide maps computed once)."""
     dev = I_hi.device
     _check(dict(I_lo=I_lo, p_lo=p_lo, I_hi=I_hi, dq=dq), I_hi.dtype, dev)
-    desc = make_desc(I_lo, I_hi, r, mean_ab, c=p_lo.shape[1], align_corners=align_corners)
+    desc = make_desc(I_lo, I_hi, r, mean_ab, c=p_lo.shape[1], align_corners=align_corners,
+                     precise=precise)
     g = None if guide is None else guide.struct()
     transform = guide is not None and guide.mode == GF_GUIDE_TRANSFORM
     if need_dparams is None:
@@ -570,9 +574,9 @@ class GuidedFilterFn(torch.autograd.Function):
     from the transform guide's 24 batch statistics)."""
 
     @staticmethod
-    def forward(ctx, I_lo, p_lo, I_hi, eps, r, mean_ab, guide, params, align_corners):
+    def forward(ctx, I_lo, p_lo, I_hi, eps, r, mean_ab, guide, params, align_corners, precise):
         e = _eps_tensor(eps, I_lo.shape[0], I_hi.device)
-        ctx.r, ctx.mean_ab, ctx.ac = r, mean_ab, align_corners
+        ctx.r, ctx.mean_ab, ctx.ac, ctx.precise = r, mean_ab, align_corners, precise
         ctx.eps_is_tensor = isinstance(eps, torch.Tensor)
         ctx.guide = guide
         stats = None
@@ -582,7 +586,8 @@ class GuidedFilterFn(torch.autograd.Function):
             guide = Guide(guide.mode, guide.c_in, guide.hidden, params, guide.bn_eps,
                           guide.slope, stats, False)
         ctx.save_for_backward(I_lo, p_lo, I_hi, e, params, stats)
-        return forward(I_lo, p_lo, I_hi, e, r, mean_ab, guide=guide, align_corners=align_corners)
+        return forward(I_lo, p_lo, I_hi, e, r, mean_ab, guide=guide, align_corners=align_corners,
+                       precise=precise)
 
     @staticmethod
     def backward(ctx, dq):
@@ -596,20 +601,22 @@ class GuidedFilterFn(torch.autograd.Function):
             I_lo, p_lo, I_hi, e, dq.contiguous(), ctx.r, ctx.mean_ab,
             need_dI_lo=need[0], need_dp_lo=need[1], need_dI_hi=need[2],
             need_deps=need[3] and ctx.eps_is_tensor, guide=guide,
-            need_dparams=len(need) > 7 and need[7], align_corners=ctx.ac)
+            need_dparams=len(need) > 7 and need[7], align_corners=ctx.ac, precise=ctx.precise)
         cast = lambda g, ref: None if g is None else g.to(ref.dtype)
         return (cast(dI_lo, I_lo), cast(dp_lo, p_lo), dI_hi, deps, None, None, None, dparams,
-                None)
+                None, None)
 
 
 def guided_filter(I_lo, p_lo, I_hi, r=1, eps=1e-8, mean_ab=True, guide=None,
-                  align_corners=False):
+                  align_corners=False, precise=False):
     """Autograd entry point: q = GF(I_lo, p_lo, I_hi) with radius r and eps
     (a float, or a float32 tensor of 1 or n entries to get its gradient).
     `guide` is None (identity) or a Guide; a transform Guide's `params`
-    tensor receives its gradient."""
+    tensor receives its gradient.  `precise`: FP64 window sums at every
+    radius (FP32-level accuracy at tiny eps on nearly flat guides)."""
     params = guide.params if guide is not None else None
-    return GuidedFilterFn.apply(I_lo, p_lo, I_hi, eps, r, mean_ab, guide, params, align_corners)
+    return GuidedFilterFn.apply(I_lo, p_lo, I_hi, eps, r, mean_ab, guide, params, align_corners,
+                                precise)
 
 
 # ------------------------------------------------------------------ batched
@@ -619,7 +626,7 @@ class BatchPlan:
     per phase and launch class (gf_plan_create / gf_batched).
 
     items: list of dicts with I_lo, p_lo, I_hi (device tensors), r, eps and
-    optionally mean_ab (default True) and the outputs q, dq, dI_lo, dp_lo,
+    optionally mean_ab (default True), precise (default False) and the outputs q, dq, dI_lo, dp_lo,
     dI_hi, deps (device tensors; deps one float32).  The plan keeps the
     tensors alive and every run reads and writes them in place."""
 
@@ -634,7 +641,8 @@ class BatchPlan:
             _check({f"item {k} " + n: it.get(n) for n in ("dI_lo", "dp_lo", "deps")},
                    torch.float32, dev)
             arr[k].d = make_desc(I_lo, I_hi, it["r"], it.get("mean_ab", True), c=p_lo.shape[1],
-                                 align_corners=it.get("align_corners", False))
+                                 align_corners=it.get("align_corners", False),
+                                 precise=it.get("precise", False))
             arr[k].eps = float(it["eps"])
             for field, key in (("I_lo", "I_lo"), ("p_lo", "p_lo"), ("I_hi", "I_hi"),
                                ("q_hi", "q"), ("dq_hi", "dq"), ("dI_lo", "dI_lo"),
@@ -668,11 +676,12 @@ class BatchPlan:
 
 
 def autotune(I_lo, p_lo, I_hi, eps, dq, r=1, mean_ab=True, iters=5, guide=None,
-             align_corners=False):
+             align_corners=False, precise=False):
     """Times the candidate launch shapes on these buffers and stores the
     fastest per kernel for this (dtype, factor, radius, guide, mean_ab)."""
     dev = I_hi.device
-    desc = make_desc(I_lo, I_hi, r, mean_ab, c=p_lo.shape[1], align_corners=align_corners)
+    desc = make_desc(I_lo, I_hi, r, mean_ab, c=p_lo.shape[1], align_corners=align_corners,
+                     precise=precise)
     g = None if guide is None else guide.struct()
     e = _eps_tensor(eps, desc.n, dev)
     f32 = dict(dtype=torch.float32, device=dev)

@@ -10,7 +10,7 @@ gf = pytest.importorskip("paper_1803_05619_amd.gf")
 
 def desc(**kw):
     d = dict(n=2, c=3, h_lo=64, w_lo=96, h_hi=256, w_hi=384, r=1, mean_ab=1, io_dtype=0,
-             align_corners=0)
+             align_corners=0, precise=0)
     d.update(kw)
     return gf.gf_desc_t(*[d[k] for k, _ in gf.gf_desc_t._fields_])
 
@@ -39,6 +39,12 @@ def test_workspace_sizes():
     assert gf.gf_workspace_size(desc(r=-1), None, 0) == 0
     for dt in (0, 1, 2):
         assert gf.gf_workspace_size(desc(io_dtype=dt), None, 1) > 0
+    # the precise walkers' plane: the backward's X quantities, FP64 for FP32
+    # I/O (32 bytes per low-res pixel), FP32 for the half types (16)
+    for dt, xb in ((0, 32), (1, 16)):
+        plain, precise = (gf.gf_workspace_size(desc(io_dtype=dt, precise=p), None, 1)
+                          for p in (0, 1))
+        assert precise >= plain + xb * lo // 4 - 256 * 4
 
 
 FAKE = 0x10000  # aligned, never dereferenced: every case below fails validation
@@ -53,6 +59,7 @@ FAKE = 0x10000  # aligned, never dereferenced: every case below fails validation
     (dict(mean_ab=2), gf.GF_ERR_INVALID_ARG),
     (dict(io_dtype=7), gf.GF_ERR_INVALID_ARG),
     (dict(align_corners=2), gf.GF_ERR_INVALID_ARG),
+    (dict(precise=2), gf.GF_ERR_INVALID_ARG),
     (dict(r=40), gf.GF_ERR_UNSUPPORTED),
     # a low-res plane above 2^31 bytes (the walkers' 32-bit buffer offsets)
     (dict(h_lo=24000, w_lo=24000, h_hi=24000, w_hi=24000), gf.GF_ERR_UNSUPPORTED),

@@ -52,7 +52,7 @@ def device_items(probs):
     for p in probs:
         it = {k: p[k].to(DEV) for k in ("I_lo", "p_lo", "I_hi", "dq")}
         it.update(r=p["r"], eps=float(np.atleast_1d(p["eps"])[0]), mean_ab=p["mean_ab"],
-                  align_corners=p.get("align_corners", False))
+                  align_corners=p.get("align_corners", False), precise=p.get("precise", False))
         it["q"] = torch.empty_like(it["I_hi"])
         it["dI_hi"] = torch.empty_like(it["I_hi"])
         it["dI_lo"] = torch.empty(it["I_lo"].shape, dtype=torch.float32, device=DEV)
@@ -63,11 +63,11 @@ def device_items(probs):
 
 
 def singles(gf, it):
-    ac = it.get("align_corners", False)
+    ac, pr = it.get("align_corners", False), it.get("precise", False)
     q = gf.forward(it["I_lo"], it["p_lo"], it["I_hi"], it["eps"], it["r"], it["mean_ab"],
-                   align_corners=ac)
+                   align_corners=ac, precise=pr)
     g = gf.backward(it["I_lo"], it["p_lo"], it["I_hi"], it["eps"], it["dq"], it["r"],
-                    it["mean_ab"], align_corners=ac)
+                    it["mean_ab"], align_corners=ac, precise=pr)
     return {"q": q, "dI_lo": g[0], "dp_lo": g[1], "dI_hi": g[2], "deps": g[3]}
 
 
@@ -87,6 +87,23 @@ def print_case(probs):
 def test_batched_equals_single_calls():
     gf = _gf()
     probs = uneven_items(10, div=6)
+    print_case(probs)
+    items = device_items(probs)
+    plan = gf.BatchPlan(items)
+    plan.run(gf.GF_RUN_FORWARD | gf.GF_RUN_BACKWARD)
+    torch.cuda.synchronize()
+    assert_equal_to_singles(gf, items)
+    plan.close()
+
+
+def test_batched_precise_items():
+    """Precise and default items of the same radius run in separate launch
+    classes (FP64 wide walkers and column walkers); each equals its single
+    calls bit for bit."""
+    gf = _gf()
+    probs = uneven_items(8, div=6, extra=False)
+    for k, p in enumerate(probs):
+        p["precise"] = k % 2 == 0
     print_case(probs)
     items = device_items(probs)
     plan = gf.BatchPlan(items)

@@ -24,20 +24,20 @@ def to_dev(prob):
             for k in ("I_lo", "p_lo", "I_hi", "dq")}
 
 
-def run_both(prob, mean_ab=True, eps=None, backward=True, align_corners=False):
+def run_both(prob, mean_ab=True, eps=None, backward=True, align_corners=False, precise=False):
     gf = _gf()
     d = to_dev(prob)
     eps = prob["eps"] if eps is None else eps
     print(f"case n={prob['n']} c={prob['c']} H={prob['H']} W={prob['W']} s={prob['s']} "
-          f"r={prob['r']} dtype={prob['io_dtype']} mean_ab={mean_ab} ac={align_corners}",
-          flush=True)
+          f"r={prob['r']} dtype={prob['io_dtype']} mean_ab={mean_ab} ac={align_corners} "
+          f"precise={precise}", flush=True)
     q = gf.forward(d["I_lo"], d["p_lo"], d["I_hi"], eps, prob["r"], mean_ab,
-                   align_corners=align_corners)
+                   align_corners=align_corners, precise=precise)
     out = {"q": q}
     if backward:
         dI_lo, dp_lo, dI_hi, deps, _ = gf.backward(d["I_lo"], d["p_lo"], d["I_hi"], eps, d["dq"],
                                                    prob["r"], mean_ab,
-                                                   align_corners=align_corners)
+                                                   align_corners=align_corners, precise=precise)
         out.update(dI_lo=dI_lo, dp_lo=dp_lo, dI_hi=dI_hi, deps=deps)
     torch.cuda.synchronize()
     out = {k: v.double().cpu().numpy() for k, v in out.items()}
@@ -90,6 +90,32 @@ def test_config4_fp16_reduced(r):
 
 
 # ------------------------------------------------------------ shapes and edge cases
+
+@pytest.mark.parametrize("mean_ab", [True, False])
+@pytest.mark.parametrize("io", ["f32", "f16"])
+@pytest.mark.parametrize("r", [0, 1, 2, 4])
+def test_precise_walkers(r, io, mean_ab):
+    """The precise descriptor: FP64 wide walkers at radii 0..4, over several
+    256-column strips with a ragged last one and row tiles with a ragged
+    tail.  With the A/b window mean (the layer's form) the second image has
+    eps = 1e-8 and near-constant patches.  Without it the upstream dA, db of
+    each window are the high-res pass's FP32 partial sums themselves, which
+    dcov = dA_t / (var + eps) amplifies at eps = 1e-8 beyond the bars of
+    either walker (the window mean averages that rounding away), so that
+    form runs at eps = 1e-4 here."""
+    eps = [1e-3, 1e-8] if mean_ab else [1e-3, 1e-4]
+    prob = datagen.make_problem(2, 3, 4 * 37, 4 * 300, 4, r, eps, io, config=91, flat_rects=2)
+    check(prob, mean_ab=mean_ab, precise=True)
+
+
+@pytest.mark.parametrize("io", ["f32", "f16"])
+def test_radius0_tiny_eps(io):
+    """Radius 0 (one-pixel windows: A = 0, dI_l = 0, dp_l = dbbar exactly)
+    at eps = 1e-8 through the default column walkers."""
+    prob = datagen.make_problem(2, 3, 4 * 37, 4 * 300, 4, 0, [1e-3, 1e-8], io, config=92,
+                                flat_rects=2)
+    check(prob)
+
 
 @pytest.mark.parametrize("s", [1, 2, 4, 8])
 @pytest.mark.parametrize("r", [0, 1, 3])
