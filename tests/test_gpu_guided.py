@@ -41,25 +41,26 @@ def make_guide(gf, mode, prob, stats=None, use_stats=False):
                     g["bn_eps"], g["slope"], stats, use_stats)
 
 
-def run_both(prob, mode, mean_ab=True, backward=True, use_stats=False):
+def run_both(prob, mode, mean_ab=True, backward=True, use_stats=False, precise=False):
     gf = _gf()
     d = {k: prob[k].to(DEV) for k in ("I_lo", "p_lo", "I_hi", "dq")}
     print(f"case mode={mode} n={prob['I_lo'].shape[0]} c_in={prob['I_lo'].shape[1]} "
           f"c={prob['p_lo'].shape[1]} hi={tuple(prob['I_hi'].shape[-2:])} r={prob['r']} "
-          f"dtype={prob['io_dtype']} mean_ab={mean_ab} use_stats={use_stats}", flush=True)
+          f"dtype={prob['io_dtype']} mean_ab={mean_ab} use_stats={use_stats} "
+          f"precise={precise}", flush=True)
     stats = None
     if mode == "transform":
         stats = torch.full((gf.gf_guide_stats_count(3),), float("nan"), device=DEV)
     guide = make_guide(gf, mode, prob, stats)
     q = gf.forward(d["I_lo"], d["p_lo"], d["I_hi"], prob["eps"], prob["r"], mean_ab,
-                   guide=guide)
+                   guide=guide, precise=precise)
     out = {"q": q}
     if backward:
         if use_stats:
             guide = make_guide(gf, mode, prob, stats, True)
         dI_lo, dp_lo, dI_hi, deps, dparams = gf.backward(
             d["I_lo"], d["p_lo"], d["I_hi"], prob["eps"], d["dq"], prob["r"], mean_ab,
-            guide=guide)
+            guide=guide, precise=precise)
         out.update(dI_lo=dI_lo, dp_lo=dp_lo, dI_hi=dI_hi, deps=deps)
         if dparams is not None:
             out["dparams"] = dparams
@@ -152,6 +153,20 @@ def test_transform_saved_stats():
 def test_transform_radius(r, mean_ab):
     prob = datagen.make_config(2, div=16, n=2, r=r)
     check(prob, "transform", mean_ab=mean_ab)
+
+
+@pytest.mark.parametrize("mode, r", [("transform", 1), ("transform", 2), ("grey", 1)])
+def test_guided_precise(mode, r):
+    """The precise descriptor on the guided paths: the trainable transform
+    on the config-2 inputs with FP32 I/O (eps = 1e-8), the grey guide."""
+    if mode == "transform":
+        prob = datagen.make_config(2, div=16, n=2, r=r)
+        prob = dict(prob, io_dtype="f32")
+        for k in ("I_lo", "p_lo", "I_hi", "dq"):
+            prob[k] = prob[k].float()
+    else:
+        prob = grey_problem(2, 3, 3, 96, 160, 4, r, 1e-6, "f32", config=131)
+    check(prob, mode, precise=True)
 
 
 def test_transform_hidden_widths():
