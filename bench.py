@@ -169,6 +169,9 @@ def identity_workload(args, dev, prob, dt, name):
 
     from paper_1803_05619_amd import gf, plain
     n, c, H, W, h, w, r = (prob[k] for k in ("n", "c", "H", "W", "h", "w", "r"))
+    pr = bool(args.precise)  # FP64 wide walkers at every radius
+    if pr:
+        name += ", precise walkers (FP64 window sums at every radius)"
     t = {k: prob[k].to(dev) for k in ("I_lo", "p_lo", "I_hi", "dq")}
     eps = torch.tensor(prob["eps"], dtype=torch.float32, device=dev)
     q = torch.empty_like(t["I_hi"])
@@ -176,16 +179,17 @@ def identity_workload(args, dev, prob, dt, name):
             torch.empty(t["p_lo"].shape, dtype=torch.float32, device=dev),
             torch.empty_like(t["I_hi"]),
             torch.empty(1, dtype=torch.float32, device=dev))
-    desc = gf.make_desc(t["I_lo"], t["I_hi"], r)
+    desc = gf.make_desc(t["I_lo"], t["I_hi"], r, precise=pr)
     ws = torch.empty(gf.gf_workspace_size(desc, None, 2), dtype=torch.uint8, device=dev)
 
     def step():
         gf.forward_backward(t["I_lo"], t["p_lo"], t["I_hi"], eps, t["dq"], r, ws=ws,
-                            outs=(q,) + outs)
+                            outs=(q,) + outs, precise=pr)
 
     def separate_step():
-        gf.forward(t["I_lo"], t["p_lo"], t["I_hi"], eps, r, out=q, ws=ws)
-        gf.backward(t["I_lo"], t["p_lo"], t["I_hi"], eps, t["dq"], r, ws=ws, outs=outs)
+        gf.forward(t["I_lo"], t["p_lo"], t["I_hi"], eps, r, out=q, ws=ws, precise=pr)
+        gf.backward(t["I_lo"], t["p_lo"], t["I_hi"], eps, t["dq"], r, ws=ws, outs=outs,
+                    precise=pr)
 
     kb = identity_bytes(n, c, H, W, h, w, BYTES[dt])
     # one gf_forward_backward call: the coefficient pass, one fused high-res
@@ -233,7 +237,7 @@ def identity_workload(args, dev, prob, dt, name):
         return H * W / 1e6, time.perf_counter() - t0, "image 0 of the batch, fwd+bwd once"
 
     def tune():
-        gf.autotune(t["I_lo"], t["p_lo"], t["I_hi"], eps, t["dq"], r=r, iters=5)
+        gf.autotune(t["I_lo"], t["p_lo"], t["I_hi"], eps, t["dq"], r=r, iters=5, precise=pr)
 
     # the layer as a training step would call it: the autograd function's
     # forward (gf_forward) and backward (gf_backward, recomputing the
@@ -244,15 +248,15 @@ def identity_workload(args, dev, prob, dt, name):
     def autograd_step():
         for x in leaves + [eps_leaf]:
             x.grad = None
-        gf.guided_filter(*leaves, r=r, eps=eps_leaf).backward(t["dq"])
+        gf.guided_filter(*leaves, r=r, eps=eps_leaf, precise=pr).backward(t["dq"])
 
     return dict(step=step, separate_step=separate_step, plain_step=plain_step,
                 cpu_sample=cpu_sample, cpu_one=cpu_one, autograd_step=autograd_step,
                 mpx=n * H * W / 1e6, tune=tune,
                 per_step=per_step, step_bytes=step_bytes, dtype=dt,
                 config={"workload": name, "n": n, "c": c, "H": H, "W": W, "s": prob["s"], "r": r,
-                        "eps": float(prob["eps"][0])},
-                traffic_ok=(dt == "f32" and n == 4 and H == 2048 and W == 3072))
+                        "eps": float(prob["eps"][0]), **({"precise": True} if pr else {})},
+                traffic_ok=(dt == "f32" and n == 4 and H == 2048 and W == 3072 and not pr))
 
 
 def workload_2(args, dev):
@@ -781,6 +785,9 @@ def main():
     ap.add_argument("--workload", type=int, default=1, choices=sorted(WORKLOADS))
     ap.add_argument("--radius", type=int, default=None, help="workload 4: radius (default 8)")
     ap.add_argument("--items", type=int, default=64, help="workload 3: images")
+    ap.add_argument("--precise", action="store_true",
+                    help="workloads 1 and 4: the precise option (FP64 wide walkers at every "
+                         "radius)")
     ap.add_argument("--autotune", type=int, default=-1,
                     help="1: run the autotuner on the workload before timing (untimed); "
                          "0: the planner's default shapes; default: 1 for workload 3 (the "
