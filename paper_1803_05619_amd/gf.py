@@ -678,7 +678,10 @@ class BatchPlan:
 def autotune(I_lo, p_lo, I_hi, eps, dq, r=1, mean_ab=True, iters=5, guide=None,
              align_corners=False, precise=False):
     """Times the candidate launch shapes on these buffers and stores the
-    fastest per kernel for this (dtype, factor, radius, guide, mean_ab)."""
+    fastest per kernel for this (dtype, factor, radius, guide, mean_ab).  The
+    key leaves out `precise`: shapes tuned with one walker kind are used by
+    the other as well (every candidate is valid for both), so tune with the
+    setting that will run."""
     dev = I_hi.device
     desc = make_desc(I_lo, I_hi, r, mean_ab, c=p_lo.shape[1], align_corners=align_corners,
                      precise=precise)
