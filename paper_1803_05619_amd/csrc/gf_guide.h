@@ -72,8 +72,8 @@ __global__ __launch_bounds__(256) void moments_kernel(MomArgs a) {
   const float s0 = to_f(X[0]), s1 = to_f(X[a.P]), s2 = to_f(X[2 * a.P]);
   const TX* xb = X + (size_t)b * 3 * a.P;
   float acc[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  for (long long p = (long long)chunk * 256 + tid; p < a.P; p += (long long)gridDim.x * 256) {
-    const float d0 = to_f(xb[p]) - s0, d1 = to_f(xb[a.P + p]) - s1, d2 = to_f(xb[2 * a.P + p]) - s2;
+  auto add = [&](float x0, float x1, float x2) __attribute__((always_inline)) {
+    const float d0 = x0 - s0, d1 = x1 - s1, d2 = x2 - s2;
     acc[0] += d0;
     acc[1] += d1;
     acc[2] += d2;
@@ -83,7 +83,28 @@ __global__ __launch_bounds__(256) void moments_kernel(MomArgs a) {
     acc[6] += d1 * d1;
     acc[7] += d1 * d2;
     acc[8] += d2 * d2;
+  };
+  const long long stride = (long long)gridDim.x * 256;
+  long long p0 = 0;
+  // four pixels per thread and step (one 4-element vector load per plane)
+  // when the planes are whole vectors and aligned; any other pixels one by one
+  constexpr int kV = 4;
+  if (a.P % kV == 0 && reinterpret_cast<uintptr_t>(X) % (kV * sizeof(TX)) == 0) {
+    typedef typename Carrier<sizeof(TX) * kV>::type C;
+    for (long long v = (long long)chunk * 256 + tid; v < a.P / kV; v += stride) {
+      TX t[3][kV];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const C c = *reinterpret_cast<const C*>(xb + k * a.P + kV * v);
+        __builtin_memcpy(t[k], &c, sizeof(C));
+      }
+#pragma unroll
+      for (int e = 0; e < kV; ++e) add(to_f(t[0][e]), to_f(t[1][e]), to_f(t[2][e]));
+    }
+    p0 = a.P;
   }
+  for (long long p = p0 + (long long)chunk * 256 + tid; p < a.P; p += stride)
+    add(to_f(xb[p]), to_f(xb[a.P + p]), to_f(xb[2 * a.P + p]));
 #pragma unroll
   for (int k = 0; k < 9; ++k) red[k][tid] = acc[k];
   __syncthreads();
