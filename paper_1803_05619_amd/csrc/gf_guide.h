@@ -407,6 +407,7 @@ struct GBwdArgs {
   int c_in, c;
   const float* fold;
   const uint16_t* mask;  // transform: the map's leaky-ReLU branches
+  int hidden;            // transform: hidden channels (the rest of kKP are zero)
 };
 
 template <typename TX, typename TDX, int MODE>
@@ -486,21 +487,27 @@ __global__ __launch_bounds__(256) void guide_bwd_kernel(GBwdArgs a) {
     }
 #pragma unroll
     for (int k = 0; k < kKP; ++k) {
+      // the padding channels have zero weights and add nothing: skipped
+      // behind a uniform (scalar) branch, the loop staying fully unrolled so
+      // that every accumulator index is a constant
+      if (k < a.hidden) {
       const float4 u = cc[2 * k], v = cc[2 * k + 1];
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
         const float y = u.w + u.x * x[j][0] + u.y * x[j][1] + u.z * x[j][2];
-        const bool pos = (mb[j] >> k) & 1u;
-        const float z = pos ? y : slope * y;
+        // the branch's factor, selected once for z and dy (x 1 is exact)
+        const float sl = (mb[j] >> k) & 1u ? 1.f : slope;
+        const float z = y * sl;
         acc[AC_DGZ + k] += d[j][0] * z;
         acc[AC_DGZ + kKP + k] += d[j][1] * z;
         acc[AC_DGZ + 2 * kKP + k] += d[j][2] * z;
         const float dz = v.x * d[j][0] + v.y * d[j][1] + v.z * d[j][2];
-        const float dy = pos ? dz : slope * dz;
+        const float dy = dz * sl;
         acc[AC_DY + k] += dy;
         acc[AC_DYX + 3 * k] += dy * xc[j][0];
         acc[AC_DYX + 3 * k + 1] += dy * xc[j][1];
         acc[AC_DYX + 3 * k + 2] += dy * xc[j][2];
+      }
       }
     }
   }
@@ -744,7 +751,7 @@ hipError_t guided_input_grad(const Plan& p, const void* x, const float* dG, void
                              hipStream_t s) {
   const long long P = lo ? (long long)p.h * p.w : (long long)p.H * p.W;
   const int chunks = lo ? p.g_chunks_lo : p.g_chunks_hi;
-  GBwdArgs g{x, dG, dx, part, P, p.c_in, p.c, fold, mask};
+  GBwdArgs g{x, dG, dx, part, P, p.c_in, p.c, fold, mask, p.hidden};
   prof_begin(lo ? "gf_guide_dx_lo" : "gf_guide_dx_hi", s);
   if (p.gmode == GF_GUIDE_GREY) {
     if (lo)
@@ -813,7 +820,8 @@ hipError_t backward_guided_t(const Plan& p, const BwdArgs& b, hipStream_t s) {
       const int chunks = lo ? p.g_chunks_lo : p.g_chunks_hi;
       GBwdArgs g{lo ? b.I_lo : b.I_hi, lo ? dGl : dGh, nullptr, part + (lo ? 0 : half), P,
                  p.c_in, p.c, fold + call * kFoldFloats,
-                 reinterpret_cast<const uint16_t*>(b.ws + (lo ? p.off_mlo : p.off_mhi))};
+                 reinterpret_cast<const uint16_t*>(b.ws + (lo ? p.off_mlo : p.off_mhi)),
+                 p.hidden};
       prof_begin("gf_guide_bwd", s);
       hipLaunchKernelGGL((guide_bwd_kernel<T, float, GF_GUIDE_TRANSFORM>), dim3(chunks, p.n),
                          dim3(256), 0, s, g);
